@@ -1,0 +1,149 @@
+"""CPU oracle for the MAP forward-backward decoder (FP64, plain C).
+
+TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It wraps
+``libmapdec_ref.so`` (built from ``mapdec_ref.c`` with gcc) through ctypes
+and shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+# MAPDEC_REF_LIB lets a mutation check load a deliberately broken copy
+LIB_PATH = os.environ.get("MAPDEC_REF_LIB", os.path.join(_HERE, "libmapdec_ref.so"))
+SOURCES = [os.path.join(_HERE, "mapdec_ref.c")]
+
+REF_OK, REF_EINVAL, REF_EDRIFT, REF_ENOPATH, REF_ENOMEM = 0, 1, 2, 3, 4
+
+
+def build() -> str:
+    """Compile the oracle with gcc (portable flags: the library also runs
+    on other hosts)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-o", LIB_PATH] + SOURCES + ["-lm"]
+    subprocess.run(cmd, check=True)
+    return LIB_PATH
+
+
+class _Code(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int), ("n", ctypes.c_int),
+                ("codebook", ctypes.POINTER(ctypes.c_uint8)),
+                ("Pi", ctypes.c_double), ("Pd", ctypes.c_double), ("Ps", ctypes.c_double),
+                ("I", ctypes.c_int), ("M", ctypes.c_int), ("mn", ctypes.c_int)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class _Out(ctypes.Structure):
+    _fields_ = [("app", _dp), ("logp", _dp), ("dparams", _dp), ("dprior", _dp),
+                ("alpha", _dp), ("beta", _dp), ("logA", _dp), ("logB", _dp), ("Z", _dp)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.mapdec_ref_run.argtypes = [ctypes.POINTER(_Code), ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_uint8), _dp, ctypes.c_int,
+                                     ctypes.POINTER(_Out)]
+        L.mapdec_ref_run.restype = ctypes.c_int
+        L.mapdec_ref_lattice.argtypes = [ctypes.POINTER(_Code), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_uint8), ctypes.c_int,
+                                         ctypes.c_int, _dp, _dp]
+        L.mapdec_ref_lattice.restype = ctypes.c_int
+        L.mapdec_ref_check.argtypes = [ctypes.POINTER(_Code)]
+        L.mapdec_ref_check.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int):
+        names = {1: "EINVAL", 2: "EDRIFT", 3: "ENOPATH", 4: "ENOMEM"}
+        super().__init__(f"oracle status {names.get(status, status)}")
+        self.status = status
+
+
+def _ptr(a: Optional[np.ndarray], ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _code(codebook, Pi, Pd, Ps, I, M, mn):
+    cb = np.ascontiguousarray(codebook, dtype=np.uint8)
+    q, n = cb.shape
+    c = _Code(q, n, _ptr(cb, ctypes.c_uint8), float(Pi), float(Pd), float(Ps), int(I),
+              int(M), int(mn))
+    return c, cb
+
+
+def decode(codebook, y, N, Pi, Pd, Ps, I, M, mn, prior=None, *, grad=False,
+           trace=False, literal=False, check=True):
+    """Run the oracle on one frame.  Returns a dict with ``status``, ``logp``,
+    ``app`` (N, q) and, on request, ``dparams`` (3,), ``dprior`` (N, q) and
+    the trace arrays ``alpha``, ``beta`` ((N+1), 2M+1), ``logA``, ``logB``,
+    ``Z``."""
+    c, cb = _code(codebook, Pi, Pd, Ps, I, M, mn)
+    q = c.q
+    yb = np.ascontiguousarray(y, dtype=np.uint8)
+    pr = None if prior is None else np.ascontiguousarray(prior, dtype=np.float64)
+    Mt = 2 * M + 1
+    res = {"app": np.zeros((N, q)), "logp": np.zeros(1)}
+    if grad:
+        res["dparams"] = np.zeros(3)
+        res["dprior"] = np.zeros((N, q))
+    if trace:
+        res["alpha"] = np.zeros((N + 1, Mt))
+        res["beta"] = np.zeros((N + 1, Mt))
+        res["logA"] = np.zeros(N + 1)
+        res["logB"] = np.zeros(N + 1)
+        res["Z"] = np.zeros(N)
+    out = _Out(*[_ptr(res.get(k), ctypes.c_double) for k in
+                 ("app", "logp", "dparams", "dprior", "alpha", "beta", "logA", "logB", "Z")])
+    st = lib().mapdec_ref_run(ctypes.byref(c), int(N), int(yb.shape[0]),
+                              _ptr(yb, ctypes.c_uint8) if yb.size else None,
+                              _ptr(pr, ctypes.c_double), int(bool(literal)), ctypes.byref(out))
+    if st and check:
+        raise OracleError(st)
+    res["status"] = st
+    res["logp"] = float(res["logp"][0])
+    return res
+
+
+def decode_frame(fr, **kw):
+    """Oracle decode of a :class:`paper_1802_08483_amd.workloads.Frame`."""
+    return decode(fr.codebook, fr.y, fr.N, fr.Pi, fr.Pd, fr.Ps, fr.I, fr.M, fr.mn,
+                  prior=fr.prior, **kw)
+
+
+def lattice(codebook, y, s, D, Pi, Pd, Ps, I, M, mn, tangents=False):
+    """R(s, D, delta) for delta in [-mn, mn] (and tangents [w][k])."""
+    c, cb = _code(codebook, Pi, Pd, Ps, I, M, mn)
+    yb = np.ascontiguousarray(y, dtype=np.uint8)
+    Mn = 2 * mn + 1
+    R = np.zeros(Mn)
+    dR = np.zeros((4, Mn)) if tangents else None
+    st = lib().mapdec_ref_lattice(ctypes.byref(c), int(yb.shape[0]),
+                                  _ptr(yb, ctypes.c_uint8) if yb.size else None, int(s),
+                                  int(D), _ptr(R, ctypes.c_double), _ptr(dR, ctypes.c_double))
+    if st:
+        raise OracleError(st)
+    return (R, dR) if tangents else R
+
+
+def check_code(codebook, Pi, Pd, Ps, I, M, mn) -> int:
+    c, cb = _code(codebook, Pi, Pd, Ps, I, M, mn)
+    return lib().mapdec_ref_check(ctypes.byref(c))

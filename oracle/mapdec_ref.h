@@ -1,0 +1,79 @@
+/*
+ * mapdec_ref.h -- plain FP64 CPU oracle for the MAP forward-backward decoder
+ * of J. A. Briffa, "GPU Implementation and Optimization of a Flexible MAP
+ * Decoder for Synchronization Correction" (Sec. II-C, eqs. 1-12).
+ *
+ * TEST INFRASTRUCTURE.  This library exists only to check the GPU decoder.
+ * It is called from the test suite, from the smoke check and from the
+ * benchmark's CPU-baseline leg, never from the product path.  It shares no
+ * source with the GPU library.
+ *
+ * All pointers are host pointers.  Everything is computed in IEEE double.
+ */
+#ifndef MAPDEC_REF_H
+#define MAPDEC_REF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    REF_OK = 0,
+    REF_EINVAL = 1,   /* bad code / channel / state-space parameters       */
+    REF_EDRIFT = 2,   /* |rho - tau| > M: end drift outside the state space */
+    REF_ENOPATH = 3,  /* P(y) = 0 under the truncated channel model         */
+    REF_ENOMEM = 4
+};
+
+/* Code, channel and state-space parameters (Sec. II-A, II-B, II-C). */
+typedef struct {
+    int q;                    /* alphabet size, 2 <= q <= 2^n               */
+    int n;                    /* codeword length in bits                     */
+    const uint8_t *codebook;  /* q*n bytes of 0/1; row D is C(D)             */
+    double Pi, Pd, Ps;        /* insertion, deletion, substitution probs     */
+    int I;                    /* max consecutive insertions per time step    */
+    int M;                    /* frame drift limit: states m in [-M, M]      */
+    int mn;                   /* per-codeword drift change limit [-mn, mn]   */
+} ref_code;
+
+/* Requested outputs; any pointer may be NULL. */
+typedef struct {
+    double *app;      /* N*q   APP L_i(D), row-major [i][D]                  */
+    double *logp;     /* 1     natural log of P(y)                           */
+    double *dparams;  /* 3     d log P(y) / d(Pi, Pd, Ps)  (forward mode)     */
+    double *dprior;   /* N*q   d log P(y) / d prior[i][D]                     */
+    double *alpha;    /* (N+1)*(2M+1) normalised forward metric  [i][m+M]    */
+    double *beta;     /* (N+1)*(2M+1) normalised backward metric [i][m+M]    */
+    double *logA;     /* N+1   log of the product of alpha normalisers        */
+    double *logB;     /* N+1   log of the product of beta normalisers         */
+    double *Z;        /* N     sum over D of the unnormalised APP row         */
+} ref_out;
+
+/* Check code parameters; returns REF_OK or REF_EINVAL. */
+int mapdec_ref_check(const ref_code *c);
+
+/*
+ * Decode one frame.  y: rho bytes of 0/1.  prior: N*q probabilities
+ * [i][D] used as given, or NULL for 1/q.  literal != 0 recomputes every
+ * receiver-metric lattice once per (i, m', D) on the extracted segment (the
+ * decoder as written); literal == 0 memoises the lattice per start index
+ * s = n*i + m'.  Returns a REF_* status.
+ */
+int mapdec_ref_run(const ref_code *c, int N, int rho, const uint8_t *y,
+                   const double *prior, int literal, ref_out *out);
+
+/*
+ * Receiver metric of one lattice: R[k] = R(y[s .. s+n+k) | C(D)) for
+ * k = delta + mn, delta in [-mn, mn] (0 where the segment is invalid).
+ * dR (may be NULL): 4*(2mn+1) forward-mode tangents, [w][k] for
+ * w = (a, d, t1, t0) with a = Pi/2, d = Pd, t1 = Pt(1-Ps), t0 = Pt Ps.
+ */
+int mapdec_ref_lattice(const ref_code *c, int rho, const uint8_t *y, int s, int D,
+                       double *R, double *dR);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,139 @@
+"""Exact brute-force reference for the truncated BSID channel model.
+
+Enumerates every message and, for each, every channel event sequence that
+turns the encoded frame into the received sequence, in exact rational
+arithmetic (``fractions.Fraction``).  It shares nothing with the oracle's
+lattice/forward-backward code: it walks the channel of Sec. II-B event by
+event, and applies the decoder's truncation as constraints on the walk:
+
+  (i)   at most I consecutive insertions at one channel time step;
+  (ii)  inside codeword c (started at received index s = c n + m'), every
+        visited node keeps |(p - t) - m'| <= mn, where t counts input bits
+        and p received bits;
+  (iii) at every codeword boundary the drift p - t lies in [-M, M];
+  plus start drift 0, all of y consumed, and no insertion after the last
+  input bit.
+
+Each path's weight is a monomial in a = Pi/2, d = Pd, t1 = Pt(1 - Ps),
+t0 = Pt Ps.  The walk carries exact derivatives of the path sums with
+respect to (Pi, Pd, Ps) by propagating first-order terms along each edge.
+Only for tiny frames (q^N messages times all event sequences).
+"""
+from __future__ import annotations
+
+import itertools
+from fractions import Fraction
+from functools import lru_cache
+from typing import Optional, Sequence
+
+F0 = Fraction(0)
+
+
+def _edge(wv, dw, sub):
+    """Extend the path sums ``sub`` = (V, dV/dPi, dV/dPd, dV/dPs) by one edge
+    of weight ``wv`` whose derivatives are ``dw``."""
+    V = sub[0]
+    return (wv * V,
+            wv * sub[1] + dw[0] * V,
+            wv * sub[2] + dw[1] * V,
+            wv * sub[3] + dw[2] * V)
+
+
+def _add(x, y):
+    return tuple(a + b for a, b in zip(x, y))
+
+
+def channel_sum(X: Sequence[int], y: Sequence[int], n: int, Pi, Pd, Ps, I: int, M: int, mn: int):
+    """Sum of the weights of all admissible event sequences X -> y, and its
+    derivatives with respect to (Pi, Pd, Ps).  Returns a 4-tuple."""
+    Pi, Pd, Ps = Fraction(Pi), Fraction(Pd), Fraction(Ps)
+    Pt = 1 - Pi - Pd
+    a, d, t1, t0 = Pi / 2, Pd, Pt * (1 - Ps), Pt * Ps
+    # d(weight)/d(Pi, Pd, Ps) of each event kind
+    da = (Fraction(1, 2), F0, F0)
+    dd = (F0, Fraction(1), F0)
+    dt1 = (-(1 - Ps), -(1 - Ps), -Pt)
+    dt0 = (-Ps, -Ps, Pt)
+    tau, rho = len(X), len(y)
+    zero = (F0, F0, F0, F0)
+
+    @lru_cache(maxsize=None)
+    def go(t: int, p: int, k: int, mp: int):
+        # state: t input bits done, p received bits consumed, k insertions so
+        # far at time t, mp = drift at the start of the current codeword
+        if t == tau:
+            return (Fraction(1), F0, F0, F0) if p == rho else zero
+        total = zero
+        # insertion: emit y[p], stay at time t
+        if k < I and p < rho and abs((p + 1 - t) - mp) <= mn:
+            total = _add(total, _edge(a, da, go(t, p + 1, k + 1, mp)))
+
+        def advance(np_):
+            nt = t + 1
+            if abs((np_ - nt) - mp) > mn:
+                return None
+            if nt % n == 0:
+                drift = np_ - nt
+                if abs(drift) > M:
+                    return None
+                return go(nt, np_, 0, drift)
+            return go(nt, np_, 0, mp)
+
+        sub = advance(p)                          # deletion
+        if sub is not None:
+            total = _add(total, _edge(d, dd, sub))
+        if p < rho:                               # transmission
+            sub = advance(p + 1)
+            if sub is not None:
+                if y[p] == X[t]:
+                    total = _add(total, _edge(t1, dt1, sub))
+                else:
+                    total = _add(total, _edge(t0, dt0, sub))
+        return total
+
+    return go(0, 0, 0, 0)
+
+
+def brute(codebook, y, N: int, Pi, Pd, Ps, I: int, M: int, mn: int,
+          prior: Optional[Sequence[Sequence]] = None):
+    """Exact P(y), APPs, d log P / d(Pi, Pd, Ps) and d log P / d prior.
+
+    ``codebook``: q rows of n bits; ``prior``: N x q (Fractions or ints/
+    floats converted exactly), default 1/q."""
+    q = len(codebook)
+    n = len(codebook[0])
+    if prior is None:
+        prior = [[Fraction(1, q)] * q for _ in range(N)]
+    else:
+        prior = [[Fraction(v) for v in row] for row in prior]
+    P = F0
+    dP = [F0, F0, F0]
+    num = [[F0] * q for _ in range(N)]          # sum over messages with D_i = D
+    dpr = [[F0] * q for _ in range(N)]          # d P / d prior_i(D)
+    for msg in itertools.product(range(q), repeat=N):
+        X = [b for D in msg for b in codebook[D]]
+        V, dPi, dPd, dPs = channel_sum(X, y, n, Pi, Pd, Ps, I, M, mn)
+        if V == 0 and dPi == 0 and dPd == 0 and dPs == 0:
+            continue
+        pw = Fraction(1)
+        for i, D in enumerate(msg):
+            pw *= prior[i][D]
+        P += pw * V
+        dP[0] += pw * dPi
+        dP[1] += pw * dPd
+        dP[2] += pw * dPs
+        for i, D in enumerate(msg):
+            num[i][D] += pw * V
+            rest = Fraction(1)
+            for j, E in enumerate(msg):
+                if j != i:
+                    rest *= prior[j][E]
+            dpr[i][D] += rest * V
+    if P == 0:
+        return {"P": P}
+    return {
+        "P": P,
+        "app": [[num[i][D] / P for D in range(q)] for i in range(N)],
+        "dparams": [g / P for g in dP],
+        "dprior": [[dpr[i][D] / P for D in range(q)] for i in range(N)],
+    }
