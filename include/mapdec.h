@@ -1,0 +1,188 @@
+/*
+ * mapdec.h -- MAP forward-backward decoder for a fixed inner codebook on the
+ * binary substitution / insertion / deletion (BSID) channel, on AMD gfx950.
+ *
+ * The decoder computes, for a received frame y of rho bits that carried N
+ * q-ary symbols D_0..D_{N-1} each encoded as an n-bit codeword C(D)
+ * (Sec. II-A), the a-posteriori probabilities L_i(D) = P(D_i = D | y) of
+ * eqs. 1-3 and log P(y), by the forward/backward recursions of eqs. 4-5 over
+ * the frame drift m in [-M, M], with the state-transition metric of eq. 6
+ * and the receiver metric of the corridor-constrained bit lattice of
+ * eqs. 7-10 (per-codeword drift change in [-mn, mn]), normalised per step as
+ * in eqs. 11-12.  An insertion cap I limits the number of consecutive
+ * insertions at one channel time step.  mapdec_grad also returns the
+ * gradient of log P(y) with respect to (Pi, Pd, Ps) and to the priors.
+ *
+ * Conventions for every call:
+ *   - All functions are plain C and never throw.  Status codes are the
+ *     MAPDEC_* values below; mapdec_strerror() names them.
+ *   - Pointers documented as "device" are HIP device pointers (e.g. from
+ *     hipMalloc or a torch tensor on the GPU) owned by the caller.  Pointers
+ *     documented as "host" are ordinary host memory owned by the caller.
+ *   - "stream" arguments are hipStream_t values passed as void* (NULL = the
+ *     default stream).  Work is enqueued asynchronously on that stream.
+ *   - precision: MAPDEC_FP64 computes everything in double precision (the
+ *     plain decoder); MAPDEC_FP32 computes the bulk arithmetic in single
+ *     precision with per-step normalisation, and keeps log-normalisers and
+ *     gradient reductions in double precision.
+ */
+#ifndef MAPDEC_H
+#define MAPDEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MAPDEC_VERSION 100
+
+enum {
+    MAPDEC_OK = 0,
+    MAPDEC_EINVAL = 1,       /* invalid argument or code/channel parameters       */
+    MAPDEC_EDRIFT = 2,       /* a frame's end drift rho - n N lies outside [-M, M] */
+    MAPDEC_ENOPATH = 3,      /* P(y) = 0 under the truncated channel model         */
+    MAPDEC_ENOMEM = 4,       /* host or device allocation failed                   */
+    MAPDEC_ESIZE = 5,        /* workspace smaller than mapdec_workspace_size()     */
+    MAPDEC_EDEVICE = 6,      /* a HIP runtime call failed                          */
+    MAPDEC_EUNSUPPORTED = 7  /* parameters beyond this build's kernel limits       */
+};
+
+enum { MAPDEC_FP32 = 0, MAPDEC_FP64 = 1 };
+
+/* Flags for mapdec_workspace_size / mapdec_plan_create. */
+enum {
+    MAPDEC_FLAG_GRAD = 1,    /* the plan will also compute gradients        */
+    MAPDEC_FLAG_GRAPH = 2    /* replay the plan's launches as a HIP graph    */
+};
+
+/* Kernel limits of this build: n <= MAPDEC_MAX_N, mn <= MAPDEC_MAX_MN,
+ * q <= MAPDEC_MAX_Q; beyond them decode calls return MAPDEC_EUNSUPPORTED. */
+#define MAPDEC_MAX_N 16
+#define MAPDEC_MAX_MN 8
+#define MAPDEC_MAX_Q 64
+
+typedef struct mapdec_code mapdec_code;
+
+/*
+ * mapdec_create -- an immutable code + channel + state-space description.
+ *
+ * q, n       alphabet size and codeword length (Sec. II-A): 2 <= q <= 2^n.
+ * codebook   host, q*n bytes of 0/1; row D (bytes D*n .. D*n+n-1) is the
+ *            codeword C(D) in transmission order.  Codewords must be
+ *            distinct (the encoding is injective).  The bytes are copied.
+ * Pi, Pd, Ps insertion, deletion and substitution probabilities of the BSID
+ *            channel (Sec. II-B): Pi, Pd, Ps >= 0, Pi + Pd < 1, Ps <= 1.
+ *            The lattice weights are Pi/2 per inserted bit, Pd per deleted
+ *            bit, Pt(1-Ps) / Pt Ps per transmitted bit received equal /
+ *            flipped, Pt = 1 - Pi - Pd (eqs. 7-10).
+ * I          maximum number of consecutive insertions at one channel time
+ *            step, I >= 0.  (For I >= 2 mn the cap never binds.)
+ * M          frame drift limit: drift states m in [-M, M] at codeword
+ *            boundaries (Sec. II-C, m_tau^- = -M, m_tau^+ = M).
+ * mn         per-codeword drift limit: every lattice node stays within
+ *            [-mn, mn] of the codeword's start drift (the corridor of
+ *            Sec. II-C, m_n^- = -mn, m_n^+ = mn); 0 <= mn <= M.
+ * Returns NULL on failure; mapdec_last_error() then gives MAPDEC_EINVAL or
+ * MAPDEC_ENOMEM.  Host-only: no device memory is touched.  A handle may be
+ * shared by any number of frames, plans and threads.
+ */
+mapdec_code *mapdec_create(int q, int n, const uint8_t *codebook, double Pi, double Pd,
+                           double Ps, int I, int M, int mn);
+
+/* Frees a handle.  NULL is a no-op.  Plans that use it must be destroyed first. */
+void mapdec_destroy(mapdec_code *code);
+
+/*
+ * One frame of a batch.  Frames of one batch may use different codes.
+ *   code   the frame's code handle.
+ *   N      number of symbols, N >= 1 (frame length tau = n N bits).
+ *   rho    number of received bits, rho >= 0, |rho - tau| <= M.
+ *   y      device, rho bytes of 0/1 (received bits in order).
+ *   prior  device, N*q prior probabilities P(D_i = D) row-major [i][D]
+ *          (float for MAPDEC_FP32, double for MAPDEC_FP64), used as given;
+ *          NULL means 1/q for every entry (eq. 6).
+ *   app    device, N*q output APPs [i][D] in the same type as prior, or NULL.
+ *   dprior device, N*q output d log P(y) / d prior[i][D] (gradient calls
+ *          only), same type, or NULL.
+ */
+typedef struct {
+    const mapdec_code *code;
+    int32_t N;
+    int32_t rho;
+    const uint8_t *y;
+    const void *prior;
+    void *app;
+    void *dprior;
+} mapdec_frame;
+
+/*
+ * mapdec_workspace_size -- bytes of device workspace that a decode (or,
+ * with MAPDEC_FLAG_GRAD, a gradient) of these frames needs.  frames: host
+ * array of nframes entries.  Returns 0 if the frames are invalid.
+ */
+size_t mapdec_workspace_size(const mapdec_frame *frames, int nframes, int precision,
+                             int flags);
+
+/*
+ * mapdec_decode -- APPs and log P(y) of every frame (eqs. 1-12).
+ *   frames   host array of nframes frame descriptions.
+ *   logp     device, nframes doubles: natural log of P(y) per frame.
+ *   status   device, nframes int32: MAPDEC_OK, or MAPDEC_ENOPATH when
+ *            P(y) = 0 (then that frame's logp is -inf and its APP row
+ *            contents are unspecified).
+ *   ws       device workspace of ws_bytes >= mapdec_workspace_size(...).
+ * The return value reports host-side validation (MAPDEC_EINVAL,
+ * MAPDEC_EDRIFT, MAPDEC_ESIZE, MAPDEC_EUNSUPPORTED) or a launch failure
+ * (MAPDEC_EDEVICE); per-frame results come through status.  Nothing is
+ * enqueued unless the return value is MAPDEC_OK.
+ */
+int mapdec_decode(const mapdec_frame *frames, int nframes, double *logp, int32_t *status,
+                  void *ws, size_t ws_bytes, int precision, void *stream);
+
+/*
+ * mapdec_grad -- everything mapdec_decode computes, plus the gradient of
+ * log P(y) with M, mn and I held fixed and Pt = 1 - Pi - Pd:
+ *   dparams  device, 3*nframes doubles: d log P / d(Pi, Pd, Ps) per frame.
+ *   frames[f].dprior receives d log P / d prior[i][D] when non-NULL.
+ * checkpoint_K: 0 stores every normalised forward metric; K > 0 stores one
+ * row every K symbols and recomputes the others, with the receiver metric,
+ * segment by segment in the backward pass (memory-bounded mode).
+ * Workspace from mapdec_workspace_size(..., flags | MAPDEC_FLAG_GRAD).
+ */
+int mapdec_grad(const mapdec_frame *frames, int nframes, double *logp, double *dparams,
+                int32_t *status, void *ws, size_t ws_bytes, int checkpoint_K, int precision,
+                void *stream);
+
+/*
+ * Plans: the same work as mapdec_decode / mapdec_grad, with validation,
+ * workspace layout and descriptor upload done once at creation and every
+ * later run replaying the same launches (as one HIP graph with
+ * MAPDEC_FLAG_GRAPH).  A plan keeps pointers to the caller's buffers (y,
+ * prior, app, dprior, logp, status, dparams, ws): they must stay valid
+ * until mapdec_plan_destroy; their contents may change between runs.
+ * dparams is used only with MAPDEC_FLAG_GRAD (may be NULL otherwise).
+ * Returns NULL on failure (see mapdec_last_error()).  The descriptor upload
+ * is enqueued on stream.
+ */
+typedef struct mapdec_plan mapdec_plan;
+
+mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double *logp,
+                                double *dparams, int32_t *status, void *ws, size_t ws_bytes,
+                                int precision, int flags, int checkpoint_K, void *stream);
+int mapdec_plan_run(mapdec_plan *plan, void *stream);
+/* Waits for the plan's pending work and frees it.  NULL is a no-op. */
+void mapdec_plan_destroy(mapdec_plan *plan);
+
+/* Status of the calling thread's last failed mapdec_create / plan_create. */
+int mapdec_last_error(void);
+/* Static string naming a status code. */
+const char *mapdec_strerror(int status);
+/* MAPDEC_VERSION of the library. */
+int mapdec_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

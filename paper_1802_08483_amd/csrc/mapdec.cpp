@@ -1,0 +1,393 @@
+// Host side of libmapdec: validation, workspace layout, descriptor upload,
+// launch sequence and HIP-graph replay.  See include/mapdec.h for the ABI.
+#include "mapdec.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace mapdec;
+
+struct mapdec_code {
+    int q, n, I, M, mn;
+    double Pi, Pd, Ps;
+    std::vector<uint32_t> cw;   // codeword D: bit (n-1-r) = C(D)[r]
+};
+
+namespace {
+
+thread_local int g_last_error = MAPDEC_OK;
+
+int fail(int st) {
+    g_last_error = st;
+    return st;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+int validate_code_params(int q, int n, double Pi, double Pd, double Ps, int I, int M, int mn) {
+    if (n < 1 || n > 30 || q < 2 || q > (1 << n)) return MAPDEC_EINVAL;
+    if (!(Pi >= 0.0) || !(Pd >= 0.0) || !(Ps >= 0.0) || !(Ps <= 1.0)) return MAPDEC_EINVAL;
+    if (!(Pi + Pd < 1.0)) return MAPDEC_EINVAL;
+    if (I < 0 || mn < 0 || M < mn) return MAPDEC_EINVAL;
+    return MAPDEC_OK;
+}
+
+// Sizes of one frame's workspace pieces.
+struct FrameLayout {
+    int nwords, sp, Mt, Mn, lat_blocks, pack_blocks, gamma_blocks;
+    size_t off_cw, off_ybits, off_R, off_G, off_alpha, off_beta, off_logA, off_logB, off_Zinv,
+        off_gacc, end;
+};
+
+struct Layout {
+    int nframes = 0, fp64 = 0, grad = 0;
+    size_t tsize = 4;
+    size_t off_fd = 0, off_pack = 0, off_gamma = 0, off_chain = 0, off_app = 0, head = 0, total = 0;
+    int n_pack = 0, n_gamma = 0, n_app = 0;
+    // lattice work grouped by template instance (mn, imode)
+    std::map<std::pair<int, int>, std::vector<Work>> lat;
+    std::map<std::pair<int, int>, size_t> off_lat;
+    size_t chain_lds = 0, app_lds = 0;
+    std::vector<FrameLayout> fl;
+};
+
+int frame_imode(const mapdec_code *c) { return c->I <= 2 ? 0 : 1; }
+
+// Validates the frames and lays out the workspace.
+int build_layout(const mapdec_frame *frames, int nframes, int precision, int flags, Layout &L) {
+    if (!frames || nframes < 1) return MAPDEC_EINVAL;
+    if (precision != MAPDEC_FP32 && precision != MAPDEC_FP64) return MAPDEC_EINVAL;
+    L.nframes = nframes;
+    L.fp64 = precision == MAPDEC_FP64;
+    L.grad = (flags & MAPDEC_FLAG_GRAD) != 0;
+    L.tsize = L.fp64 ? 8 : 4;
+    L.fl.resize(nframes);
+    size_t max_chain = 0, max_app = 0;
+    for (int f = 0; f < nframes; ++f) {
+        const mapdec_frame &fr = frames[f];
+        const mapdec_code *c = fr.code;
+        if (!c || fr.N < 1 || fr.rho < 0 || (fr.rho > 0 && !fr.y)) return MAPDEC_EINVAL;
+        const long long tau = (long long)c->n * fr.N;
+        if (tau > (1LL << 30) || fr.rho > (1 << 30)) return MAPDEC_EUNSUPPORTED;
+        if (std::llabs((long long)fr.rho - tau) > c->M) return MAPDEC_EDRIFT;
+        if (c->n > kMaxN || c->mn > kMaxMn || c->q > kMaxQ) return MAPDEC_EUNSUPPORTED;
+        FrameLayout &F = L.fl[f];
+        F.Mt = 2 * c->M + 1;
+        F.Mn = 2 * c->mn + 1;
+        F.sp = (int)(((size_t)fr.rho + 1 + 63) / 64 * 64);
+        F.nwords = (fr.rho + 63) / 32 + 2;
+        F.pack_blocks = (F.nwords + kPackWords - 1) / kPackWords;
+        F.lat_blocks = (fr.rho + 1 + kLatticeLanes - 1) / kLatticeLanes;
+        F.gamma_blocks = fr.prior ? fr.N * ((F.Mt + kGammaLanes - 1) / kGammaLanes) : 0;
+        L.n_pack += F.pack_blocks;
+        L.n_gamma += F.gamma_blocks;
+        L.n_app += fr.N;
+        const size_t W = (size_t)F.Mt + 2 * c->mn;
+        max_chain = std::max(max_chain, ((2 * W * L.tsize + 15) & ~(size_t)15) + 16 * sizeof(double));
+        max_app = std::max(max_app, (2 * (size_t)F.Mt + 2 * c->mn + c->q) * L.tsize);
+        auto key = std::make_pair(c->mn, frame_imode(c));
+        auto &v = L.lat[key];
+        for (int b = 0; b < F.lat_blocks; ++b) v.push_back(Work{f, b * kLatticeLanes});
+    }
+    if (max_chain > 65536 || max_app > 65536) return MAPDEC_EUNSUPPORTED;
+    L.chain_lds = max_chain;
+    L.app_lds = max_app;
+
+    // head: descriptors and work tables
+    size_t off = 0;
+    L.off_fd = off;
+    off = align_up(off + sizeof(FrameDesc) * nframes);
+    L.off_pack = off;
+    off = align_up(off + sizeof(Work) * L.n_pack);
+    for (auto &kv : L.lat) {
+        L.off_lat[kv.first] = off;
+        off = align_up(off + sizeof(Work) * kv.second.size());
+    }
+    L.off_gamma = off;
+    off = align_up(off + sizeof(Work) * L.n_gamma);
+    L.off_chain = off;
+    off = align_up(off + sizeof(int) * nframes);
+    L.off_app = off;
+    off = align_up(off + sizeof(Work) * L.n_app);
+    L.head = off;
+
+    // per-frame regions
+    for (int f = 0; f < nframes; ++f) {
+        const mapdec_frame &fr = frames[f];
+        const mapdec_code *c = fr.code;
+        FrameLayout &F = L.fl[f];
+        const size_t T = L.tsize;
+        F.off_cw = off;
+        off = align_up(off + sizeof(uint32_t) * c->q);
+        F.off_ybits = off;
+        off = align_up(off + sizeof(uint32_t) * F.nwords);
+        F.off_R = off;
+        off = align_up(off + T * c->q * F.Mn * (size_t)F.sp);
+        F.off_G = off;
+        off = align_up(off + T * (fr.prior ? (size_t)fr.N * F.Mn * F.Mt : (size_t)F.Mn * F.sp));
+        F.off_alpha = off;
+        off = align_up(off + T * (size_t)(fr.N + 1) * F.Mt);
+        F.off_beta = off;
+        off = align_up(off + T * (size_t)(fr.N + 1) * F.Mt);
+        F.off_logA = off;
+        off = align_up(off + sizeof(double) * (fr.N + 1));
+        F.off_logB = off;
+        off = align_up(off + sizeof(double) * (fr.N + 1));
+        F.off_Zinv = off;
+        off = align_up(off + sizeof(double) * fr.N);
+        F.off_gacc = off;
+        off = align_up(off + sizeof(double) * 4);
+        F.end = off;
+    }
+    L.total = off;
+    return MAPDEC_OK;
+}
+
+}  // namespace
+
+struct mapdec_plan {
+    Layout L;
+    unsigned char *ws = nullptr;
+    int flags = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool ran = false;
+
+    template <typename P>
+    P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
+
+    hipError_t enqueue(hipStream_t st) const {
+        const FrameDesc *fd = at<FrameDesc>(L.off_fd);
+        hipError_t e = launch_init(fd, L.nframes, st);
+        if (e == hipSuccess) e = launch_pack(fd, at<Work>(L.off_pack), L.n_pack, st);
+        for (auto &kv : L.lat) {
+            if (e != hipSuccess) break;
+            e = launch_lattice(L.fp64, kv.first.first, kv.first.second, fd,
+                               at<Work>(L.off_lat.at(kv.first)), (int)kv.second.size(), st);
+        }
+        if (e == hipSuccess) e = launch_gamma(L.fp64, fd, at<Work>(L.off_gamma), L.n_gamma, st);
+        if (e == hipSuccess)
+            e = launch_chain(L.fp64, fd, at<int>(L.off_chain), L.nframes, L.chain_lds, st);
+        if (e == hipSuccess)
+            e = launch_app(L.fp64, fd, at<Work>(L.off_app), L.n_app, L.app_lds, st);
+        return e;
+    }
+};
+
+extern "C" {
+
+mapdec_code *mapdec_create(int q, int n, const uint8_t *codebook, double Pi, double Pd,
+                           double Ps, int I, int M, int mn) {
+    if (!codebook || validate_code_params(q, n, Pi, Pd, Ps, I, M, mn) != MAPDEC_OK) {
+        fail(MAPDEC_EINVAL);
+        return nullptr;
+    }
+    mapdec_code *c = new (std::nothrow) mapdec_code;
+    if (!c) {
+        fail(MAPDEC_ENOMEM);
+        return nullptr;
+    }
+    c->q = q; c->n = n; c->I = I; c->M = M; c->mn = mn;
+    c->Pi = Pi; c->Pd = Pd; c->Ps = Ps;
+    c->cw.resize(q);
+    for (int D = 0; D < q; ++D) {
+        uint32_t w = 0;
+        for (int r = 0; r < n; ++r) {
+            const uint8_t b = codebook[(size_t)D * n + r];
+            if (b > 1) {
+                delete c;
+                fail(MAPDEC_EINVAL);
+                return nullptr;
+            }
+            w |= (uint32_t)b << (n - 1 - r);
+        }
+        c->cw[D] = w;
+    }
+    std::vector<uint32_t> sorted = c->cw;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) {
+        delete c;
+        fail(MAPDEC_EINVAL);   // the encoding must be injective
+        return nullptr;
+    }
+    return c;
+}
+
+void mapdec_destroy(mapdec_code *code) { delete code; }
+
+size_t mapdec_workspace_size(const mapdec_frame *frames, int nframes, int precision, int flags) {
+    Layout L;
+    if (build_layout(frames, nframes, precision, flags, L) != MAPDEC_OK) return 0;
+    return L.total;
+}
+
+mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double *logp,
+                                double *dparams, int32_t *status, void *ws, size_t ws_bytes,
+                                int precision, int flags, int checkpoint_K, void *stream) {
+    if (!logp || !status || !ws || checkpoint_K < 0 ||
+        ((flags & MAPDEC_FLAG_GRAD) && !dparams)) {
+        fail(MAPDEC_EINVAL);
+        return nullptr;
+    }
+    if (flags & MAPDEC_FLAG_GRAD) {   // the adjoint is not part of this build yet
+        fail(MAPDEC_EUNSUPPORTED);
+        return nullptr;
+    }
+    mapdec_plan *p = new (std::nothrow) mapdec_plan;
+    if (!p) {
+        fail(MAPDEC_ENOMEM);
+        return nullptr;
+    }
+    int st = build_layout(frames, nframes, precision, flags, p->L);
+    if (st == MAPDEC_OK && ws_bytes < p->L.total) st = MAPDEC_ESIZE;
+    if (st != MAPDEC_OK) {
+        delete p;
+        fail(st);
+        return nullptr;
+    }
+    const Layout &L = p->L;
+    p->ws = static_cast<unsigned char *>(ws);
+    p->flags = flags;
+
+    // descriptors, work tables and codewords, staged on the host
+    std::vector<unsigned char> stage(L.head, 0);
+    FrameDesc *fd = reinterpret_cast<FrameDesc *>(stage.data() + L.off_fd);
+    Work *pack = reinterpret_cast<Work *>(stage.data() + L.off_pack);
+    Work *gam = reinterpret_cast<Work *>(stage.data() + L.off_gamma);
+    int *chain = reinterpret_cast<int *>(stage.data() + L.off_chain);
+    Work *app = reinterpret_cast<Work *>(stage.data() + L.off_app);
+    int ip = 0, ig = 0, ia = 0;
+    unsigned char *base = p->ws;
+    for (int f = 0; f < nframes; ++f) {
+        const mapdec_frame &fr = frames[f];
+        const mapdec_code *c = fr.code;
+        const FrameLayout &F = L.fl[f];
+        FrameDesc &d = fd[f];
+        d.q = c->q; d.n = c->n; d.N = fr.N; d.rho = fr.rho;
+        d.M = c->M; d.mn = c->mn; d.I = c->I; d.tau = c->n * fr.N;
+        d.Mt = F.Mt; d.Mn = F.Mn; d.sp = F.sp; d.uniform = fr.prior ? 0 : 1;
+        d.nwords = F.nwords; d.imode = frame_imode(c); d.grad = L.grad; d.ck = 0;
+        const double Pt = 1.0 - c->Pi - c->Pd;
+        d.a = 0.5 * c->Pi; d.d = c->Pd; d.t1 = Pt * (1.0 - c->Ps); d.t0 = Pt * c->Ps;
+        d.y = fr.y; d.prior = fr.prior; d.app = fr.app; d.dprior = fr.dprior;
+        d.logp = logp + f; d.status = status + f;
+        d.dparams = dparams ? dparams + 3 * f : nullptr;
+        d.cw = reinterpret_cast<uint32_t *>(base + F.off_cw);
+        d.ybits = reinterpret_cast<uint32_t *>(base + F.off_ybits);
+        d.R = base + F.off_R;
+        d.G = base + F.off_G;
+        d.alpha = base + F.off_alpha;
+        d.beta = base + F.off_beta;
+        d.logA = reinterpret_cast<double *>(base + F.off_logA);
+        d.logB = reinterpret_cast<double *>(base + F.off_logB);
+        d.Zinv = L.grad ? reinterpret_cast<double *>(base + F.off_Zinv) : nullptr;
+        d.gacc = reinterpret_cast<double *>(base + F.off_gacc);
+        for (int b = 0; b < F.pack_blocks; ++b) pack[ip++] = Work{f, b * kPackWords};
+        for (int b = 0; b < F.gamma_blocks; ++b) gam[ig++] = Work{f, b};
+        chain[f] = f;
+        for (int i = 0; i < fr.N; ++i) app[ia++] = Work{f, i};
+    }
+    for (auto &kv : L.lat)
+        std::memcpy(stage.data() + L.off_lat.at(kv.first), kv.second.data(),
+                    sizeof(Work) * kv.second.size());
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(p->ws, stage.data(), L.head, hipMemcpyHostToDevice, s);
+    // codewords go straight into each frame's region
+    for (int f = 0; f < nframes && e == hipSuccess; ++f)
+        e = hipMemcpyAsync(base + L.fl[f].off_cw, frames[f].code->cw.data(),
+                           sizeof(uint32_t) * frames[f].code->q, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete p;
+        fail(MAPDEC_EDEVICE);
+        return nullptr;
+    }
+    return p;
+}
+
+int mapdec_plan_run(mapdec_plan *p, void *stream) {
+    if (!p) return MAPDEC_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (p->flags & MAPDEC_FLAG_GRAPH) {
+        if (!p->exec) {
+            if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t e2 = p->enqueue(p->cap_stream);
+                e = hipStreamEndCapture(p->cap_stream, &p->graph);
+                if (e2 != hipSuccess) e = e2;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        }
+        if (e == hipSuccess) e = hipGraphLaunch(p->exec, s);
+    } else {
+        e = p->enqueue(s);
+    }
+    p->last_stream = s;
+    p->ran = true;
+    return e == hipSuccess ? MAPDEC_OK : MAPDEC_EDEVICE;
+}
+
+void mapdec_plan_destroy(mapdec_plan *p) {
+    if (!p) return;
+    if (p->exec) {
+        hipStreamSynchronize(p->last_stream);
+        hipGraphExecDestroy(p->exec);
+    }
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+    delete p;
+}
+
+int mapdec_decode(const mapdec_frame *frames, int nframes, double *logp, int32_t *status,
+                  void *ws, size_t ws_bytes, int precision, void *stream) {
+    mapdec_plan *p = mapdec_plan_create(frames, nframes, logp, nullptr, status, ws, ws_bytes,
+                                        precision, 0, 0, stream);
+    if (!p) return g_last_error;
+    int st = mapdec_plan_run(p, stream);
+    mapdec_plan_destroy(p);
+    return st;
+}
+
+int mapdec_grad(const mapdec_frame *frames, int nframes, double *logp, double *dparams,
+                int32_t *status, void *ws, size_t ws_bytes, int checkpoint_K, int precision,
+                void *stream) {
+    mapdec_plan *p = mapdec_plan_create(frames, nframes, logp, dparams, status, ws, ws_bytes,
+                                        precision, MAPDEC_FLAG_GRAD, checkpoint_K, stream);
+    if (!p) return g_last_error;
+    int st = mapdec_plan_run(p, stream);
+    mapdec_plan_destroy(p);
+    return st;
+}
+
+int mapdec_last_error(void) { return g_last_error; }
+
+const char *mapdec_strerror(int status) {
+    switch (status) {
+        case MAPDEC_OK: return "MAPDEC_OK";
+        case MAPDEC_EINVAL: return "MAPDEC_EINVAL: invalid argument";
+        case MAPDEC_EDRIFT: return "MAPDEC_EDRIFT: end drift outside [-M, M]";
+        case MAPDEC_ENOPATH: return "MAPDEC_ENOPATH: P(y) = 0 under the truncated model";
+        case MAPDEC_ENOMEM: return "MAPDEC_ENOMEM: allocation failed";
+        case MAPDEC_ESIZE: return "MAPDEC_ESIZE: workspace too small";
+        case MAPDEC_EDEVICE: return "MAPDEC_EDEVICE: HIP runtime error";
+        case MAPDEC_EUNSUPPORTED: return "MAPDEC_EUNSUPPORTED: beyond this build's kernel limits";
+        default: return "unknown mapdec status";
+    }
+}
+
+int mapdec_version(void) { return MAPDEC_VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,251 @@
+"""ctypes binding of libmapdec (include/mapdec.h).
+
+Argument marshalling only: every step of the decode runs in the HIP
+kernels of ``libmapdec.so``.  PyTorch supplies device memory and streams.
+There is no CPU fallback: without the built library, or without a GPU,
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmapdec.so")
+
+OK, EINVAL, EDRIFT, ENOPATH, ENOMEM, ESIZE, EDEVICE, EUNSUPPORTED = range(8)
+FP32, FP64 = 0, 1
+FLAG_GRAD, FLAG_GRAPH = 1, 2
+MAX_N, MAX_MN = 16, 8
+
+# every symbol include/mapdec.h declares
+EXPORTS = ["mapdec_create", "mapdec_destroy", "mapdec_workspace_size", "mapdec_decode",
+           "mapdec_grad", "mapdec_plan_create", "mapdec_plan_run", "mapdec_plan_destroy",
+           "mapdec_last_error", "mapdec_strerror", "mapdec_version"]
+
+
+class MapdecError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)}" if what else strerror(status))
+
+
+class _Frame(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_void_p), ("N", ctypes.c_int32), ("rho", ctypes.c_int32),
+                ("y", ctypes.c_void_p), ("prior", ctypes.c_void_p), ("app", ctypes.c_void_p),
+                ("dprior", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "paper_1802_08483_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        fp = ctypes.POINTER(_Frame)
+        L.mapdec_create.argtypes = [i32, i32, vp, dbl, dbl, dbl, i32, i32, i32]
+        L.mapdec_create.restype = vp
+        L.mapdec_destroy.argtypes = [vp]
+        L.mapdec_destroy.restype = None
+        L.mapdec_workspace_size.argtypes = [fp, i32, i32, i32]
+        L.mapdec_workspace_size.restype = sz
+        L.mapdec_decode.argtypes = [fp, i32, vp, vp, vp, sz, i32, vp]
+        L.mapdec_decode.restype = i32
+        L.mapdec_grad.argtypes = [fp, i32, vp, vp, vp, vp, sz, i32, i32, vp]
+        L.mapdec_grad.restype = i32
+        L.mapdec_plan_create.argtypes = [fp, i32, vp, vp, vp, vp, sz, i32, i32, i32, vp]
+        L.mapdec_plan_create.restype = vp
+        L.mapdec_plan_run.argtypes = [vp, vp]
+        L.mapdec_plan_run.restype = i32
+        L.mapdec_plan_destroy.argtypes = [vp]
+        L.mapdec_plan_destroy.restype = None
+        L.mapdec_last_error.argtypes = []
+        L.mapdec_last_error.restype = i32
+        L.mapdec_strerror.argtypes = [i32]
+        L.mapdec_strerror.restype = ctypes.c_char_p
+        L.mapdec_version.argtypes = []
+        L.mapdec_version.restype = i32
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().mapdec_strerror(int(status)).decode()
+
+
+class Code:
+    """Owns a ``mapdec_code`` handle (host-only, immutable)."""
+
+    def __init__(self, codebook, Pi: float, Pd: float, Ps: float, I: int, M: int, mn: int):
+        import numpy as np
+        cb = np.ascontiguousarray(np.asarray(codebook, dtype=np.uint8))
+        if cb.ndim != 2:
+            raise ValueError("codebook must be (q, n)")
+        self.q, self.n = int(cb.shape[0]), int(cb.shape[1])
+        self.Pi, self.Pd, self.Ps = float(Pi), float(Pd), float(Ps)
+        self.I, self.M, self.mn = int(I), int(M), int(mn)
+        self._h = lib().mapdec_create(self.q, self.n, cb.ctypes.data, self.Pi, self.Pd,
+                                      self.Ps, self.I, self.M, self.mn)
+        if not self._h:
+            raise MapdecError(lib().mapdec_last_error(), "mapdec_create")
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mapdec_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Batch:
+    """Device buffers and frame table for a batch of frames.
+
+    ``frames``: sequence of (code, y, N, prior) with ``y`` a uint8 CUDA tensor
+    of 0/1 and ``prior`` an (N, q) CUDA tensor of the batch precision or
+    None (uniform).  Allocates the outputs (APP per frame, log P, status,
+    gradient buffers) and the workspace.
+    """
+
+    def __init__(self, frames: Sequence, precision: int = FP32, grad: bool = False,
+                 device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmapdec needs a GPU; no device is visible")
+        self.device = torch.device(device or "cuda")
+        self.precision = precision
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        self.grad = grad
+        self.codes = []
+        self.ys, self.priors, self.apps, self.dpriors = [], [], [], []
+        arr = (_Frame * len(frames))()
+        for f, (code, y, N, prior) in enumerate(frames):
+            if y.dtype != torch.uint8 or not y.is_cuda:
+                raise TypeError("y must be a uint8 CUDA tensor")
+            y = y.contiguous()
+            if prior is not None:
+                if prior.dtype != self.dtype or tuple(prior.shape) != (N, code.q):
+                    raise TypeError("prior must be (N, q) in the batch precision")
+                prior = prior.contiguous()
+            app = torch.empty((N, code.q), dtype=self.dtype, device=self.device)
+            dpr = torch.empty((N, code.q), dtype=self.dtype, device=self.device) if grad else None
+            self.codes.append(code)
+            self.ys.append(y)
+            self.priors.append(prior)
+            self.apps.append(app)
+            self.dpriors.append(dpr)
+            arr[f] = _Frame(code.handle, int(N), int(y.numel()), _ptr(y), _ptr(prior),
+                            _ptr(app), _ptr(dpr))
+        self.frames = arr
+        self.nframes = len(frames)
+        self.logp = torch.empty(self.nframes, dtype=torch.float64, device=self.device)
+        self.status = torch.empty(self.nframes, dtype=torch.int32, device=self.device)
+        self.dparams = (torch.empty((self.nframes, 3), dtype=torch.float64, device=self.device)
+                        if grad else None)
+        flags = FLAG_GRAD if grad else 0
+        self.ws_bytes = lib().mapdec_workspace_size(self.frames, self.nframes, precision, flags)
+        if self.ws_bytes == 0:
+            raise MapdecError(EINVAL, "mapdec_workspace_size")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def decode(self, stream=None):
+        st = lib().mapdec_decode(self.frames, self.nframes, _ptr(self.logp), _ptr(self.status),
+                                 _ptr(self.ws), self.ws_bytes, self.precision,
+                                 _stream_handle(stream))
+        if st:
+            raise MapdecError(st, "mapdec_decode")
+        return self
+
+    def run_grad(self, checkpoint_K: int = 0, stream=None):
+        if not self.grad:
+            raise RuntimeError("batch was built without gradient buffers")
+        st = lib().mapdec_grad(self.frames, self.nframes, _ptr(self.logp), _ptr(self.dparams),
+                               _ptr(self.status), _ptr(self.ws), self.ws_bytes, checkpoint_K,
+                               self.precision, _stream_handle(stream))
+        if st:
+            raise MapdecError(st, "mapdec_grad")
+        return self
+
+    def plan(self, graph: bool = True, checkpoint_K: int = 0, stream=None) -> "Plan":
+        return Plan(self, graph=graph, checkpoint_K=checkpoint_K, stream=stream)
+
+
+class Plan:
+    """A ``mapdec_plan``: the batch's launches recorded once, replayed by run()."""
+
+    def __init__(self, batch: Batch, graph: bool = True, checkpoint_K: int = 0, stream=None):
+        self.batch = batch
+        flags = (FLAG_GRAPH if graph else 0) | (FLAG_GRAD if batch.grad else 0)
+        self._h = lib().mapdec_plan_create(batch.frames, batch.nframes, _ptr(batch.logp),
+                                           _ptr(batch.dparams), _ptr(batch.status),
+                                           _ptr(batch.ws), batch.ws_bytes, batch.precision,
+                                           flags, checkpoint_K, _stream_handle(stream))
+        if not self._h:
+            raise MapdecError(lib().mapdec_last_error(), "mapdec_plan_create")
+
+    def run(self, stream=None):
+        st = lib().mapdec_plan_run(self._h, _stream_handle(stream))
+        if st:
+            raise MapdecError(st, "mapdec_plan_run")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mapdec_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def code_for(frame, cache: Optional[dict] = None) -> Code:
+    """A :class:`Code` for a workloads.Frame (shared when the parameters match)."""
+    key = (frame.codebook.tobytes(), frame.codebook.shape, frame.Pi, frame.Pd, frame.Ps,
+           frame.I, frame.M, frame.mn)
+    if cache is not None and key in cache:
+        return cache[key]
+    c = Code(frame.codebook, frame.Pi, frame.Pd, frame.Ps, frame.I, frame.M, frame.mn)
+    if cache is not None:
+        cache[key] = c
+    return c
+
+
+def batch_from_frames(frames: List, precision: int = FP32, grad: bool = False,
+                      device=None) -> Batch:
+    """Uploads workloads.Frame objects and builds a :class:`Batch`."""
+    dev = torch.device(device or "cuda")
+    dtype = torch.float64 if precision == FP64 else torch.float32
+    cache: dict = {}
+    items = []
+    for fr in frames:
+        code = code_for(fr, cache)
+        y = torch.from_numpy(fr.y).to(dev)
+        prior = None if fr.prior is None else torch.from_numpy(fr.prior).to(dev, dtype)
+        items.append((code, y, fr.N, prior))
+    return Batch(items, precision=precision, grad=grad, device=dev)

@@ -1,0 +1,109 @@
+"""Host-side checks of libmapdec: symbols and argument validation.
+
+No kernel runs here: every call below returns before any HIP work is
+enqueued (validation happens first), so these run without a GPU.  Device
+pointers passed to the library in these tests are never dereferenced.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1802_08483_amd import build as libbuild
+from paper_1802_08483_amd import mapdec
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(libbuild.LIB):
+        libbuild.build()
+    return mapdec.lib()
+
+
+def _declared_functions():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"\b(mapdec_[a-z_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(L):
+    declared = _declared_functions()
+    assert set(declared) == set(mapdec.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+    assert L.mapdec_version() == 100
+    for st in range(8):
+        assert L.mapdec_strerror(st)
+
+
+def _code(q=4, n=3, Pi=0.1, Pd=0.1, Ps=0.01, I=2, M=6, mn=2, cb=None):
+    if cb is None:
+        cb = np.array([[(w >> (n - 1 - r)) & 1 for r in range(n)] for w in range(q)], np.uint8)
+    return mapdec.Code(cb, Pi, Pd, Ps, I, M, mn)
+
+
+@pytest.mark.parametrize("kw", [dict(Pi=0.6, Pd=0.5), dict(Pi=-0.1), dict(Ps=1.5), dict(I=-1),
+                                dict(M=1, mn=2), dict(q=9, n=3), dict(q=1)])
+def test_create_rejects_invalid(L, kw):
+    with pytest.raises(mapdec.MapdecError) as e:
+        _code(**kw)
+    assert e.value.status == mapdec.EINVAL
+
+
+def test_create_rejects_duplicate_and_nonbinary_codewords(L):
+    with pytest.raises(mapdec.MapdecError):
+        _code(q=2, n=2, cb=np.array([[0, 1], [0, 1]], np.uint8))
+    with pytest.raises(mapdec.MapdecError):
+        _code(q=2, n=2, cb=np.array([[0, 2], [1, 1]], np.uint8))
+
+
+def _frames(specs):
+    arr = (mapdec._Frame * len(specs))()
+    for i, (code, N, rho) in enumerate(specs):
+        arr[i] = mapdec._Frame(code.handle, N, rho, 0x1000 if rho else None, None, None, None)
+    return arr
+
+
+def test_workspace_size_and_validation(L):
+    c = _code()
+    fr = _frames([(c, 10, 30), (c, 5, 17)])
+    ws32 = L.mapdec_workspace_size(fr, 2, mapdec.FP32, 0)
+    ws64 = L.mapdec_workspace_size(fr, 2, mapdec.FP64, 0)
+    assert 0 < ws32 < ws64
+    # end drift outside [-M, M]
+    bad = _frames([(c, 10, 30 + 7)])
+    assert L.mapdec_workspace_size(bad, 1, mapdec.FP32, 0) == 0
+    dummy = ctypes.c_void_p(0x1000)
+    st = L.mapdec_decode(bad, 1, dummy, dummy, dummy, 1 << 30, mapdec.FP32, None)
+    assert st == mapdec.EDRIFT
+    # workspace too small
+    st = L.mapdec_decode(fr, 2, dummy, dummy, dummy, ws32 - 1, mapdec.FP32, None)
+    assert st == mapdec.ESIZE
+    # bad precision, no frames, y missing
+    assert L.mapdec_decode(fr, 2, dummy, dummy, dummy, ws32, 7, None) == mapdec.EINVAL
+    assert L.mapdec_decode(fr, 0, dummy, dummy, dummy, ws32, mapdec.FP32, None) == mapdec.EINVAL
+    noy = (mapdec._Frame * 1)()
+    noy[0] = mapdec._Frame(c.handle, 10, 30, None, None, None, None)
+    assert L.mapdec_decode(noy, 1, dummy, dummy, dummy, ws32, mapdec.FP32, None) == mapdec.EINVAL
+
+
+def test_unsupported_sizes(L):
+    big_n = np.zeros((2, 17), np.uint8)
+    big_n[1, 0] = 1
+    c = mapdec.Code(big_n, 0.01, 0.01, 0, 2, 10, 2)
+    fr = _frames([(c, 3, 51)])
+    dummy = ctypes.c_void_p(0x1000)
+    assert L.mapdec_decode(fr, 1, dummy, dummy, dummy, 1 << 30, mapdec.FP32, None) \
+        == mapdec.EUNSUPPORTED
+    c2 = _code(M=20, mn=9)
+    fr2 = _frames([(c2, 10, 30)])
+    assert L.mapdec_decode(fr2, 1, dummy, dummy, dummy, 1 << 30, mapdec.FP32, None) \
+        == mapdec.EUNSUPPORTED

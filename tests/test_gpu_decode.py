@@ -1,0 +1,145 @@
+"""GPU parity: libmapdec (through the C ABI) against the FP64 CPU oracle.
+
+Bars: FP64 plain decode -- APP max abs error <= 1e-12 and relative log P(y)
+error <= 1e-12; FP32 decode -- APP max abs error <= 1e-5 and relative
+log P(y) error <= 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1802_08483_amd import mapdec
+from paper_1802_08483_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {mapdec.FP64: (1e-12, 1e-12), mapdec.FP32: (1e-5, 1e-6)}
+
+
+def _decode(frames, prec, graph=None):
+    b = mapdec.batch_from_frames(frames, precision=prec)
+    if graph is None:
+        b.decode()
+    else:
+        p = b.plan(graph=graph)
+        p.run()
+        b._plan = p
+    torch.cuda.synchronize()
+    return b
+
+
+def _check_frame(b, f, fr, ref, prec, label=""):
+    tol_app, tol_lp = TOL[prec]
+    st = int(b.status[f])
+    if ref["status"] != 0:
+        assert st == mapdec.ENOPATH, f"{label}: expected no path"
+        return
+    assert st == 0, f"{label}: status {st}"
+    app = b.apps[f].double().cpu().numpy()
+    err = float(np.abs(app - ref["app"]).max())
+    lp = float(b.logp[f])
+    rel = abs(lp - ref["logp"]) / max(1.0, abs(ref["logp"]))
+    assert err <= tol_app, f"{label}: APP err {err:.3e}"
+    assert rel <= tol_lp, f"{label}: logP rel err {rel:.3e} ({lp} vs {ref['logp']})"
+
+
+@pytest.mark.parametrize("prec", [mapdec.FP64, mapdec.FP32])
+def test_workload1(prec):
+    fr = wl.make_workload(1)[0]
+    ref = oracle.decode_frame(fr)
+    b = _decode([fr], prec)
+    _check_frame(b, 0, fr, ref, prec, "workload1")
+
+
+def _mixed_frames():
+    """Uneven small frames spanning n, q, mn, I, M, priors and ragged rho."""
+    specs = [
+        # seed, q, n, N, Pi, Pd, Ps, I, M, mn, prior
+        (1, 2, 1, 40, 0.05, 0.05, 0.02, 2, 8, 2, False),
+        (2, 4, 2, 33, 0.10, 0.08, 0.05, 1, 10, 3, True),
+        (3, 8, 5, 70, 0.03, 0.04, 0.01, 2, 14, 4, False),
+        (4, 16, 8, 50, 0.02, 0.02, 0.00, 0, 12, 5, True),
+        (5, 8, 6, 90, 0.05, 0.05, 0.00, 3, 16, 4, False),      # general insertion cap
+        (6, 32, 10, 45, 0.04, 0.03, 0.02, 2, 20, 6, True),
+        (7, 16, 12, 30, 0.06, 0.06, 0.00, 2, 22, 7, False),
+        (8, 64, 16, 20, 0.05, 0.05, 0.01, 20, 24, 8, True),    # cap never binds
+        (9, 2, 4, 130, 0.01, 0.01, 0.00, 2, 10, 0, False),     # corridor of width 1
+        (10, 4, 3, 64, 0.08, 0.02, 0.10, 2, 18, 1, True),
+    ]
+    frames = []
+    for (seed, q, n, N, Pi, Pd, Ps, I, M, mn, pr) in specs:
+        frames.append(wl.random_frame(seed, q, n, N, Pi, Pd, Ps, I, M, mn, with_prior=pr))
+    return frames
+
+
+@pytest.mark.parametrize("prec", [mapdec.FP64, mapdec.FP32])
+def test_mixed_small_frames(prec):
+    frames = _mixed_frames()
+    refs = [oracle.decode_frame(fr, check=False) for fr in frames]
+    b = _decode(frames, prec)
+    for f, (fr, ref) in enumerate(zip(frames, refs)):
+        _check_frame(b, f, fr, ref, prec, f"frame {f} q={fr.q} n={fr.n} mn={fr.mn} I={fr.I}")
+
+
+def test_no_path_frame_is_reported():
+    # no insertions or deletions and no substitutions: y must be an exact
+    # concatenation of codewords, which this y is not
+    cb = np.array([[0, 0, 1], [1, 1, 0]], np.uint8)
+    y = np.array([0, 0, 1, 1, 1, 1], np.uint8)
+    bad = wl.Frame(q=2, n=3, N=2, codebook=cb, message=np.zeros(2, int), y=y, Pi=0.0, Pd=0.0,
+                   Ps=0.0, I=2, M=2, mn=1)
+    good = wl.random_frame(21, 4, 4, 20, 0.03, 0.03, 0.01, 2, 8, 3)
+    ref_bad = oracle.decode_frame(bad, check=False)
+    assert ref_bad["status"] == oracle.REF_ENOPATH
+    for prec in (mapdec.FP64, mapdec.FP32):
+        b = _decode([bad, good], prec)
+        assert int(b.status[0]) == mapdec.ENOPATH
+        assert math.isinf(float(b.logp[0])) and float(b.logp[0]) < 0
+        _check_frame(b, 1, good, oracle.decode_frame(good), prec, "good frame")
+
+
+def test_empty_received_sequence():
+    # every bit deleted: rho = 0 is a valid frame when M >= tau
+    cb = np.array([[0, 1], [1, 0], [1, 1]], np.uint8)
+    fr = wl.Frame(q=3, n=2, N=3, codebook=cb, message=np.zeros(3, int),
+                  y=np.zeros(0, np.uint8), Pi=0.1, Pd=0.3, Ps=0.0, I=2, M=6, mn=2)
+    ref = oracle.decode_frame(fr)
+    for prec in (mapdec.FP64, mapdec.FP32):
+        b = _decode([fr], prec)
+        _check_frame(b, 0, fr, ref, prec, "rho=0")
+
+
+def test_workload2_full_batch_sampled():
+    frames = wl.make_workload(2)
+    b = _decode(frames, mapdec.FP32)
+    st = b.status.cpu().numpy()
+    assert (st == 0).all()
+    lp = b.logp.cpu().numpy()
+    assert np.isfinite(lp).all()
+    for f in range(len(frames)):
+        s = b.apps[f].double().sum(1).cpu().numpy()
+        assert np.abs(s - 1).max() < 1e-5
+    for f in (0, 97, 255):
+        ref = oracle.decode_frame(frames[f])
+        _check_frame(b, f, frames[f], ref, mapdec.FP32, f"workload2 frame {f}")
+
+
+def test_plan_graph_replays_match_eager():
+    frames = _mixed_frames()[:6]
+    eager = _decode(frames, mapdec.FP32)
+    b = mapdec.batch_from_frames(frames, precision=mapdec.FP32)
+    plan = b.plan(graph=True)
+    for rep in range(3):
+        b.logp.fill_(0)
+        for a in b.apps:
+            a.fill_(-1)
+        plan.run()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+        assert torch.equal(b.logp, eager.logp), f"replay {rep}"
+        for x, y in zip(b.apps, eager.apps):
+            assert torch.equal(x, y), f"replay {rep}"
+    plan.close()
