@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput of the MAP forward-backward decoder on one MI355X.
+
+Workload: 256 frames, q=16 codewords of n=10 bits, N=500 symbols per frame
+(tau = 5000 bits), BSID channel Pi=Pd=0.05, Ps=0.01, insertion cap I=2,
+drift limits M=98 and mn=6, uniform priors, seeded synthetic frames.  A
+step is one FP32 batched decode of the whole batch (receiver-metric
+lattice, forward/backward chains, APPs and log P(y)) replayed as one HIP
+graph, with every input already in HBM.
+
+Prints one JSON line: symbols decoded per second, the roofline of the
+dominant kernel (live HIP-event timing per phase), the FP64 plain GPU
+decode of the same frames, the FP32 error against the FP64 CPU oracle, and
+the oracle's own throughput on a bounded sample (host cores).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed); unpacked issue is half of it
+PEAK_FP64_TFLOPS = 78.6
+WORKLOAD = 2
+
+
+def corridor_nodes(n, mn):
+    """Lattice nodes (r, j), 0 <= r <= n, max(0, r - mn) <= j <= r + mn."""
+    return sum(r + mn - max(0, r - mn) + 1 for r in range(n + 1))
+
+
+def phase_flops(frames):
+    """Algorithmic flops of each phase for a batch (FMA = 2 flops).
+    lattice: rho q C(n, mn) (3 + 2I); chain: 4 N M_tau M_n (alpha and beta);
+    app: 2 N M_tau M_n (q + 1)."""
+    out = {"lattice": 0.0, "chain": 0.0, "app": 0.0}
+    for fr in frames:
+        Mt, Mn = 2 * fr.M + 1, 2 * fr.mn + 1
+        out["lattice"] += fr.rho * fr.q * corridor_nodes(fr.n, fr.mn) * (3 + 2 * fr.I)
+        out["chain"] += 4.0 * fr.N * Mt * Mn
+        out["app"] += 2.0 * fr.N * Mt * Mn * (fr.q + 1)
+    return out
+
+
+def time_plan(plan, steps, warmup, torch):
+    for _ in range(warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        plan.run()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(frames, budget_s=15.0):
+    """The FP64 oracle on a bounded sample of the batch, one frame per host
+    thread.  Returns (baseline dict, {frame index: oracle result})."""
+    import oracle
+    nthreads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    first = oracle.decode_frame(frames[0])
+    t1 = time.perf_counter() - t0
+    nsample = int(min(len(frames), max(nthreads, round(budget_s / max(t1, 1e-3)))))
+    nsample = max(nthreads, (nsample // nthreads) * nthreads) if nsample >= nthreads else nsample
+    idx = list(range(nsample))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=nthreads) as ex:
+        res = list(ex.map(lambda f: oracle.decode_frame(frames[f]), idx))
+    wall = time.perf_counter() - t0
+    syms = sum(frames[f].N for f in idx)
+    refs = dict(zip(idx, res))
+    refs.setdefault(0, first)
+    return ({"value": syms / wall, "unit": "symbols/s", "cores": nthreads, "kind": "oracle",
+             "sample": f"{nsample} of {len(frames)} frames (oracle FP64 decode, one frame per "
+                       f"thread, {wall:.2f} s wall, ~{t1 * nsample:.1f} s CPU)"}, refs)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the decoder's frames "
+              "are independent and would shard by frame across GPUs, which this build does "
+              "not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1802_08483_amd import build as libbuild
+    from paper_1802_08483_amd import mapdec, workloads
+
+    if not os.path.exists(libbuild.LIB):
+        libbuild.build()
+    frames = workloads.make_workload(WORKLOAD)
+    total_syms = sum(fr.N for fr in frames)
+
+    b32 = mapdec.batch_from_frames(frames, precision=mapdec.FP32)
+    plan = b32.plan(graph=True)
+    ms = time_plan(plan, args.steps, args.warmup, torch)
+    if not (b32.status == 0).all():
+        raise RuntimeError("a frame reported no path")
+
+    # per-phase times (HIP events between phases, same stream), averaged
+    acc = {}
+    for _ in range(args.steps):
+        for k, v in plan.profile().items():
+            acc[k] = acc.get(k, 0.0) + v
+    phases = {k: v / args.steps for k, v in acc.items()}
+    flops = phase_flops(frames)
+    dom = max((k for k in flops), key=lambda k: phases.get(k, 0.0))
+    achieved = flops[dom] / (phases[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": None, "kernel": dom,
+                "flops_per_launch": flops[dom], "launch_ms": round(phases[dom], 4)}
+
+    fp64 = None
+    if not args.no_fp64:
+        b64 = mapdec.batch_from_frames(frames, precision=mapdec.FP64)
+        p64 = b64.plan(graph=True)
+        ms64 = time_plan(p64, max(3, args.steps // 2), 1, torch)
+        fp64 = {"value": round(total_syms / (ms64 * 1e-3), 1), "ms_per_step": round(ms64, 4)}
+        p64.close()
+        del b64
+
+    cpu, refs = (None, {})
+    if not args.no_cpu_baseline:
+        cpu, refs = cpu_baseline(frames)
+    else:
+        import oracle
+        refs = {0: oracle.decode_frame(frames[0])}
+    app_err, lp_err = 0.0, 0.0
+    for f, ref in refs.items():
+        app = b32.apps[f].double().cpu().numpy()
+        app_err = max(app_err, float(np.abs(app - ref["app"]).max()))
+        lp_err = max(lp_err, abs(float(b32.logp[f]) - ref["logp"]) / abs(ref["logp"]))
+
+    line = {
+        "metric": "symbols decoded/sec, FP32 batched vs FP64 plain, APP err <=1e-5",
+        "value": round(total_syms / (ms * 1e-3), 1),
+        "unit": "symbols/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": workloads.WORKLOAD_NAMES[WORKLOAD], "frames": len(frames),
+                   "q": 16, "n": 10, "N": 500, "Pi": 0.05, "Pd": 0.05, "Ps": 0.01, "I": 2,
+                   "M": frames[0].M, "mn": frames[0].mn, "priors": "uniform",
+                   "graph": True},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64_plain": fp64,
+        "accuracy": {"frames_checked": len(refs), "app_max_abs_err": app_err,
+                     "logp_max_rel_err": lp_err},
+        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+    }
+    plan.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -175,6 +175,19 @@ int mapdec_plan_run(mapdec_plan *plan, void *stream);
 /* Waits for the plan's pending work and frees it.  NULL is a no-op. */
 void mapdec_plan_destroy(mapdec_plan *plan);
 
+/*
+ * mapdec_plan_profile -- per-phase time split of one run (the decoder's
+ * time per metric, Sec. VI).  Enqueues the plan's launches once, without
+ * the graph, on stream with a HIP event recorded between phases, waits for
+ * them, and writes the milliseconds of phase k into phase_ms[k] for
+ * k < max_phases.  Returns the number of phases, or a negative MAPDEC_*
+ * status.  Results land in the plan's outputs as after mapdec_plan_run.
+ */
+int mapdec_plan_profile(mapdec_plan *plan, void *stream, float *phase_ms, int max_phases);
+/* Static name of profile phase k ("pack", "lattice", "gamma", "chain",
+ * "app", ...), or NULL past the last phase. */
+const char *mapdec_phase_name(int phase);
+
 /* Status of the calling thread's last failed mapdec_create / plan_create. */
 int mapdec_last_error(void);
 /* Static string naming a status code. */

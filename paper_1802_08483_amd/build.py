@@ -15,16 +15,25 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmapdec.so")
-SOURCES = ["kernels.hip", "mapdec.cpp"]
+SOURCES = ["k_misc.hip", "k_lattice.hip", "k_chain.hip", "k_app.hip", "mapdec.cpp"]
+# k_chain_ring.hip is compiled once per (precision, workgroup shape); the
+# shapes (waves, states per thread) match kRingShapes in csrc/kernels.h
+RING_SHAPES = [(1, 1), (2, 1), (4, 1), (4, 2), (8, 2), (16, 2)]
+VARIANTS = [("k_chain_ring.hip", f"chain_ring_{tag}_{k}",
+             [f"-DCHAIN_T={t}", f"-DCHAIN_NW={nw}", f"-DCHAIN_SPL={spl}",
+              f"-DCHAIN_FN=chain_ring_{tag}_{k}"])
+            for tag, t in (("f32", "float"), ("f64", "double"))
+            for k, (nw, spl) in enumerate(RING_SHAPES)]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job) -> str:
+    src, name, defines = job
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [HIPCC] + FLAGS + defines + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -36,8 +45,12 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    jobs = [(s, s, []) for s in SOURCES] + VARIANTS
+    # longest compiles first
+    jobs.sort(key=lambda j: 0 if j[0] == "k_chain_ring.hip" else 1)
+    workers = max(1, min(16, os.cpu_count() or 1, len(jobs)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, jobs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -1,0 +1,161 @@
+// Forward/backward recursions (eqs. 4, 5, 11, 12).
+#include "device_common.h"
+
+namespace mapdec {
+
+// ---------------------------------------------------------------------------
+// alpha / beta chains.  Workgroup 2c runs the forward chain of frame
+// frames[c], workgroup 2c+1 the backward chain.  Rows live in LDS with mn
+// zero entries of padding on each side (states outside [-M, M] are 0).
+
+template <typename T>
+__device__ __forceinline__ T gamma_at(const FrameDesc &f, const T *G, int i, int mp, int k) {
+    if (mp < -f.M || mp > f.M) return T(0);
+    if (f.uniform) {
+        const int s = f.n * i + mp;
+        return (s >= 0 && s <= f.rho) ? G[(size_t)k * f.sp + s] : T(0);
+    }
+    return G[((size_t)i * f.Mn + k) * f.Mt + (mp + f.M)];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__restrict__ fd,
+                                                         const int *__restrict__ frames) {
+    const int fi = frames[blockIdx.x >> 1];
+    const int dir = blockIdx.x & 1;
+    const FrameDesc &f = fd[fi];
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Mt = f.Mt, mn = f.mn, M = f.M, N = f.N, Mn = f.Mn;
+    const int W = Mt + 2 * mn;
+    T *buf0 = (T *)smem;
+    T *buf1 = buf0 + W;
+    double *red = (double *)(smem + (((size_t)2 * W * sizeof(T) + 15) & ~(size_t)15));
+    const int tid = threadIdx.x, nth = blockDim.x;
+
+    for (int j = tid; j < 2 * W; j += nth) buf0[j] = T(0);
+    __syncthreads();
+    const int m0 = dir == 0 ? 0 : f.rho - f.tau;
+    T *out = (T *)(dir == 0 ? f.alpha : f.beta);
+    double *logX = dir == 0 ? f.logA : f.logB;
+    const int row0 = dir == 0 ? 0 : N;
+    if (tid == 0) {
+        buf0[mn + m0 + M] = T(1);
+        logX[row0] = 0.0;
+    }
+    for (int mi = tid; mi < Mt; mi += nth)
+        out[(size_t)row0 * Mt + mi] = (mi == m0 + M) ? T(1) : T(0);
+    __syncthreads();
+
+    const T *G = (const T *)f.G;
+    double lsum = 0.0;
+    T *cur = buf0, *nxt = buf1;
+    bool dead = false;
+    for (int step = 0; step < N; ++step) {
+        const int i = dir == 0 ? step : N - 1 - step;
+        double part = 0.0;
+        for (int mi = tid; mi < Mt; mi += nth) {
+            const int m = mi - M;
+            T acc = T(0);
+            if (dir == 0) {
+                // alpha'_{i+1}(m) = sum_delta alpha_i(m - delta) Gamma_i(m - delta, delta)
+                for (int k = 0; k < Mn; ++k) {
+                    const int dl = k - mn;
+                    acc += cur[mn + mi - dl] * gamma_at(f, G, i, m - dl, k);
+                }
+            } else {
+                // beta'_i(m) = sum_delta Gamma_i(m, delta) beta_{i+1}(m + delta)
+                for (int k = 0; k < Mn; ++k) {
+                    const int dl = k - mn;
+                    acc += gamma_at(f, G, i, m, k) * cur[mn + mi + dl];
+                }
+            }
+            nxt[mn + mi] = acc;
+            part += (double)acc;
+        }
+        const double c = block_sum(part, red);
+        if (!(c > 0.0) || !isfinite(c)) {
+            dead = true;
+            break;
+        }
+        const T inv = (T)(1.0 / c);
+        const int row = dir == 0 ? i + 1 : i;
+        for (int mi = tid; mi < Mt; mi += nth) {
+            const T v = nxt[mn + mi] * inv;
+            nxt[mn + mi] = v;
+            out[(size_t)row * Mt + mi] = v;
+        }
+        lsum += log(c);
+        if (tid == 0) logX[row] = lsum;
+        T *t = cur;
+        cur = nxt;
+        nxt = t;
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    if (dead) {
+        atomicOr(f.status, kStatusNoPath);
+        if (dir == 0) *f.logp = -INFINITY;
+        return;
+    }
+    if (dir == 0) {
+        // P(y) = alpha_N(rho - tau) in unnormalised terms
+        const T aN = cur[mn + (f.rho - f.tau) + M];
+        if (!(aN > T(0))) {
+            atomicOr(f.status, kStatusNoPath);
+            *f.logp = -INFINITY;
+        } else {
+            *f.logp = lsum + log((double)aN);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+hipError_t launch_chain(int fp64, const FrameDesc *fd, const int *frames, int nchains,
+                        size_t lds_bytes, hipStream_t st) {
+    if (nchains == 0) return hipSuccess;
+    if (fp64)
+        hipLaunchKernelGGL(k_chain<double>, dim3(2 * nchains), dim3(kChainThreads), lds_bytes,
+                           st, fd, frames);
+    else
+        hipLaunchKernelGGL(k_chain<float>, dim3(2 * nchains), dim3(kChainThreads), lds_bytes,
+                           st, fd, frames);
+    return hipGetLastError();
+}
+
+}  // namespace mapdec
+
+namespace mapdec {
+
+// One object per (precision, shape) built from k_chain_ring.hip.
+#define MAPDEC_RING_DECL(name)                                                            \
+    hipError_t name(int mn, int nchains, size_t lds, hipStream_t st, const FrameDesc *fd, \
+                    const int *frames);
+MAPDEC_RING_DECL(chain_ring_f32_0)
+MAPDEC_RING_DECL(chain_ring_f32_1)
+MAPDEC_RING_DECL(chain_ring_f32_2)
+MAPDEC_RING_DECL(chain_ring_f32_3)
+MAPDEC_RING_DECL(chain_ring_f32_4)
+MAPDEC_RING_DECL(chain_ring_f32_5)
+MAPDEC_RING_DECL(chain_ring_f64_0)
+MAPDEC_RING_DECL(chain_ring_f64_1)
+MAPDEC_RING_DECL(chain_ring_f64_2)
+MAPDEC_RING_DECL(chain_ring_f64_3)
+MAPDEC_RING_DECL(chain_ring_f64_4)
+MAPDEC_RING_DECL(chain_ring_f64_5)
+#undef MAPDEC_RING_DECL
+
+hipError_t launch_chain_ring(int fp64, int shape, int mn, const FrameDesc *fd, const int *frames,
+                             int nchains, size_t lds, hipStream_t st) {
+    if (nchains == 0) return hipSuccess;
+    using Fn = hipError_t (*)(int, int, size_t, hipStream_t, const FrameDesc *, const int *);
+    static const Fn f32[kNumRingShapes] = {chain_ring_f32_0, chain_ring_f32_1, chain_ring_f32_2,
+                                           chain_ring_f32_3, chain_ring_f32_4, chain_ring_f32_5};
+    static const Fn f64[kNumRingShapes] = {chain_ring_f64_0, chain_ring_f64_1, chain_ring_f64_2,
+                                           chain_ring_f64_3, chain_ring_f64_4, chain_ring_f64_5};
+    if (shape < 0 || shape >= kNumRingShapes) return hipErrorInvalidValue;
+    return (fp64 ? f64 : f32)[shape](mn, nchains, lds, st, fd, frames);
+}
+
+}  // namespace mapdec

@@ -1,0 +1,291 @@
+// Forward/backward recursions for uniform priors (eqs. 4, 5, 11, 12), where
+// Gamma depends on the start index s = n i + m' only.
+//
+// This file is compiled once per (precision, waves, states per thread):
+// build with -DCHAIN_T=float|double -DCHAIN_NW=<waves> -DCHAIN_SPL=<states>
+// -DCHAIN_FN=<launcher name>.
+//
+// One workgroup of NT = 64 NW threads runs one chain; thread t owns
+// drift-state indices t, t + NT, ..., t + NT (SPL - 1).  Rows are padded to
+// NT SPL states (zero beyond 2M+1) plus mn zeros on each side, so no thread
+// branches on its state.  One workgroup barrier per step.
+//
+// Rows kept are the paper's pre-normalisation metrics: row i+1 is
+// alpha'_{i+1} = sum alpha_i Gamma_i with alpha_i = alpha'_i / c_i and
+// c_i = sum_m alpha'_i(m) (eqs. 11, 12).  Each wave reduces its share of the
+// new row with DPP moves and leaves the partial in LDS; after the barrier
+// every thread adds the partials in the same order, so c_i is known at the
+// start of the next step and scales that step's results.  beta is handled
+// the same way from the other end.  Consumers of the rows are invariant to
+// a per-row scale, and log P(y) = sum_{k<N} log c_k + log alpha'_N(rho -
+// tau); the product of normalisers is carried as mantissa * 2^exponent.
+//
+// Gamma(s, delta) for the start indices a chunk of C steps reads sits in an
+// LDS ring of RING (a power of two) slots of Mn values each, slot-major
+// (threads read with a stride of Mn words, which is odd: no bank conflicts).
+// For small state spaces the slots near both ends are duplicated past the
+// ends, so one step's reads never wrap and every read is a base register
+// plus a compile-time offset; large state spaces index the ring modulo RING.
+// The n C columns the next chunk adds are loaded into registers one chunk
+// ahead and written to the ring when that chunk starts, so global-memory
+// latency overlaps a whole chunk of steps.
+#include "device_common.h"
+
+#if !defined(CHAIN_T) || !defined(CHAIN_NW) || !defined(CHAIN_SPL) || !defined(CHAIN_FN)
+#error "compile with -DCHAIN_T, -DCHAIN_NW, -DCHAIN_SPL and -DCHAIN_FN"
+#endif
+
+namespace mapdec {
+
+template <typename T, int NW, int SPL, int MN, int DIR>
+__device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned char *smem) {
+    constexpr int NT = 64 * NW;
+    constexpr int Mn = 2 * MN + 1;
+    constexpr int ROWW = NT * SPL + 2 * MN;            // padded row
+    constexpr bool DUP = ring_duplicates(NT * SPL);
+    constexpr int PF = kRingPrefetchRegs;
+    const int Mt = f.Mt, M = f.M, N = f.N, n = f.n, rho = f.rho;
+    const int C = f.ring_chunk, RING = f.ring_cols, mask = RING - 1;
+    const int RPHYS = DUP ? RING + NT * SPL + 2 * MN : RING;
+    T *row0 = (T *)smem;
+    T *row1 = row0 + ROWW;
+    T *part = row1 + ROWW;                             // [2][NW] wave partial sums
+    T *ring = part + 2 * NW;                           // [RPHYS][Mn]
+    const int tid = threadIdx.x, wv = tid >> 6;
+    const gptr<const T> G = to_global((const T *)f.G);   // [Mn][sp]
+    const size_t sp = (size_t)f.sp;
+
+    for (int j = tid; j < 2 * ROWW + 2 * NW + RPHYS * Mn; j += NT) row0[j] = T(0);
+    __syncthreads();
+    const int m0 = DIR == 0 ? 0 : f.rho - f.tau;
+    if (tid == 0) row0[MN + m0 + M] = T(1);
+    const gptr<T> out = to_global((T *)(DIR == 0 ? f.alpha : f.beta));
+    const int rowA = DIR == 0 ? 0 : N;
+    for (int mi = tid; mi < Mt; mi += NT)
+        out[(size_t)rowA * Mt + mi] = (mi == m0 + M) ? T(1) : T(0);
+
+    // chunk k covers steps kC .. kC+C-1 (forward) or N-1-kC down to N-C-kC
+    // (backward), which read s in [n i_lo - M, n i_hi + M]
+    auto chunk_lo_s = [&](int k) { return n * (DIR == 0 ? k * C : N - C - k * C) - M; };
+    auto chunk_hi_s = [&](int k) { return n * (DIR == 0 ? k * C + C - 1 : N - 1 - k * C) + M; };
+    auto new_base = [&](int k) { return DIR == 0 ? chunk_hi_s(k - 1) + 1 : chunk_lo_s(k); };
+
+    auto put = [&](int s, int kk, T v) {
+        const int L = s & mask;
+        if (DUP) {
+            ring[(L + MN) * Mn + kk] = v;
+            if (L < NT * SPL + MN) ring[(L + RING + MN) * Mn + kk] = v;
+            if (L >= RING - MN) ring[(L - RING + MN) * Mn + kk] = v;
+        } else {
+            ring[L * Mn + kk] = v;
+        }
+    };
+
+    // Prefetch registers: element p = tid + NT r is column base + (p mod nC)
+    // of drift change p / nC.  (kk, col) advance by (NT / nC, NT mod nC)
+    // per register with one carry test; loads are unconditional (clamped
+    // address) so all of them stay in flight, validity kept as a bit mask.
+    const int nC = n * C;
+    const int dq = NT / nC, dr = NT - dq * nC;
+    T pre[PF];
+    uint32_t pvalid = 0;
+    auto issue = [&](int base) {
+        int kk = tid / nC, col = tid - kk * nC;
+        pvalid = 0;
+#pragma unroll
+        for (int r = 0; r < PF; ++r) {
+            const int s = base + col;
+            const int sc = min(max(s, 0), rho);
+            const int kc = min(kk, Mn - 1);
+            pre[r] = G[(size_t)kc * sp + sc];
+            pvalid |= (s == sc) ? (1u << r) : 0u;
+            col += dr;
+            kk += dq;
+            const bool carry = col >= nC;
+            col -= carry ? nC : 0;
+            kk += carry ? 1 : 0;
+        }
+    };
+    auto commit = [&](int base, int lo, int hi) {   // columns in [lo, hi] only
+        int kk = tid / nC, col = tid - kk * nC;
+#pragma unroll
+        for (int r = 0; r < PF; ++r) {
+            const int s = base + col;
+            if (kk < Mn && s >= lo && s <= hi) put(s, kk, ((pvalid >> r) & 1u) ? pre[r] : T(0));
+            col += dr;
+            kk += dq;
+            const bool carry = col >= nC;
+            col -= carry ? nC : 0;
+            kk += carry ? 1 : 0;
+        }
+    };
+    {   // chunk 0's window, nC columns at a time
+        const int lo = chunk_lo_s(0), hi = chunk_hi_s(0);
+        for (int base = lo; base <= hi; base += nC) {
+            issue(base);
+            commit(base, lo, hi);
+        }
+    }
+    const int nchunks = (N + C - 1) / C;
+    if (nchunks > 1) issue(new_base(1));
+
+    T *cur = row0, *nxt = row1;
+    T own[SPL];
+    __syncthreads();
+    {
+        T p = T(0);
+#pragma unroll
+        for (int j = 0; j < SPL; ++j) {
+            own[j] = cur[MN + tid + NT * j];
+            p += own[j];
+        }
+        p = wave_sum_dpp(p);
+        if ((tid & 63) == 0) part[wv] = p;
+    }
+    __syncthreads();
+    int pp = 0;   // partial-sum buffer of the current input row
+    double pmant = 1.0;
+    int pexp = 0;
+    bool dead = false;
+    for (int k = 0; k < nchunks && !dead; ++k) {
+        if (k >= 1) {
+            const int b = new_base(k);
+            commit(b, b, b + nC - 1);
+            if (k + 1 < nchunks) issue(new_base(k + 1));
+            __syncthreads();
+        }
+        const int steps = min(C, N - k * C);
+        for (int t = 0; t < steps; ++t) {
+            const int i = DIR == 0 ? k * C + t : N - 1 - k * C - t;
+            T csum = T(0);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) csum += part[pp * NW + w];
+            const int sb = (n * i - M) & mask;
+            const T *cb = cur + MN + tid;
+            T acc[SPL];
+            if (DIR == 0) {
+                // alpha'_{i+1}(m) = sum_delta alpha_i(m - delta) Gamma(n i + m - delta, delta)
+                if (DUP) {
+                    const T *rb = ring + (sb + tid + MN) * Mn + MN;
+#pragma unroll
+                    for (int j = 0; j < SPL; ++j) {
+                        T a = T(0);
+#pragma unroll
+                        for (int d = -MN; d <= MN; ++d)
+                            a += cb[NT * j - d] * rb[(NT * j - d) * Mn + d];
+                        acc[j] = a;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < SPL; ++j) {
+                        T a = T(0);
+#pragma unroll
+                        for (int d = -MN; d <= MN; ++d)
+                            a += cb[NT * j - d] *
+                                 ring[((sb + tid + NT * j - d) & mask) * Mn + d + MN];
+                        acc[j] = a;
+                    }
+                }
+            } else {
+                // beta'_i(m) = sum_delta Gamma(n i + m, delta) beta_{i+1}(m + delta)
+#pragma unroll
+                for (int j = 0; j < SPL; ++j) {
+                    const T *rb = DUP ? ring + (sb + tid + MN + NT * j) * Mn
+                                      : ring + ((sb + tid + NT * j) & mask) * Mn;
+                    T a = T(0);
+#pragma unroll
+                    for (int kk = 0; kk < Mn; ++kk) a += rb[kk] * cb[NT * j + kk - MN];
+                    acc[j] = a;
+                }
+            }
+            if (!(csum > T(0))) {
+                dead = true;
+                break;
+            }
+            const T inv = T(1) / csum;
+            if (i != (DIR == 0 ? 0 : N - 1)) {
+                int e;
+                pmant = frexp(pmant * (double)csum, &e);
+                pexp += e;
+            }
+            const int row = DIR == 0 ? i + 1 : i;
+            T *nb = nxt + MN + tid;
+            T p = T(0);
+#pragma unroll
+            for (int j = 0; j < SPL; ++j) {
+                const int mi = tid + NT * j;
+                const T v = (mi < Mt) ? acc[j] * inv : T(0);
+                own[j] = v;
+                p += v;
+                nb[NT * j] = v;
+                if (mi < Mt) out[(size_t)row * Mt + mi] = v;
+            }
+            p = wave_sum_dpp(p);
+            if ((tid & 63) == 0) part[(pp ^ 1) * NW + wv] = p;
+            pp ^= 1;
+            T *tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+            __syncthreads();
+        }
+    }
+    const double lsum = log(pmant) + (double)pexp * 0.69314718055994530942;
+    if (tid != 0) return;
+    (DIR == 0 ? f.logA : f.logB)[DIR == 0 ? N : 0] = lsum;
+    if (dead) {
+        atomicOr(f.status, kStatusNoPath);
+        if (DIR == 0) *f.logp = -INFINITY;
+        return;
+    }
+    if (DIR == 0) {
+        const T aN = cur[MN + (f.rho - f.tau) + M];
+        if (!(aN > T(0))) {
+            atomicOr(f.status, kStatusNoPath);
+            *f.logp = -INFINITY;
+        } else {
+            *f.logp = lsum + log((double)aN);
+        }
+    }
+}
+
+template <typename T, int NW, int SPL, int MN>
+__global__ __launch_bounds__(64 * NW) void k_chain_ring(const FrameDesc *__restrict__ fd,
+                                                        const int *__restrict__ frames) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const FrameDesc &f = fd[frames[blockIdx.x >> 1]];
+    if (blockIdx.x & 1)
+        chain_ring_body<T, NW, SPL, MN, 1>(f, smem);
+    else
+        chain_ring_body<T, NW, SPL, MN, 0>(f, smem);
+}
+
+template <int MN>
+static hipError_t ring_launch(int nchains, size_t lds, hipStream_t st, const FrameDesc *fd,
+                              const int *frames) {
+    auto kern = k_chain_ring<CHAIN_T, CHAIN_NW, CHAIN_SPL, MN>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(2 * nchains), dim3(64 * CHAIN_NW), lds, st, fd, frames);
+    return hipGetLastError();
+}
+
+hipError_t CHAIN_FN(int mn, int nchains, size_t lds, hipStream_t st, const FrameDesc *fd,
+                    const int *frames) {
+    switch (mn) {
+        case 0: return ring_launch<0>(nchains, lds, st, fd, frames);
+        case 1: return ring_launch<1>(nchains, lds, st, fd, frames);
+        case 2: return ring_launch<2>(nchains, lds, st, fd, frames);
+        case 3: return ring_launch<3>(nchains, lds, st, fd, frames);
+        case 4: return ring_launch<4>(nchains, lds, st, fd, frames);
+        case 5: return ring_launch<5>(nchains, lds, st, fd, frames);
+        case 6: return ring_launch<6>(nchains, lds, st, fd, frames);
+        case 7: return ring_launch<7>(nchains, lds, st, fd, frames);
+        case 8: return ring_launch<8>(nchains, lds, st, fd, frames);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mapdec

@@ -1,0 +1,160 @@
+// Receiver-metric lattice kernel (eqs. 7-10).
+#include "device_common.h"
+
+namespace mapdec {
+
+// ---------------------------------------------------------------------------
+// Receiver-metric lattice (eqs. 7-10), corridor form.
+//
+// A lane owns one start index s and walks all q codewords; the wave's lanes
+// hold 64 consecutive s, so the codeword (and each of its bits) is uniform
+// across the wave.  Row r of the lattice is kept in registers in corridor
+// coordinates k = j - r + MN (j = received bits consumed), k in [0, 2 MN]:
+//   G_r[k] = d F_{r-1}[k+1] + Q(y[s + r + k - MN - 1] | x_r) F_{r-1}[k]
+//   F_r[k] = G_r[k] + sum_{t=1..min(IM,k)} a_t G_r[k-t]     (r < n)
+//   F_n[k] = G_n[k]                                          (last row)
+// with a_t = a^t for t <= I and 0 beyond (at most I insertions in a row).
+// The two possible values of Q for each received position are prepared once
+// per lane (qx0 for a 0 codeword bit, qx1 for a 1), so a node costs one
+// multiply and 1 + IM fused multiply-adds.
+
+template <typename T, int MN, int NB>
+__device__ __forceinline__ void lattice_row_in(T (&G)[2 * MN + 1], const T (&F)[2 * MN + 1],
+                                               const T (&qx)[NB], T d, int r) {
+#pragma unroll
+    for (int k = 0; k < 2 * MN + 1; ++k) {
+        T v = (k + 1 < 2 * MN + 1) ? d * F[k + 1] : T(0);
+        const int b = r + k - MN - 1;
+        if (b >= 0) v += qx[b] * F[k];
+        G[k] = v;
+    }
+}
+
+template <typename T, int MN, int IM>
+__global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__restrict__ fd,
+                                                           const Work *__restrict__ tab) {
+    constexpr int KW = 2 * MN + 1;
+    constexpr int NB = kMaxN + MN;   // received positions a lattice can read
+    const Work w = tab[blockIdx.x];
+    const FrameDesc &f = fd[w.frame];
+    const int s = w.item + (int)threadIdx.x;
+    if (s > f.rho) return;
+    const int n = f.n, q = f.q, rho = f.rho;
+    const T d = (T)f.d, t1 = (T)f.t1, t0 = (T)f.t0;
+
+    T apow[IM + 1];
+    {
+        T p = T(1);
+        apow[0] = T(1);
+#pragma unroll
+        for (int t = 1; t <= IM; ++t) {
+            p *= (T)f.a;
+            apow[t] = (t <= f.I) ? p : T(0);
+        }
+    }
+
+    // received bits y[s .. s+32) of this lane
+    const int wi = s >> 5, sh = s & 31;
+    const uint32_t lo = f.ybits[wi], hi = f.ybits[wi + 1];
+    const uint32_t win = sh ? ((lo >> sh) | (hi << (32 - sh))) : lo;
+    T qx0[NB], qx1[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const bool one = (win >> b) & 1u;
+        qx0[b] = one ? t0 : t1;
+        qx1[b] = one ? t1 : t0;
+    }
+
+    T gsum[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) gsum[k] = T(0);
+
+    T *R = (T *)f.R;
+    const size_t sp = (size_t)f.sp;
+    for (int D = 0; D < q; ++D) {
+        const uint32_t cw = f.cw[D];
+        T F[KW];
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            const int dl = k - MN;   // row 0: dl insertions before the first bit
+            F[k] = (dl >= 0 && dl <= IM) ? apow[dl] : T(0);
+        }
+#pragma unroll
+        for (int r = 1; r <= kMaxN; ++r) {
+            if (r > n) break;
+            T G[KW];
+            if ((cw >> (n - r)) & 1u)
+                lattice_row_in<T, MN, NB>(G, F, qx1, d, r);
+            else
+                lattice_row_in<T, MN, NB>(G, F, qx0, d, r);
+            if (r < n) {
+#pragma unroll
+                for (int k = 0; k < KW; ++k) {
+                    T v = G[k];
+#pragma unroll
+                    for (int t = 1; t <= IM; ++t)
+                        if (t <= k) v += apow[t] * G[k - t];
+                    F[k] = v;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < KW; ++k) F[k] = G[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            const int len = n + k - MN;   // segment length n + delta
+            const T v = (len >= 0 && s + len <= rho) ? F[k] : T(0);
+            R[((size_t)D * KW + k) * sp + s] = v;
+            gsum[k] += v;
+        }
+    }
+    if (f.uniform) {
+        T *G = (T *)f.G;
+        const T invq = T(1) / T(q);
+#pragma unroll
+        for (int k = 0; k < KW; ++k) G[(size_t)k * sp + s] = gsum[k] * invq;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launcher
+
+template <typename T, int MN>
+static void lattice_mn(int imode, const FrameDesc *fd, const Work *tab, int nblocks,
+                       hipStream_t st) {
+    constexpr int IM2 = (2 < 2 * MN) ? 2 : 2 * MN;
+    if (imode == 0)
+        hipLaunchKernelGGL((k_lattice<T, MN, IM2>), dim3(nblocks), dim3(kLatticeLanes), 0, st,
+                           fd, tab);
+    else
+        hipLaunchKernelGGL((k_lattice<T, MN, 2 * MN>), dim3(nblocks), dim3(kLatticeLanes), 0,
+                           st, fd, tab);
+}
+
+template <typename T>
+static hipError_t lattice_t(int mn, int imode, const FrameDesc *fd, const Work *tab,
+                            int nblocks, hipStream_t st) {
+    switch (mn) {
+        case 0: lattice_mn<T, 0>(imode, fd, tab, nblocks, st); break;
+        case 1: lattice_mn<T, 1>(imode, fd, tab, nblocks, st); break;
+        case 2: lattice_mn<T, 2>(imode, fd, tab, nblocks, st); break;
+        case 3: lattice_mn<T, 3>(imode, fd, tab, nblocks, st); break;
+        case 4: lattice_mn<T, 4>(imode, fd, tab, nblocks, st); break;
+        case 5: lattice_mn<T, 5>(imode, fd, tab, nblocks, st); break;
+        case 6: lattice_mn<T, 6>(imode, fd, tab, nblocks, st); break;
+        case 7: lattice_mn<T, 7>(imode, fd, tab, nblocks, st); break;
+        case 8: lattice_mn<T, 8>(imode, fd, tab, nblocks, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice(int fp64, int mn, int imode, const FrameDesc *fd, const Work *tab,
+                          int nblocks, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    return fp64 ? lattice_t<double>(mn, imode, fd, tab, nblocks, st)
+                : lattice_t<float>(mn, imode, fd, tab, nblocks, st);
+}
+
+}  // namespace mapdec

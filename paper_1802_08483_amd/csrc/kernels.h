@@ -1,4 +1,20 @@
-// Launchers for the gfx950 kernels (implemented in kernels.hip).
+// Launchers for the gfx950 kernels of the MAP forward-backward decoder
+// (Sec. II-C), implemented in k_misc.hip, k_lattice.hip, k_chain.hip and
+// k_app.hip.
+//
+// Data flow per frame (one workspace region per frame, see FrameDesc):
+//   k_pack     received bytes -> 32-bit words of bits
+//   k_lattice  receiver metric R(s, D, delta) of eqs. 7-10 for every start
+//              index s and symbol D (one lattice per (s, D) serves every
+//              (i, m') with n i + m' = s, since the codebook is fixed), plus
+//              Gamma(s, delta) = sum_D R / q when the priors are uniform
+//   k_gamma    Gamma_i(m', delta) = sum_D prior_i(D) R(n i + m', D, delta)
+//              for general priors (eq. 6 summed over D)
+//   k_chain    normalised alpha (eqs. 4, 11, 12) and beta (eq. 5) chains,
+//              one workgroup per frame and direction, log-normalisers in FP64
+//   k_app      APP of eqs. 1-3: S_i(D) = prior_i(D) sum_{m', delta}
+//              alpha_i(m') R(n i + m', D, delta) beta_{i+1}(m' + delta),
+//              each row divided by its own sum
 #pragma once
 
 #include "mapdec_internal.h"
@@ -14,6 +30,21 @@ hipError_t launch_gamma(int fp64, const FrameDesc *fd, const Work *tab, int nblo
                         hipStream_t st);
 hipError_t launch_chain(int fp64, const FrameDesc *fd, const int *frames, int nchains,
                         size_t lds_bytes, hipStream_t st);
+// Chains for uniform priors with Gamma in an LDS ring (k_chain_ring.hip):
+// shape = index into kRingShapes; every frame of the launch has drift
+// limit mn.
+hipError_t launch_chain_ring(int fp64, int shape, int mn, const FrameDesc *fd, const int *frames,
+                             int nchains, size_t lds_bytes, hipStream_t st);
+
+// Workgroup shapes of the ring chain kernel: waves per chain and drift
+// states per thread; a frame takes the first shape with 64 nw spl >= 2M+1.
+struct RingShape {
+    int nw, spl;
+};
+constexpr RingShape kRingShapes[] = {{1, 1}, {2, 1}, {4, 1}, {4, 2}, {8, 2}, {16, 2}};
+constexpr int kNumRingShapes = 6;
+// Rings of at most this many padded states duplicate their edge slots.
+constexpr bool ring_duplicates(int slots) { return slots <= 512; }
 hipError_t launch_app(int fp64, const FrameDesc *fd, const Work *tab, int nblocks,
                       size_t lds_bytes, hipStream_t st);
 
@@ -23,5 +54,6 @@ constexpr int kLatticeLanes = 64;  // start indices per lattice workgroup
 constexpr int kGammaLanes = 256;   // drift states per Gamma workgroup
 constexpr int kChainThreads = 256;
 constexpr int kAppThreads = 64;
+constexpr int kRingPrefetchRegs = 16;   // prefetch registers per thread in k_chain_ring
 
 }  // namespace mapdec

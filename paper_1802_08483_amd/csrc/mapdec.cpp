@@ -31,6 +31,7 @@ int fail(int st) {
 }
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxPhases = 8;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 int validate_code_params(int q, int n, double Pi, double Pd, double Ps, int I, int M, int mn) {
@@ -44,6 +45,7 @@ int validate_code_params(int q, int n, double Pi, double Pd, double Ps, int I, i
 // Sizes of one frame's workspace pieces.
 struct FrameLayout {
     int nwords, sp, Mt, Mn, lat_blocks, pack_blocks, gamma_blocks;
+    int ring_chunk = 0, ring_cols = 0;
     size_t off_cw, off_ybits, off_R, off_G, off_alpha, off_beta, off_logA, off_logB, off_Zinv,
         off_gacc, end;
 };
@@ -57,10 +59,59 @@ struct Layout {
     std::map<std::pair<int, int>, std::vector<Work>> lat;
     std::map<std::pair<int, int>, size_t> off_lat;
     size_t chain_lds = 0, app_lds = 0;
+    // chains: single-wave ring kernel grouped by states per lane, else the
+    // workgroup kernel
+    std::vector<int> chain_plain;
+    // keyed by (states per lane, mn)
+    std::map<std::pair<int, int>, std::vector<int>> chain_ring;
+    std::map<std::pair<int, int>, size_t> off_chain_ring, ring_lds;
     std::vector<FrameLayout> fl;
 };
 
+// Ring-chain parameters for a uniform-prior frame (workgroup shape, steps
+// per prefetch chunk, ring slots, LDS bytes); false when the frame needs
+// the plain workgroup chain kernel instead.
+bool ring_params(int Mt, int Mn, int n, int mn, size_t tsize, size_t lds_limit, int &shape,
+                 int &chunk, int &cols, size_t &lds) {
+    shape = -1;
+    for (int k = 0; k < kNumRingShapes; ++k)
+        if (64 * kRingShapes[k].nw * kRingShapes[k].spl >= Mt) {
+            shape = k;
+            break;
+        }
+    if (shape < 0) return false;
+    const int nt = 64 * kRingShapes[shape].nw, slots = nt * kRingShapes[shape].spl;
+    // ring: a power of two covering the window of at least 8 steps; the
+    // chunk is as long as the ring and the prefetch registers allow
+    cols = 1;
+    while (cols < Mt + n * 7) cols *= 2;
+    chunk = std::min({(cols - Mt) / n + 1, (nt * kRingPrefetchRegs) / (n * Mn), 64});
+    if (chunk < 1) return false;
+    const size_t roww = (size_t)slots + 2 * mn;
+    const size_t rphys = ring_duplicates(slots) ? cols + roww : cols;
+    lds = (2 * roww + 2 * kRingShapes[shape].nw + rphys * Mn) * tsize;
+    return lds <= lds_limit;
+}
+
 int frame_imode(const mapdec_code *c) { return c->I <= 2 ? 0 : 1; }
+
+// LDS bytes one workgroup may use on the current device (64 KiB when the
+// device cannot be queried, e.g. on a host without a GPU).
+size_t device_lds_limit() {
+    static thread_local int cached_dev = -1;
+    static thread_local size_t cached = 65536;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (dev != cached_dev) {
+        int v = 0;
+        cached = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                      hipSuccess && v > 0)
+                     ? (size_t)v
+                     : 65536;
+        cached_dev = dev;
+    }
+    return cached;
+}
 
 // Validates the frames and lays out the workspace.
 int build_layout(const mapdec_frame *frames, int nframes, int precision, int flags, Layout &L) {
@@ -92,7 +143,19 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         L.n_gamma += F.gamma_blocks;
         L.n_app += fr.N;
         const size_t W = (size_t)F.Mt + 2 * c->mn;
-        max_chain = std::max(max_chain, ((2 * W * L.tsize + 15) & ~(size_t)15) + 16 * sizeof(double));
+        int spl = 0;
+        size_t rlds = 0;
+        if (!fr.prior && ring_params(F.Mt, F.Mn, c->n, c->mn, L.tsize, device_lds_limit(),
+                                     spl, F.ring_chunk, F.ring_cols, rlds)) {
+            const auto key = std::make_pair(spl, c->mn);
+            L.chain_ring[key].push_back(f);
+            L.ring_lds[key] = std::max(L.ring_lds[key], rlds);
+        } else {
+            F.ring_chunk = F.ring_cols = 0;
+            L.chain_plain.push_back(f);
+            max_chain = std::max(max_chain,
+                                 ((2 * W * L.tsize + 15) & ~(size_t)15) + 16 * sizeof(double));
+        }
         max_app = std::max(max_app, (2 * (size_t)F.Mt + 2 * c->mn + c->q) * L.tsize);
         auto key = std::make_pair(c->mn, frame_imode(c));
         auto &v = L.lat[key];
@@ -115,7 +178,11 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
     L.off_gamma = off;
     off = align_up(off + sizeof(Work) * L.n_gamma);
     L.off_chain = off;
-    off = align_up(off + sizeof(int) * nframes);
+    off = align_up(off + sizeof(int) * L.chain_plain.size());
+    for (auto &kv : L.chain_ring) {
+        L.off_chain_ring[kv.first] = off;
+        off = align_up(off + sizeof(int) * kv.second.size());
+    }
     L.off_app = off;
     off = align_up(off + sizeof(Work) * L.n_app);
     L.head = off;
@@ -167,20 +234,46 @@ struct mapdec_plan {
     template <typename P>
     P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
 
-    hipError_t enqueue(hipStream_t st) const {
+    hipEvent_t ev[kMaxPhases + 1] = {};
+    bool have_events = false;
+
+    // Enqueues every launch of one run.  With ev != nullptr an event is
+    // recorded before the first phase and after each phase.
+    hipError_t enqueue(hipStream_t st, hipEvent_t *ev = nullptr, int *nphases = nullptr) const {
         const FrameDesc *fd = at<FrameDesc>(L.off_fd);
-        hipError_t e = launch_init(fd, L.nframes, st);
+        hipError_t e = hipSuccess;
+        int k = 0;
+        auto mark = [&]() {
+            if (ev && e == hipSuccess) e = hipEventRecord(ev[k], st);
+            ++k;
+        };
+        mark();
+        e = launch_init(fd, L.nframes, st);   // phase "pack"
         if (e == hipSuccess) e = launch_pack(fd, at<Work>(L.off_pack), L.n_pack, st);
-        for (auto &kv : L.lat) {
+        mark();
+        for (auto &kv : L.lat) {               // phase "lattice"
             if (e != hipSuccess) break;
             e = launch_lattice(L.fp64, kv.first.first, kv.first.second, fd,
                                at<Work>(L.off_lat.at(kv.first)), (int)kv.second.size(), st);
         }
-        if (e == hipSuccess) e = launch_gamma(L.fp64, fd, at<Work>(L.off_gamma), L.n_gamma, st);
-        if (e == hipSuccess)
-            e = launch_chain(L.fp64, fd, at<int>(L.off_chain), L.nframes, L.chain_lds, st);
-        if (e == hipSuccess)
+        mark();
+        if (e == hipSuccess)                   // phase "gamma"
+            e = launch_gamma(L.fp64, fd, at<Work>(L.off_gamma), L.n_gamma, st);
+        mark();
+        if (e == hipSuccess)                   // phase "chain"
+            e = launch_chain(L.fp64, fd, at<int>(L.off_chain), (int)L.chain_plain.size(),
+                             L.chain_lds, st);
+        for (auto &kv : L.chain_ring) {
+            if (e != hipSuccess) break;
+            e = launch_chain_ring(L.fp64, kv.first.first, kv.first.second, fd,
+                                  at<int>(L.off_chain_ring.at(kv.first)),
+                                  (int)kv.second.size(), L.ring_lds.at(kv.first), st);
+        }
+        mark();
+        if (e == hipSuccess)                   // phase "app"
             e = launch_app(L.fp64, fd, at<Work>(L.off_app), L.n_app, L.app_lds, st);
+        mark();
+        if (nphases) *nphases = k - 1;
         return e;
     }
 };
@@ -278,6 +371,7 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
         d.M = c->M; d.mn = c->mn; d.I = c->I; d.tau = c->n * fr.N;
         d.Mt = F.Mt; d.Mn = F.Mn; d.sp = F.sp; d.uniform = fr.prior ? 0 : 1;
         d.nwords = F.nwords; d.imode = frame_imode(c); d.grad = L.grad; d.ck = 0;
+        d.ring_chunk = F.ring_chunk; d.ring_cols = F.ring_cols;
         const double Pt = 1.0 - c->Pi - c->Pd;
         d.a = 0.5 * c->Pi; d.d = c->Pd; d.t1 = Pt * (1.0 - c->Ps); d.t0 = Pt * c->Ps;
         d.y = fr.y; d.prior = fr.prior; d.app = fr.app; d.dprior = fr.dprior;
@@ -295,12 +389,17 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
         d.gacc = reinterpret_cast<double *>(base + F.off_gacc);
         for (int b = 0; b < F.pack_blocks; ++b) pack[ip++] = Work{f, b * kPackWords};
         for (int b = 0; b < F.gamma_blocks; ++b) gam[ig++] = Work{f, b};
-        chain[f] = f;
+
         for (int i = 0; i < fr.N; ++i) app[ia++] = Work{f, i};
     }
     for (auto &kv : L.lat)
         std::memcpy(stage.data() + L.off_lat.at(kv.first), kv.second.data(),
                     sizeof(Work) * kv.second.size());
+    if (!L.chain_plain.empty())
+        std::memcpy(chain, L.chain_plain.data(), sizeof(int) * L.chain_plain.size());
+    for (auto &kv : L.chain_ring)
+        std::memcpy(stage.data() + L.off_chain_ring.at(kv.first), kv.second.data(),
+                    sizeof(int) * kv.second.size());
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(p->ws, stage.data(), L.head, hipMemcpyHostToDevice, s);
     // codewords go straight into each frame's region
@@ -340,8 +439,36 @@ int mapdec_plan_run(mapdec_plan *p, void *stream) {
     return e == hipSuccess ? MAPDEC_OK : MAPDEC_EDEVICE;
 }
 
+int mapdec_plan_profile(mapdec_plan *p, void *stream, float *phase_ms, int max_phases) {
+    if (!p || (max_phases > 0 && !phase_ms)) return -MAPDEC_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (!p->have_events) {
+        for (int k = 0; k <= kMaxPhases && e == hipSuccess; ++k) e = hipEventCreate(&p->ev[k]);
+        if (e != hipSuccess) return -MAPDEC_EDEVICE;
+        p->have_events = true;
+    }
+    int nph = 0;
+    e = p->enqueue(s, p->ev, &nph);
+    p->last_stream = s;
+    if (e == hipSuccess) e = hipEventSynchronize(p->ev[nph]);
+    for (int k = 0; k < nph && k < max_phases && e == hipSuccess; ++k)
+        e = hipEventElapsedTime(&phase_ms[k], p->ev[k], p->ev[k + 1]);
+    return e == hipSuccess ? nph : -MAPDEC_EDEVICE;
+}
+
+const char *mapdec_phase_name(int phase) {
+    static const char *names[] = {"pack", "lattice", "gamma", "chain", "app"};
+    return (phase >= 0 && phase < (int)(sizeof(names) / sizeof(names[0]))) ? names[phase]
+                                                                           : nullptr;
+}
+
 void mapdec_plan_destroy(mapdec_plan *p) {
     if (!p) return;
+    if (p->have_events) {
+        hipStreamSynchronize(p->last_stream);
+        for (int k = 0; k <= kMaxPhases; ++k) hipEventDestroy(p->ev[k]);
+    }
     if (p->exec) {
         hipStreamSynchronize(p->last_stream);
         hipGraphExecDestroy(p->exec);

@@ -23,6 +23,8 @@ struct FrameDesc {
     int imode;          // 0: I <= 2 (two-term insertion runs); 1: any I
     int grad;           // the adjoint pass runs for this frame
     int ck;             // checkpoint spacing of the forward metric (0 = all rows)
+    int ring_chunk;     // chain steps per prefetch chunk (single-wave chains)
+    int ring_cols;      // LDS ring columns (power of two) for Gamma(s, .)
     double a, d, t1, t0;  // lattice weights: Pi/2, Pd, Pt(1-Ps), Pt Ps
     // caller buffers (device)
     const uint8_t *y;

@@ -24,7 +24,8 @@ MAX_N, MAX_MN = 16, 8
 # every symbol include/mapdec.h declares
 EXPORTS = ["mapdec_create", "mapdec_destroy", "mapdec_workspace_size", "mapdec_decode",
            "mapdec_grad", "mapdec_plan_create", "mapdec_plan_run", "mapdec_plan_destroy",
-           "mapdec_last_error", "mapdec_strerror", "mapdec_version"]
+           "mapdec_plan_profile", "mapdec_phase_name", "mapdec_last_error",
+           "mapdec_strerror", "mapdec_version"]
 
 
 class MapdecError(RuntimeError):
@@ -68,6 +69,10 @@ def lib() -> ctypes.CDLL:
         L.mapdec_plan_run.restype = i32
         L.mapdec_plan_destroy.argtypes = [vp]
         L.mapdec_plan_destroy.restype = None
+        L.mapdec_plan_profile.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float), i32]
+        L.mapdec_plan_profile.restype = i32
+        L.mapdec_phase_name.argtypes = [i32]
+        L.mapdec_phase_name.restype = ctypes.c_char_p
         L.mapdec_last_error.argtypes = []
         L.mapdec_last_error.restype = i32
         L.mapdec_strerror.argtypes = [i32]
@@ -211,6 +216,14 @@ class Plan:
         st = lib().mapdec_plan_run(self._h, _stream_handle(stream))
         if st:
             raise MapdecError(st, "mapdec_plan_run")
+
+    def profile(self, stream=None) -> dict:
+        """One eager run with a HIP event between phases: {phase: ms}."""
+        buf = (ctypes.c_float * 16)()
+        n = lib().mapdec_plan_profile(self._h, _stream_handle(stream), buf, 16)
+        if n < 0:
+            raise MapdecError(-n, "mapdec_plan_profile")
+        return {lib().mapdec_phase_name(k).decode(): float(buf[k]) for k in range(n)}
 
     def close(self):
         if getattr(self, "_h", None):

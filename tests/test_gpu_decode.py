@@ -143,3 +143,17 @@ def test_plan_graph_replays_match_eager():
         for x, y in zip(b.apps, eager.apps):
             assert torch.equal(x, y), f"replay {rep}"
     plan.close()
+
+
+@pytest.mark.parametrize("prec", [mapdec.FP32, mapdec.FP64])
+def test_large_drift_ranges(prec):
+    # 2M+1 from 301 to 1401 states: every chain workgroup shape, including
+    # the ring indexed modulo its size
+    specs = [(31, 8, 6, 60, 0.08, 0.08, 0.01, 2, 150, 5),
+             (32, 4, 5, 40, 0.10, 0.10, 0.00, 2, 400, 6),
+             (33, 2, 4, 30, 0.10, 0.10, 0.00, 2, 700, 8)]
+    frames = [wl.random_frame(*s) for s in specs]
+    refs = [oracle.decode_frame(fr) for fr in frames]
+    b = _decode(frames, prec)
+    for f, (fr, ref) in enumerate(zip(frames, refs)):
+        _check_frame(b, f, fr, ref, prec, f"M={fr.M}")
