@@ -91,4 +91,18 @@ hipError_t launch_app(int fp64, const FrameDesc *fd, const Work *tab, int nblock
     return hipGetLastError();
 }
 
+
+// One object per precision built from k_app_tile.hip.
+hipError_t app_tile_f32(int td, int mn, int nwaves, const FrameDesc *fd, const Work *tab,
+                        int nblocks, size_t lds, hipStream_t st);
+hipError_t app_tile_f64(int td, int mn, int nwaves, const FrameDesc *fd, const Work *tab,
+                        int nblocks, size_t lds, hipStream_t st);
+
+hipError_t launch_app_tile(int fp64, int td, int mn, int nwaves, const FrameDesc *fd,
+                           const Work *tab, int nblocks, size_t lds_bytes, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    return fp64 ? app_tile_f64(td, mn, nwaves, fd, tab, nblocks, lds_bytes, st)
+                : app_tile_f32(td, mn, nwaves, fd, tab, nblocks, lds_bytes, st);
+}
+
 }  // namespace mapdec

@@ -47,6 +47,11 @@ constexpr int kNumRingShapes = 6;
 constexpr bool ring_duplicates(int slots) { return slots <= 512; }
 hipError_t launch_app(int fp64, const FrameDesc *fd, const Work *tab, int nblocks,
                       size_t lds_bytes, hipStream_t st);
+// Tiled APP (k_app_tile.hip): td symbol values per wave (2 or 4), nwaves =
+// ceil(q / td) waves per workgroup, kAppTI symbols per workgroup; every
+// frame of the launch has drift limit mn.
+hipError_t launch_app_tile(int fp64, int td, int mn, int nwaves, const FrameDesc *fd,
+                           const Work *tab, int nblocks, size_t lds_bytes, hipStream_t st);
 
 // Block sizes the host uses to build work tables.
 constexpr int kPackWords = 8;      // packed words per pack workgroup (256 threads)
@@ -54,6 +59,16 @@ constexpr int kLatticeLanes = 64;  // start indices per lattice workgroup
 constexpr int kGammaLanes = 256;   // drift states per Gamma workgroup
 constexpr int kChainThreads = 256;
 constexpr int kAppThreads = 64;
+constexpr int kAppTI = 8;   // consecutive symbols per tiled-APP workgroup
+// zero padding (states) on each side of the rows staged by the tiled APP
+__host__ __device__ constexpr int app_tile_pad(int n) { return (kAppTI - 1) * n; }
+// symbol values per wave of the tiled APP for an alphabet of size q
+constexpr int app_tile_td(int q) { return q <= 2 ? 2 : 4; }
+// LDS bytes of one tiled-APP workgroup
+constexpr size_t app_tile_lds(int Mt, int mn, int n, int q, size_t tsize) {
+    return (size_t)kAppTI * ((size_t)(Mt + 2 * app_tile_pad(n)) + (size_t)(Mt + 2 * (app_tile_pad(n) + mn)) +
+                             (size_t)q) * tsize + kAppTI * sizeof(double);
+}
 constexpr int kRingPrefetchRegs = 16;   // prefetch registers per thread in k_chain_ring
 
 }  // namespace mapdec

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "kernels.h"
@@ -54,7 +55,7 @@ struct Layout {
     int nframes = 0, fp64 = 0, grad = 0;
     size_t tsize = 4;
     size_t off_fd = 0, off_pack = 0, off_gamma = 0, off_chain = 0, off_app = 0, head = 0, total = 0;
-    int n_pack = 0, n_gamma = 0, n_app = 0;
+    int n_pack = 0, n_gamma = 0;
     // lattice work grouped by template instance (mn, imode)
     std::map<std::pair<int, int>, std::vector<Work>> lat;
     std::map<std::pair<int, int>, size_t> off_lat;
@@ -65,8 +66,29 @@ struct Layout {
     // keyed by (states per lane, mn)
     std::map<std::pair<int, int>, std::vector<int>> chain_ring;
     std::map<std::pair<int, int>, size_t> off_chain_ring, ring_lds;
+    // tiled APP work grouped by (symbols per wave, waves per workgroup, mn);
+    // frames whose rows do not fit in LDS use the one-wave APP kernel
+    std::map<std::tuple<int, int, int>, std::vector<Work>> app_tile;
+    std::map<std::tuple<int, int, int>, size_t> off_app_tile, app_tile_lds;
+    std::vector<Work> app_plain;
     std::vector<FrameLayout> fl;
 };
+
+// Reorders a work list so that the workgroups the dispatcher sends to one
+// XCD (workgroup ids congruent mod 8) take consecutive items: neighbouring
+// symbol blocks of a frame then share that XCD's L2.
+std::vector<Work> xcd_order(const std::vector<Work> &items) {
+    constexpr int kXcd = 8;
+    const size_t nb = items.size();
+    std::vector<Work> out(nb);
+    size_t start = 0;
+    for (int x = 0; x < kXcd; ++x) {
+        const size_t cnt = nb > (size_t)x ? (nb - x + kXcd - 1) / kXcd : 0;
+        for (size_t j = 0; j < cnt; ++j) out[x + kXcd * j] = items[start + j];
+        start += cnt;
+    }
+    return out;
+}
 
 // Ring-chain parameters for a uniform-prior frame (workgroup shape, steps
 // per prefetch chunk, ring slots, LDS bytes); false when the frame needs
@@ -141,7 +163,19 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         F.gamma_blocks = fr.prior ? fr.N * ((F.Mt + kGammaLanes - 1) / kGammaLanes) : 0;
         L.n_pack += F.pack_blocks;
         L.n_gamma += F.gamma_blocks;
-        L.n_app += fr.N;
+        {
+            const size_t tl = app_tile_lds(F.Mt, c->mn, c->n, c->q, L.tsize);
+            if (tl <= device_lds_limit()) {
+                const int td = app_tile_td(c->q);
+                const auto key = std::make_tuple(td, std::min(8, (c->q + td - 1) / td), c->mn);
+                auto &v = L.app_tile[key];
+                for (int b = 0; b * kAppTI < fr.N; ++b) v.push_back(Work{f, b});
+                L.app_tile_lds[key] = std::max(L.app_tile_lds[key], tl);
+            } else {
+                for (int i = 0; i < fr.N; ++i) L.app_plain.push_back(Work{f, i});
+                max_app = std::max(max_app, (2 * (size_t)F.Mt + 2 * c->mn + c->q) * L.tsize);
+            }
+        }
         const size_t W = (size_t)F.Mt + 2 * c->mn;
         int spl = 0;
         size_t rlds = 0;
@@ -156,7 +190,6 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             max_chain = std::max(max_chain,
                                  ((2 * W * L.tsize + 15) & ~(size_t)15) + 16 * sizeof(double));
         }
-        max_app = std::max(max_app, (2 * (size_t)F.Mt + 2 * c->mn + c->q) * L.tsize);
         auto key = std::make_pair(c->mn, frame_imode(c));
         auto &v = L.lat[key];
         for (int b = 0; b < F.lat_blocks; ++b) v.push_back(Work{f, b * kLatticeLanes});
@@ -183,8 +216,13 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         L.off_chain_ring[kv.first] = off;
         off = align_up(off + sizeof(int) * kv.second.size());
     }
+    for (auto &kv : L.app_tile) {
+        kv.second = xcd_order(kv.second);
+        L.off_app_tile[kv.first] = off;
+        off = align_up(off + sizeof(Work) * kv.second.size());
+    }
     L.off_app = off;
-    off = align_up(off + sizeof(Work) * L.n_app);
+    off = align_up(off + sizeof(Work) * L.app_plain.size());
     L.head = off;
 
     // per-frame regions
@@ -271,7 +309,14 @@ struct mapdec_plan {
         }
         mark();
         if (e == hipSuccess)                   // phase "app"
-            e = launch_app(L.fp64, fd, at<Work>(L.off_app), L.n_app, L.app_lds, st);
+            e = launch_app(L.fp64, fd, at<Work>(L.off_app), (int)L.app_plain.size(), L.app_lds,
+                           st);
+        for (auto &kv : L.app_tile) {
+            if (e != hipSuccess) break;
+            e = launch_app_tile(L.fp64, std::get<0>(kv.first), std::get<2>(kv.first),
+                                std::get<1>(kv.first), fd, at<Work>(L.off_app_tile.at(kv.first)),
+                                (int)kv.second.size(), L.app_tile_lds.at(kv.first), st);
+        }
         mark();
         if (nphases) *nphases = k - 1;
         return e;
@@ -360,7 +405,7 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
     Work *gam = reinterpret_cast<Work *>(stage.data() + L.off_gamma);
     int *chain = reinterpret_cast<int *>(stage.data() + L.off_chain);
     Work *app = reinterpret_cast<Work *>(stage.data() + L.off_app);
-    int ip = 0, ig = 0, ia = 0;
+    int ip = 0, ig = 0;
     unsigned char *base = p->ws;
     for (int f = 0; f < nframes; ++f) {
         const mapdec_frame &fr = frames[f];
@@ -390,10 +435,15 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
         for (int b = 0; b < F.pack_blocks; ++b) pack[ip++] = Work{f, b * kPackWords};
         for (int b = 0; b < F.gamma_blocks; ++b) gam[ig++] = Work{f, b};
 
-        for (int i = 0; i < fr.N; ++i) app[ia++] = Work{f, i};
+
     }
     for (auto &kv : L.lat)
         std::memcpy(stage.data() + L.off_lat.at(kv.first), kv.second.data(),
+                    sizeof(Work) * kv.second.size());
+    if (!L.app_plain.empty())
+        std::memcpy(app, L.app_plain.data(), sizeof(Work) * L.app_plain.size());
+    for (auto &kv : L.app_tile)
+        std::memcpy(stage.data() + L.off_app_tile.at(kv.first), kv.second.data(),
                     sizeof(Work) * kv.second.size());
     if (!L.chain_plain.empty())
         std::memcpy(chain, L.chain_plain.data(), sizeof(int) * L.chain_plain.size());
