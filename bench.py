@@ -47,6 +47,32 @@ def phase_flops(frames):
     return out
 
 
+PHASE_KERNEL = {"lattice": "k_lattice", "chain": "k_chain_ring", "app": "k_app_tile"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE counters (scaled by a 1 GiB copy's readings), or
+    None when the kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    k = rec["kernels"].get(kernel)
+    if not k:
+        return None
+    h = hashlib.sha256()
+    for f in k["sources"] + ["paper_1802_08483_amd/csrc/device_common.h",
+                             "paper_1802_08483_amd/csrc/kernels.h",
+                             "paper_1802_08483_amd/csrc/mapdec_internal.h"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != k["sha256"]:
+        return None
+    return round((k["fetch_kib"] * rec["copy_factor_fetch"] +
+                  k["write_kib"] * rec["copy_factor_write"]) * 1024)
+
+
 def time_plan(plan, steps, warmup, torch):
     for _ in range(warmup):
         plan.run()
@@ -91,6 +117,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES bytes device-to-device a few times (a plain copy "
+                         "kernel of known size, to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the decoder's frames "
@@ -100,6 +129,14 @@ def main():
 
     import numpy as np
     import torch
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "dispatches": 3}))
+        return
     from paper_1802_08483_amd import build as libbuild
     from paper_1802_08483_amd import mapdec, workloads
 
@@ -125,7 +162,7 @@ def main():
     achieved = flops[dom] / (phases[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": None, "kernel": dom,
+                "traffic": measured_traffic(PHASE_KERNEL[dom]), "kernel": PHASE_KERNEL[dom],
                 "flops_per_launch": flops[dom], "launch_ms": round(phases[dom], 4)}
 
     fp64 = None
