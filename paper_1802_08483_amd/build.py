@@ -24,6 +24,9 @@ VARIANTS = [("k_chain_ring.hip", f"chain_ring_{tag}_{k}",
               f"-DCHAIN_FN=chain_ring_{tag}_{k}"])
             for tag, t in (("f32", "float"), ("f64", "double"))
             for k, (nw, spl) in enumerate(RING_SHAPES)]
+# k_adjoint.hip is compiled once per precision
+VARIANTS += [("k_adjoint.hip", f"adj_{tag}", [f"-DADJ_T={t}", f"-DADJ_FN=adj_{tag}"])
+             for tag, t in (("f32", "float"), ("f64", "double"))]
 # k_app_tile.hip is compiled once per precision
 VARIANTS += [("k_app_tile.hip", f"app_tile_{tag}", [f"-DAPP_T={t}", f"-DAPP_FN=app_tile_{tag}"])
              for tag, t in (("f32", "float"), ("f64", "double"))]
@@ -50,7 +53,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = [(s, s, []) for s in SOURCES] + VARIANTS
     # longest compiles first
-    jobs.sort(key=lambda j: 0 if j[0] in ("k_chain_ring.hip", "k_app_tile.hip") else 1)
+    jobs.sort(key=lambda j: 0 if j[0] in ("k_chain_ring.hip", "k_app_tile.hip",
+                                         "k_adjoint.hip") else 1)
     workers = max(1, min(16, os.cpu_count() or 1, len(jobs)))
     with ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(_compile, jobs))

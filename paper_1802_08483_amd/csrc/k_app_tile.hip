@@ -7,7 +7,7 @@
 // coalesced row segment, and each loaded R(s, D, delta) feeds the TI
 // symbols whose drift band covers s:
 //   U_i(D) += alpha_i(s - n i) beta_{i+1}(s - n i + delta) R(s, D, delta).
-// alpha and beta rows are staged in LDS with zero padding wide enough that
+// FP64 alpha and beta rows are staged in LDS with zero padding wide enough that
 // no lane branches on the band edges (states outside the band, and start
 // indices outside [0, rho], have zero metrics).  The R values of the next
 // 64 start indices are loaded while the current ones are used.  The TI x TD
@@ -62,20 +62,41 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
     const int i0 = w.item * TI;
     const int PAD = app_tile_pad(n);
     const int WA = Mt + 2 * PAD, WB = Mt + 2 * (PAD + MN);
-    T *ar = (T *)smem;             // [TI][WA]  alpha_i(m) at m + M + PAD
-    T *br = ar + TI * WA;          // [TI][WB]  beta_{i+1}(m) at m + M + PAD + mn
-    T *Ush = br + TI * WB;         // [TI][q]
-    double *Zsh = (double *)(Ush + TI * q);
+    double *ar = (double *)smem;   // [TI][WA]  sc_i alpha_i(m) at m + M + PAD
+    double *br = ar + TI * WA;     // [TI][WB]  beta_{i+1}(m) at m + M + PAD + mn
+    double *Zsh = br + TI * WB;    // [TI]
+    unsigned long long *smax = (unsigned long long *)(Zsh + TI);   // [TI]
+    T *Ush = (T *)(smax + TI);     // [TI][q]
     const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6;
-    const gptr<const T> A = to_global((const T *)f.alpha);
-    const gptr<const T> B = to_global((const T *)f.beta);
+    const gptr<const double> A = to_global((const double *)f.alpha);
+    const gptr<const double> B = to_global((const double *)f.beta);
+    if (tid < TI) smax[tid] = 0ull;
     for (int j = tid; j < TI * WA; j += nth) {
         const int ii = j / WA, m = j - ii * WA - PAD, i = i0 + ii;
-        ar[j] = (i < N && m >= 0 && m < Mt) ? A[(size_t)i * Mt + m] : T(0);
+        ar[j] = (i < N && m >= 0 && m < Mt) ? A[(size_t)i * Mt + m] : 0.0;
     }
     for (int j = tid; j < TI * WB; j += nth) {
         const int ii = j / WB, m = j - ii * WB - PAD - MN, i = i0 + ii;
-        br[j] = (i < N && m >= 0 && m < Mt) ? B[(size_t)(i + 1) * Mt + m] : T(0);
+        br[j] = (i < N && m >= 0 && m < Mt) ? B[(size_t)(i + 1) * Mt + m] : 0.0;
+    }
+    __syncthreads();
+    // Two-slice scale: the rows' product alpha_i(m') beta_{i+1}(m'+delta)
+    // spans far less than either row, so dividing it by its maximum brings
+    // it into the FP32 range; the scale is folded into the staged alpha row.
+    // (Max of non-negative doubles through their bit patterns.)
+    for (int j = tid; j < TI * Mt; j += nth) {
+        const int ii = j / Mt, m = j - ii * Mt;
+        double bm = 0.0;
+#pragma unroll
+        for (int k = 0; k < Mn; ++k) bm = fmax(bm, br[ii * WB + PAD + m + k]);
+        const double v = ar[ii * WA + PAD + m] * bm;
+        if (v > 0.0) atomicMax(&smax[ii], (unsigned long long)__double_as_longlong(v));
+    }
+    __syncthreads();
+    for (int j = tid; j < TI * WA; j += nth) {
+        const int ii = j / WA;
+        const double mx = __longlong_as_double((long long)smax[ii]);
+        ar[j] = mx > 0.0 ? ar[j] / mx : 0.0;
     }
 
     const gptr<const T> R = to_global((const T *)f.R);
@@ -107,15 +128,16 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
             if (it + 1 < iters) load_r(rn, c + 64);
             const int cc = min(c, span - 1);
             const T live = c < span ? T(1) : T(0);
-            T a[TI];
+            double a[TI];
 #pragma unroll
-            for (int ii = 0; ii < TI; ++ii) a[ii] = live * ar[ii * WA + PAD + cc - n * ii];
-            const T *bb = br + PAD + cc;
+            for (int ii = 0; ii < TI; ++ii)
+                a[ii] = (double)live * ar[ii * WA + PAD + cc - n * ii];
+            const double *bb = br + PAD + cc;
 #pragma unroll
             for (int k = 0; k < Mn; ++k) {
 #pragma unroll
                 for (int ii = 0; ii < TI; ++ii) {
-                    const T kv = a[ii] * bb[ii * (WB - n) + k];
+                    const T kv = (T)(a[ii] * bb[ii * (WB - n) + k]);
 #pragma unroll
                     for (int d = 0; d < TD; ++d) acc[ii * TD + d] += kv * rc[k][d];
                 }
@@ -137,7 +159,9 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
         const T *pr = f.uniform ? nullptr : (const T *)f.prior + (size_t)(i0 + tid) * q;
         for (int D = 0; D < q; ++D) Z += (double)((pr ? pr[D] : up) * Ush[tid * q + D]);
         Zsh[tid] = Z;
-        if (f.Zinv) f.Zinv[i0 + tid] = 1.0 / Z;
+        // 1/Z_i in the units of the unscaled FP64 rows
+        const double mx = __longlong_as_double((long long)smax[tid]);
+        if (f.Zinv) f.Zinv[i0 + tid] = Z > 0.0 ? 1.0 / (Z * mx) : 0.0;
     }
     __syncthreads();
     for (int j = tid; j < TI * q; j += nth) {

@@ -27,66 +27,66 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
     extern __shared__ __align__(16) unsigned char smem[];
     const int Mt = f.Mt, mn = f.mn, M = f.M, N = f.N, Mn = f.Mn;
     const int W = Mt + 2 * mn;
-    T *buf0 = (T *)smem;
-    T *buf1 = buf0 + W;
-    double *red = (double *)(smem + (((size_t)2 * W * sizeof(T) + 15) & ~(size_t)15));
+    double *buf0 = (double *)smem;   // rows in FP64 whatever the precision
+    double *buf1 = buf0 + W;
+    double *red = buf1 + W;
     const int tid = threadIdx.x, nth = blockDim.x;
 
-    for (int j = tid; j < 2 * W; j += nth) buf0[j] = T(0);
+    for (int j = tid; j < 2 * W; j += nth) buf0[j] = 0.0;
     __syncthreads();
     const int m0 = dir == 0 ? 0 : f.rho - f.tau;
-    T *out = (T *)(dir == 0 ? f.alpha : f.beta);
+    double *out = dir == 0 ? f.alpha : f.beta;
     double *logX = dir == 0 ? f.logA : f.logB;
     const int row0 = dir == 0 ? 0 : N;
     if (tid == 0) {
-        buf0[mn + m0 + M] = T(1);
+        buf0[mn + m0 + M] = 1.0;
         logX[row0] = 0.0;
     }
     for (int mi = tid; mi < Mt; mi += nth)
-        out[(size_t)row0 * Mt + mi] = (mi == m0 + M) ? T(1) : T(0);
+        out[(size_t)row0 * Mt + mi] = (mi == m0 + M) ? 1.0 : 0.0;
     __syncthreads();
 
     const T *G = (const T *)f.G;
     double lsum = 0.0;
-    T *cur = buf0, *nxt = buf1;
+    double *cur = buf0, *nxt = buf1;
     bool dead = false;
     for (int step = 0; step < N; ++step) {
         const int i = dir == 0 ? step : N - 1 - step;
         double part = 0.0;
         for (int mi = tid; mi < Mt; mi += nth) {
             const int m = mi - M;
-            T acc = T(0);
+            double acc = 0.0;
             if (dir == 0) {
                 // alpha'_{i+1}(m) = sum_delta alpha_i(m - delta) Gamma_i(m - delta, delta)
                 for (int k = 0; k < Mn; ++k) {
                     const int dl = k - mn;
-                    acc += cur[mn + mi - dl] * gamma_at(f, G, i, m - dl, k);
+                    acc += cur[mn + mi - dl] * (double)gamma_at(f, G, i, m - dl, k);
                 }
             } else {
                 // beta'_i(m) = sum_delta Gamma_i(m, delta) beta_{i+1}(m + delta)
                 for (int k = 0; k < Mn; ++k) {
                     const int dl = k - mn;
-                    acc += gamma_at(f, G, i, m, k) * cur[mn + mi + dl];
+                    acc += (double)gamma_at(f, G, i, m, k) * cur[mn + mi + dl];
                 }
             }
             nxt[mn + mi] = acc;
-            part += (double)acc;
+            part += acc;
         }
         const double c = block_sum(part, red);
         if (!(c > 0.0) || !isfinite(c)) {
             dead = true;
             break;
         }
-        const T inv = (T)(1.0 / c);
+        const double inv = 1.0 / c;
         const int row = dir == 0 ? i + 1 : i;
         for (int mi = tid; mi < Mt; mi += nth) {
-            const T v = nxt[mn + mi] * inv;
+            const double v = nxt[mn + mi] * inv;
             nxt[mn + mi] = v;
             out[(size_t)row * Mt + mi] = v;
         }
         lsum += log(c);
         if (tid == 0) logX[row] = lsum;
-        T *t = cur;
+        double *t = cur;
         cur = nxt;
         nxt = t;
         __syncthreads();
@@ -99,12 +99,12 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
     }
     if (dir == 0) {
         // P(y) = alpha_N(rho - tau) in unnormalised terms
-        const T aN = cur[mn + (f.rho - f.tau) + M];
-        if (!(aN > T(0))) {
+        const double aN = cur[mn + (f.rho - f.tau) + M];
+        if (!(aN > 0.0)) {
             atomicOr(f.status, kStatusNoPath);
             *f.logp = -INFINITY;
         } else {
-            *f.logp = lsum + log((double)aN);
+            *f.logp = lsum + log(aN);
         }
     }
 }

@@ -10,7 +10,9 @@
 // NT SPL states (zero beyond 2M+1) plus mn zeros on each side, so no thread
 // branches on its state.  One workgroup barrier per step.
 //
-// Rows kept are the paper's pre-normalisation metrics: row i+1 is
+// Rows are FP64 at every precision (their spread within a row can exceed
+// the FP32 range); Gamma stays in the batch precision.  Rows kept are the
+// paper's pre-normalisation metrics: row i+1 is
 // alpha'_{i+1} = sum alpha_i Gamma_i with alpha_i = alpha'_i / c_i and
 // c_i = sum_m alpha'_i(m) (eqs. 11, 12).  Each wave reduces its share of the
 // new row with DPP moves and leaves the partial in LDS; after the barrier
@@ -47,22 +49,24 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     const int Mt = f.Mt, M = f.M, N = f.N, n = f.n, rho = f.rho;
     const int C = f.ring_chunk, RING = f.ring_cols, mask = RING - 1;
     const int RPHYS = DUP ? RING + NT * SPL + 2 * MN : RING;
-    T *row0 = (T *)smem;
-    T *row1 = row0 + ROWW;
-    T *part = row1 + ROWW;                             // [2][NW] wave partial sums
-    T *ring = part + 2 * NW;                           // [RPHYS][Mn]
+    using R = double;                                  // metric rows: FP64 always
+    R *row0 = (R *)smem;
+    R *row1 = row0 + ROWW;
+    R *part = row1 + ROWW;                             // [2][NW] wave partial sums
+    T *ring = (T *)(part + 2 * NW);                    // [RPHYS][Mn], batch precision
     const int tid = threadIdx.x, wv = tid >> 6;
     const gptr<const T> G = to_global((const T *)f.G);   // [Mn][sp]
     const size_t sp = (size_t)f.sp;
 
-    for (int j = tid; j < 2 * ROWW + 2 * NW + RPHYS * Mn; j += NT) row0[j] = T(0);
+    for (int j = tid; j < 2 * ROWW + 2 * NW; j += NT) row0[j] = R(0);
+    for (int j = tid; j < RPHYS * Mn; j += NT) ring[j] = T(0);
     __syncthreads();
     const int m0 = DIR == 0 ? 0 : f.rho - f.tau;
-    if (tid == 0) row0[MN + m0 + M] = T(1);
-    const gptr<T> out = to_global((T *)(DIR == 0 ? f.alpha : f.beta));
+    if (tid == 0) row0[MN + m0 + M] = R(1);
+    const gptr<R> out = to_global(DIR == 0 ? f.alpha : f.beta);
     const int rowA = DIR == 0 ? 0 : N;
     for (int mi = tid; mi < Mt; mi += NT)
-        out[(size_t)rowA * Mt + mi] = (mi == m0 + M) ? T(1) : T(0);
+        out[(size_t)rowA * Mt + mi] = (mi == m0 + M) ? R(1) : R(0);
 
     // chunk k covers steps kC .. kC+C-1 (forward) or N-1-kC down to N-C-kC
     // (backward), which read s in [n i_lo - M, n i_hi + M]
@@ -129,11 +133,11 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     const int nchunks = (N + C - 1) / C;
     if (nchunks > 1) issue(new_base(1));
 
-    T *cur = row0, *nxt = row1;
-    T own[SPL];
+    R *cur = row0, *nxt = row1;
+    R own[SPL];
     __syncthreads();
     {
-        T p = T(0);
+        R p = R(0);
 #pragma unroll
         for (int j = 0; j < SPL; ++j) {
             own[j] = cur[MN + tid + NT * j];
@@ -157,32 +161,32 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
         const int steps = min(C, N - k * C);
         for (int t = 0; t < steps; ++t) {
             const int i = DIR == 0 ? k * C + t : N - 1 - k * C - t;
-            T csum = T(0);
+            R csum = R(0);
 #pragma unroll
             for (int w = 0; w < NW; ++w) csum += part[pp * NW + w];
             const int sb = (n * i - M) & mask;
-            const T *cb = cur + MN + tid;
-            T acc[SPL];
+            const R *cb = cur + MN + tid;
+            R acc[SPL];
             if (DIR == 0) {
                 // alpha'_{i+1}(m) = sum_delta alpha_i(m - delta) Gamma(n i + m - delta, delta)
                 if (DUP) {
                     const T *rb = ring + (sb + tid + MN) * Mn + MN;
 #pragma unroll
                     for (int j = 0; j < SPL; ++j) {
-                        T a = T(0);
+                        R a = R(0);
 #pragma unroll
                         for (int d = -MN; d <= MN; ++d)
-                            a += cb[NT * j - d] * rb[(NT * j - d) * Mn + d];
+                            a += cb[NT * j - d] * (R)rb[(NT * j - d) * Mn + d];
                         acc[j] = a;
                     }
                 } else {
 #pragma unroll
                     for (int j = 0; j < SPL; ++j) {
-                        T a = T(0);
+                        R a = R(0);
 #pragma unroll
                         for (int d = -MN; d <= MN; ++d)
                             a += cb[NT * j - d] *
-                                 ring[((sb + tid + NT * j - d) & mask) * Mn + d + MN];
+                                 (R)ring[((sb + tid + NT * j - d) & mask) * Mn + d + MN];
                         acc[j] = a;
                     }
                 }
@@ -192,29 +196,29 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
                 for (int j = 0; j < SPL; ++j) {
                     const T *rb = DUP ? ring + (sb + tid + MN + NT * j) * Mn
                                       : ring + ((sb + tid + NT * j) & mask) * Mn;
-                    T a = T(0);
+                    R a = R(0);
 #pragma unroll
-                    for (int kk = 0; kk < Mn; ++kk) a += rb[kk] * cb[NT * j + kk - MN];
+                    for (int kk = 0; kk < Mn; ++kk) a += (R)rb[kk] * cb[NT * j + kk - MN];
                     acc[j] = a;
                 }
             }
-            if (!(csum > T(0))) {
+            if (!(csum > R(0))) {
                 dead = true;
                 break;
             }
-            const T inv = T(1) / csum;
+            const R inv = R(1) / csum;
             if (i != (DIR == 0 ? 0 : N - 1)) {
                 int e;
                 pmant = frexp(pmant * (double)csum, &e);
                 pexp += e;
             }
             const int row = DIR == 0 ? i + 1 : i;
-            T *nb = nxt + MN + tid;
-            T p = T(0);
+            R *nb = nxt + MN + tid;
+            R p = R(0);
 #pragma unroll
             for (int j = 0; j < SPL; ++j) {
                 const int mi = tid + NT * j;
-                const T v = (mi < Mt) ? acc[j] * inv : T(0);
+                const R v = (mi < Mt) ? acc[j] * inv : R(0);
                 own[j] = v;
                 p += v;
                 nb[NT * j] = v;
@@ -223,7 +227,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             p = wave_sum_dpp(p);
             if ((tid & 63) == 0) part[(pp ^ 1) * NW + wv] = p;
             pp ^= 1;
-            T *tmp = cur;
+            R *tmp = cur;
             cur = nxt;
             nxt = tmp;
             __syncthreads();
@@ -238,12 +242,12 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
         return;
     }
     if (DIR == 0) {
-        const T aN = cur[MN + (f.rho - f.tau) + M];
-        if (!(aN > T(0))) {
+        const R aN = cur[MN + (f.rho - f.tau) + M];
+        if (!(aN > R(0))) {
             atomicOr(f.status, kStatusNoPath);
             *f.logp = -INFINITY;
         } else {
-            *f.logp = lsum + log((double)aN);
+            *f.logp = lsum + log(aN);
         }
     }
 }

@@ -62,6 +62,30 @@ __global__ __launch_bounds__(kGammaLanes) void k_gamma(const FrameDesc *__restri
 }
 
 // ---------------------------------------------------------------------------
+// Per frame: sum the lattice workgroups' partials and apply the chain rule
+//   d/dPi = g_a / 2 - (1 - Ps) g_t1 - Ps g_t0
+//   d/dPd = g_d     - (1 - Ps) g_t1 - Ps g_t0
+//   d/dPs = -Pt g_t1 + Pt g_t0
+
+__global__ void k_dparams(const FrameDesc *__restrict__ fd, int nframes) {
+    const int fi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (fi >= nframes) return;
+    const FrameDesc &f = fd[fi];
+    if (!f.dparams) return;
+    if (*f.status != kStatusOk) {
+        f.dparams[0] = f.dparams[1] = f.dparams[2] = NAN;
+        return;
+    }
+    double g[4] = {0, 0, 0, 0};
+    for (int b = 0; b < f.lat_blocks; ++b)
+        for (int t = 0; t < 4; ++t) g[t] += f.gacc[(size_t)b * 4 + t];
+    const double Ps = f.Ps, Pt = 1.0 - f.Pi - f.Pd;
+    f.dparams[0] = 0.5 * g[0] - (1.0 - Ps) * g[2] - Ps * g[3];
+    f.dparams[1] = g[1] - (1.0 - Ps) * g[2] - Ps * g[3];
+    f.dparams[2] = -Pt * g[2] + Pt * g[3];
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 
 hipError_t launch_init(const FrameDesc *fd, int nframes, hipStream_t st) {
@@ -82,6 +106,11 @@ hipError_t launch_gamma(int fp64, const FrameDesc *fd, const Work *tab, int nblo
         hipLaunchKernelGGL(k_gamma<double>, dim3(nblocks), dim3(kGammaLanes), 0, st, fd, tab);
     else
         hipLaunchKernelGGL(k_gamma<float>, dim3(nblocks), dim3(kGammaLanes), 0, st, fd, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_dparams(const FrameDesc *fd, int nframes, hipStream_t st) {
+    hipLaunchKernelGGL(k_dparams, dim3((nframes + 63) / 64), dim3(64), 0, st, fd, nframes);
     return hipGetLastError();
 }
 

@@ -53,6 +53,17 @@ hipError_t launch_app(int fp64, const FrameDesc *fd, const Work *tab, int nblock
 hipError_t launch_app_tile(int fp64, int td, int mn, int nwaves, const FrameDesc *fd,
                            const Work *tab, int nblocks, size_t lds_bytes, hipStream_t st);
 
+// Adjoint (k_adjoint.hip, one object per precision): output adjoints W,
+// the backward lattice sweep (per (mn, imode) group, lds = n KW 64 T), and
+// the per-frame reduction with the chain rule (k_misc.hip).
+hipError_t adj_f32_w(const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st);
+hipError_t adj_f64_w(const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st);
+hipError_t adj_f32_lattice(int mn, int imode, const FrameDesc *fd, const Work *tab, int nblocks,
+                           size_t lds, hipStream_t st);
+hipError_t adj_f64_lattice(int mn, int imode, const FrameDesc *fd, const Work *tab, int nblocks,
+                           size_t lds, hipStream_t st);
+hipError_t launch_dparams(const FrameDesc *fd, int nframes, hipStream_t st);
+
 // Block sizes the host uses to build work tables.
 constexpr int kPackWords = 8;      // packed words per pack workgroup (256 threads)
 constexpr int kLatticeLanes = 64;  // start indices per lattice workgroup
@@ -64,10 +75,12 @@ constexpr int kAppTI = 8;   // consecutive symbols per tiled-APP workgroup
 __host__ __device__ constexpr int app_tile_pad(int n) { return (kAppTI - 1) * n; }
 // symbol values per wave of the tiled APP for an alphabet of size q
 constexpr int app_tile_td(int q) { return q <= 2 ? 2 : 4; }
-// LDS bytes of one tiled-APP workgroup
+// LDS bytes of one tiled-APP workgroup: FP64 rows, Z and scale per symbol,
+// the U tile in the batch precision
 constexpr size_t app_tile_lds(int Mt, int mn, int n, int q, size_t tsize) {
-    return (size_t)kAppTI * ((size_t)(Mt + 2 * app_tile_pad(n)) + (size_t)(Mt + 2 * (app_tile_pad(n) + mn)) +
-                             (size_t)q) * tsize + kAppTI * sizeof(double);
+    return (size_t)kAppTI * ((size_t)(Mt + 2 * app_tile_pad(n)) +
+                             (size_t)(Mt + 2 * (app_tile_pad(n) + mn)) + 2) * sizeof(double) +
+           (size_t)kAppTI * q * tsize;
 }
 constexpr int kRingPrefetchRegs = 16;   // prefetch registers per thread in k_chain_ring
 

@@ -59,6 +59,7 @@ struct Layout {
     // lattice work grouped by template instance (mn, imode)
     std::map<std::pair<int, int>, std::vector<Work>> lat;
     std::map<std::pair<int, int>, size_t> off_lat;
+    std::map<std::pair<int, int>, int> lat_nmax;   // longest codeword per group
     size_t chain_lds = 0, app_lds = 0;
     // chains: single-wave ring kernel grouped by states per lane, else the
     // workgroup kernel
@@ -111,7 +112,8 @@ bool ring_params(int Mt, int Mn, int n, int mn, size_t tsize, size_t lds_limit, 
     if (chunk < 1) return false;
     const size_t roww = (size_t)slots + 2 * mn;
     const size_t rphys = ring_duplicates(slots) ? cols + roww : cols;
-    lds = (2 * roww + 2 * kRingShapes[shape].nw + rphys * Mn) * tsize;
+    // FP64 rows and wave partials, Gamma ring in the batch precision
+    lds = (2 * roww + 2 * kRingShapes[shape].nw) * sizeof(double) + rphys * Mn * tsize;
     return lds <= lds_limit;
 }
 
@@ -173,7 +175,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                 L.app_tile_lds[key] = std::max(L.app_tile_lds[key], tl);
             } else {
                 for (int i = 0; i < fr.N; ++i) L.app_plain.push_back(Work{f, i});
-                max_app = std::max(max_app, (2 * (size_t)F.Mt + 2 * c->mn + c->q) * L.tsize);
+                max_app = std::max(max_app, (2 * (size_t)F.Mt + 2 * c->mn + c->q) * sizeof(double));
             }
         }
         const size_t W = (size_t)F.Mt + 2 * c->mn;
@@ -187,10 +189,10 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         } else {
             F.ring_chunk = F.ring_cols = 0;
             L.chain_plain.push_back(f);
-            max_chain = std::max(max_chain,
-                                 ((2 * W * L.tsize + 15) & ~(size_t)15) + 16 * sizeof(double));
+            max_chain = std::max(max_chain, (2 * W + 16) * sizeof(double));
         }
         auto key = std::make_pair(c->mn, frame_imode(c));
+        L.lat_nmax[key] = std::max(L.lat_nmax[key], c->n);
         auto &v = L.lat[key];
         for (int b = 0; b < F.lat_blocks; ++b) v.push_back(Work{f, b * kLatticeLanes});
     }
@@ -239,10 +241,10 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         off = align_up(off + T * c->q * F.Mn * (size_t)F.sp);
         F.off_G = off;
         off = align_up(off + T * (fr.prior ? (size_t)fr.N * F.Mn * F.Mt : (size_t)F.Mn * F.sp));
-        F.off_alpha = off;
-        off = align_up(off + T * (size_t)(fr.N + 1) * F.Mt);
+        F.off_alpha = off;   // metric rows are FP64 at every precision
+        off = align_up(off + sizeof(double) * (size_t)(fr.N + 1) * F.Mt);
         F.off_beta = off;
-        off = align_up(off + T * (size_t)(fr.N + 1) * F.Mt);
+        off = align_up(off + sizeof(double) * (size_t)(fr.N + 1) * F.Mt);
         F.off_logA = off;
         off = align_up(off + sizeof(double) * (fr.N + 1));
         F.off_logB = off;
@@ -250,7 +252,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         F.off_Zinv = off;
         off = align_up(off + sizeof(double) * fr.N);
         F.off_gacc = off;
-        off = align_up(off + sizeof(double) * 4);
+        off = align_up(off + sizeof(double) * 4 * F.lat_blocks);
         F.end = off;
     }
     L.total = off;
@@ -318,6 +320,27 @@ struct mapdec_plan {
                                 (int)kv.second.size(), L.app_tile_lds.at(kv.first), st);
         }
         mark();
+        if (L.grad) {
+            for (auto &kv : L.lat) {           // phase "wgrad"
+                if (e != hipSuccess) break;
+                const Work *tab = at<Work>(L.off_lat.at(kv.first));
+                e = L.fp64 ? adj_f64_w(fd, tab, (int)kv.second.size(), st)
+                           : adj_f32_w(fd, tab, (int)kv.second.size(), st);
+            }
+            mark();
+            for (auto &kv : L.lat) {           // phase "adjoint"
+                if (e != hipSuccess) break;
+                const Work *tab = at<Work>(L.off_lat.at(kv.first));
+                const int mn = kv.first.first, imode = kv.first.second;
+                const size_t lds =
+                    (size_t)L.lat_nmax.at(kv.first) * (2 * mn + 1) * 64 * L.tsize;
+                e = L.fp64 ? adj_f64_lattice(mn, imode, fd, tab, (int)kv.second.size(), lds, st)
+                           : adj_f32_lattice(mn, imode, fd, tab, (int)kv.second.size(), lds, st);
+            }
+            mark();
+            if (e == hipSuccess) e = launch_dparams(fd, L.nframes, st);   // phase "dparams"
+            mark();
+        }
         if (nphases) *nphases = k - 1;
         return e;
     }
@@ -378,7 +401,7 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
         fail(MAPDEC_EINVAL);
         return nullptr;
     }
-    if (flags & MAPDEC_FLAG_GRAD) {   // the adjoint is not part of this build yet
+    if (checkpoint_K > 0) {   // checkpointed forward metric: not part of this build yet
         fail(MAPDEC_EUNSUPPORTED);
         return nullptr;
     }
@@ -419,6 +442,8 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
         d.ring_chunk = F.ring_chunk; d.ring_cols = F.ring_cols;
         const double Pt = 1.0 - c->Pi - c->Pd;
         d.a = 0.5 * c->Pi; d.d = c->Pd; d.t1 = Pt * (1.0 - c->Ps); d.t0 = Pt * c->Ps;
+        d.Pi = c->Pi; d.Pd = c->Pd; d.Ps = c->Ps;
+        d.lat_blocks = F.lat_blocks;
         d.y = fr.y; d.prior = fr.prior; d.app = fr.app; d.dprior = fr.dprior;
         d.logp = logp + f; d.status = status + f;
         d.dparams = dparams ? dparams + 3 * f : nullptr;
@@ -426,8 +451,8 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
         d.ybits = reinterpret_cast<uint32_t *>(base + F.off_ybits);
         d.R = base + F.off_R;
         d.G = base + F.off_G;
-        d.alpha = base + F.off_alpha;
-        d.beta = base + F.off_beta;
+        d.alpha = reinterpret_cast<double *>(base + F.off_alpha);
+        d.beta = reinterpret_cast<double *>(base + F.off_beta);
         d.logA = reinterpret_cast<double *>(base + F.off_logA);
         d.logB = reinterpret_cast<double *>(base + F.off_logB);
         d.Zinv = L.grad ? reinterpret_cast<double *>(base + F.off_Zinv) : nullptr;
@@ -508,7 +533,8 @@ int mapdec_plan_profile(mapdec_plan *p, void *stream, float *phase_ms, int max_p
 }
 
 const char *mapdec_phase_name(int phase) {
-    static const char *names[] = {"pack", "lattice", "gamma", "chain", "app"};
+    static const char *names[] = {"pack", "lattice", "gamma", "chain", "app",
+                                  "wgrad", "adjoint", "dparams"};
     return (phase >= 0 && phase < (int)(sizeof(names) / sizeof(names[0]))) ? names[phase]
                                                                            : nullptr;
 }

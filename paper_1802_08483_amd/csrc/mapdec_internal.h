@@ -26,6 +26,7 @@ struct FrameDesc {
     int ring_chunk;     // chain steps per prefetch chunk (single-wave chains)
     int ring_cols;      // LDS ring columns (power of two) for Gamma(s, .)
     double a, d, t1, t0;  // lattice weights: Pi/2, Pd, Pt(1-Ps), Pt Ps
+    double Pi, Pd, Ps;    // channel parameters (for the gradient's chain rule)
     // caller buffers (device)
     const uint8_t *y;
     const void *prior;    // [N][q] or NULL
@@ -39,12 +40,14 @@ struct FrameDesc {
     uint32_t *ybits;      // [nwords] bit b of word w = y[32w + b]
     void *R;              // [q][Mn][sp] receiver metric R(s, D, delta)
     void *G;              // uniform: [Mn][sp] sum_D R / q; else [N][Mn][Mt]
-    void *alpha;          // [N+1][Mt] normalised forward metric
-    void *beta;           // [N+1][Mt] normalised backward metric
+    double *alpha;        // [N+1][Mt] forward metric rows (FP64 at every precision)
+    double *beta;         // [N+1][Mt] backward metric rows (FP64 at every precision)
     double *logA;         // [N+1] log of the product of forward normalisers
     double *logB;         // [N+1] log of the product of backward normalisers
     double *Zinv;         // [N] 1 / sum_D S_i(D)  (gradient passes)
-    double *gacc;         // [4] d log P / d(a, d, t1, t0) accumulators
+    double *gacc;         // [lat_blocks][4] partial d log P / d(a, d, t1, t0)
+    int lat_blocks;       // lattice workgroups of this frame
+    int pad1;
 };
 
 // Work-table entry: which frame a workgroup serves and where in it.
