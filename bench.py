@@ -4,14 +4,16 @@
 Workload: 256 frames, q=16 codewords of n=10 bits, N=500 symbols per frame
 (tau = 5000 bits), BSID channel Pi=Pd=0.05, Ps=0.01, insertion cap I=2,
 drift limits M=98 and mn=6, uniform priors, seeded synthetic frames.  A
-step is one FP32 batched decode of the whole batch (receiver-metric
-lattice, forward/backward chains, APPs and log P(y)) replayed as one HIP
+step is one FP32 batched decode plus adjoint of the whole batch
+(receiver-metric lattice, forward/backward chains, APPs, log P(y), then
+d log P(y) / d(Pi, Pd, Ps) and d log P(y) / d prior) replayed as one HIP
 graph, with every input already in HBM.
 
-Prints one JSON line: symbols decoded per second, the roofline of the
-dominant kernel (live HIP-event timing per phase), the FP64 plain GPU
-decode of the same frames, the FP32 error against the FP64 CPU oracle, and
-the oracle's own throughput on a bounded sample (host cores).
+Prints one JSON line: symbols per second, the roofline of the dominant
+kernel (live HIP-event timing per phase), the FP32 decode alone and the
+FP64 plain GPU decode of the same frames, the FP32 errors against the FP64
+CPU oracle, and the oracle's own throughput (decode plus gradient) on a
+bounded sample (host cores).
 """
 import argparse
 import json
@@ -37,17 +39,23 @@ def corridor_nodes(n, mn):
 def phase_flops(frames):
     """Algorithmic flops of each phase for a batch (FMA = 2 flops).
     lattice: rho q C(n, mn) (3 + 2I); chain: 4 N M_tau M_n (alpha and beta);
-    app: 2 N M_tau M_n (q + 1)."""
-    out = {"lattice": 0.0, "chain": 0.0, "app": 0.0}
+    app: 2 N M_tau M_n (q + 1); wgrad: 3 N M_tau M_n (uniform priors) or
+    4 N M_tau M_n q; adjoint: three lattice passes (forward recompute,
+    adjoint propagation, parameter products)."""
+    out = {"lattice": 0.0, "chain": 0.0, "app": 0.0, "wgrad": 0.0, "adjoint": 0.0}
     for fr in frames:
         Mt, Mn = 2 * fr.M + 1, 2 * fr.mn + 1
-        out["lattice"] += fr.rho * fr.q * corridor_nodes(fr.n, fr.mn) * (3 + 2 * fr.I)
+        lat = fr.rho * fr.q * corridor_nodes(fr.n, fr.mn) * (3 + 2 * fr.I)
+        out["lattice"] += lat
         out["chain"] += 4.0 * fr.N * Mt * Mn
         out["app"] += 2.0 * fr.N * Mt * Mn * (fr.q + 1)
+        out["wgrad"] += (3.0 if fr.prior is None else 4.0 * fr.q) * fr.N * Mt * Mn
+        out["adjoint"] += 3.0 * lat
     return out
 
 
-PHASE_KERNEL = {"lattice": "k_lattice", "chain": "k_chain_ring", "app": "k_app_tile"}
+PHASE_KERNEL = {"lattice": "k_lattice", "chain": "k_chain_ring", "app": "k_app_tile",
+                "wgrad": "k_wadj", "adjoint": "k_adjoint"}
 
 
 def measured_traffic(kernel):
@@ -88,25 +96,26 @@ def time_plan(plan, steps, warmup, torch):
 
 
 def cpu_baseline(frames, budget_s=15.0):
-    """The FP64 oracle on a bounded sample of the batch, one frame per host
-    thread.  Returns (baseline dict, {frame index: oracle result})."""
+    """The FP64 oracle (decode and gradient) on a bounded sample of the
+    batch, one frame per host thread.  Returns (baseline dict, {frame index:
+    oracle result})."""
     import oracle
     nthreads = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
-    first = oracle.decode_frame(frames[0])
+    first = oracle.decode_frame(frames[0], grad=True)
     t1 = time.perf_counter() - t0
     nsample = int(min(len(frames), max(nthreads, round(budget_s / max(t1, 1e-3)))))
     nsample = max(nthreads, (nsample // nthreads) * nthreads) if nsample >= nthreads else nsample
     idx = list(range(nsample))
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=nthreads) as ex:
-        res = list(ex.map(lambda f: oracle.decode_frame(frames[f]), idx))
+        res = list(ex.map(lambda f: oracle.decode_frame(frames[f], grad=True), idx))
     wall = time.perf_counter() - t0
     syms = sum(frames[f].N for f in idx)
     refs = dict(zip(idx, res))
     refs.setdefault(0, first)
     return ({"value": syms / wall, "unit": "symbols/s", "cores": nthreads, "kind": "oracle",
-             "sample": f"{nsample} of {len(frames)} frames (oracle FP64 decode, one frame per "
+             "sample": f"{nsample} of {len(frames)} frames (oracle FP64 decode and gradient, one frame per "
                        f"thread, {wall:.2f} s wall, ~{t1 * nsample:.1f} s CPU)"}, refs)
 
 
@@ -145,11 +154,18 @@ def main():
     frames = workloads.make_workload(WORKLOAD)
     total_syms = sum(fr.N for fr in frames)
 
-    b32 = mapdec.batch_from_frames(frames, precision=mapdec.FP32)
+    b32 = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True)
     plan = b32.plan(graph=True)
     ms = time_plan(plan, args.steps, args.warmup, torch)
     if not (b32.status == 0).all():
         raise RuntimeError("a frame reported no path")
+
+    bdec = mapdec.batch_from_frames(frames, precision=mapdec.FP32)
+    pdec = bdec.plan(graph=True)
+    msdec = time_plan(pdec, args.steps, 1, torch)
+    decode_only = {"value": round(total_syms / (msdec * 1e-3), 1), "ms_per_step": round(msdec, 4)}
+    pdec.close()
+    del bdec
 
     # per-phase times (HIP events between phases, same stream), averaged
     acc = {}
@@ -179,15 +195,21 @@ def main():
         cpu, refs = cpu_baseline(frames)
     else:
         import oracle
-        refs = {0: oracle.decode_frame(frames[0])}
-    app_err, lp_err = 0.0, 0.0
+        refs = {0: oracle.decode_frame(frames[0], grad=True)}
+    app_err, lp_err, g_err = 0.0, 0.0, 0.0
     for f, ref in refs.items():
         app = b32.apps[f].double().cpu().numpy()
         app_err = max(app_err, float(np.abs(app - ref["app"]).max()))
         lp_err = max(lp_err, abs(float(b32.logp[f]) - ref["logp"]) / abs(ref["logp"]))
+        gp = b32.dparams[f].cpu().numpy()
+        g_err = max(g_err, float(np.abs(gp - ref["dparams"]).max() /
+                                 np.abs(ref["dparams"]).max()))
+        dpr = b32.dpriors[f].double().cpu().numpy()
+        g_err = max(g_err, float(np.abs(dpr - ref["dprior"]).max() /
+                                 np.abs(ref["dprior"]).max()))
 
     line = {
-        "metric": "symbols decoded/sec, FP32 batched vs FP64 plain, APP err <=1e-5",
+        "metric": "symbols decoded/sec, FP32 batched+adjoint vs FP64 plain, APP err <=1e-5",
         "value": round(total_syms / (ms * 1e-3), 1),
         "unit": "symbols/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -197,12 +219,13 @@ def main():
         "config": {"workload": workloads.WORKLOAD_NAMES[WORKLOAD], "frames": len(frames),
                    "q": 16, "n": 10, "N": 500, "Pi": 0.05, "Pd": 0.05, "Ps": 0.01, "I": 2,
                    "M": frames[0].M, "mn": frames[0].mn, "priors": "uniform",
-                   "graph": True},
+                   "graph": True, "step": "decode+adjoint"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "decode_only": decode_only,
         "fp64_plain": fp64,
         "accuracy": {"frames_checked": len(refs), "app_max_abs_err": app_err,
-                     "logp_max_rel_err": lp_err},
+                     "logp_max_rel_err": lp_err, "grad_max_rel_err": g_err},
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
     }
     plan.close()

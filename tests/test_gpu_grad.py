@@ -102,3 +102,24 @@ def test_central_differences_of_gpu_decode():
             vals.append(float(bb.logp[0]))
         fd.append((vals[0] - vals[1]) / (2 * h))
     assert _rel(g32, fd) <= 1e-4, f"{g32} vs {fd}"
+
+
+def test_autograd_function_logits_and_params():
+    # autograd through softmax logits and (Pi, Pd, Ps) against the closed
+    # form APP - prior for the logits and the oracle for the parameters
+    from paper_1802_08483_amd.autograd import MapDecFn
+    frames = wl.make_workload(4, nframes=3)
+    fr0 = frames[0]
+    logits = torch.from_numpy(np.log(np.stack([f.prior for f in frames]))).cuda()
+    logits = logits.float().requires_grad_(True)
+    params = torch.tensor([fr0.Pi, fr0.Pd, fr0.Ps], dtype=torch.float64, requires_grad=True)
+    ys = [torch.from_numpy(f.y).cuda() for f in frames]
+    prior = torch.softmax(logits, dim=-1)
+    logp, app = MapDecFn.apply(prior, params, ys, fr0.codebook, fr0.I, fr0.M, fr0.mn)
+    logp.sum().backward()
+    gl = logits.grad.double().cpu().numpy()
+    closed = app.double().cpu().numpy() - prior.detach().double().cpu().numpy()
+    assert _rel(gl, closed) <= 1e-4
+    refs = [oracle.decode_frame(f, grad=True) for f in frames]
+    gp_ref = np.sum([r["dparams"] for r in refs], axis=0)
+    assert _rel(params.grad.numpy(), gp_ref) <= 1e-4
