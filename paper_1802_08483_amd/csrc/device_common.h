@@ -105,4 +105,9 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return tot;
 }
 
+// Ends one arm of a wave-uniform branch whose two arms differ only in an
+// operand: the empty volatile asm keeps the compiler from merging the arms
+// into one with per-lane selects, so the branch stays a scalar branch.
+__device__ __forceinline__ void keep_branch() { asm volatile(""); }
+
 }  // namespace mapdec

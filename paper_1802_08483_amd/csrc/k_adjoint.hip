@@ -10,10 +10,16 @@
 //   W(s, D, delta) = sum_{i : |s - n i| <= M} prior_i(D) alpha_i(s - n i)
 //                    beta_{i+1}(s - n i + delta) / Z_i                 (k_wadj)
 // followed by one backward sweep through every lattice of eqs. 7-10 seeded
-// with the output adjoints W, accumulating d/d(a, d, t1, t0) of the
-// lattice weights a = Pi/2, d = Pd, t1 = Pt(1-Ps), t0 = Pt Ps (k_adjoint),
-// and the chain rule to (Pi, Pd, Ps) with Pt = 1 - Pi - Pd (k_dparams, in
-// k_misc.hip).
+// with the output adjoints W (k_adjoint), which accumulates the partials
+// g_d, g_1, g_0 of log P with respect to the lattice weights d = Pd,
+// t1 = Pt(1-Ps), t0 = Pt Ps, and, where needed, g_a for a = Pi/2.
+//
+// Every path through the frame's lattices inserts rho - tau more bits than it
+// deletes, so a g_a - d g_d = rho - tau exactly; k_dparams (k_misc.hip) uses
+// that to obtain g_a from g_d, except when Pi is zero or small against Pd
+// (a g_a would then be a small difference of larger terms), where the sweep
+// accumulates g_a itself.  k_dparams then applies the chain rule to
+// (Pi, Pd, Ps) with Pt = 1 - Pi - Pd.
 // Per-lattice sums are single-pass in T; every sum across lattices is FP64.
 #include "device_common.h"
 
@@ -24,48 +30,93 @@
 namespace mapdec {
 
 // ---------------------------------------------------------------------------
-// W(s, D, delta): lane = start index s.  Uniform priors give W independent
-// of D (one [Mn][sp] table, written over Gamma); general priors give
-// [q][Mn][sp] (written over R, which the APP no longer needs).
+// W(s, D, delta): lane = start index s; the 64 lanes of a workgroup take
+// consecutive s, so the symbols i whose drift band reaches the wave form one
+// wave-uniform range and every alpha / beta load is a coalesced row segment.
+// Products and sums are FP64 (the metric rows are FP64); W is stored in T.
+// Uniform priors give W independent of D (one [Mn][sp] table, written over
+// Gamma); general priors give [q][Mn][sp] (written over R, which the APP no
+// longer needs), computed in chunks of kWadjDC symbol values.
 
-template <typename T>
+constexpr int kWadjDC = 4;
+
+template <typename T, int MN>
 __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
                                              const Work *__restrict__ tab) {
+    constexpr int KW = 2 * MN + 1;
     const Work w = tab[blockIdx.x];
     const FrameDesc &f = fd[w.frame];
     if (*f.status != kStatusOk) return;
-    const int s = w.item + (int)threadIdx.x;
-    if (s > f.rho) return;
-    const int n = f.n, M = f.M, Mt = f.Mt, Mn = f.Mn, mn = f.mn, N = f.N, q = f.q;
+    const int s0 = w.item, s = s0 + (int)threadIdx.x;
+    const int n = f.n, M = f.M, Mt = f.Mt, N = f.N, q = f.q, rho = f.rho;
+    const bool live = s <= rho;
     const gptr<const double> A = to_global((const double *)f.alpha);
     const gptr<const double> B = to_global((const double *)f.beta);
+    const gptr<const double> Zi = to_global((const double *)f.Zinv);
     const size_t sp = (size_t)f.sp;
-    // symbols whose drift band [n i - M, n i + M] contains s
-    const int ilo = max(0, (s - M + n - 1) / n), ihi = min(N - 1, (s + M) / n);
-    if (f.uniform) {
-        const gptr<T> W = to_global((T *)f.G);
-        for (int k = 0; k < Mn; ++k) {
-            double acc = 0.0;
-            for (int i = ilo; i <= ihi; ++i) {
-                const int mp = s - n * i, m = mp + k - mn;
-                if (m < -M || m > M) continue;
-                acc += A[(size_t)i * Mt + mp + M] * B[(size_t)(i + 1) * Mt + m + M] * f.Zinv[i];
-            }
-            W[(size_t)k * sp + s] = (T)(acc / q);
+    // symbols whose band [n i - M, n i + M] meets [s0, s0 + 63]
+    const int ilo = s0 - M <= 0 ? 0 : (s0 - M + n - 1) / n;
+    const int ihi = min(N - 1, (s0 + 63 + M) / n);
+    // one term of the sum over i: the lane's alpha_i(m') / Z_i and beta_{i+1}(m' + delta).
+    // Every load is issued (addresses clamped into the row, out-of-band values
+    // multiplied by 0), so the compiler cannot turn them into one branch and
+    // one wait per load.
+    auto term = [&](int i, double &av, double (&bv)[KW]) {
+        const int mp = s - n * i;
+        const double in = (live && mp >= -M && mp <= M) ? 1.0 : 0.0;
+        const int mc = min(max(mp, -M), M);
+        av = A[(size_t)i * Mt + mc + M] * Zi[i] * in;
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            const int m = mp + k - MN;
+            const int cm = min(max(m, -M), M);
+            const double b = B[(size_t)(i + 1) * Mt + cm + M];
+            bv[k] = b * ((m >= -M && m <= M) ? 1.0 : 0.0);
         }
+    };
+    if (f.uniform) {
+        double acc[KW];
+#pragma unroll
+        for (int k = 0; k < KW; ++k) acc[k] = 0.0;
+#pragma unroll 2
+        for (int i = ilo; i <= ihi; ++i) {
+            double av, bv[KW];
+            term(i, av, bv);
+#pragma unroll
+            for (int k = 0; k < KW; ++k) acc[k] += av * bv[k];
+        }
+        if (!live) return;
+        const gptr<T> W = to_global((T *)f.G);
+        const double invq = 1.0 / q;
+#pragma unroll
+        for (int k = 0; k < KW; ++k) W[(size_t)k * sp + s] = (T)(acc[k] * invq);
     } else {
         const gptr<T> W = to_global((T *)f.R);
         const T *pr = (const T *)f.prior;
-        for (int D = 0; D < q; ++D) {
-            for (int k = 0; k < Mn; ++k) {
-                double acc = 0.0;
-                for (int i = ilo; i <= ihi; ++i) {
-                    const int mp = s - n * i, m = mp + k - mn;
-                    if (m < -M || m > M) continue;
-                    acc += (double)pr[(size_t)i * q + D] * A[(size_t)i * Mt + mp + M] *
-                           B[(size_t)(i + 1) * Mt + m + M] * f.Zinv[i];
+        for (int D0 = 0; D0 < q; D0 += kWadjDC) {
+            double acc[kWadjDC][KW];
+#pragma unroll
+            for (int c = 0; c < kWadjDC; ++c)
+#pragma unroll
+                for (int k = 0; k < KW; ++k) acc[c][k] = 0.0;
+            for (int i = ilo; i <= ihi; ++i) {
+                double av, bv[KW];
+                term(i, av, bv);
+#pragma unroll
+                for (int c = 0; c < kWadjDC; ++c) {
+                    const int D = min(D0 + c, q - 1);
+                    const double pa = (double)pr[(size_t)i * q + D] * av;
+#pragma unroll
+                    for (int k = 0; k < KW; ++k) acc[c][k] += pa * bv[k];
                 }
-                W[((size_t)D * Mn + k) * sp + s] = (T)acc;
+            }
+            if (!live) continue;
+#pragma unroll
+            for (int c = 0; c < kWadjDC; ++c) {
+                if (D0 + c >= q) break;
+#pragma unroll
+                for (int k = 0; k < KW; ++k)
+                    W[((size_t)(D0 + c) * KW + k) * sp + s] = (T)acc[c][k];
             }
         }
     }
@@ -73,16 +124,24 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
 
 // ---------------------------------------------------------------------------
 // Backward sweep through the lattices.  Lane = start index s, loop over D
-// (codeword bits are wave-uniform).  Forward rows F_0 .. F_{n-1} are parked
-// in LDS ([row][k][lane], conflict-free); the sweep then runs from the last
-// row up, with corridor coordinates k = j - r + MN as in the lattice kernel:
+// (codeword bits are wave-uniform).  The even forward rows F_2, F_4, .. below
+// row n are parked in LDS as 16-byte slots ([row][slot][lane],
+// conflict-free) and each odd row is recomputed from the even row under it
+// when the sweep needs it (half the LDS, so twice the waves per SIMD, for
+// one extra forward row per two rows); the sweep then
+// runs from the last row up, with corridor coordinates k = j - r + MN as in
+// the lattice kernel:
 //   Gbar_n = Fbar_n = W
 //   Gbar_r[k] = Fbar_r[k] + sum_t a_t Fbar_r[k + t]        (r < n)
-//   abar += Fbar_r[k] sum_t (t a^(t-1)) G_r[k - t]         (r < n, t <= I)
 //   dbar += Gbar_r[k] F_{r-1}[k + 1]
-//   t1bar / t0bar += Gbar_r[k] F_{r-1}[k] (bit received equal / flipped)
+//   P_x[b] += Gbar_r[k] F_{r-1}[k]     (x = codeword bit x_r, b = received
+//                                       position of the diagonal move)
 //   Fbar_{r-1}[k] = Q_r[k] Gbar_r[k] + d Gbar_r[k - 1]
-// and row 0, F_0[k] = a^(k - MN), adds its own term to abar.
+// After each lattice, t1bar = sum_b P_{y_b}[b] (received bit equal to the
+// codeword bit) and t0bar = sum_b P_{1 - y_b}[b].  With SA the sweep also
+// accumulates
+//   abar += Fbar_r[k] sum_t (t a^(t-1)) G_r[k - t]         (r < n, t <= I)
+// and row 0, F_0[k] = a^(k - MN), adds its own term.
 
 template <typename T, int MN, int NB>
 __device__ __forceinline__ void adj_row_in(T (&G)[2 * MN + 1], const T (&F)[2 * MN + 1],
@@ -96,11 +155,19 @@ __device__ __forceinline__ void adj_row_in(T (&G)[2 * MN + 1], const T (&F)[2 * 
     }
 }
 
-template <typename T, int MN, int IM>
+template <typename T>
+struct alignas(16) Slot {
+    static constexpr int E = 16 / sizeof(T);
+    T v[E];
+};
+
+template <typename T, int MN, int IM, bool SA>
 __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd,
                                                 const Work *__restrict__ tab) {
     constexpr int KW = 2 * MN + 1;
     constexpr int NB = kMaxN + MN;
+    constexpr int VE = Slot<T>::E;
+    constexpr int KV = (KW + VE - 1) / VE;
     extern __shared__ __align__(16) unsigned char smem[];
     const Work w = tab[blockIdx.x];
     const FrameDesc &f = fd[w.frame];
@@ -110,7 +177,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
     const bool live = s <= f.rho;
     const int n = f.n, q = f.q, rho = f.rho;
     const T d = (T)f.d, t1 = (T)f.t1, t0 = (T)f.t0;
-    T *rows = (T *)smem;   // [n][KW][64]
+    Slot<T> *rows = (Slot<T> *)smem;   // [(n - 1) / 2][KV][64]: F_2, F_4, ..
 
     T apow[IM + 1], dapow[IM + 1];
     {
@@ -124,27 +191,50 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
             apow[t] = (t <= f.I) ? p : T(0);
         }
     }
+    T F0[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+        const int dl = k - MN;   // row 0: dl insertions before the first bit
+        F0[k] = (dl >= 0 && dl <= IM) ? apow[dl] : T(0);
+    }
     const int sl = live ? s : 0;
     const int wi = sl >> 5, sh = sl & 31;
     const uint32_t lo = f.ybits[wi], hi = f.ybits[wi + 1];
     const uint32_t win = sh ? ((lo >> sh) | (hi << (32 - sh))) : lo;
-    // Q values for a 0 / 1 codeword bit, and the received bit as 0/1 weights
-    // (exact) to split the transmission adjoint into equal / flipped bits
-    T qx0[NB], qx1[NB], ym[NB], yn[NB];
+    // Q values for a 0 / 1 codeword bit
+    T qx0[NB], qx1[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const bool one = (win >> b) & 1u;
         qx0[b] = one ? t0 : t1;
         qx1[b] = one ? t1 : t0;
-        ym[b] = one ? T(1) : T(0);
-        yn[b] = one ? T(0) : T(1);
     }
     const gptr<const T> Wt = to_global((const T *)(f.uniform ? f.G : f.R));
     const size_t sp = (size_t)f.sp;
     double ga = 0.0, gd = 0.0, g1 = 0.0, g0 = 0.0;
 
+    // slot r / 2 - 1 holds the even row F_r
+    auto park = [&](int r, const T(&F)[KW]) {
+#pragma unroll
+        for (int c = 0; c < KV; ++c) {
+            Slot<T> sv;
+#pragma unroll
+            for (int e = 0; e < VE; ++e) sv.v[e] = (c * VE + e < KW) ? F[c * VE + e] : T(0);
+            rows[((r / 2 - 1) * KV + c) * 64 + lane] = sv;
+        }
+    };
+    auto unpark = [&](int r, T(&F)[KW]) {
+#pragma unroll
+        for (int c = 0; c < KV; ++c) {
+            const Slot<T> sv = rows[((r / 2 - 1) * KV + c) * 64 + lane];
+#pragma unroll
+            for (int e = 0; e < VE; ++e)
+                if (c * VE + e < KW) F[c * VE + e] = sv.v[e];
+        }
+    };
+
     for (int D = 0; D < q; ++D) {
-        const uint32_t cw = f.cw[D];
+        const uint32_t cw = __builtin_amdgcn_readfirstlane(f.cw[D]);   // wave-uniform
         // output adjoints of this lattice (zero for invalid segments)
         T Fb[KW];
         const size_t wbase = (size_t)(f.uniform ? 0 : D) * KW * sp;
@@ -153,55 +243,78 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
             const int len = n + k - MN;
             Fb[k] = (live && len >= 0 && s + len <= rho) ? Wt[wbase + (size_t)k * sp + sl] : T(0);
         }
-        // forward rows F_0 .. F_{n-1} to LDS
-        T F[KW];
+        // forward rows F_1 .. F_{n-1}; the even ones to LDS
+        {
+            T F[KW];
 #pragma unroll
-        for (int k = 0; k < KW; ++k) {
-            const int dl = k - MN;
-            F[k] = (dl >= 0 && dl <= IM) ? apow[dl] : T(0);
-        }
+            for (int k = 0; k < KW; ++k) F[k] = F0[k];
 #pragma unroll
-        for (int r = 1; r <= kMaxN; ++r) {
-            if (r > n - 1) break;
+            for (int r = 1; r <= kMaxN; ++r) {
+                if (r > n - 1) continue;   // constant trip count: the loop unrolls
+                T G[KW];
+                if ((cw >> (n - r)) & 1u) {
+                    adj_row_in<T, MN, NB>(G, F, qx1, d, r);
+                    keep_branch();
+                } else {
+                    adj_row_in<T, MN, NB>(G, F, qx0, d, r);
+                }
 #pragma unroll
-            for (int k = 0; k < KW; ++k) rows[((r - 1) * KW + k) * 64 + lane] = F[k];
-            T G[KW];
-            if ((cw >> (n - r)) & 1u)
-                adj_row_in<T, MN, NB>(G, F, qx1, d, r);
-            else
-                adj_row_in<T, MN, NB>(G, F, qx0, d, r);
+                for (int k = 0; k < KW; ++k) {
+                    T v = G[k];
 #pragma unroll
-            for (int k = 0; k < KW; ++k) {
-                T v = G[k];
-#pragma unroll
-                for (int t = 1; t <= IM; ++t)
-                    if (t <= k) v += apow[t] * G[k - t];
-                F[k] = v;
+                    for (int t = 1; t <= IM; ++t)
+                        if (t <= k) v += apow[t] * G[k - t];
+                    F[k] = v;
+                }
+                if ((r & 1) == 0) park(r, F);
             }
         }
-#pragma unroll
-        for (int k = 0; k < KW; ++k) rows[((n - 1) * KW + k) * 64 + lane] = F[k];
         // backward sweep, rows n .. 1
-        T sa = T(0), sd = T(0), s1 = T(0), s0 = T(0);
+        T P0[NB], P1[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) P0[b] = P1[b] = T(0);
+        T sa = T(0), sd = T(0);
 #pragma unroll
         for (int rr = kMaxN; rr >= 1; --rr) {
             if (rr > n) continue;
             const int r = rr;
+            // F_{r-1}: parked (even), row 0, or recomputed from F_{r-2} (odd)
             T Fp[KW];
+            if (r == 1) {
 #pragma unroll
-            for (int k = 0; k < KW; ++k) Fp[k] = rows[((r - 1) * KW + k) * 64 + lane];
+                for (int k = 0; k < KW; ++k) Fp[k] = F0[k];
+            } else if (((r - 1) & 1) == 0) {
+                unpark(r - 1, Fp);
+            } else {
+                T E[KW];
+                if (r == 2) {
+#pragma unroll
+                    for (int k = 0; k < KW; ++k) E[k] = F0[k];
+                } else {
+                    unpark(r - 2, E);
+                }
+                T G[KW];
+                if ((cw >> (n - (r - 1))) & 1u) {
+                    adj_row_in<T, MN, NB>(G, E, qx1, d, r - 1);
+                    keep_branch();
+                } else {
+                    adj_row_in<T, MN, NB>(G, E, qx0, d, r - 1);
+                }
+#pragma unroll
+                for (int k = 0; k < KW; ++k) {
+                    T v = G[k];
+#pragma unroll
+                    for (int t = 1; t <= IM; ++t)
+                        if (t <= k) v += apow[t] * G[k - t];
+                    Fp[k] = v;
+                }
+            }
             const bool xb = (cw >> (n - r)) & 1u;
             T Gb[KW];
             if (r == n) {
 #pragma unroll
                 for (int k = 0; k < KW; ++k) Gb[k] = Fb[k];
             } else {
-                // G_r recomputed from F_{r-1} for the insertion-weight term
-                T G[KW];
-                if (xb)
-                    adj_row_in<T, MN, NB>(G, Fp, qx1, d, r);
-                else
-                    adj_row_in<T, MN, NB>(G, Fp, qx0, d, r);
 #pragma unroll
                 for (int k = 0; k < KW; ++k) {
                     T v = Fb[k];
@@ -209,25 +322,34 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
                     for (int t = 1; t <= IM; ++t)
                         if (k + t < KW) v += apow[t] * Fb[k + t];
                     Gb[k] = v;
-                    T u = T(0);
+                }
+                if constexpr (SA) {
+                    // G_r recomputed from F_{r-1} for the insertion-weight term
+                    T G[KW];
+                    if (xb) {
+                        adj_row_in<T, MN, NB>(G, Fp, qx1, d, r);
+                        keep_branch();
+                    } else {
+                        adj_row_in<T, MN, NB>(G, Fp, qx0, d, r);
+                    }
 #pragma unroll
-                    for (int t = 1; t <= IM; ++t)
-                        if (t <= k) u += dapow[t] * G[k - t];
-                    sa += Fb[k] * u;
+                    for (int k = 0; k < KW; ++k) {
+                        T u = T(0);
+#pragma unroll
+                        for (int t = 1; t <= IM; ++t)
+                            if (t <= k) u += dapow[t] * G[k - t];
+                        sa += Fb[k] * u;
+                    }
                 }
             }
-            // diagonal and vertical moves into row r; yeq / yne are the 0/1
-            // weights of "received bit equal to / different from x_r"
-            auto back = [&](const T(&qx)[NB], const T(&yeq)[NB], const T(&yne)[NB]) {
+#pragma unroll
+            for (int k = 0; k + 1 < KW; ++k) sd += Gb[k] * Fp[k + 1];
+            // diagonal moves into row r and the adjoint of F_{r-1}
+            auto back = [&](const T(&qx)[NB], T(&P)[NB]) {
 #pragma unroll
                 for (int k = 0; k < KW; ++k) {
-                    if (k + 1 < KW) sd += Gb[k] * Fp[k + 1];
                     const int b = r + k - MN - 1;
-                    if (b >= 0) {
-                        const T prod = Gb[k] * Fp[k];
-                        s1 += prod * yeq[b];
-                        s0 += prod * yne[b];
-                    }
+                    if (b >= 0) P[b] += Gb[k] * Fp[k];
                 }
 #pragma unroll
                 for (int k = 0; k < KW; ++k) {
@@ -237,21 +359,33 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
                     Fb[k] = v;
                 }
             };
-            if (xb)
-                back(qx1, ym, yn);
-            else
-                back(qx0, yn, ym);
+            if (xb) {
+                back(qx1, P1);
+                keep_branch();
+            } else {
+                back(qx0, P0);
+            }
         }
-        // row 0: F_0[k] = a^(k - MN) for 1 <= k - MN <= I
+        if constexpr (SA) {
+            // row 0: F_0[k] = a^(k - MN) for 1 <= k - MN <= I
 #pragma unroll
-        for (int k = 0; k < KW; ++k) {
-            const int dl = k - MN;
-            if (dl >= 1 && dl <= IM) sa += Fb[k] * dapow[dl];
+            for (int k = 0; k < KW; ++k) {
+                const int dl = k - MN;
+                if (dl >= 1 && dl <= IM) sa += Fb[k] * dapow[dl];
+            }
+            ga += (double)sa;
         }
-        ga += (double)sa;
+        // received bit equal to / different from the codeword bit
+        T se = T(0), sn = T(0);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const bool one = (win >> b) & 1u;
+            se += one ? P1[b] : P0[b];
+            sn += one ? P0[b] : P1[b];
+        }
         gd += (double)sd;
-        g1 += (double)s1;
-        g0 += (double)s0;
+        g1 += (double)se;
+        g0 += (double)sn;
     }
     ga = wave_sum(ga);
     gd = wave_sum(gd);
@@ -272,39 +406,66 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
 #define ADJ_CAT2(a, b) a##b
 #define ADJ_CAT(a, b) ADJ_CAT2(a, b)
 
-hipError_t ADJ_CAT(ADJ_FN, _w)(const FrameDesc *fd, const Work *tab, int nblocks,
+template <int MN>
+static hipError_t wadj_mn(const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_wadj<ADJ_T, MN>), dim3(nblocks), dim3(64), 0, st, fd, tab);
+    return hipGetLastError();
+}
+
+hipError_t ADJ_CAT(ADJ_FN, _w)(int mn, const FrameDesc *fd, const Work *tab, int nblocks,
                                hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_wadj<ADJ_T>, dim3(nblocks), dim3(64), 0, st, fd, tab);
+    switch (mn) {
+        case 0: return wadj_mn<0>(fd, tab, nblocks, st);
+        case 1: return wadj_mn<1>(fd, tab, nblocks, st);
+        case 2: return wadj_mn<2>(fd, tab, nblocks, st);
+        case 3: return wadj_mn<3>(fd, tab, nblocks, st);
+        case 4: return wadj_mn<4>(fd, tab, nblocks, st);
+        case 5: return wadj_mn<5>(fd, tab, nblocks, st);
+        case 6: return wadj_mn<6>(fd, tab, nblocks, st);
+        case 7: return wadj_mn<7>(fd, tab, nblocks, st);
+        case 8: return wadj_mn<8>(fd, tab, nblocks, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int MN, int IM, bool SA>
+static hipError_t adj_launch(const FrameDesc *fd, const Work *tab, int nblocks, size_t lds,
+                             hipStream_t st) {
+    auto kern = k_adjoint<ADJ_T, MN, IM, SA>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(64), lds, st, fd, tab);
     return hipGetLastError();
 }
 
 template <int MN>
-static hipError_t adj_mn(int imode, const FrameDesc *fd, const Work *tab, int nblocks,
+static hipError_t adj_mn(int imode, int sa, const FrameDesc *fd, const Work *tab, int nblocks,
                          size_t lds, hipStream_t st) {
     constexpr int IM2 = (2 < 2 * MN) ? 2 : 2 * MN;
     if (imode == 0)
-        hipLaunchKernelGGL((k_adjoint<ADJ_T, MN, IM2>), dim3(nblocks), dim3(64), lds, st, fd,
-                           tab);
-    else
-        hipLaunchKernelGGL((k_adjoint<ADJ_T, MN, 2 * MN>), dim3(nblocks), dim3(64), lds, st, fd,
-                           tab);
-    return hipGetLastError();
+        return sa ? adj_launch<MN, IM2, true>(fd, tab, nblocks, lds, st)
+                  : adj_launch<MN, IM2, false>(fd, tab, nblocks, lds, st);
+    return sa ? adj_launch<MN, 2 * MN, true>(fd, tab, nblocks, lds, st)
+              : adj_launch<MN, 2 * MN, false>(fd, tab, nblocks, lds, st);
 }
 
-hipError_t ADJ_CAT(ADJ_FN, _lattice)(int mn, int imode, const FrameDesc *fd, const Work *tab,
-                                     int nblocks, size_t lds, hipStream_t st) {
+hipError_t ADJ_CAT(ADJ_FN, _lattice)(int mn, int imode, int sa, const FrameDesc *fd,
+                                     const Work *tab, int nblocks, size_t lds, hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
     switch (mn) {
-        case 0: return adj_mn<0>(imode, fd, tab, nblocks, lds, st);
-        case 1: return adj_mn<1>(imode, fd, tab, nblocks, lds, st);
-        case 2: return adj_mn<2>(imode, fd, tab, nblocks, lds, st);
-        case 3: return adj_mn<3>(imode, fd, tab, nblocks, lds, st);
-        case 4: return adj_mn<4>(imode, fd, tab, nblocks, lds, st);
-        case 5: return adj_mn<5>(imode, fd, tab, nblocks, lds, st);
-        case 6: return adj_mn<6>(imode, fd, tab, nblocks, lds, st);
-        case 7: return adj_mn<7>(imode, fd, tab, nblocks, lds, st);
-        case 8: return adj_mn<8>(imode, fd, tab, nblocks, lds, st);
+        case 0: return adj_mn<0>(imode, sa, fd, tab, nblocks, lds, st);
+        case 1: return adj_mn<1>(imode, sa, fd, tab, nblocks, lds, st);
+        case 2: return adj_mn<2>(imode, sa, fd, tab, nblocks, lds, st);
+        case 3: return adj_mn<3>(imode, sa, fd, tab, nblocks, lds, st);
+        case 4: return adj_mn<4>(imode, sa, fd, tab, nblocks, lds, st);
+        case 5: return adj_mn<5>(imode, sa, fd, tab, nblocks, lds, st);
+        case 6: return adj_mn<6>(imode, sa, fd, tab, nblocks, lds, st);
+        case 7: return adj_mn<7>(imode, sa, fd, tab, nblocks, lds, st);
+        case 8: return adj_mn<8>(imode, sa, fd, tab, nblocks, lds, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -1,17 +1,25 @@
 // Tiled APP kernel (eqs. 1-3).  Compiled once per precision: build with
 // -DAPP_T=float|double -DAPP_FN=<launcher name>.
 //
-// One workgroup per (frame, TI = 8 consecutive symbols i); wave w owns the
-// symbol values D in [w TD, w TD + TD).  The 64 lanes of a wave walk
-// consecutive start indices s of the block's window, so every R load is a
-// coalesced row segment, and each loaded R(s, D, delta) feeds the TI
-// symbols whose drift band covers s:
-//   U_i(D) += alpha_i(s - n i) beta_{i+1}(s - n i + delta) R(s, D, delta).
-// FP64 alpha and beta rows are staged in LDS with zero padding wide enough that
-// no lane branches on the band edges (states outside the band, and start
-// indices outside [0, rho], have zero metrics).  The R values of the next
-// 64 start indices are loaded while the current ones are used.  The TI x TD
-// accumulators are summed across lanes by a butterfly reduce-scatter, then
+// One workgroup per (frame, TI = kAppTI consecutive symbols i).  With
+// s_lo = n i0 - M the start indices the block needs are s = s_lo + c,
+// c in [0, span), span = n (TI - 1) + 2M + 1; the waves of the workgroup
+// split c into chunks of 64 (wave w takes chunks w, w + nw, ...) and the 64
+// lanes of a wave walk consecutive s, so every R load is a coalesced row
+// segment.  A lane accumulates, for the TD symbol values of the current
+// D tile and every symbol of the block,
+//   U_i(D) += K_i(s, k) R(s, D, k),
+//   K_i(s, k) = alpha_i(s - n i) beta_{i+1}(s - n i + k - mn),
+// streaming over k: per k the TI products K_i are formed once (FP64, then
+// the batch precision) and each of the TD loaded R values feeds TI fused
+// multiply-adds.  FP64 alpha and beta rows are staged in LDS with zero padding
+// wide enough that no lane branches on the band edges (states outside the
+// band, and start indices outside [0, rho], have zero metrics).  R is read
+// through a buffer descriptor with the D row offset in a scalar register and
+// one vector add per k, so the loads cost almost no vector instructions (and
+// the descriptor's size bounds every access).  The TI x TD accumulators
+// are summed across lanes by a butterfly reduce-scatter and across waves
+// through LDS, then
 //   S_i(D) = prior_i(D) U_i(D),  Z_i = sum_D S_i(D),  APP = S / Z,
 //   d log P / d prior_i(D) = U_i(D) / Z_i.
 #include "device_common.h"
@@ -24,8 +32,10 @@ namespace mapdec {
 
 template <typename T, int CNT, int H>
 struct ReduceScatter {
-    // After run(), v[0] of lane l holds the sum over the wave of the value
-    // each lane had at index l >> (6 - log2 CNT0), CNT0 the initial count.
+    // Butterfly over the wave.  With CNT0 = m 64 (m >= 1) initial values,
+    // afterwards v[j] (j < m) of lane l holds the wave sum of index m l + j;
+    // with CNT0 < 64, v[0] of lane l holds the sum of index
+    // l >> (6 - log2 CNT0).
     static __device__ __forceinline__ void run(T *v, int lane) {
         if constexpr (H >= 1) {
             if constexpr (CNT > 1) {
@@ -48,6 +58,15 @@ struct ReduceScatter {
 template <int V>
 constexpr int log2_of() { return V <= 1 ? 0 : 1 + log2_of<V / 2>(); }
 
+template <typename T>
+__device__ __forceinline__ T rload(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+    } else {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+    }
+}
+
 template <typename T, int TD, int MN>
 __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ fd,
                                                    const Work *__restrict__ tab) {
@@ -62,12 +81,14 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
     const int i0 = w.item * TI;
     const int PAD = app_tile_pad(n);
     const int WA = Mt + 2 * PAD, WB = Mt + 2 * (PAD + MN);
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6;
+    const int nwaves = nth >> 6;
     double *ar = (double *)smem;   // [TI][WA]  sc_i alpha_i(m) at m + M + PAD
     double *br = ar + TI * WA;     // [TI][WB]  beta_{i+1}(m) at m + M + PAD + mn
     double *Zsh = br + TI * WB;    // [TI]
     unsigned long long *smax = (unsigned long long *)(Zsh + TI);   // [TI]
     T *Ush = (T *)(smax + TI);     // [TI][q]
-    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6;
+    T *part = Ush + TI * q;        // [nwaves][V] per-wave sums
     const gptr<const double> A = to_global((const double *)f.alpha);
     const gptr<const double> B = to_global((const double *)f.beta);
     if (tid < TI) smax[tid] = 0ull;
@@ -98,61 +119,104 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
         const double mx = __longlong_as_double((long long)smax[ii]);
         ar[j] = mx > 0.0 ? ar[j] / mx : 0.0;
     }
+    __syncthreads();
 
-    const gptr<const T> R = to_global((const T *)f.R);
-    const size_t sp = (size_t)f.sp;
+    // R(s, D, k) lives at ((D Mn + k) sp + s) in the frame's table
+    const int sp = f.sp;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        f.R, (short)0, (int)((size_t)q * Mn * sp * sizeof(T)), 0x00020000);
     const int s_lo = n * i0 - M;
     const int span = n * (TI - 1) + Mt;   // s in [s_lo, s_lo + span)
-    const int iters = (span + 63) / 64;
-    const int nwaves = nth >> 6;
-    __syncthreads();
-    // wave wv handles the symbol-value tiles wv, wv + nwaves, ...
-    for (int d0 = wv * TD; d0 < q; d0 += nwaves * TD) {
-        size_t rrow[TD];
+    const int nchunks = (span + 63) / 64;
+    const int nmy = (nchunks - wv + nwaves - 1) / nwaves;   // chunks of this wave
+    const int ntiles = (q + TD - 1) / TD;
+    // One flat sequence of (tile, chunk) pairs per wave, k unrolled inside;
+    // the R loads run PF steps ahead, across chunk and tile boundaries.
+    constexpr int PF = 2;
+    T r[PF + 1][TD];
+    auto voff_of = [&](int j) {
+        const int ch = wv + (j % nmy) * nwaves;
+        return min(max(s_lo + 64 * ch + lane, 0), rho) * (int)sizeof(T);
+    };
+    auto load_k = [&](T(&dst)[TD], int j, int k) {
+        const int vk = voff_of(j) + k * sp * (int)sizeof(T);
+        const int d0 = (j / nmy) * TD;
 #pragma unroll
-        for (int d = 0; d < TD; ++d) rrow[d] = (size_t)min(d0 + d, q - 1) * Mn * sp;
-        auto load_r = [&](T (&r)[Mn][TD], int c) {
-            const int sc = min(max(s_lo + c, 0), rho);
+        for (int d = 0; d < TD; ++d) {
+            const int D = min(d0 + d, q - 1);
+            dst[d] = rload<T>(rs, vk, D * Mn * sp * (int)sizeof(T));
+        }
+    };
+    const int total = ntiles * nmy;
+    if (total > 0) {
 #pragma unroll
-            for (int k = 0; k < Mn; ++k)
+        for (int e = 0; e < PF; ++e) load_k(r[e], 0, e);
+    }
+    T acc[V];
 #pragma unroll
-                for (int d = 0; d < TD; ++d) r[k][d] = R[rrow[d] + (size_t)k * sp + sc];
-        };
-        T rc[Mn][TD], rn[Mn][TD];
-        load_r(rc, lane);
-        T acc[V];
+    for (int v = 0; v < V; ++v) acc[v] = T(0);
+    for (int j = 0; j < total; ++j) {
+        const int c = 64 * (wv + (j % nmy) * nwaves) + lane;
+        const int cc = min(c, span - 1);
+        const double live = c < span ? 1.0 : 0.0;
+        double a[TI];
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] = T(0);
-        for (int it = 0; it < iters; ++it) {
-            const int c = lane + 64 * it;
-            if (it + 1 < iters) load_r(rn, c + 64);
-            const int cc = min(c, span - 1);
-            const T live = c < span ? T(1) : T(0);
-            double a[TI];
+        for (int ii = 0; ii < TI; ++ii) a[ii] = live * ar[ii * WA + PAD + cc - n * ii];
+        const double *bb = br + PAD + cc;
+        const int jn = min(j + 1, total - 1);   // a repeated load past the end is harmless
+#pragma unroll
+        for (int k = 0; k < Mn; ++k) {
+            // issue the loads of step (j, k + PF), or of the next pair's first steps
+            if (k + PF < Mn)
+                load_k(r[(k + PF) % (PF + 1)], j, k + PF);
+            else
+                load_k(r[(k + PF) % (PF + 1)], jn, k + PF - Mn);
+            T kv[TI];
+#pragma unroll
+            for (int ii = 0; ii < TI; ++ii) kv[ii] = (T)(a[ii] * bb[ii * (WB - n) + k]);
 #pragma unroll
             for (int ii = 0; ii < TI; ++ii)
-                a[ii] = (double)live * ar[ii * WA + PAD + cc - n * ii];
-            const double *bb = br + PAD + cc;
 #pragma unroll
-            for (int k = 0; k < Mn; ++k) {
-#pragma unroll
-                for (int ii = 0; ii < TI; ++ii) {
-                    const T kv = (T)(a[ii] * bb[ii * (WB - n) + k]);
-#pragma unroll
-                    for (int d = 0; d < TD; ++d) acc[ii * TD + d] += kv * rc[k][d];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < Mn; ++k)
-#pragma unroll
-                for (int d = 0; d < TD; ++d) rc[k][d] = rn[k][d];
+                for (int d = 0; d < TD; ++d)
+                    acc[ii * TD + d] += kv[ii] * r[k % (PF + 1)][d];
         }
-        ReduceScatter<T, V, 32>::run(acc, lane);
-        constexpr int SH = 6 - log2_of<V>();
-        const int idx = lane >> SH, ii = idx / TD, d = idx - ii * TD;
-        if ((lane & ((1 << SH) - 1)) == 0 && d0 + d < q) Ush[ii * q + d0 + d] = acc[0];
+        // the ring position of step (j + 1, 0) must be slot 0
+        if constexpr (Mn % (PF + 1) != 0) {
+            T tmp[PF + 1][TD];
+#pragma unroll
+            for (int e = 0; e <= PF; ++e)
+#pragma unroll
+                for (int d = 0; d < TD; ++d) tmp[e][d] = r[(e + Mn) % (PF + 1)][d];
+#pragma unroll
+            for (int e = 0; e <= PF; ++e)
+#pragma unroll
+                for (int d = 0; d < TD; ++d) r[e][d] = tmp[e][d];
+        }
+        if ((j + 1) % nmy == 0) {
+            // tile j / nmy complete: sum over lanes, then over waves
+            const int d0 = (j / nmy) * TD;
+            ReduceScatter<T, V, 32>::run(acc, lane);
+            if constexpr (V >= 64) {
+                constexpr int m = V / 64;
+#pragma unroll
+                for (int x = 0; x < m; ++x) part[wv * V + m * lane + x] = acc[x];
+            } else {
+                constexpr int SH = 6 - log2_of<V>();
+                if ((lane & ((1 << SH) - 1)) == 0) part[wv * V + (lane >> SH)] = acc[0];
+            }
+            __syncthreads();
+            for (int x = tid; x < V; x += nth) {
+                const int ii = x / TD, d = x - ii * TD;
+                if (d0 + d >= q) continue;
+                T u = T(0);
+                for (int y = 0; y < nwaves; ++y) u += part[y * V + x];
+                Ush[ii * q + d0 + d] = u;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] = T(0);
+        }
     }
-    __syncthreads();
     const T up = T(1) / T(q);
     if (tid < TI && i0 + tid < N) {
         double Z = 0.0;
@@ -207,9 +271,13 @@ static hipError_t tile_td(int mn, int nwaves, const FrameDesc *fd, const Work *t
 
 hipError_t APP_FN(int td, int mn, int nwaves, const FrameDesc *fd, const Work *tab, int nblocks,
                   size_t lds, hipStream_t st) {
+    if (nwaves < 1 || nwaves > kAppMaxWaves) return hipErrorInvalidValue;
     switch (td) {
         case 2: return tile_td<2>(mn, nwaves, fd, tab, nblocks, lds, st);
         case 4: return tile_td<4>(mn, nwaves, fd, tab, nblocks, lds, st);
+        case 8:
+            if constexpr (sizeof(APP_T) == 4) return tile_td<8>(mn, nwaves, fd, tab, nblocks, lds, st);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
     T *R = (T *)f.R;
     const size_t sp = (size_t)f.sp;
     for (int D = 0; D < q; ++D) {
-        const uint32_t cw = f.cw[D];
+        const uint32_t cw = __builtin_amdgcn_readfirstlane(f.cw[D]);   // wave-uniform
         T F[KW];
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
@@ -81,12 +81,14 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
         }
 #pragma unroll
         for (int r = 1; r <= kMaxN; ++r) {
-            if (r > n) break;
+            if (r > n) continue;   // constant trip count: the loop unrolls
             T G[KW];
-            if ((cw >> (n - r)) & 1u)
+            if ((cw >> (n - r)) & 1u) {
                 lattice_row_in<T, MN, NB>(G, F, qx1, d, r);
-            else
+                keep_branch();
+            } else {
                 lattice_row_in<T, MN, NB>(G, F, qx0, d, r);
+            }
             if (r < n) {
 #pragma unroll
                 for (int k = 0; k < KW; ++k) {

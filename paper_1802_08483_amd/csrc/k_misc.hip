@@ -79,6 +79,9 @@ __global__ void k_dparams(const FrameDesc *__restrict__ fd, int nframes) {
     double g[4] = {0, 0, 0, 0};
     for (int b = 0; b < f.lat_blocks; ++b)
         for (int t = 0; t < 4; ++t) g[t] += f.gacc[(size_t)b * 4 + t];
+    // without the d/da sweep: a g_a - d g_d = rho - tau (every path inserts
+    // rho - tau more bits than it deletes)
+    if (!f.adj_da) g[0] = ((double)(f.rho - f.tau) + f.d * g[1]) / f.a;
     const double Ps = f.Ps, Pt = 1.0 - f.Pi - f.Pd;
     f.dparams[0] = 0.5 * g[0] - (1.0 - Ps) * g[2] - Ps * g[3];
     f.dparams[1] = g[1] - (1.0 - Ps) * g[2] - Ps * g[3];

@@ -47,21 +47,31 @@ constexpr int kNumRingShapes = 6;
 constexpr bool ring_duplicates(int slots) { return slots <= 512; }
 hipError_t launch_app(int fp64, const FrameDesc *fd, const Work *tab, int nblocks,
                       size_t lds_bytes, hipStream_t st);
-// Tiled APP (k_app_tile.hip): td symbol values per wave (2 or 4), nwaves =
-// ceil(q / td) waves per workgroup, kAppTI symbols per workgroup; every
-// frame of the launch has drift limit mn.
+// Tiled APP (k_app_tile.hip): td symbol values per D tile (2, 4 or 8; at
+// most 4 in FP64), nwaves waves splitting the block's start indices,
+// kAppTI symbols per workgroup; every frame of the launch has drift limit mn.
 hipError_t launch_app_tile(int fp64, int td, int mn, int nwaves, const FrameDesc *fd,
                            const Work *tab, int nblocks, size_t lds_bytes, hipStream_t st);
 
-// Adjoint (k_adjoint.hip, one object per precision): output adjoints W,
-// the backward lattice sweep (per (mn, imode) group, lds = n KW 64 T), and
-// the per-frame reduction with the chain rule (k_misc.hip).
-hipError_t adj_f32_w(const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st);
-hipError_t adj_f64_w(const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st);
-hipError_t adj_f32_lattice(int mn, int imode, const FrameDesc *fd, const Work *tab, int nblocks,
-                           size_t lds, hipStream_t st);
-hipError_t adj_f64_lattice(int mn, int imode, const FrameDesc *fd, const Work *tab, int nblocks,
-                           size_t lds, hipStream_t st);
+// Adjoint (k_adjoint.hip, one object per precision): output adjoints W
+// (per mn group), the backward lattice sweep (per (mn, imode, sa) group, sa =
+// the sweep accumulates d/da itself; LDS from adjoint_lds), and the
+// per-frame reduction with the chain rule (k_misc.hip).
+hipError_t adj_f32_w(int mn, const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st);
+hipError_t adj_f64_w(int mn, const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st);
+hipError_t adj_f32_lattice(int mn, int imode, int sa, const FrameDesc *fd, const Work *tab,
+                           int nblocks, size_t lds, hipStream_t st);
+hipError_t adj_f64_lattice(int mn, int imode, int sa, const FrameDesc *fd, const Work *tab,
+                           int nblocks, size_t lds, hipStream_t st);
+// LDS bytes of one adjoint workgroup: the even rows F_2, F_4, .. below row
+// n of 64 lattices, each row in 16-byte slots
+constexpr size_t adjoint_lds(int nmax, int mn, size_t tsize) {
+    return (size_t)(nmax > 1 ? (nmax - 1) / 2 : 0) *
+           (((size_t)(2 * mn + 1) + 16 / tsize - 1) / (16 / tsize)) * 64 * 16;
+}
+// The sweep accumulates d/da itself when a g_a = rho - tau + d g_d would be
+// a small difference of larger terms (Pi zero or below Pd / 4).
+inline bool adjoint_needs_da(double Pi, double Pd) { return !(Pi > 0.0) || 4.0 * Pi < Pd; }
 hipError_t launch_dparams(const FrameDesc *fd, int nframes, hipStream_t st);
 
 // Block sizes the host uses to build work tables.
@@ -70,17 +80,31 @@ constexpr int kLatticeLanes = 64;  // start indices per lattice workgroup
 constexpr int kGammaLanes = 256;   // drift states per Gamma workgroup
 constexpr int kChainThreads = 256;
 constexpr int kAppThreads = 64;
-constexpr int kAppTI = 8;   // consecutive symbols per tiled-APP workgroup
+constexpr int kAppTI = 4;   // consecutive symbols per tiled-APP workgroup
 // zero padding (states) on each side of the rows staged by the tiled APP
 __host__ __device__ constexpr int app_tile_pad(int n) { return (kAppTI - 1) * n; }
-// symbol values per wave of the tiled APP for an alphabet of size q
-constexpr int app_tile_td(int q) { return q <= 2 ? 2 : 4; }
+constexpr int kAppMaxWaves = 8;
+// symbol values per D tile of the tiled APP: the next power of two >= q,
+// between 2 and 8 (4 in FP64)
+constexpr int app_tile_td(int q, size_t tsize) {
+    const int cap = tsize == 8 ? 4 : 8;
+    int td = 2;
+    while (td < q && td < cap) td *= 2;
+    return td;
+}
+// waves of a tiled-APP workgroup: one per 64 of the span of start indices
+// n (kAppTI - 1) + Mt, at most kAppMaxWaves
+constexpr int app_tile_waves(int Mt, int n) {
+    const int chunks = ((kAppTI - 1) * n + Mt + 63) / 64;
+    return chunks < kAppMaxWaves ? chunks : kAppMaxWaves;
+}
 // LDS bytes of one tiled-APP workgroup: FP64 rows, Z and scale per symbol,
-// the U tile in the batch precision
+// the U tile and the per-wave partial sums in the batch precision
 constexpr size_t app_tile_lds(int Mt, int mn, int n, int q, size_t tsize) {
     return (size_t)kAppTI * ((size_t)(Mt + 2 * app_tile_pad(n)) +
                              (size_t)(Mt + 2 * (app_tile_pad(n) + mn)) + 2) * sizeof(double) +
-           (size_t)kAppTI * q * tsize;
+           (size_t)kAppTI * q * tsize +
+           (size_t)app_tile_waves(Mt, n) * kAppTI * app_tile_td(q, tsize) * tsize;
 }
 constexpr int kRingPrefetchRegs = 16;   // prefetch registers per thread in k_chain_ring
 

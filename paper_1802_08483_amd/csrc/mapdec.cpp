@@ -60,6 +60,9 @@ struct Layout {
     std::map<std::pair<int, int>, std::vector<Work>> lat;
     std::map<std::pair<int, int>, size_t> off_lat;
     std::map<std::pair<int, int>, int> lat_nmax;   // longest codeword per group
+    // adjoint sweep work grouped by (mn, imode, accumulates d/da)
+    std::map<std::tuple<int, int, int>, std::vector<Work>> adj;
+    std::map<std::tuple<int, int, int>, size_t> off_adj, adj_lds;
     size_t chain_lds = 0, app_lds = 0;
     // chains: single-wave ring kernel grouped by states per lane, else the
     // workgroup kernel
@@ -167,9 +170,11 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         L.n_gamma += F.gamma_blocks;
         {
             const size_t tl = app_tile_lds(F.Mt, c->mn, c->n, c->q, L.tsize);
-            if (tl <= device_lds_limit()) {
-                const int td = app_tile_td(c->q);
-                const auto key = std::make_tuple(td, std::min(8, (c->q + td - 1) / td), c->mn);
+            // the tile kernel addresses R with 32-bit byte offsets
+            const bool fits = (double)c->q * F.Mn * F.sp * L.tsize < 2147483648.0;
+            if (fits && tl <= device_lds_limit()) {
+                const int td = app_tile_td(c->q, L.tsize);
+                const auto key = std::make_tuple(td, app_tile_waves(F.Mt, c->n), c->mn);
                 auto &v = L.app_tile[key];
                 for (int b = 0; b * kAppTI < fr.N; ++b) v.push_back(Work{f, b});
                 L.app_tile_lds[key] = std::max(L.app_tile_lds[key], tl);
@@ -195,6 +200,15 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         L.lat_nmax[key] = std::max(L.lat_nmax[key], c->n);
         auto &v = L.lat[key];
         for (int b = 0; b < F.lat_blocks; ++b) v.push_back(Work{f, b * kLatticeLanes});
+        if (L.grad) {
+            const auto akey = std::make_tuple(c->mn, frame_imode(c),
+                                              adjoint_needs_da(c->Pi, c->Pd) ? 1 : 0);
+            auto &av = L.adj[akey];
+            for (int b = 0; b < F.lat_blocks; ++b) av.push_back(Work{f, b * kLatticeLanes});
+            const size_t al = adjoint_lds(c->n, c->mn, L.tsize);
+            if (al > device_lds_limit()) return MAPDEC_EUNSUPPORTED;
+            L.adj_lds[akey] = std::max(L.adj_lds[akey], al);
+        }
     }
     if (max_chain > 65536 || max_app > 65536) return MAPDEC_EUNSUPPORTED;
     L.chain_lds = max_chain;
@@ -208,6 +222,10 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
     off = align_up(off + sizeof(Work) * L.n_pack);
     for (auto &kv : L.lat) {
         L.off_lat[kv.first] = off;
+        off = align_up(off + sizeof(Work) * kv.second.size());
+    }
+    for (auto &kv : L.adj) {
+        L.off_adj[kv.first] = off;
         off = align_up(off + sizeof(Work) * kv.second.size());
     }
     L.off_gamma = off;
@@ -324,18 +342,20 @@ struct mapdec_plan {
             for (auto &kv : L.lat) {           // phase "wgrad"
                 if (e != hipSuccess) break;
                 const Work *tab = at<Work>(L.off_lat.at(kv.first));
-                e = L.fp64 ? adj_f64_w(fd, tab, (int)kv.second.size(), st)
-                           : adj_f32_w(fd, tab, (int)kv.second.size(), st);
+                const int mn = kv.first.first;
+                e = L.fp64 ? adj_f64_w(mn, fd, tab, (int)kv.second.size(), st)
+                           : adj_f32_w(mn, fd, tab, (int)kv.second.size(), st);
             }
             mark();
-            for (auto &kv : L.lat) {           // phase "adjoint"
+            for (auto &kv : L.adj) {           // phase "adjoint"
                 if (e != hipSuccess) break;
-                const Work *tab = at<Work>(L.off_lat.at(kv.first));
-                const int mn = kv.first.first, imode = kv.first.second;
-                const size_t lds =
-                    (size_t)L.lat_nmax.at(kv.first) * (2 * mn + 1) * 64 * L.tsize;
-                e = L.fp64 ? adj_f64_lattice(mn, imode, fd, tab, (int)kv.second.size(), lds, st)
-                           : adj_f32_lattice(mn, imode, fd, tab, (int)kv.second.size(), lds, st);
+                const Work *tab = at<Work>(L.off_adj.at(kv.first));
+                const int mn = std::get<0>(kv.first), imode = std::get<1>(kv.first),
+                          da = std::get<2>(kv.first);
+                const size_t lds = L.adj_lds.at(kv.first);
+                const int nb = (int)kv.second.size();
+                e = L.fp64 ? adj_f64_lattice(mn, imode, da, fd, tab, nb, lds, st)
+                           : adj_f32_lattice(mn, imode, da, fd, tab, nb, lds, st);
             }
             mark();
             if (e == hipSuccess) e = launch_dparams(fd, L.nframes, st);   // phase "dparams"
@@ -444,6 +464,7 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
         d.a = 0.5 * c->Pi; d.d = c->Pd; d.t1 = Pt * (1.0 - c->Ps); d.t0 = Pt * c->Ps;
         d.Pi = c->Pi; d.Pd = c->Pd; d.Ps = c->Ps;
         d.lat_blocks = F.lat_blocks;
+        d.adj_da = adjoint_needs_da(c->Pi, c->Pd) ? 1 : 0;
         d.y = fr.y; d.prior = fr.prior; d.app = fr.app; d.dprior = fr.dprior;
         d.logp = logp + f; d.status = status + f;
         d.dparams = dparams ? dparams + 3 * f : nullptr;
@@ -464,6 +485,9 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
     }
     for (auto &kv : L.lat)
         std::memcpy(stage.data() + L.off_lat.at(kv.first), kv.second.data(),
+                    sizeof(Work) * kv.second.size());
+    for (auto &kv : L.adj)
+        std::memcpy(stage.data() + L.off_adj.at(kv.first), kv.second.data(),
                     sizeof(Work) * kv.second.size());
     if (!L.app_plain.empty())
         std::memcpy(app, L.app_plain.data(), sizeof(Work) * L.app_plain.size());

@@ -47,7 +47,7 @@ struct FrameDesc {
     double *Zinv;         // [N] 1 / sum_D S_i(D)  (gradient passes)
     double *gacc;         // [lat_blocks][4] partial d log P / d(a, d, t1, t0)
     int lat_blocks;       // lattice workgroups of this frame
-    int pad1;
+    int adj_da;           // the adjoint sweep accumulates d/da (else from rho - tau)
 };
 
 // Work-table entry: which frame a workgroup serves and where in it.
