@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MAPDEC_VERSION 100
+#define MAPDEC_VERSION 101
 
 enum {
     MAPDEC_OK = 0,
@@ -119,11 +119,13 @@ typedef struct {
 
 /*
  * mapdec_workspace_size -- bytes of device workspace that a decode (or,
- * with MAPDEC_FLAG_GRAD, a gradient) of these frames needs.  frames: host
- * array of nframes entries.  Returns 0 if the frames are invalid.
+ * with MAPDEC_FLAG_GRAD, a gradient) of these frames needs with forward
+ * checkpoints every checkpoint_K symbols (0: none; see mapdec_grad).
+ * frames: host array of nframes entries.  Returns 0 if the frames are
+ * invalid or checkpoint_K < 0.
  */
 size_t mapdec_workspace_size(const mapdec_frame *frames, int nframes, int precision,
-                             int flags);
+                             int flags, int checkpoint_K);
 
 /*
  * mapdec_decode -- APPs and log P(y) of every frame (eqs. 1-12).
@@ -146,10 +148,19 @@ int mapdec_decode(const mapdec_frame *frames, int nframes, double *logp, int32_t
  * log P(y) with M, mn and I held fixed and Pt = 1 - Pi - Pd:
  *   dparams  device, 3*nframes doubles: d log P / d(Pi, Pd, Ps) per frame.
  *   frames[f].dprior receives d log P / d prior[i][D] when non-NULL.
- * checkpoint_K: 0 stores every normalised forward metric; K > 0 stores one
- * row every K symbols and recomputes the others, with the receiver metric,
- * segment by segment in the backward pass (memory-bounded mode).
- * Workspace from mapdec_workspace_size(..., flags | MAPDEC_FLAG_GRAD).
+ * checkpoint_K: 0 keeps the receiver metric, Gamma and every forward and
+ * backward metric row of the whole frame in the workspace.  K > 0 splits
+ * each frame into segments of K symbols (the last may be shorter): a
+ * forward pass computes each segment's receiver metric and forward rows and
+ * keeps only the forward row at every segment boundary (a checkpoint); the
+ * backward pass then recomputes, segment by segment from the last, the
+ * receiver metric, Gamma and the forward rows from the checkpoint, and runs
+ * the backward rows, APPs and gradient terms of that segment.  The
+ * workspace then holds one segment's tables (O(K) rows instead of O(N))
+ * plus N/K checkpoint rows; K = ceil(sqrt(N)) balances the two.  Results
+ * equal those of K = 0 up to rounding.
+ * Workspace from mapdec_workspace_size(..., flags | MAPDEC_FLAG_GRAD,
+ * checkpoint_K).
  */
 int mapdec_grad(const mapdec_frame *frames, int nframes, double *logp, double *dparams,
                 int32_t *status, void *ws, size_t ws_bytes, int checkpoint_K, int precision,
@@ -163,8 +174,10 @@ int mapdec_grad(const mapdec_frame *frames, int nframes, double *logp, double *d
  * prior, app, dprior, logp, status, dparams, ws): they must stay valid
  * until mapdec_plan_destroy; their contents may change between runs.
  * dparams is used only with MAPDEC_FLAG_GRAD (may be NULL otherwise).
- * Returns NULL on failure (see mapdec_last_error()).  The descriptor upload
- * is enqueued on stream.
+ * checkpoint_K as for mapdec_grad (it applies to decode-only plans too);
+ * ws_bytes >= mapdec_workspace_size(frames, nframes, precision, flags,
+ * checkpoint_K).  Returns NULL on failure (see mapdec_last_error()).  The
+ * descriptor upload is enqueued on stream.
  */
 typedef struct mapdec_plan mapdec_plan;
 
@@ -178,10 +191,12 @@ void mapdec_plan_destroy(mapdec_plan *plan);
 /*
  * mapdec_plan_profile -- per-phase time split of one run (the decoder's
  * time per metric, Sec. VI).  Enqueues the plan's launches once, without
- * the graph, on stream with a HIP event recorded between phases, waits for
- * them, and writes the milliseconds of phase k into phase_ms[k] for
- * k < max_phases.  Returns the number of phases, or a negative MAPDEC_*
- * status.  Results land in the plan's outputs as after mapdec_plan_run.
+ * the graph, on stream with a HIP event recorded after each group of
+ * launches, waits for them, and writes into phase_ms[k] (k < max_phases)
+ * the milliseconds of all launch groups of phase k (with checkpoints a
+ * phase runs once per segment).  Returns the number of phases, or a
+ * negative MAPDEC_* status.  Results land in the plan's outputs as after
+ * mapdec_plan_run.
  */
 int mapdec_plan_profile(mapdec_plan *plan, void *stream, float *phase_ms, int max_phases);
 /* Static name of profile phase k ("pack", "lattice", "gamma", "chain",

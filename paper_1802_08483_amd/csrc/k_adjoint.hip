@@ -47,16 +47,16 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
     const Work w = tab[blockIdx.x];
     const FrameDesc &f = fd[w.frame];
     if (*f.status != kStatusOk) return;
-    const int s0 = w.item, s = s0 + (int)threadIdx.x;
-    const int n = f.n, M = f.M, Mt = f.Mt, N = f.N, q = f.q, rho = f.rho;
-    const bool live = s <= rho;
+    const int sa = f.s0 + w.item, s = sa + (int)threadIdx.x;   // column s - s0
+    const int n = f.n, M = f.M, Mt = f.Mt, q = f.q, ib = f.i0;
+    const bool live = s <= f.s1;
     const gptr<const double> A = to_global((const double *)f.alpha);
     const gptr<const double> B = to_global((const double *)f.beta);
     const gptr<const double> Zi = to_global((const double *)f.Zinv);
     const size_t sp = (size_t)f.sp;
-    // symbols whose band [n i - M, n i + M] meets [s0, s0 + 63]
-    const int ilo = s0 - M <= 0 ? 0 : (s0 - M + n - 1) / n;
-    const int ihi = min(N - 1, (s0 + 63 + M) / n);
+    // symbols of the segment whose band [n i - M, n i + M] meets [sa, sa + 63]
+    const int ilo = max(f.i0, sa - M <= 0 ? 0 : (sa - M + n - 1) / n);
+    const int ihi = min(f.i1 - 1, (sa + 63 + M) / n);
     // one term of the sum over i: the lane's alpha_i(m') / Z_i and beta_{i+1}(m' + delta).
     // Every load is issued (addresses clamped into the row, out-of-band values
     // multiplied by 0), so the compiler cannot turn them into one branch and
@@ -65,12 +65,12 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
         const int mp = s - n * i;
         const double in = (live && mp >= -M && mp <= M) ? 1.0 : 0.0;
         const int mc = min(max(mp, -M), M);
-        av = A[(size_t)i * Mt + mc + M] * Zi[i] * in;
+        av = A[(size_t)(i - ib) * Mt + mc + M] * Zi[i] * in;
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int m = mp + k - MN;
             const int cm = min(max(m, -M), M);
-            const double b = B[(size_t)(i + 1) * Mt + cm + M];
+            const double b = B[(size_t)(i + 1 - ib) * Mt + cm + M];
             bv[k] = b * ((m >= -M && m <= M) ? 1.0 : 0.0);
         }
     };
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
         const gptr<T> W = to_global((T *)f.G);
         const double invq = 1.0 / q;
 #pragma unroll
-        for (int k = 0; k < KW; ++k) W[(size_t)k * sp + s] = (T)(acc[k] * invq);
+        for (int k = 0; k < KW; ++k) W[(size_t)k * sp + (s - f.s0)] = (T)(acc[k] * invq);
     } else {
         const gptr<T> W = to_global((T *)f.R);
         const T *pr = (const T *)f.prior;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
                 if (D0 + c >= q) break;
 #pragma unroll
                 for (int k = 0; k < KW; ++k)
-                    W[((size_t)(D0 + c) * KW + k) * sp + s] = (T)acc[c][k];
+                    W[((size_t)(D0 + c) * KW + k) * sp + (s - f.s0)] = (T)acc[c][k];
             }
         }
     }
@@ -173,8 +173,8 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
     const FrameDesc &f = fd[w.frame];
     if (*f.status != kStatusOk) return;
     const int lane = threadIdx.x;
-    const int s = w.item + lane;
-    const bool live = s <= f.rho;
+    const int s = f.s0 + w.item + lane;   // column s - s0 of W
+    const bool live = s <= f.s1;
     const int n = f.n, q = f.q, rho = f.rho;
     const T d = (T)f.d, t1 = (T)f.t1, t0 = (T)f.t0;
     Slot<T> *rows = (Slot<T> *)smem;   // [(n - 1) / 2][KV][64]: F_2, F_4, ..
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
         const int dl = k - MN;   // row 0: dl insertions before the first bit
         F0[k] = (dl >= 0 && dl <= IM) ? apow[dl] : T(0);
     }
-    const int sl = live ? s : 0;
+    const int sl = live ? s : f.s0;
     const int wi = sl >> 5, sh = sl & 31;
     const uint32_t lo = f.ybits[wi], hi = f.ybits[wi + 1];
     const uint32_t win = sh ? ((lo >> sh) | (hi << (32 - sh))) : lo;
@@ -241,7 +241,8 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int len = n + k - MN;
-            Fb[k] = (live && len >= 0 && s + len <= rho) ? Wt[wbase + (size_t)k * sp + sl] : T(0);
+            Fb[k] = (live && len >= 0 && s + len <= rho) ? Wt[wbase + (size_t)k * sp + (sl - f.s0)]
+                                                         : T(0);
         }
         // forward rows F_1 .. F_{n-1}; the even ones to LDS
         {

@@ -17,16 +17,17 @@ __global__ __launch_bounds__(kAppThreads) void k_app(const FrameDesc *__restrict
     // accumulates in FP64 (the rows are FP64); R and the outputs are T
     const Work w = tab[blockIdx.x];
     const FrameDesc &f = fd[w.frame];
-    const int i = w.item;
+    const int i = f.i0 + w.item;
     if (*f.status != kStatusOk) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int Mt = f.Mt, mn = f.mn, M = f.M, Mn = f.Mn, q = f.q, n = f.n, rho = f.rho;
+    const int s0 = f.s0;
     double *al = (double *)smem;
     double *be = al + Mt;            // Mt + 2 mn, padded
     double *U = be + Mt + 2 * mn;    // q
     const int tid = threadIdx.x;
-    const double *A = f.alpha + (size_t)i * Mt;
-    const double *B = f.beta + (size_t)(i + 1) * Mt;
+    const double *A = f.alpha + (size_t)(i - f.i0) * Mt;
+    const double *B = f.beta + (size_t)(i + 1 - f.i0) * Mt;
     for (int j = tid; j < Mt; j += kAppThreads) {
         al[j] = A[j];
         be[mn + j] = B[j];
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(kAppThreads) void k_app(const FrameDesc *__restrict
 #pragma unroll
             for (int e = 0; e < kAppChunk; ++e) {
                 if (dc + e < q) {
-                    const T *Rp = R + (size_t)(dc + e) * Mn * sp + s;
+                    const T *Rp = R + (size_t)(dc + e) * Mn * sp + (s - s0);
                     double t = 0.0;
                     for (int k = 0; k < Mn; ++k) t += (double)Rp[(size_t)k * sp] * be[mi + k];
                     acc[e] += av * t;

@@ -77,8 +77,10 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
     const FrameDesc &f = fd[w.frame];
     if (*f.status != kStatusOk) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int Mt = f.Mt, M = f.M, q = f.q, n = f.n, rho = f.rho, N = f.N;
-    const int i0 = w.item * TI;
+    const int Mt = f.Mt, M = f.M, q = f.q, n = f.n, s0 = f.s0, s1 = f.s1;
+    const int N = f.i1;                  // symbols of the segment end here
+    const int i0 = f.i0 + w.item * TI;   // first symbol of the block
+    const int ib = f.i0;                 // row index base of alpha / beta
     const int PAD = app_tile_pad(n);
     const int WA = Mt + 2 * PAD, WB = Mt + 2 * (PAD + MN);
     const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6;
@@ -94,11 +96,11 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
     if (tid < TI) smax[tid] = 0ull;
     for (int j = tid; j < TI * WA; j += nth) {
         const int ii = j / WA, m = j - ii * WA - PAD, i = i0 + ii;
-        ar[j] = (i < N && m >= 0 && m < Mt) ? A[(size_t)i * Mt + m] : 0.0;
+        ar[j] = (i < N && m >= 0 && m < Mt) ? A[(size_t)(i - ib) * Mt + m] : 0.0;
     }
     for (int j = tid; j < TI * WB; j += nth) {
         const int ii = j / WB, m = j - ii * WB - PAD - MN, i = i0 + ii;
-        br[j] = (i < N && m >= 0 && m < Mt) ? B[(size_t)(i + 1) * Mt + m] : 0.0;
+        br[j] = (i < N && m >= 0 && m < Mt) ? B[(size_t)(i + 1 - ib) * Mt + m] : 0.0;
     }
     __syncthreads();
     // Two-slice scale: the rows' product alpha_i(m') beta_{i+1}(m'+delta)
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
     }
     __syncthreads();
 
-    // R(s, D, k) lives at ((D Mn + k) sp + s) in the frame's table
+    // R(s, D, k) lives at ((D Mn + k) sp + s - s0) in the frame's table
     const int sp = f.sp;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         f.R, (short)0, (int)((size_t)q * Mn * sp * sizeof(T)), 0x00020000);
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
     T r[PF + 1][TD];
     auto voff_of = [&](int j) {
         const int ch = wv + (j % nmy) * nwaves;
-        return min(max(s_lo + 64 * ch + lane, 0), rho) * (int)sizeof(T);
+        return (min(max(s_lo + 64 * ch + lane, s0), s1) - s0) * (int)sizeof(T);
     };
     auto load_k = [&](T(&dst)[TD], int j, int k) {
         const int vk = voff_of(j) + k * sp * (int)sizeof(T);

@@ -4,28 +4,36 @@
 namespace mapdec {
 
 // ---------------------------------------------------------------------------
-// alpha / beta chains.  Workgroup 2c runs the forward chain of frame
-// frames[c], workgroup 2c+1 the backward chain.  Rows live in LDS with mn
-// zero entries of padding on each side (states outside [-M, M] are 0).
+// alpha / beta chains over the symbols [i0, i1) of a segment.  With both
+// directions, workgroup 2c runs the forward chain of frame frames[c] and
+// workgroup 2c+1 the backward chain; with one direction, workgroup c runs
+// that chain.  Rows live in LDS with mn zero entries of padding on each side
+// (states outside [-M, M] are 0).  A chain starts from the row given by the
+// descriptor (a_init / b_init) or from the known boundary state, stores the
+// rows it computes, optionally copies its last row out (a_fin / b_fin), and
+// continues the cumulative log of its normalisers (logA / logB).
 
 template <typename T>
 __device__ __forceinline__ T gamma_at(const FrameDesc &f, const T *G, int i, int mp, int k) {
     if (mp < -f.M || mp > f.M) return T(0);
     if (f.uniform) {
         const int s = f.n * i + mp;
-        return (s >= 0 && s <= f.rho) ? G[(size_t)k * f.sp + s] : T(0);
+        return (s >= 0 && s <= f.rho) ? G[(size_t)k * f.sp + (s - f.s0)] : T(0);
     }
-    return G[((size_t)i * f.Mn + k) * f.Mt + (mp + f.M)];
+    return G[((size_t)(i - f.i0) * f.Mn + k) * f.Mt + (mp + f.M)];
 }
 
 template <typename T>
 __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__restrict__ fd,
-                                                         const int *__restrict__ frames) {
-    const int fi = frames[blockIdx.x >> 1];
-    const int dir = blockIdx.x & 1;
+                                                         const int *__restrict__ frames,
+                                                         int dirs) {
+    const int nd = dirs == 3 ? 2 : 1;
+    const int fi = frames[blockIdx.x / nd];
+    const int dir = nd == 2 ? (int)(blockIdx.x & 1) : (dirs == 1 ? 0 : 1);
     const FrameDesc &f = fd[fi];
+    if (*f.status != kStatusOk) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int Mt = f.Mt, mn = f.mn, M = f.M, N = f.N, Mn = f.Mn;
+    const int Mt = f.Mt, mn = f.mn, M = f.M, N = f.N, Mn = f.Mn, i0 = f.i0, i1 = f.i1;
     const int W = Mt + 2 * mn;
     double *buf0 = (double *)smem;   // rows in FP64 whatever the precision
     double *buf1 = buf0 + W;
@@ -37,21 +45,23 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
     const int m0 = dir == 0 ? 0 : f.rho - f.tau;
     double *out = dir == 0 ? f.alpha : f.beta;
     double *logX = dir == 0 ? f.logA : f.logB;
-    const int row0 = dir == 0 ? 0 : N;
-    if (tid == 0) {
-        buf0[mn + m0 + M] = 1.0;
-        logX[row0] = 0.0;
+    const double *init = dir == 0 ? f.a_init : f.b_init;
+    const int row0 = dir == 0 ? i0 : i1;
+    const double lbase = (dir == 0 ? i0 > 0 : i1 < N) ? logX[row0] : 0.0;
+    for (int mi = tid; mi < Mt; mi += nth) {
+        const double v = init ? init[mi] : ((mi == m0 + M) ? 1.0 : 0.0);
+        buf0[mn + mi] = v;
+        out[(size_t)(row0 - i0) * Mt + mi] = v;
     }
-    for (int mi = tid; mi < Mt; mi += nth)
-        out[(size_t)row0 * Mt + mi] = (mi == m0 + M) ? 1.0 : 0.0;
+    if (tid == 0) logX[row0] = lbase;
     __syncthreads();
 
     const T *G = (const T *)f.G;
-    double lsum = 0.0;
+    double lsum = lbase;
     double *cur = buf0, *nxt = buf1;
     bool dead = false;
-    for (int step = 0; step < N; ++step) {
-        const int i = dir == 0 ? step : N - 1 - step;
+    for (int step = 0; step < i1 - i0; ++step) {
+        const int i = dir == 0 ? i0 + step : i1 - 1 - step;
         double part = 0.0;
         for (int mi = tid; mi < Mt; mi += nth) {
             const int m = mi - M;
@@ -82,7 +92,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
         for (int mi = tid; mi < Mt; mi += nth) {
             const double v = nxt[mn + mi] * inv;
             nxt[mn + mi] = v;
-            out[(size_t)row * Mt + mi] = v;
+            out[(size_t)(row - i0) * Mt + mi] = v;
         }
         lsum += log(c);
         if (tid == 0) logX[row] = lsum;
@@ -91,13 +101,18 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
         nxt = t;
         __syncthreads();
     }
-    if (tid != 0) return;
     if (dead) {
-        atomicOr(f.status, kStatusNoPath);
-        if (dir == 0) *f.logp = -INFINITY;
+        if (tid == 0) {
+            atomicOr(f.status, kStatusNoPath);
+            if (dir == 0) *f.logp = -INFINITY;
+        }
         return;
     }
-    if (dir == 0) {
+    double *fin = dir == 0 ? f.a_fin : f.b_fin;
+    if (fin)
+        for (int mi = tid; mi < Mt; mi += nth) fin[mi] = cur[mn + mi];
+    if (tid != 0) return;
+    if (dir == 0 && i1 == N) {
         // P(y) = alpha_N(rho - tau) in unnormalised terms
         const double aN = cur[mn + (f.rho - f.tau) + M];
         if (!(aN > 0.0)) {
@@ -113,14 +128,16 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
 // launchers
 
 hipError_t launch_chain(int fp64, const FrameDesc *fd, const int *frames, int nchains,
-                        size_t lds_bytes, hipStream_t st) {
+                        int dirs, size_t lds_bytes, hipStream_t st) {
     if (nchains == 0) return hipSuccess;
+    if (dirs < 1 || dirs > 3) return hipErrorInvalidValue;
+    const int nb = nchains * (dirs == 3 ? 2 : 1);
     if (fp64)
-        hipLaunchKernelGGL(k_chain<double>, dim3(2 * nchains), dim3(kChainThreads), lds_bytes,
-                           st, fd, frames);
+        hipLaunchKernelGGL(k_chain<double>, dim3(nb), dim3(kChainThreads), lds_bytes, st, fd,
+                           frames, dirs);
     else
-        hipLaunchKernelGGL(k_chain<float>, dim3(2 * nchains), dim3(kChainThreads), lds_bytes,
-                           st, fd, frames);
+        hipLaunchKernelGGL(k_chain<float>, dim3(nb), dim3(kChainThreads), lds_bytes, st, fd,
+                           frames, dirs);
     return hipGetLastError();
 }
 
@@ -130,8 +147,8 @@ namespace mapdec {
 
 // One object per (precision, shape) built from k_chain_ring.hip.
 #define MAPDEC_RING_DECL(name)                                                            \
-    hipError_t name(int mn, int nchains, size_t lds, hipStream_t st, const FrameDesc *fd, \
-                    const int *frames);
+    hipError_t name(int mn, int nchains, int dirs, size_t lds, hipStream_t st,            \
+                    const FrameDesc *fd, const int *frames);
 MAPDEC_RING_DECL(chain_ring_f32_0)
 MAPDEC_RING_DECL(chain_ring_f32_1)
 MAPDEC_RING_DECL(chain_ring_f32_2)
@@ -147,15 +164,16 @@ MAPDEC_RING_DECL(chain_ring_f64_5)
 #undef MAPDEC_RING_DECL
 
 hipError_t launch_chain_ring(int fp64, int shape, int mn, const FrameDesc *fd, const int *frames,
-                             int nchains, size_t lds, hipStream_t st) {
+                             int nchains, int dirs, size_t lds, hipStream_t st) {
     if (nchains == 0) return hipSuccess;
-    using Fn = hipError_t (*)(int, int, size_t, hipStream_t, const FrameDesc *, const int *);
+    if (dirs < 1 || dirs > 3) return hipErrorInvalidValue;
+    using Fn = hipError_t (*)(int, int, int, size_t, hipStream_t, const FrameDesc *, const int *);
     static const Fn f32[kNumRingShapes] = {chain_ring_f32_0, chain_ring_f32_1, chain_ring_f32_2,
                                            chain_ring_f32_3, chain_ring_f32_4, chain_ring_f32_5};
     static const Fn f64[kNumRingShapes] = {chain_ring_f64_0, chain_ring_f64_1, chain_ring_f64_2,
                                            chain_ring_f64_3, chain_ring_f64_4, chain_ring_f64_5};
     if (shape < 0 || shape >= kNumRingShapes) return hipErrorInvalidValue;
-    return (fp64 ? f64 : f32)[shape](mn, nchains, lds, st, fd, frames);
+    return (fp64 ? f64 : f32)[shape](mn, nchains, dirs, lds, st, fd, frames);
 }
 
 }  // namespace mapdec

@@ -21,6 +21,10 @@
 // the same way from the other end.  Consumers of the rows are invariant to
 // a per-row scale, and log P(y) = sum_{k<N} log c_k + log alpha'_N(rho -
 // tau); the product of normalisers is carried as mantissa * 2^exponent.
+// A chain covers the symbols [i0, i1) of its frame's segment: it starts from
+// the row the descriptor gives (a checkpoint) or from the boundary state,
+// continues the cumulative log of the normalisers, and can copy its last
+// row out (the next checkpoint).
 //
 // Gamma(s, delta) for the start indices a chunk of C steps reads sits in an
 // LDS ring of RING (a power of two) slots of Mn values each, slot-major
@@ -46,7 +50,8 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     constexpr int ROWW = NT * SPL + 2 * MN;            // padded row
     constexpr bool DUP = ring_duplicates(NT * SPL);
     constexpr int PF = kRingPrefetchRegs;
-    const int Mt = f.Mt, M = f.M, N = f.N, n = f.n, rho = f.rho;
+    const int Mt = f.Mt, M = f.M, N = f.N, n = f.n;
+    const int i0 = f.i0, i1 = f.i1, s0 = f.s0, s1 = f.s1, NS = i1 - i0;
     const int C = f.ring_chunk, RING = f.ring_cols, mask = RING - 1;
     const int RPHYS = DUP ? RING + NT * SPL + 2 * MN : RING;
     using R = double;                                  // metric rows: FP64 always
@@ -62,16 +67,23 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     for (int j = tid; j < RPHYS * Mn; j += NT) ring[j] = T(0);
     __syncthreads();
     const int m0 = DIR == 0 ? 0 : f.rho - f.tau;
-    if (tid == 0) row0[MN + m0 + M] = R(1);
+    const double *init = DIR == 0 ? f.a_init : f.b_init;
     const gptr<R> out = to_global(DIR == 0 ? f.alpha : f.beta);
-    const int rowA = DIR == 0 ? 0 : N;
-    for (int mi = tid; mi < Mt; mi += NT)
-        out[(size_t)rowA * Mt + mi] = (mi == m0 + M) ? R(1) : R(0);
+    const int rowA = DIR == 0 ? i0 : i1;
+    for (int mi = tid; mi < Mt; mi += NT) {
+        const R v = init ? (R)init[mi] : ((mi == m0 + M) ? R(1) : R(0));
+        row0[MN + mi] = v;
+        out[(size_t)(rowA - i0) * Mt + mi] = v;
+    }
+    double *logX = DIR == 0 ? f.logA : f.logB;
+    const double lbase = (DIR == 0 ? i0 > 0 : i1 < N) ? logX[rowA] : 0.0;
 
-    // chunk k covers steps kC .. kC+C-1 (forward) or N-1-kC down to N-C-kC
-    // (backward), which read s in [n i_lo - M, n i_hi + M]
-    auto chunk_lo_s = [&](int k) { return n * (DIR == 0 ? k * C : N - C - k * C) - M; };
-    auto chunk_hi_s = [&](int k) { return n * (DIR == 0 ? k * C + C - 1 : N - 1 - k * C) + M; };
+    // chunk k covers steps i0+kC .. i0+kC+C-1 (forward) or i1-1-kC down to
+    // i1-C-kC (backward), which read s in [n i_lo - M, n i_hi + M]
+    auto chunk_lo_s = [&](int k) { return n * (DIR == 0 ? i0 + k * C : i1 - C - k * C) - M; };
+    auto chunk_hi_s = [&](int k) {
+        return n * (DIR == 0 ? i0 + k * C + C - 1 : i1 - 1 - k * C) + M;
+    };
     auto new_base = [&](int k) { return DIR == 0 ? chunk_hi_s(k - 1) + 1 : chunk_lo_s(k); };
 
     auto put = [&](int s, int kk, T v) {
@@ -99,9 +111,9 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
 #pragma unroll
         for (int r = 0; r < PF; ++r) {
             const int s = base + col;
-            const int sc = min(max(s, 0), rho);
+            const int sc = min(max(s, s0), s1);   // the table holds [s0, s1]
             const int kc = min(kk, Mn - 1);
-            pre[r] = G[(size_t)kc * sp + sc];
+            pre[r] = G[(size_t)kc * sp + (sc - s0)];
             pvalid |= (s == sc) ? (1u << r) : 0u;
             col += dr;
             kk += dq;
@@ -130,7 +142,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             commit(base, lo, hi);
         }
     }
-    const int nchunks = (N + C - 1) / C;
+    const int nchunks = (NS + C - 1) / C;
     if (nchunks > 1) issue(new_base(1));
 
     R *cur = row0, *nxt = row1;
@@ -158,9 +170,9 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             if (k + 1 < nchunks) issue(new_base(k + 1));
             __syncthreads();
         }
-        const int steps = min(C, N - k * C);
+        const int steps = min(C, NS - k * C);
         for (int t = 0; t < steps; ++t) {
-            const int i = DIR == 0 ? k * C + t : N - 1 - k * C - t;
+            const int i = DIR == 0 ? i0 + k * C + t : i1 - 1 - k * C - t;
             R csum = R(0);
 #pragma unroll
             for (int w = 0; w < NW; ++w) csum += part[pp * NW + w];
@@ -222,7 +234,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
                 own[j] = v;
                 p += v;
                 nb[NT * j] = v;
-                if (mi < Mt) out[(size_t)row * Mt + mi] = v;
+                if (mi < Mt) out[(size_t)(row - i0) * Mt + mi] = v;
             }
             p = wave_sum_dpp(p);
             if ((tid & 63) == 0) part[(pp ^ 1) * NW + wv] = p;
@@ -233,15 +245,20 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             __syncthreads();
         }
     }
-    const double lsum = log(pmant) + (double)pexp * 0.69314718055994530942;
-    if (tid != 0) return;
-    (DIR == 0 ? f.logA : f.logB)[DIR == 0 ? N : 0] = lsum;
+    const double lsum = lbase + log(pmant) + (double)pexp * 0.69314718055994530942;
     if (dead) {
-        atomicOr(f.status, kStatusNoPath);
-        if (DIR == 0) *f.logp = -INFINITY;
+        if (tid == 0) {
+            atomicOr(f.status, kStatusNoPath);
+            if (DIR == 0) *f.logp = -INFINITY;
+        }
         return;
     }
-    if (DIR == 0) {
+    double *fin = DIR == 0 ? f.a_fin : f.b_fin;
+    if (fin)
+        for (int mi = tid; mi < Mt; mi += NT) fin[mi] = cur[MN + mi];
+    if (tid != 0) return;
+    logX[DIR == 0 ? i1 : i0] = lsum;
+    if (DIR == 0 && i1 == N) {
         const R aN = cur[MN + (f.rho - f.tau) + M];
         if (!(aN > R(0))) {
             atomicOr(f.status, kStatusNoPath);
@@ -252,42 +269,48 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     }
 }
 
+// dirs: 1 forward only, 2 backward only, 3 both (workgroups 2c, 2c+1)
 template <typename T, int NW, int SPL, int MN>
 __global__ __launch_bounds__(64 * NW) void k_chain_ring(const FrameDesc *__restrict__ fd,
-                                                        const int *__restrict__ frames) {
+                                                        const int *__restrict__ frames,
+                                                        int dirs) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const FrameDesc &f = fd[frames[blockIdx.x >> 1]];
-    if (blockIdx.x & 1)
+    const int nd = dirs == 3 ? 2 : 1;
+    const FrameDesc &f = fd[frames[blockIdx.x / nd]];
+    if (*f.status != kStatusOk) return;
+    const int dir = nd == 2 ? (int)(blockIdx.x & 1) : (dirs == 1 ? 0 : 1);
+    if (dir)
         chain_ring_body<T, NW, SPL, MN, 1>(f, smem);
     else
         chain_ring_body<T, NW, SPL, MN, 0>(f, smem);
 }
 
 template <int MN>
-static hipError_t ring_launch(int nchains, size_t lds, hipStream_t st, const FrameDesc *fd,
-                              const int *frames) {
+static hipError_t ring_launch(int nchains, int dirs, size_t lds, hipStream_t st,
+                              const FrameDesc *fd, const int *frames) {
     auto kern = k_chain_ring<CHAIN_T, CHAIN_NW, CHAIN_SPL, MN>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(2 * nchains), dim3(64 * CHAIN_NW), lds, st, fd, frames);
+    hipLaunchKernelGGL(kern, dim3(nchains * (dirs == 3 ? 2 : 1)), dim3(64 * CHAIN_NW), lds, st,
+                       fd, frames, dirs);
     return hipGetLastError();
 }
 
-hipError_t CHAIN_FN(int mn, int nchains, size_t lds, hipStream_t st, const FrameDesc *fd,
-                    const int *frames) {
+hipError_t CHAIN_FN(int mn, int nchains, int dirs, size_t lds, hipStream_t st,
+                    const FrameDesc *fd, const int *frames) {
     switch (mn) {
-        case 0: return ring_launch<0>(nchains, lds, st, fd, frames);
-        case 1: return ring_launch<1>(nchains, lds, st, fd, frames);
-        case 2: return ring_launch<2>(nchains, lds, st, fd, frames);
-        case 3: return ring_launch<3>(nchains, lds, st, fd, frames);
-        case 4: return ring_launch<4>(nchains, lds, st, fd, frames);
-        case 5: return ring_launch<5>(nchains, lds, st, fd, frames);
-        case 6: return ring_launch<6>(nchains, lds, st, fd, frames);
-        case 7: return ring_launch<7>(nchains, lds, st, fd, frames);
-        case 8: return ring_launch<8>(nchains, lds, st, fd, frames);
+        case 0: return ring_launch<0>(nchains, dirs, lds, st, fd, frames);
+        case 1: return ring_launch<1>(nchains, dirs, lds, st, fd, frames);
+        case 2: return ring_launch<2>(nchains, dirs, lds, st, fd, frames);
+        case 3: return ring_launch<3>(nchains, dirs, lds, st, fd, frames);
+        case 4: return ring_launch<4>(nchains, dirs, lds, st, fd, frames);
+        case 5: return ring_launch<5>(nchains, dirs, lds, st, fd, frames);
+        case 6: return ring_launch<6>(nchains, dirs, lds, st, fd, frames);
+        case 7: return ring_launch<7>(nchains, dirs, lds, st, fd, frames);
+        case 8: return ring_launch<8>(nchains, dirs, lds, st, fd, frames);
         default: return hipErrorInvalidValue;
     }
 }

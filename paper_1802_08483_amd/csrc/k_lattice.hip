@@ -37,8 +37,8 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
     constexpr int NB = kMaxN + MN;   // received positions a lattice can read
     const Work w = tab[blockIdx.x];
     const FrameDesc &f = fd[w.frame];
-    const int s = w.item + (int)threadIdx.x;
-    if (s > f.rho) return;
+    const int s = f.s0 + w.item + (int)threadIdx.x;   // column s - s0 of the tables
+    if (s > f.s1) return;
     const int n = f.n, q = f.q, rho = f.rho;
     const T d = (T)f.d, t1 = (T)f.t1, t0 = (T)f.t0;
 
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
         for (int k = 0; k < KW; ++k) {
             const int len = n + k - MN;   // segment length n + delta
             const T v = (len >= 0 && s + len <= rho) ? F[k] : T(0);
-            R[((size_t)D * KW + k) * sp + s] = v;
+            R[((size_t)D * KW + k) * sp + (s - f.s0)] = v;
             gsum[k] += v;
         }
     }
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
         T *G = (T *)f.G;
         const T invq = T(1) / T(q);
 #pragma unroll
-        for (int k = 0; k < KW; ++k) G[(size_t)k * sp + s] = gsum[k] * invq;
+        for (int k = 0; k < KW; ++k) G[(size_t)k * sp + (s - f.s0)] = gsum[k] * invq;
     }
 }
 

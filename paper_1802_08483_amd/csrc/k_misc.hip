@@ -41,18 +41,18 @@ __global__ __launch_bounds__(kGammaLanes) void k_gamma(const FrameDesc *__restri
     const Work w = tab[blockIdx.x];
     const FrameDesc &f = fd[w.frame];
     const int per_i = (f.Mt + kGammaLanes - 1) / kGammaLanes;
-    const int i = w.item / per_i;
+    const int i = f.i0 + w.item / per_i;
     const int mi = (w.item % per_i) * kGammaLanes + (int)threadIdx.x;
     if (mi >= f.Mt) return;
     const int Mn = f.Mn, Mt = f.Mt, q = f.q;
     const int s = f.n * i + mi - f.M;
-    T *G = (T *)f.G + (size_t)i * Mn * Mt + mi;
+    T *G = (T *)f.G + (size_t)(i - f.i0) * Mn * Mt + mi;
     if (s < 0 || s > f.rho) {
         for (int k = 0; k < Mn; ++k) G[(size_t)k * Mt] = T(0);
         return;
     }
     const T *pr = (const T *)f.prior + (size_t)i * q;
-    const T *R = (const T *)f.R + s;
+    const T *R = (const T *)f.R + (s - f.s0);   // s in [s0, s1] for the segment's symbols
     const size_t sp = (size_t)f.sp;
     for (int k = 0; k < Mn; ++k) {
         T acc = T(0);
@@ -77,8 +77,8 @@ __global__ void k_dparams(const FrameDesc *__restrict__ fd, int nframes) {
         return;
     }
     double g[4] = {0, 0, 0, 0};
-    for (int b = 0; b < f.lat_blocks; ++b)
-        for (int t = 0; t < 4; ++t) g[t] += f.gacc[(size_t)b * 4 + t];
+    for (int b = 0; b < f.gacc_n; ++b)
+        for (int t = 0; t < 4; ++t) g[t] += f.gacc_all[(size_t)b * 4 + t];
     // without the d/da sweep: a g_a - d g_d = rho - tau (every path inserts
     // rho - tau more bits than it deletes)
     if (!f.adj_da) g[0] = ((double)(f.rho - f.tau) + f.d * g[1]) / f.a;

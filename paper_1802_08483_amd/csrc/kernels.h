@@ -28,13 +28,16 @@ hipError_t launch_lattice(int fp64, int mn, int imode, const FrameDesc *fd, cons
                           int nblocks, hipStream_t st);
 hipError_t launch_gamma(int fp64, const FrameDesc *fd, const Work *tab, int nblocks,
                         hipStream_t st);
+// Chains over each frame's segment; dirs: 1 forward (alpha) only, 2 backward
+// (beta) only, 3 both (one workgroup per chain).
+constexpr int kDirFwd = 1, kDirBwd = 2, kDirBoth = 3;
 hipError_t launch_chain(int fp64, const FrameDesc *fd, const int *frames, int nchains,
-                        size_t lds_bytes, hipStream_t st);
+                        int dirs, size_t lds_bytes, hipStream_t st);
 // Chains for uniform priors with Gamma in an LDS ring (k_chain_ring.hip):
 // shape = index into kRingShapes; every frame of the launch has drift
 // limit mn.
 hipError_t launch_chain_ring(int fp64, int shape, int mn, const FrameDesc *fd, const int *frames,
-                             int nchains, size_t lds_bytes, hipStream_t st);
+                             int nchains, int dirs, size_t lds_bytes, hipStream_t st);
 
 // Workgroup shapes of the ring chain kernel: waves per chain and drift
 // states per thread; a frame takes the first shape with 64 nw spl >= 2M+1.

@@ -32,7 +32,6 @@ int fail(int st) {
 }
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxPhases = 8;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 int validate_code_params(int q, int n, double Pi, double Pd, double Ps, int I, int M, int mn) {
@@ -43,38 +42,70 @@ int validate_code_params(int q, int n, double Pi, double Pd, double Ps, int I, i
     return MAPDEC_OK;
 }
 
-// Sizes of one frame's workspace pieces.
+// Sizes and places of one frame's workspace pieces.
 struct FrameLayout {
-    int nwords, sp, Mt, Mn, lat_blocks, pack_blocks, gamma_blocks;
-    int ring_chunk = 0, ring_cols = 0;
-    size_t off_cw, off_ybits, off_R, off_G, off_alpha, off_beta, off_logA, off_logB, off_Zinv,
-        off_gacc, end;
+    int nwords = 0, sp = 0, Mt = 0, Mn = 0, pack_blocks = 0;
+    int K = 0, nseg = 1;   // symbols per segment, segments (1 unless checkpointed)
+    int ring_shape = -1, ring_chunk = 0, ring_cols = 0;   // ring_shape -1: plain chain
+    bool app_tiled = false;
+    std::tuple<int, int, int> app_key;                     // (td, waves, mn) when tiled
+    size_t off_cw = 0, off_ybits = 0, off_R = 0, off_G = 0, off_alpha = 0, off_beta = 0,
+           off_logA = 0, off_logB = 0, off_Zinv = 0, off_gacc = 0, off_ck = 0, off_bcarry = 0;
+    std::vector<int> gacc_first;   // first [4] partial of each segment
+    int gacc_n = 0;
+};
+
+// Segment j of a frame: symbols [i0, i1) and the start indices [s0, s1]
+// their drift bands reach (s0 <= s1 whenever |rho - tau| <= M).
+struct Segment {
+    int i0, i1, s0, s1;
+};
+Segment segment_of(const mapdec_frame &fr, const FrameLayout &F, int j) {
+    const mapdec_code *c = fr.code;
+    Segment g;
+    g.i0 = j * F.K;
+    g.i1 = std::min(fr.N, g.i0 + F.K);
+    g.s0 = std::max(0, c->n * g.i0 - c->M);
+    g.s1 = std::min(fr.rho, c->n * (g.i1 - 1) + c->M);
+    return g;
+}
+int lattice_blocks(const Segment &g) { return (g.s1 - g.s0 + 1 + kLatticeLanes - 1) / kLatticeLanes; }
+
+// The launches of one pass over segment j of every frame that has one.  A
+// forward pass (checkpointed frames only) runs the lattice, Gamma and the
+// forward chain, which leaves the next checkpoint; a main pass runs the
+// lattice, Gamma, both chains, the APP and, for gradients, W and the
+// adjoint sweep.
+struct Pass {
+    bool forward = false;
+    int seg = 0;
+    size_t off_fd = 0;
+    std::map<std::pair<int, int>, std::vector<Work>> lat;          // (mn, imode)
+    std::map<std::pair<int, int>, size_t> off_lat;
+    std::vector<Work> gamma;
+    size_t off_gamma = 0;
+    std::vector<int> chain_plain;
+    size_t off_chain = 0;
+    std::map<std::pair<int, int>, std::vector<int>> chain_ring;    // (shape, mn)
+    std::map<std::pair<int, int>, size_t> off_chain_ring;
+    std::map<std::tuple<int, int, int>, std::vector<Work>> app_tile;   // (td, waves, mn)
+    std::map<std::tuple<int, int, int>, size_t> off_app_tile;
+    std::vector<Work> app_plain;
+    size_t off_app = 0;
+    std::map<std::tuple<int, int, int>, std::vector<Work>> adj;    // (mn, imode, d/da)
+    std::map<std::tuple<int, int, int>, size_t> off_adj;
 };
 
 struct Layout {
-    int nframes = 0, fp64 = 0, grad = 0;
+    int nframes = 0, fp64 = 0, grad = 0, ckK = 0;
     size_t tsize = 4;
-    size_t off_fd = 0, off_pack = 0, off_gamma = 0, off_chain = 0, off_app = 0, head = 0, total = 0;
-    int n_pack = 0, n_gamma = 0;
-    // lattice work grouped by template instance (mn, imode)
-    std::map<std::pair<int, int>, std::vector<Work>> lat;
-    std::map<std::pair<int, int>, size_t> off_lat;
-    std::map<std::pair<int, int>, int> lat_nmax;   // longest codeword per group
-    // adjoint sweep work grouped by (mn, imode, accumulates d/da)
-    std::map<std::tuple<int, int, int>, std::vector<Work>> adj;
-    std::map<std::tuple<int, int, int>, size_t> off_adj, adj_lds;
+    size_t off_pack = 0, head = 0, total = 0;
+    std::vector<Work> pack;
+    std::vector<Pass> passes;
+    // LDS bytes of each kernel instance (maxima over its launches)
     size_t chain_lds = 0, app_lds = 0;
-    // chains: single-wave ring kernel grouped by states per lane, else the
-    // workgroup kernel
-    std::vector<int> chain_plain;
-    // keyed by (states per lane, mn)
-    std::map<std::pair<int, int>, std::vector<int>> chain_ring;
-    std::map<std::pair<int, int>, size_t> off_chain_ring, ring_lds;
-    // tiled APP work grouped by (symbols per wave, waves per workgroup, mn);
-    // frames whose rows do not fit in LDS use the one-wave APP kernel
-    std::map<std::tuple<int, int, int>, std::vector<Work>> app_tile;
-    std::map<std::tuple<int, int, int>, size_t> off_app_tile, app_tile_lds;
-    std::vector<Work> app_plain;
+    std::map<std::pair<int, int>, size_t> ring_lds;
+    std::map<std::tuple<int, int, int>, size_t> app_tile_lds, adj_lds;
     std::vector<FrameLayout> fl;
 };
 
@@ -131,8 +162,8 @@ size_t device_lds_limit() {
     if (hipGetDevice(&dev) != hipSuccess) return 65536;
     if (dev != cached_dev) {
         int v = 0;
-        cached = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
-                      hipSuccess && v > 0)
+        cached = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                         hipSuccess && v > 0
                      ? (size_t)v
                      : 65536;
         cached_dev = dev;
@@ -140,16 +171,20 @@ size_t device_lds_limit() {
     return cached;
 }
 
-// Validates the frames and lays out the workspace.
-int build_layout(const mapdec_frame *frames, int nframes, int precision, int flags, Layout &L) {
-    if (!frames || nframes < 1) return MAPDEC_EINVAL;
+// Validates the frames and lays out the workspace.  ckK > 0 splits every
+// frame into segments of ckK symbols with forward-metric checkpoints.
+int build_layout(const mapdec_frame *frames, int nframes, int precision, int flags, int ckK,
+                 Layout &L) {
+    if (!frames || nframes < 1 || ckK < 0) return MAPDEC_EINVAL;
     if (precision != MAPDEC_FP32 && precision != MAPDEC_FP64) return MAPDEC_EINVAL;
     L.nframes = nframes;
     L.fp64 = precision == MAPDEC_FP64;
     L.grad = (flags & MAPDEC_FLAG_GRAD) != 0;
+    L.ckK = ckK;
     L.tsize = L.fp64 ? 8 : 4;
     L.fl.resize(nframes);
-    size_t max_chain = 0, max_app = 0;
+    const size_t lds_limit = device_lds_limit();
+    int smax = 1;
     for (int f = 0; f < nframes; ++f) {
         const mapdec_frame &fr = frames[f];
         const mapdec_code *c = fr.code;
@@ -161,91 +196,147 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         FrameLayout &F = L.fl[f];
         F.Mt = 2 * c->M + 1;
         F.Mn = 2 * c->mn + 1;
-        F.sp = (int)(((size_t)fr.rho + 1 + 63) / 64 * 64);
+        F.K = ckK > 0 ? std::min(ckK, fr.N) : fr.N;
+        F.nseg = (fr.N + F.K - 1) / F.K;
+        smax = std::max(smax, F.nseg);
+        F.sp = 0;
+        F.gacc_first.resize(F.nseg);
+        for (int j = 0; j < F.nseg; ++j) {
+            const Segment g = segment_of(fr, F, j);
+            F.sp = std::max(F.sp, (g.s1 - g.s0 + 1 + 63) / 64 * 64);
+            F.gacc_first[j] = F.gacc_n;
+            F.gacc_n += lattice_blocks(g);
+        }
         F.nwords = (fr.rho + 63) / 32 + 2;
         F.pack_blocks = (F.nwords + kPackWords - 1) / kPackWords;
-        F.lat_blocks = (fr.rho + 1 + kLatticeLanes - 1) / kLatticeLanes;
-        F.gamma_blocks = fr.prior ? fr.N * ((F.Mt + kGammaLanes - 1) / kGammaLanes) : 0;
-        L.n_pack += F.pack_blocks;
-        L.n_gamma += F.gamma_blocks;
+        for (int b = 0; b < F.pack_blocks; ++b) L.pack.push_back(Work{f, b * kPackWords});
         {
             const size_t tl = app_tile_lds(F.Mt, c->mn, c->n, c->q, L.tsize);
             // the tile kernel addresses R with 32-bit byte offsets
             const bool fits = (double)c->q * F.Mn * F.sp * L.tsize < 2147483648.0;
-            if (fits && tl <= device_lds_limit()) {
+            F.app_tiled = fits && tl <= lds_limit;
+            if (F.app_tiled) {
                 const int td = app_tile_td(c->q, L.tsize);
-                const auto key = std::make_tuple(td, app_tile_waves(F.Mt, c->n), c->mn);
-                auto &v = L.app_tile[key];
-                for (int b = 0; b * kAppTI < fr.N; ++b) v.push_back(Work{f, b});
-                L.app_tile_lds[key] = std::max(L.app_tile_lds[key], tl);
+                F.app_key = std::make_tuple(td, app_tile_waves(F.Mt, c->n), c->mn);
+                L.app_tile_lds[F.app_key] = std::max(L.app_tile_lds[F.app_key], tl);
             } else {
-                for (int i = 0; i < fr.N; ++i) L.app_plain.push_back(Work{f, i});
-                max_app = std::max(max_app, (2 * (size_t)F.Mt + 2 * c->mn + c->q) * sizeof(double));
+                L.app_lds = std::max(L.app_lds, (2 * (size_t)F.Mt + 2 * c->mn + c->q) * sizeof(double));
             }
         }
-        const size_t W = (size_t)F.Mt + 2 * c->mn;
-        int spl = 0;
+        int shape = -1;
         size_t rlds = 0;
-        if (!fr.prior && ring_params(F.Mt, F.Mn, c->n, c->mn, L.tsize, device_lds_limit(),
-                                     spl, F.ring_chunk, F.ring_cols, rlds)) {
-            const auto key = std::make_pair(spl, c->mn);
-            L.chain_ring[key].push_back(f);
+        if (!fr.prior && ring_params(F.Mt, F.Mn, c->n, c->mn, L.tsize, lds_limit, shape,
+                                     F.ring_chunk, F.ring_cols, rlds)) {
+            F.ring_shape = shape;
+            const auto key = std::make_pair(shape, c->mn);
             L.ring_lds[key] = std::max(L.ring_lds[key], rlds);
         } else {
+            F.ring_shape = -1;
             F.ring_chunk = F.ring_cols = 0;
-            L.chain_plain.push_back(f);
-            max_chain = std::max(max_chain, (2 * W + 16) * sizeof(double));
+            L.chain_lds = std::max(L.chain_lds, (2 * ((size_t)F.Mt + 2 * c->mn) + 16) * sizeof(double));
         }
-        auto key = std::make_pair(c->mn, frame_imode(c));
-        L.lat_nmax[key] = std::max(L.lat_nmax[key], c->n);
-        auto &v = L.lat[key];
-        for (int b = 0; b < F.lat_blocks; ++b) v.push_back(Work{f, b * kLatticeLanes});
         if (L.grad) {
             const auto akey = std::make_tuple(c->mn, frame_imode(c),
                                               adjoint_needs_da(c->Pi, c->Pd) ? 1 : 0);
-            auto &av = L.adj[akey];
-            for (int b = 0; b < F.lat_blocks; ++b) av.push_back(Work{f, b * kLatticeLanes});
             const size_t al = adjoint_lds(c->n, c->mn, L.tsize);
-            if (al > device_lds_limit()) return MAPDEC_EUNSUPPORTED;
+            if (al > lds_limit) return MAPDEC_EUNSUPPORTED;
             L.adj_lds[akey] = std::max(L.adj_lds[akey], al);
         }
     }
-    if (max_chain > 65536 || max_app > 65536) return MAPDEC_EUNSUPPORTED;
-    L.chain_lds = max_chain;
-    L.app_lds = max_app;
+    if (L.chain_lds > 65536 || L.app_lds > 65536) return MAPDEC_EUNSUPPORTED;
 
-    // head: descriptors and work tables
+    // passes: forward over segments 0 .. S-2, then main passes S-1 .. 0
+    for (int j = 0; j + 1 < smax; ++j) {
+        Pass P;
+        P.forward = true;
+        P.seg = j;
+        L.passes.push_back(P);
+    }
+    for (int j = smax - 1; j >= 0; --j) {
+        Pass P;
+        P.forward = false;
+        P.seg = j;
+        L.passes.push_back(P);
+    }
+    for (Pass &P : L.passes) {
+        const int j = P.seg;
+        std::vector<std::pair<int, int>> chains;   // (steps, frame)
+        for (int f = 0; f < nframes; ++f) {
+            const mapdec_frame &fr = frames[f];
+            const mapdec_code *c = fr.code;
+            const FrameLayout &F = L.fl[f];
+            if (P.forward ? j + 1 >= F.nseg : j >= F.nseg) continue;
+            const Segment g = segment_of(fr, F, j);
+            auto &lv = P.lat[std::make_pair(c->mn, frame_imode(c))];
+            const int nb = lattice_blocks(g);
+            for (int b = 0; b < nb; ++b) lv.push_back(Work{f, b * kLatticeLanes});
+            if (fr.prior) {
+                const int per_i = (F.Mt + kGammaLanes - 1) / kGammaLanes;
+                for (int b = 0; b < (g.i1 - g.i0) * per_i; ++b) P.gamma.push_back(Work{f, b});
+            }
+            chains.push_back(std::make_pair(g.i1 - g.i0, f));
+            if (P.forward) continue;
+            if (F.app_tiled) {
+                auto &v = P.app_tile[F.app_key];
+                for (int b = 0; b * kAppTI < g.i1 - g.i0; ++b) v.push_back(Work{f, b});
+            } else {
+                for (int i = g.i0; i < g.i1; ++i) P.app_plain.push_back(Work{f, i - g.i0});
+            }
+            if (L.grad) {
+                auto &av = P.adj[std::make_tuple(c->mn, frame_imode(c),
+                                                 adjoint_needs_da(c->Pi, c->Pd) ? 1 : 0)];
+                for (int b = 0; b < nb; ++b) av.push_back(Work{f, b * kLatticeLanes});
+            }
+        }
+        // longest chains first, so that the longest ones do not start last
+        std::stable_sort(chains.begin(), chains.end(),
+                         [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+                             return a.first > b.first;
+                         });
+        for (const auto &ch : chains) {
+            const int f = ch.second;
+            const FrameLayout &F = L.fl[f];
+            if (F.ring_shape >= 0)
+                P.chain_ring[std::make_pair(F.ring_shape, frames[f].code->mn)].push_back(f);
+            else
+                P.chain_plain.push_back(f);
+        }
+        for (auto &kv : P.app_tile) kv.second = xcd_order(kv.second);
+    }
+
+    // head: work tables and, per pass, descriptors and work tables
     size_t off = 0;
-    L.off_fd = off;
-    off = align_up(off + sizeof(FrameDesc) * nframes);
     L.off_pack = off;
-    off = align_up(off + sizeof(Work) * L.n_pack);
-    for (auto &kv : L.lat) {
-        L.off_lat[kv.first] = off;
-        off = align_up(off + sizeof(Work) * kv.second.size());
+    off = align_up(off + sizeof(Work) * L.pack.size());
+    for (Pass &P : L.passes) {
+        P.off_fd = off;
+        off = align_up(off + sizeof(FrameDesc) * nframes);
+        for (auto &kv : P.lat) {
+            P.off_lat[kv.first] = off;
+            off = align_up(off + sizeof(Work) * kv.second.size());
+        }
+        for (auto &kv : P.adj) {
+            P.off_adj[kv.first] = off;
+            off = align_up(off + sizeof(Work) * kv.second.size());
+        }
+        P.off_gamma = off;
+        off = align_up(off + sizeof(Work) * P.gamma.size());
+        P.off_chain = off;
+        off = align_up(off + sizeof(int) * P.chain_plain.size());
+        for (auto &kv : P.chain_ring) {
+            P.off_chain_ring[kv.first] = off;
+            off = align_up(off + sizeof(int) * kv.second.size());
+        }
+        for (auto &kv : P.app_tile) {
+            P.off_app_tile[kv.first] = off;
+            off = align_up(off + sizeof(Work) * kv.second.size());
+        }
+        P.off_app = off;
+        off = align_up(off + sizeof(Work) * P.app_plain.size());
     }
-    for (auto &kv : L.adj) {
-        L.off_adj[kv.first] = off;
-        off = align_up(off + sizeof(Work) * kv.second.size());
-    }
-    L.off_gamma = off;
-    off = align_up(off + sizeof(Work) * L.n_gamma);
-    L.off_chain = off;
-    off = align_up(off + sizeof(int) * L.chain_plain.size());
-    for (auto &kv : L.chain_ring) {
-        L.off_chain_ring[kv.first] = off;
-        off = align_up(off + sizeof(int) * kv.second.size());
-    }
-    for (auto &kv : L.app_tile) {
-        kv.second = xcd_order(kv.second);
-        L.off_app_tile[kv.first] = off;
-        off = align_up(off + sizeof(Work) * kv.second.size());
-    }
-    L.off_app = off;
-    off = align_up(off + sizeof(Work) * L.app_plain.size());
     L.head = off;
 
-    // per-frame regions
+    // per-frame regions (R, Gamma, alpha and beta hold one segment)
     for (int f = 0; f < nframes; ++f) {
         const mapdec_frame &fr = frames[f];
         const mapdec_code *c = fr.code;
@@ -258,11 +349,11 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         F.off_R = off;
         off = align_up(off + T * c->q * F.Mn * (size_t)F.sp);
         F.off_G = off;
-        off = align_up(off + T * (fr.prior ? (size_t)fr.N * F.Mn * F.Mt : (size_t)F.Mn * F.sp));
+        off = align_up(off + T * (fr.prior ? (size_t)F.K * F.Mn * F.Mt : (size_t)F.Mn * F.sp));
         F.off_alpha = off;   // metric rows are FP64 at every precision
-        off = align_up(off + sizeof(double) * (size_t)(fr.N + 1) * F.Mt);
+        off = align_up(off + sizeof(double) * (size_t)(F.K + 1) * F.Mt);
         F.off_beta = off;
-        off = align_up(off + sizeof(double) * (size_t)(fr.N + 1) * F.Mt);
+        off = align_up(off + sizeof(double) * (size_t)(F.K + 1) * F.Mt);
         F.off_logA = off;
         off = align_up(off + sizeof(double) * (fr.N + 1));
         F.off_logB = off;
@@ -270,12 +361,20 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         F.off_Zinv = off;
         off = align_up(off + sizeof(double) * fr.N);
         F.off_gacc = off;
-        off = align_up(off + sizeof(double) * 4 * F.lat_blocks);
-        F.end = off;
+        off = align_up(off + sizeof(double) * 4 * (size_t)F.gacc_n);
+        if (F.nseg > 1) {
+            F.off_ck = off;      // alpha rows K, 2K, .. (row jK at index j)
+            off = align_up(off + sizeof(double) * (size_t)F.nseg * F.Mt);
+            F.off_bcarry = off;  // beta row at the current segment's end
+            off = align_up(off + sizeof(double) * (size_t)F.Mt);
+        }
     }
     L.total = off;
     return MAPDEC_OK;
 }
+
+// Per-launch phase names, in the order of mapdec_phase_name().
+enum Phase { kPhPack, kPhLattice, kPhGamma, kPhChain, kPhApp, kPhWgrad, kPhAdjoint, kPhDparams };
 
 }  // namespace
 
@@ -292,64 +391,80 @@ struct mapdec_plan {
     template <typename P>
     P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
 
-    hipEvent_t ev[kMaxPhases + 1] = {};
-    bool have_events = false;
+    // profiling: an event after each launch group, tagged with its phase
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_phase;
 
-    // Enqueues every launch of one run.  With ev != nullptr an event is
-    // recorded before the first phase and after each phase.
-    hipError_t enqueue(hipStream_t st, hipEvent_t *ev = nullptr, int *nphases = nullptr) const {
-        const FrameDesc *fd = at<FrameDesc>(L.off_fd);
+    // Enqueues every launch of one run.  With prof, an event is recorded
+    // first and after each launch group, and ev_phase[k] names the phase of
+    // the group that ends at event k.
+    hipError_t enqueue(hipStream_t st, bool prof = false) {
         hipError_t e = hipSuccess;
-        int k = 0;
-        auto mark = [&]() {
-            if (ev && e == hipSuccess) e = hipEventRecord(ev[k], st);
+        size_t k = 0;
+        auto mark = [&](int phase) {
+            if (!prof || e != hipSuccess) return;
+            if (k >= ev.size()) {
+                hipEvent_t x;
+                e = hipEventCreate(&x);
+                if (e != hipSuccess) return;
+                ev.push_back(x);
+                ev_phase.push_back(phase);
+            }
+            ev_phase[k] = phase;
+            e = hipEventRecord(ev[k], st);
             ++k;
         };
-        mark();
-        e = launch_init(fd, L.nframes, st);   // phase "pack"
-        if (e == hipSuccess) e = launch_pack(fd, at<Work>(L.off_pack), L.n_pack, st);
-        mark();
-        for (auto &kv : L.lat) {               // phase "lattice"
-            if (e != hipSuccess) break;
-            e = launch_lattice(L.fp64, kv.first.first, kv.first.second, fd,
-                               at<Work>(L.off_lat.at(kv.first)), (int)kv.second.size(), st);
-        }
-        mark();
-        if (e == hipSuccess)                   // phase "gamma"
-            e = launch_gamma(L.fp64, fd, at<Work>(L.off_gamma), L.n_gamma, st);
-        mark();
-        if (e == hipSuccess)                   // phase "chain"
-            e = launch_chain(L.fp64, fd, at<int>(L.off_chain), (int)L.chain_plain.size(),
-                             L.chain_lds, st);
-        for (auto &kv : L.chain_ring) {
-            if (e != hipSuccess) break;
-            e = launch_chain_ring(L.fp64, kv.first.first, kv.first.second, fd,
-                                  at<int>(L.off_chain_ring.at(kv.first)),
-                                  (int)kv.second.size(), L.ring_lds.at(kv.first), st);
-        }
-        mark();
-        if (e == hipSuccess)                   // phase "app"
-            e = launch_app(L.fp64, fd, at<Work>(L.off_app), (int)L.app_plain.size(), L.app_lds,
-                           st);
-        for (auto &kv : L.app_tile) {
-            if (e != hipSuccess) break;
-            e = launch_app_tile(L.fp64, std::get<0>(kv.first), std::get<2>(kv.first),
-                                std::get<1>(kv.first), fd, at<Work>(L.off_app_tile.at(kv.first)),
-                                (int)kv.second.size(), L.app_tile_lds.at(kv.first), st);
-        }
-        mark();
-        if (L.grad) {
-            for (auto &kv : L.lat) {           // phase "wgrad"
+        const FrameDesc *fd0 = at<FrameDesc>(L.passes.front().off_fd);
+        mark(kPhPack);
+        e = launch_init(fd0, L.nframes, st);
+        if (e == hipSuccess) e = launch_pack(fd0, at<Work>(L.off_pack), (int)L.pack.size(), st);
+        mark(kPhPack);
+        for (const Pass &P : L.passes) {
+            const FrameDesc *fd = at<FrameDesc>(P.off_fd);
+            for (auto &kv : P.lat) {
                 if (e != hipSuccess) break;
-                const Work *tab = at<Work>(L.off_lat.at(kv.first));
+                e = launch_lattice(L.fp64, kv.first.first, kv.first.second, fd,
+                                   at<Work>(P.off_lat.at(kv.first)), (int)kv.second.size(), st);
+            }
+            mark(kPhLattice);
+            if (e == hipSuccess)
+                e = launch_gamma(L.fp64, fd, at<Work>(P.off_gamma), (int)P.gamma.size(), st);
+            mark(kPhGamma);
+            const int dirs = P.forward ? kDirFwd : kDirBoth;
+            if (e == hipSuccess)
+                e = launch_chain(L.fp64, fd, at<int>(P.off_chain), (int)P.chain_plain.size(), dirs,
+                                 L.chain_lds, st);
+            for (auto &kv : P.chain_ring) {
+                if (e != hipSuccess) break;
+                e = launch_chain_ring(L.fp64, kv.first.first, kv.first.second, fd,
+                                      at<int>(P.off_chain_ring.at(kv.first)),
+                                      (int)kv.second.size(), dirs, L.ring_lds.at(kv.first), st);
+            }
+            mark(kPhChain);
+            if (P.forward) continue;
+            if (e == hipSuccess)
+                e = launch_app(L.fp64, fd, at<Work>(P.off_app), (int)P.app_plain.size(), L.app_lds,
+                               st);
+            for (auto &kv : P.app_tile) {
+                if (e != hipSuccess) break;
+                e = launch_app_tile(L.fp64, std::get<0>(kv.first), std::get<2>(kv.first),
+                                    std::get<1>(kv.first), fd,
+                                    at<Work>(P.off_app_tile.at(kv.first)), (int)kv.second.size(),
+                                    L.app_tile_lds.at(kv.first), st);
+            }
+            mark(kPhApp);
+            if (!L.grad) continue;
+            for (auto &kv : P.lat) {
+                if (e != hipSuccess) break;
+                const Work *tab = at<Work>(P.off_lat.at(kv.first));
                 const int mn = kv.first.first;
                 e = L.fp64 ? adj_f64_w(mn, fd, tab, (int)kv.second.size(), st)
                            : adj_f32_w(mn, fd, tab, (int)kv.second.size(), st);
             }
-            mark();
-            for (auto &kv : L.adj) {           // phase "adjoint"
+            mark(kPhWgrad);
+            for (auto &kv : P.adj) {
                 if (e != hipSuccess) break;
-                const Work *tab = at<Work>(L.off_adj.at(kv.first));
+                const Work *tab = at<Work>(P.off_adj.at(kv.first));
                 const int mn = std::get<0>(kv.first), imode = std::get<1>(kv.first),
                           da = std::get<2>(kv.first);
                 const size_t lds = L.adj_lds.at(kv.first);
@@ -357,13 +472,16 @@ struct mapdec_plan {
                 e = L.fp64 ? adj_f64_lattice(mn, imode, da, fd, tab, nb, lds, st)
                            : adj_f32_lattice(mn, imode, da, fd, tab, nb, lds, st);
             }
-            mark();
-            if (e == hipSuccess) e = launch_dparams(fd, L.nframes, st);   // phase "dparams"
-            mark();
+            mark(kPhAdjoint);
         }
-        if (nphases) *nphases = k - 1;
+        if (L.grad) {
+            if (e == hipSuccess) e = launch_dparams(at<FrameDesc>(L.passes.back().off_fd), L.nframes, st);
+            mark(kPhDparams);
+        }
+        nev = k;
         return e;
     }
+    size_t nev = 0;
 };
 
 extern "C" {
@@ -407,9 +525,10 @@ mapdec_code *mapdec_create(int q, int n, const uint8_t *codebook, double Pi, dou
 
 void mapdec_destroy(mapdec_code *code) { delete code; }
 
-size_t mapdec_workspace_size(const mapdec_frame *frames, int nframes, int precision, int flags) {
+size_t mapdec_workspace_size(const mapdec_frame *frames, int nframes, int precision, int flags,
+                             int checkpoint_K) {
     Layout L;
-    if (build_layout(frames, nframes, precision, flags, L) != MAPDEC_OK) return 0;
+    if (build_layout(frames, nframes, precision, flags, checkpoint_K, L) != MAPDEC_OK) return 0;
     return L.total;
 }
 
@@ -421,16 +540,12 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
         fail(MAPDEC_EINVAL);
         return nullptr;
     }
-    if (checkpoint_K > 0) {   // checkpointed forward metric: not part of this build yet
-        fail(MAPDEC_EUNSUPPORTED);
-        return nullptr;
-    }
     mapdec_plan *p = new (std::nothrow) mapdec_plan;
     if (!p) {
         fail(MAPDEC_ENOMEM);
         return nullptr;
     }
-    int st = build_layout(frames, nframes, precision, flags, p->L);
+    int st = build_layout(frames, nframes, precision, flags, checkpoint_K, p->L);
     if (st == MAPDEC_OK && ws_bytes < p->L.total) st = MAPDEC_ESIZE;
     if (st != MAPDEC_OK) {
         delete p;
@@ -441,64 +556,79 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
     p->ws = static_cast<unsigned char *>(ws);
     p->flags = flags;
 
-    // descriptors, work tables and codewords, staged on the host
+    // descriptors and work tables, staged on the host
     std::vector<unsigned char> stage(L.head, 0);
-    FrameDesc *fd = reinterpret_cast<FrameDesc *>(stage.data() + L.off_fd);
-    Work *pack = reinterpret_cast<Work *>(stage.data() + L.off_pack);
-    Work *gam = reinterpret_cast<Work *>(stage.data() + L.off_gamma);
-    int *chain = reinterpret_cast<int *>(stage.data() + L.off_chain);
-    Work *app = reinterpret_cast<Work *>(stage.data() + L.off_app);
-    int ip = 0, ig = 0;
+    if (!L.pack.empty())
+        std::memcpy(stage.data() + L.off_pack, L.pack.data(), sizeof(Work) * L.pack.size());
     unsigned char *base = p->ws;
-    for (int f = 0; f < nframes; ++f) {
-        const mapdec_frame &fr = frames[f];
-        const mapdec_code *c = fr.code;
-        const FrameLayout &F = L.fl[f];
-        FrameDesc &d = fd[f];
-        d.q = c->q; d.n = c->n; d.N = fr.N; d.rho = fr.rho;
-        d.M = c->M; d.mn = c->mn; d.I = c->I; d.tau = c->n * fr.N;
-        d.Mt = F.Mt; d.Mn = F.Mn; d.sp = F.sp; d.uniform = fr.prior ? 0 : 1;
-        d.nwords = F.nwords; d.imode = frame_imode(c); d.grad = L.grad; d.ck = 0;
-        d.ring_chunk = F.ring_chunk; d.ring_cols = F.ring_cols;
-        const double Pt = 1.0 - c->Pi - c->Pd;
-        d.a = 0.5 * c->Pi; d.d = c->Pd; d.t1 = Pt * (1.0 - c->Ps); d.t0 = Pt * c->Ps;
-        d.Pi = c->Pi; d.Pd = c->Pd; d.Ps = c->Ps;
-        d.lat_blocks = F.lat_blocks;
-        d.adj_da = adjoint_needs_da(c->Pi, c->Pd) ? 1 : 0;
-        d.y = fr.y; d.prior = fr.prior; d.app = fr.app; d.dprior = fr.dprior;
-        d.logp = logp + f; d.status = status + f;
-        d.dparams = dparams ? dparams + 3 * f : nullptr;
-        d.cw = reinterpret_cast<uint32_t *>(base + F.off_cw);
-        d.ybits = reinterpret_cast<uint32_t *>(base + F.off_ybits);
-        d.R = base + F.off_R;
-        d.G = base + F.off_G;
-        d.alpha = reinterpret_cast<double *>(base + F.off_alpha);
-        d.beta = reinterpret_cast<double *>(base + F.off_beta);
-        d.logA = reinterpret_cast<double *>(base + F.off_logA);
-        d.logB = reinterpret_cast<double *>(base + F.off_logB);
-        d.Zinv = L.grad ? reinterpret_cast<double *>(base + F.off_Zinv) : nullptr;
-        d.gacc = reinterpret_cast<double *>(base + F.off_gacc);
-        for (int b = 0; b < F.pack_blocks; ++b) pack[ip++] = Work{f, b * kPackWords};
-        for (int b = 0; b < F.gamma_blocks; ++b) gam[ig++] = Work{f, b};
-
-
+    for (const Pass &P : L.passes) {
+        FrameDesc *fd = reinterpret_cast<FrameDesc *>(stage.data() + P.off_fd);
+        for (int f = 0; f < nframes; ++f) {
+            const mapdec_frame &fr = frames[f];
+            const mapdec_code *c = fr.code;
+            const FrameLayout &F = L.fl[f];
+            FrameDesc &d = fd[f];
+            d.q = c->q; d.n = c->n; d.N = fr.N; d.rho = fr.rho;
+            d.M = c->M; d.mn = c->mn; d.I = c->I; d.tau = c->n * fr.N;
+            d.Mt = F.Mt; d.Mn = F.Mn; d.sp = F.sp; d.uniform = fr.prior ? 0 : 1;
+            d.nwords = F.nwords; d.imode = frame_imode(c); d.grad = L.grad; d.ck = F.K;
+            d.ring_chunk = F.ring_chunk; d.ring_cols = F.ring_cols;
+            const double Pt = 1.0 - c->Pi - c->Pd;
+            d.a = 0.5 * c->Pi; d.d = c->Pd; d.t1 = Pt * (1.0 - c->Ps); d.t0 = Pt * c->Ps;
+            d.Pi = c->Pi; d.Pd = c->Pd; d.Ps = c->Ps;
+            d.adj_da = adjoint_needs_da(c->Pi, c->Pd) ? 1 : 0;
+            d.y = fr.y; d.prior = fr.prior; d.app = fr.app; d.dprior = fr.dprior;
+            d.logp = logp + f; d.status = status + f;
+            d.dparams = dparams ? dparams + 3 * f : nullptr;
+            d.cw = reinterpret_cast<uint32_t *>(base + F.off_cw);
+            d.ybits = reinterpret_cast<uint32_t *>(base + F.off_ybits);
+            d.R = base + F.off_R;
+            d.G = base + F.off_G;
+            d.alpha = reinterpret_cast<double *>(base + F.off_alpha);
+            d.beta = reinterpret_cast<double *>(base + F.off_beta);
+            d.logA = reinterpret_cast<double *>(base + F.off_logA);
+            d.logB = reinterpret_cast<double *>(base + F.off_logB);
+            d.Zinv = L.grad ? reinterpret_cast<double *>(base + F.off_Zinv) : nullptr;
+            d.gacc_all = reinterpret_cast<double *>(base + F.off_gacc);
+            d.gacc_n = F.gacc_n;
+            const int j = std::min(P.seg, F.nseg - 1);
+            const Segment g = segment_of(fr, F, j);
+            d.i0 = g.i0; d.i1 = g.i1; d.s0 = g.s0; d.s1 = g.s1;
+            d.gacc = d.gacc_all + 4 * (size_t)F.gacc_first[j];
+            double *ck = F.nseg > 1 ? reinterpret_cast<double *>(base + F.off_ck) : nullptr;
+            double *bc = F.nseg > 1 ? reinterpret_cast<double *>(base + F.off_bcarry) : nullptr;
+            d.a_init = j > 0 ? ck + (size_t)j * F.Mt : nullptr;
+            if (P.forward) {   // frames without segment P.seg + 1 sit this pass out
+                d.a_fin = P.seg + 1 < F.nseg ? ck + (size_t)(j + 1) * F.Mt : nullptr;
+                d.b_init = nullptr;
+                d.b_fin = nullptr;
+            } else {
+                d.a_fin = nullptr;
+                d.b_init = j + 1 < F.nseg ? bc : nullptr;
+                d.b_fin = j > 0 ? bc : nullptr;
+            }
+        }
+        for (auto &kv : P.lat)
+            std::memcpy(stage.data() + P.off_lat.at(kv.first), kv.second.data(),
+                        sizeof(Work) * kv.second.size());
+        for (auto &kv : P.adj)
+            std::memcpy(stage.data() + P.off_adj.at(kv.first), kv.second.data(),
+                        sizeof(Work) * kv.second.size());
+        if (!P.gamma.empty())
+            std::memcpy(stage.data() + P.off_gamma, P.gamma.data(), sizeof(Work) * P.gamma.size());
+        if (!P.chain_plain.empty())
+            std::memcpy(stage.data() + P.off_chain, P.chain_plain.data(),
+                        sizeof(int) * P.chain_plain.size());
+        for (auto &kv : P.chain_ring)
+            std::memcpy(stage.data() + P.off_chain_ring.at(kv.first), kv.second.data(),
+                        sizeof(int) * kv.second.size());
+        for (auto &kv : P.app_tile)
+            std::memcpy(stage.data() + P.off_app_tile.at(kv.first), kv.second.data(),
+                        sizeof(Work) * kv.second.size());
+        if (!P.app_plain.empty())
+            std::memcpy(stage.data() + P.off_app, P.app_plain.data(),
+                        sizeof(Work) * P.app_plain.size());
     }
-    for (auto &kv : L.lat)
-        std::memcpy(stage.data() + L.off_lat.at(kv.first), kv.second.data(),
-                    sizeof(Work) * kv.second.size());
-    for (auto &kv : L.adj)
-        std::memcpy(stage.data() + L.off_adj.at(kv.first), kv.second.data(),
-                    sizeof(Work) * kv.second.size());
-    if (!L.app_plain.empty())
-        std::memcpy(app, L.app_plain.data(), sizeof(Work) * L.app_plain.size());
-    for (auto &kv : L.app_tile)
-        std::memcpy(stage.data() + L.off_app_tile.at(kv.first), kv.second.data(),
-                    sizeof(Work) * kv.second.size());
-    if (!L.chain_plain.empty())
-        std::memcpy(chain, L.chain_plain.data(), sizeof(int) * L.chain_plain.size());
-    for (auto &kv : L.chain_ring)
-        std::memcpy(stage.data() + L.off_chain_ring.at(kv.first), kv.second.data(),
-                    sizeof(int) * kv.second.size());
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(p->ws, stage.data(), L.head, hipMemcpyHostToDevice, s);
     // codewords go straight into each frame's region
@@ -541,18 +671,17 @@ int mapdec_plan_run(mapdec_plan *p, void *stream) {
 int mapdec_plan_profile(mapdec_plan *p, void *stream, float *phase_ms, int max_phases) {
     if (!p || (max_phases > 0 && !phase_ms)) return -MAPDEC_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipSuccess;
-    if (!p->have_events) {
-        for (int k = 0; k <= kMaxPhases && e == hipSuccess; ++k) e = hipEventCreate(&p->ev[k]);
-        if (e != hipSuccess) return -MAPDEC_EDEVICE;
-        p->have_events = true;
-    }
-    int nph = 0;
-    e = p->enqueue(s, p->ev, &nph);
+    hipError_t e = p->enqueue(s, true);
     p->last_stream = s;
-    if (e == hipSuccess) e = hipEventSynchronize(p->ev[nph]);
-    for (int k = 0; k < nph && k < max_phases && e == hipSuccess; ++k)
-        e = hipEventElapsedTime(&phase_ms[k], p->ev[k], p->ev[k + 1]);
+    const int nph = p->L.grad ? kPhDparams + 1 : kPhApp + 1;
+    for (int k = 0; k < max_phases && k < nph; ++k) phase_ms[k] = 0.f;
+    if (e == hipSuccess && p->nev > 0) e = hipEventSynchronize(p->ev[p->nev - 1]);
+    // the time between consecutive events belongs to the later event's phase
+    for (size_t k = 1; k < p->nev && e == hipSuccess; ++k) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, p->ev[k - 1], p->ev[k]);
+        if (p->ev_phase[k] < max_phases) phase_ms[p->ev_phase[k]] += ms;
+    }
     return e == hipSuccess ? nph : -MAPDEC_EDEVICE;
 }
 
@@ -565,14 +694,9 @@ const char *mapdec_phase_name(int phase) {
 
 void mapdec_plan_destroy(mapdec_plan *p) {
     if (!p) return;
-    if (p->have_events) {
-        hipStreamSynchronize(p->last_stream);
-        for (int k = 0; k <= kMaxPhases; ++k) hipEventDestroy(p->ev[k]);
-    }
-    if (p->exec) {
-        hipStreamSynchronize(p->last_stream);
-        hipGraphExecDestroy(p->exec);
-    }
+    if (!p->ev.empty() || p->exec) hipStreamSynchronize(p->last_stream);
+    for (hipEvent_t x : p->ev) hipEventDestroy(x);
+    if (p->exec) hipGraphExecDestroy(p->exec);
     if (p->graph) hipGraphDestroy(p->graph);
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);
     delete p;

@@ -45,9 +45,21 @@ struct FrameDesc {
     double *logA;         // [N+1] log of the product of forward normalisers
     double *logB;         // [N+1] log of the product of backward normalisers
     double *Zinv;         // [N] 1 / sum_D S_i(D)  (gradient passes)
-    double *gacc;         // [lat_blocks][4] partial d log P / d(a, d, t1, t0)
-    int lat_blocks;       // lattice workgroups of this frame
+    double *gacc;         // [lattice workgroups of this segment][4] partial
+                          // d log P / d(a, d, t1, t0)
+    double *gacc_all;     // every segment's partials of the frame, contiguous
+    int gacc_n;           // number of [4] partials at gacc_all
     int adj_da;           // the adjoint sweep accumulates d/da (else from rho - tau)
+    // Segment of the frame that this descriptor's launches cover (the whole
+    // frame unless the forward metric is checkpointed): symbols [i0, i1),
+    // start indices [s0, s1].  Column c of R and of the uniform Gamma holds
+    // start index s0 + c; row r of alpha / beta (and Gamma_i for general
+    // priors) sits at index r - i0.
+    int i0, i1, s0, s1;
+    const double *a_init; // alpha row i0 ([Mt]) or NULL: the start state (i0 = 0)
+    double *a_fin;        // receives alpha row i1, or NULL
+    const double *b_init; // beta row i1 or NULL: the end state (i1 = N)
+    double *b_fin;        // receives beta row i0, or NULL
 };
 
 // Work-table entry: which frame a workgroup serves and where in it.

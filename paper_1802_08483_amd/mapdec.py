@@ -57,7 +57,7 @@ def lib() -> ctypes.CDLL:
         L.mapdec_create.restype = vp
         L.mapdec_destroy.argtypes = [vp]
         L.mapdec_destroy.restype = None
-        L.mapdec_workspace_size.argtypes = [fp, i32, i32, i32]
+        L.mapdec_workspace_size.argtypes = [fp, i32, i32, i32, i32]
         L.mapdec_workspace_size.restype = sz
         L.mapdec_decode.argtypes = [fp, i32, vp, vp, vp, sz, i32, vp]
         L.mapdec_decode.restype = i32
@@ -134,11 +134,12 @@ class Batch:
     ``frames``: sequence of (code, y, N, prior) with ``y`` a uint8 CUDA tensor
     of 0/1 and ``prior`` an (N, q) CUDA tensor of the batch precision or
     None (uniform).  Allocates the outputs (APP per frame, log P, status,
-    gradient buffers) and the workspace.
+    gradient buffers) and the workspace, sized for forward checkpoints every
+    ``checkpoint_K`` symbols (0: none), which every run of the batch uses.
     """
 
     def __init__(self, frames: Sequence, precision: int = FP32, grad: bool = False,
-                 device=None):
+                 device=None, checkpoint_K: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("libmapdec needs a GPU; no device is visible")
         self.device = torch.device(device or "cuda")
@@ -172,7 +173,9 @@ class Batch:
         self.dparams = (torch.empty((self.nframes, 3), dtype=torch.float64, device=self.device)
                         if grad else None)
         flags = FLAG_GRAD if grad else 0
-        self.ws_bytes = lib().mapdec_workspace_size(self.frames, self.nframes, precision, flags)
+        self.checkpoint_K = int(checkpoint_K)
+        self.ws_bytes = lib().mapdec_workspace_size(self.frames, self.nframes, precision, flags,
+                                                    self.checkpoint_K)
         if self.ws_bytes == 0:
             raise MapdecError(EINVAL, "mapdec_workspace_size")
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
@@ -185,30 +188,30 @@ class Batch:
             raise MapdecError(st, "mapdec_decode")
         return self
 
-    def run_grad(self, checkpoint_K: int = 0, stream=None):
+    def run_grad(self, stream=None):
         if not self.grad:
             raise RuntimeError("batch was built without gradient buffers")
         st = lib().mapdec_grad(self.frames, self.nframes, _ptr(self.logp), _ptr(self.dparams),
-                               _ptr(self.status), _ptr(self.ws), self.ws_bytes, checkpoint_K,
+                               _ptr(self.status), _ptr(self.ws), self.ws_bytes, self.checkpoint_K,
                                self.precision, _stream_handle(stream))
         if st:
             raise MapdecError(st, "mapdec_grad")
         return self
 
-    def plan(self, graph: bool = True, checkpoint_K: int = 0, stream=None) -> "Plan":
-        return Plan(self, graph=graph, checkpoint_K=checkpoint_K, stream=stream)
+    def plan(self, graph: bool = True, stream=None) -> "Plan":
+        return Plan(self, graph=graph, stream=stream)
 
 
 class Plan:
     """A ``mapdec_plan``: the batch's launches recorded once, replayed by run()."""
 
-    def __init__(self, batch: Batch, graph: bool = True, checkpoint_K: int = 0, stream=None):
+    def __init__(self, batch: Batch, graph: bool = True, stream=None):
         self.batch = batch
         flags = (FLAG_GRAPH if graph else 0) | (FLAG_GRAD if batch.grad else 0)
         self._h = lib().mapdec_plan_create(batch.frames, batch.nframes, _ptr(batch.logp),
                                            _ptr(batch.dparams), _ptr(batch.status),
                                            _ptr(batch.ws), batch.ws_bytes, batch.precision,
-                                           flags, checkpoint_K, _stream_handle(stream))
+                                           flags, batch.checkpoint_K, _stream_handle(stream))
         if not self._h:
             raise MapdecError(lib().mapdec_last_error(), "mapdec_plan_create")
 
@@ -250,7 +253,7 @@ def code_for(frame, cache: Optional[dict] = None) -> Code:
 
 
 def batch_from_frames(frames: List, precision: int = FP32, grad: bool = False,
-                      device=None) -> Batch:
+                      device=None, checkpoint_K: int = 0) -> Batch:
     """Uploads workloads.Frame objects and builds a :class:`Batch`."""
     dev = torch.device(device or "cuda")
     dtype = torch.float64 if precision == FP64 else torch.float32
@@ -261,4 +264,4 @@ def batch_from_frames(frames: List, precision: int = FP32, grad: bool = False,
         y = torch.from_numpy(fr.y).to(dev)
         prior = None if fr.prior is None else torch.from_numpy(fr.prior).to(dev, dtype)
         items.append((code, y, fr.N, prior))
-    return Batch(items, precision=precision, grad=grad, device=dev)
+    return Batch(items, precision=precision, grad=grad, device=dev, checkpoint_K=checkpoint_K)

@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol(L):
     assert set(declared) == set(mapdec.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
-    assert L.mapdec_version() == 100
+    assert L.mapdec_version() == 101
     for st in range(8):
         assert L.mapdec_strerror(st)
 
@@ -75,12 +75,13 @@ def _frames(specs):
 def test_workspace_size_and_validation(L):
     c = _code()
     fr = _frames([(c, 10, 30), (c, 5, 17)])
-    ws32 = L.mapdec_workspace_size(fr, 2, mapdec.FP32, 0)
-    ws64 = L.mapdec_workspace_size(fr, 2, mapdec.FP64, 0)
+    ws32 = L.mapdec_workspace_size(fr, 2, mapdec.FP32, 0, 0)
+    ws64 = L.mapdec_workspace_size(fr, 2, mapdec.FP64, 0, 0)
     assert 0 < ws32 < ws64
+    assert L.mapdec_workspace_size(fr, 2, mapdec.FP32, 0, -1) == 0
     # end drift outside [-M, M]
     bad = _frames([(c, 10, 30 + 7)])
-    assert L.mapdec_workspace_size(bad, 1, mapdec.FP32, 0) == 0
+    assert L.mapdec_workspace_size(bad, 1, mapdec.FP32, 0, 0) == 0
     dummy = ctypes.c_void_p(0x1000)
     st = L.mapdec_decode(bad, 1, dummy, dummy, dummy, 1 << 30, mapdec.FP32, None)
     assert st == mapdec.EDRIFT
@@ -93,6 +94,18 @@ def test_workspace_size_and_validation(L):
     noy = (mapdec._Frame * 1)()
     noy[0] = mapdec._Frame(c.handle, 10, 30, None, None, None, None)
     assert L.mapdec_decode(noy, 1, dummy, dummy, dummy, ws32, mapdec.FP32, None) == mapdec.EINVAL
+
+
+def test_checkpointed_workspace_is_smaller(L):
+    # a long frame: segments of K symbols keep O(K) metric rows and one
+    # segment's receiver metric instead of the whole frame's
+    c = _code()
+    fr = _frames([(c, 2000, 6000)])
+    full = L.mapdec_workspace_size(fr, 1, mapdec.FP32, mapdec.FLAG_GRAD, 0)
+    ck = L.mapdec_workspace_size(fr, 1, mapdec.FP32, mapdec.FLAG_GRAD, 45)
+    assert 0 < ck < full / 4
+    # K >= N is a single segment: the same layout as K = 0
+    assert L.mapdec_workspace_size(fr, 1, mapdec.FP32, mapdec.FLAG_GRAD, 2000) == full
 
 
 def test_unsupported_sizes(L):

@@ -1,0 +1,126 @@
+"""Checkpointed forward metric (segments of K symbols, receiver metric, Gamma
+and forward rows recomputed per segment in the backward pass) against the
+unsegmented GPU path and against the FP64 oracle.
+
+Bars: against the oracle as in the decode and gradient tests (FP64 APP
+<= 1e-12, log P <= 1e-12, gradient <= 1e-9; FP32 APP <= 1e-5, log P <= 1e-6,
+gradient <= 1e-4).  Against the unsegmented GPU run the arithmetic per
+metric row is the same and only summation orders change, so FP64 agrees to
+1e-11 and FP32 to 1e-5 (APP) / 1e-6 (log P) / 1e-4 (gradient).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1802_08483_amd import mapdec
+from paper_1802_08483_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+ORACLE_TOL = {mapdec.FP64: (1e-12, 1e-12, 1e-9), mapdec.FP32: (1e-5, 1e-6, 1e-4)}
+SELF_TOL = {mapdec.FP64: (1e-11, 1e-11, 1e-9), mapdec.FP32: (1e-5, 1e-6, 1e-4)}
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _run(frames, prec, K, grad=True, graph=False):
+    b = mapdec.batch_from_frames(frames, precision=prec, grad=grad, checkpoint_K=K)
+    if graph:
+        p = b.plan(graph=True)
+        p.run()
+        b._plan = p
+    elif grad:
+        b.run_grad()
+    else:
+        b.decode()
+    torch.cuda.synchronize()
+    return b
+
+
+def _compare(b, f, app_ref, logp_ref, dparams_ref, dprior_ref, tol, label):
+    t_app, t_lp, t_g = tol
+    assert int(b.status[f]) == 0, label
+    app = b.apps[f].double().cpu().numpy()
+    assert float(np.abs(app - app_ref).max()) <= t_app, f"{label}: APP"
+    lp = float(b.logp[f])
+    assert abs(lp - logp_ref) <= t_lp * max(1.0, abs(logp_ref)), f"{label}: logP {lp} {logp_ref}"
+    if dparams_ref is not None:
+        gp = b.dparams[f].cpu().numpy()
+        assert _rel(gp, dparams_ref) <= t_g, f"{label}: dparams {gp} vs {dparams_ref}"
+        dpr = b.dpriors[f].double().cpu().numpy()
+        assert _rel(dpr, dprior_ref) <= t_g, f"{label}: dprior"
+
+
+def _frames():
+    specs = [
+        # seed, q, n, N, Pi, Pd, Ps, I, M, mn, prior
+        (61, 4, 3, 47, 0.06, 0.05, 0.03, 2, 12, 3, True),
+        (62, 8, 6, 61, 0.04, 0.04, 0.01, 2, 16, 4, False),
+        (63, 16, 10, 29, 0.05, 0.05, 0.02, 2, 20, 6, True),
+        (64, 2, 4, 83, 0.03, 0.02, 0.00, 1, 14, 2, False),
+        (65, 8, 5, 40, 0.05, 0.06, 0.05, 3, 14, 4, True),     # general insertion cap
+        (66, 4, 5, 50, 0.10, 0.10, 0.00, 2, 300, 6, False),   # 601 drift states
+        (67, 2, 6, 35, 0.004, 0.05, 0.00, 2, 18, 4, False),   # Pi << Pd: the d/da sweep
+    ]
+    return [wl.random_frame(s, q, n, N, Pi, Pd, Ps, I, M, mn, with_prior=pr)
+            for (s, q, n, N, Pi, Pd, Ps, I, M, mn, pr) in specs]
+
+
+@pytest.mark.parametrize("prec", [mapdec.FP64, mapdec.FP32])
+def test_checkpointed_grad_matches_oracle(prec):
+    frames = _frames()
+    refs = [oracle.decode_frame(fr, grad=True) for fr in frames]
+    # K = 7: every frame has a ragged last segment; K = 1: one symbol per segment
+    for K in (7, 1):
+        b = _run(frames, prec, K)
+        for f, (fr, ref) in enumerate(zip(frames, refs)):
+            _compare(b, f, ref["app"], ref["logp"], ref["dparams"], ref["dprior"],
+                     ORACLE_TOL[prec], f"K={K} frame {f} N={fr.N} M={fr.M}")
+
+
+@pytest.mark.parametrize("prec", [mapdec.FP64, mapdec.FP32])
+def test_checkpointed_equals_unsegmented(prec):
+    frames = _frames()
+    full = _run(frames, prec, 0)
+    for K in (5, 16, 34):
+        b = _run(frames, prec, K)
+        for f in range(len(frames)):
+            _compare(b, f, full.apps[f].double().cpu().numpy(), float(full.logp[f]),
+                     full.dparams[f].cpu().numpy(), full.dpriors[f].double().cpu().numpy(),
+                     SELF_TOL[prec], f"K={K} frame {f}")
+
+
+def test_checkpointed_decode_only_and_graph_replay():
+    frames = _frames()[:4]
+    refs = [oracle.decode_frame(fr) for fr in frames]
+    b = _run(frames, mapdec.FP32, 9, grad=False, graph=True)
+    for rep in range(3):
+        b.logp.fill_(0)
+        for a in b.apps:
+            a.fill_(-1)
+        b._plan.run()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+        for f, (fr, ref) in enumerate(zip(frames, refs)):
+            _compare(b, f, ref["app"], ref["logp"], None, None, ORACLE_TOL[mapdec.FP32],
+                     f"replay {rep} frame {f}")
+    b._plan.close()
+
+
+def test_long_frame_workload_shape_reduced():
+    # the long-frame workload's code and channel (q=64, n=12, Pi=Pd=0.1,
+    # Ps=0, I=2, mn=8) on frames short enough for the oracle, with
+    # K = ceil(sqrt(N)) as in the memory-bounded configuration
+    N = 150
+    M = wl.drift_limit(12 * N, 0.1)
+    frames = [wl.random_frame(70 + f, 64, 12, N, 0.1, 0.1, 0.0, 2, M, 8) for f in range(2)]
+    K = int(np.ceil(np.sqrt(N)))
+    b = _run(frames, mapdec.FP32, K)
+    for f, fr in enumerate(frames):
+        ref = oracle.decode_frame(fr, grad=True)
+        _compare(b, f, ref["app"], ref["logp"], ref["dparams"], ref["dprior"],
+                 ORACLE_TOL[mapdec.FP32], f"long-frame shape frame {f} K={K}")

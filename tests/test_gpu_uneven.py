@@ -1,0 +1,68 @@
+"""The uneven batch: 4096 frames with q in {2, 8, 16}, n in [4, 10],
+N in [50, 2000] and Pi = Pd log-uniform in [1e-3, 1e-1], decoded in FP32
+by one plan replayed as one HIP graph.
+
+Checks: every frame decodes (status OK, finite log P, APP rows sum to 1
+within 1e-5), and sampled frames (the two cheapest, a median one, the one
+with the widest drift range and a spread of others) match the FP64 oracle
+within the FP32 bars (APP max abs <= 1e-5, relative log P <= 1e-6).  The
+gradient path runs on a 512-frame slice with the oracle gradient on sampled
+frames (relative <= 1e-4).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1802_08483_amd import mapdec
+from paper_1802_08483_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _sample(frames):
+    cost = np.array([f.N * (2 * f.M + 1) * (2 * f.mn + 1) * f.q for f in frames])
+    order = np.argsort(cost, kind="stable")
+    pick = {int(order[0]), int(order[1]), int(order[len(order) // 2]),
+            int(np.argmax([f.M for f in frames]))}
+    pick |= {int(x) for x in order[:: max(1, len(order) // 6)][:6]}
+    return sorted(pick)
+
+
+def test_uneven_batch_one_graph():
+    frames = wl.make_workload(3)
+    b = mapdec.batch_from_frames(frames, precision=mapdec.FP32)
+    plan = b.plan(graph=True)
+    plan.run()
+    torch.cuda.synchronize()
+    st = b.status.cpu().numpy()
+    assert (st == 0).all(), f"{int((st != 0).sum())} frames without a path"
+    assert np.isfinite(b.logp.cpu().numpy()).all()
+    worst = max(float((a.double().sum(1) - 1).abs().max()) for a in b.apps)
+    assert worst < 1e-5, worst
+    for f in _sample(frames):
+        fr = frames[f]
+        ref = oracle.decode_frame(fr)
+        app = b.apps[f].double().cpu().numpy()
+        assert float(np.abs(app - ref["app"]).max()) <= 1e-5, f"frame {f}"
+        lp = float(b.logp[f])
+        assert abs(lp - ref["logp"]) <= 1e-6 * max(1.0, abs(ref["logp"])), f"frame {f}"
+    plan.close()
+
+
+def test_uneven_batch_gradient_slice():
+    frames = wl.make_workload(3, nframes=512)
+    b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True)
+    b.run_grad()
+    torch.cuda.synchronize()
+    assert (b.status.cpu().numpy() == 0).all()
+    assert np.isfinite(b.dparams.cpu().numpy()).all()
+    for f in _sample(frames)[:5]:
+        ref = oracle.decode_frame(frames[f], grad=True)
+        assert _rel(b.dparams[f].cpu().numpy(), ref["dparams"]) <= 1e-4, f"frame {f}"
+        assert _rel(b.dpriors[f].double().cpu().numpy(), ref["dprior"]) <= 1e-4, f"frame {f}"
