@@ -43,7 +43,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 class _Out(ctypes.Structure):
     _fields_ = [("app", _dp), ("logp", _dp), ("dparams", _dp), ("dprior", _dp),
-                ("alpha", _dp), ("beta", _dp), ("logA", _dp), ("logB", _dp), ("Z", _dp)]
+                ("alpha", _dp), ("beta", _dp), ("logA", _dp), ("logB", _dp), ("logZ", _dp)]
 
 
 _lib = None
@@ -95,7 +95,7 @@ def decode(codebook, y, N, Pi, Pd, Ps, I, M, mn, prior=None, *, grad=False,
     """Run the oracle on one frame.  Returns a dict with ``status``, ``logp``,
     ``app`` (N, q) and, on request, ``dparams`` (3,), ``dprior`` (N, q) and
     the trace arrays ``alpha``, ``beta`` ((N+1), 2M+1), ``logA``, ``logB``,
-    ``Z``."""
+    ``logZ``."""
     c, cb = _code(codebook, Pi, Pd, Ps, I, M, mn)
     q = c.q
     yb = np.ascontiguousarray(y, dtype=np.uint8)
@@ -110,9 +110,9 @@ def decode(codebook, y, N, Pi, Pd, Ps, I, M, mn, prior=None, *, grad=False,
         res["beta"] = np.zeros((N + 1, Mt))
         res["logA"] = np.zeros(N + 1)
         res["logB"] = np.zeros(N + 1)
-        res["Z"] = np.zeros(N)
+        res["logZ"] = np.zeros(N)
     out = _Out(*[_ptr(res.get(k), ctypes.c_double) for k in
-                 ("app", "logp", "dparams", "dprior", "alpha", "beta", "logA", "logB", "Z")])
+                 ("app", "logp", "dparams", "dprior", "alpha", "beta", "logA", "logB", "logZ")])
     st = lib().mapdec_ref_run(ctypes.byref(c), int(N), int(yb.shape[0]),
                               _ptr(yb, ctypes.c_uint8) if yb.size else None,
                               _ptr(pr, ctypes.c_double), int(bool(literal)), ctypes.byref(out))

@@ -19,6 +19,15 @@
  *   7. APP by eqs. 1-3, each row normalised by its own sum;
  *   8. gradient of log P(y) by forward-mode tangents through the lattice.
  *
+ * Every quantity is FP64 except the products of a forward and a backward
+ * metric row in steps 7-8 and their sums, which are long double: on long
+ * frames with uninformative priors the normalised alpha_i and beta_{i+1}
+ * rows peak at opposite ends of the drift range, and their product at the
+ * drifts that carry the posterior can lie below the FP64 range (about
+ * 1e-420 on 120 000-bit frames at Pi = Pd = 0.1), although each factor is
+ * representable.  The extended exponent range keeps those products exact
+ * to FP64 precision.
+ *
  * Readings where the paper is silent (each one is listed with the design
  * notes):
  *   - I caps the number of consecutive insertions at one channel time step,
@@ -291,8 +300,8 @@ int mapdec_ref_run(const ref_code *c, int N, int rho, const uint8_t *y,
     double *beta = calloc((size_t)(N + 1) * Mt, sizeof(double));
     double *logA = calloc((size_t)N + 1, sizeof(double));
     double *logB = calloc((size_t)N + 1, sizeof(double));
-    double *S = calloc((size_t)q, sizeof(double));
-    double *U = calloc((size_t)q, sizeof(double));
+    long double *S = calloc((size_t)q, sizeof(long double));
+    long double *U = calloc((size_t)q, sizeof(long double));
     double *acc = calloc((size_t)Mt, sizeof(double));
     if (!alpha || !beta || !logA || !logB || !S || !U || !acc) { st = REF_ENOMEM; goto done; }
 
@@ -387,9 +396,9 @@ int mapdec_ref_run(const ref_code *c, int N, int rho, const uint8_t *y,
      * d log P / d prior_i(D) = sum alpha R beta / Z_i;
      * d log P / d w = sum_i sum alpha prior dR/dw beta / Z_i. */
     {
-        double g[4] = {0, 0, 0, 0};
+        long double g[4] = {0, 0, 0, 0};
         for (int i = 0; i < N; i++) {
-            double gi[4] = {0, 0, 0, 0};
+            long double gi[4] = {0, 0, 0, 0};
             for (int D = 0; D < q; D++) { S[D] = 0.0; U[D] = 0.0; }
             for (int mp = -M; mp <= M; mp++) {
                 for (int D = 0; D < q; D++) {
@@ -400,9 +409,9 @@ int mapdec_ref_run(const ref_code *c, int N, int rho, const uint8_t *y,
                     for (int delta = -mn; delta <= mn; delta++) {
                         int m = mp + delta;
                         if (m < -M || m > M) continue;
-                        double ab = ALPHA(i, mp) * BETA(i + 1, m);
+                        long double ab = (long double)ALPHA(i, mp) * BETA(i + 1, m);
                         double gamma = prior_of(&dc, i, D) * R[delta + mn];
-                        S[D] += ALPHA(i, mp) * gamma * BETA(i + 1, m);
+                        S[D] += ab * gamma;
                         U[D] += ab * R[delta + mn];
                         if (tangents)
                             for (int t = 0; t < 4; t++)
@@ -410,22 +419,22 @@ int mapdec_ref_run(const ref_code *c, int N, int rho, const uint8_t *y,
                     }
                 }
             }
-            double Zi = 0.0;
+            long double Zi = 0.0L;
             for (int D = 0; D < q; D++) Zi += S[D];
-            if (!(Zi > 0.0)) { st = REF_ENOPATH; goto done; }
-            if (out->Z) out->Z[i] = Zi;
+            if (!(Zi > 0.0L)) { st = REF_ENOPATH; goto done; }
+            if (out->logZ) out->logZ[i] = (double)logl(Zi);
             for (int D = 0; D < q; D++) {
-                if (out->app) out->app[(size_t)i * q + D] = S[D] / Zi;
-                if (out->dprior) out->dprior[(size_t)i * q + D] = U[D] / Zi;
+                if (out->app) out->app[(size_t)i * q + D] = (double)(S[D] / Zi);
+                if (out->dprior) out->dprior[(size_t)i * q + D] = (double)(U[D] / Zi);
             }
             for (int t = 0; t < 4; t++) g[t] += gi[t] / Zi;
         }
         if (out->dparams) {
             /* chain rule: a = Pi/2, d = Pd, t1 = (1-Pi-Pd)(1-Ps), t0 = (1-Pi-Pd)Ps */
             double Ps = c->Ps, Pt = 1.0 - c->Pi - c->Pd;
-            out->dparams[0] = 0.5 * g[0] - (1.0 - Ps) * g[2] - Ps * g[3];
-            out->dparams[1] = g[1] - (1.0 - Ps) * g[2] - Ps * g[3];
-            out->dparams[2] = -Pt * g[2] + Pt * g[3];
+            out->dparams[0] = (double)(0.5L * g[0] - (1.0L - Ps) * g[2] - Ps * g[3]);
+            out->dparams[1] = (double)(g[1] - (1.0L - Ps) * g[2] - Ps * g[3]);
+            out->dparams[2] = (double)(-Pt * g[2] + Pt * g[3]);
         }
     }
     if (out->alpha) memcpy(out->alpha, alpha, sizeof(double) * (size_t)(N + 1) * Mt);

@@ -48,7 +48,8 @@ typedef struct {
     double *beta;     /* (N+1)*(2M+1) normalised backward metric [i][m+M]    */
     double *logA;     /* N+1   log of the product of alpha normalisers        */
     double *logB;     /* N+1   log of the product of beta normalisers         */
-    double *Z;        /* N     sum over D of the unnormalised APP row         */
+    double *logZ;     /* N     log of the sum over D of the unnormalised APP
+                       *       row alpha_i gamma_i beta_{i+1} (normalised rows)  */
 } ref_out;
 
 /* Check code parameters; returns REF_OK or REF_EINVAL. */

@@ -5,7 +5,8 @@ model, closed forms or exact enumeration, never from the oracle itself.
   P2  total mass of the truncated channel: sum_y P(y) = (1 - Pi^(I+1))^tau
   P3  memoryless substitution channel (Pi = Pd = 0) closed form
   P4  Pi = Pd = 0, Ps = 1/2: output carries no information
-  P5  APP rows sum to 1; sum_m alpha_i beta_i gives P(y) at every i
+  P5  APP rows sum to 1; sum_m alpha_i beta_i gives P(y) at every i, also
+      where the product of the two rows lies below the FP64 range
   P6  limits: I >= 2 mn never binds; P(y) nondecreasing in I, M, mn
   P7  hand-derived lattice values for n = 1
   P8  complementing y and every codeword changes nothing
@@ -157,6 +158,25 @@ def test_p5_invariants(k):
 
 
 # ---- P6 --------------------------------------------------------------------
+
+def test_p5_products_below_fp64_range():
+    # a long, noisy frame (q=4, n=4, N=5000, Pi=Pd=0.1, M=900): the
+    # normalised forward and backward rows peak at opposite ends of the
+    # drift range and max_m alpha_i(m) beta_i(m) falls below 1e-308 mid-
+    # frame; the invariants must still hold at every i (evaluated in
+    # extended precision)
+    fr = wl.random_frame(913, 4, 4, 5000, 0.1, 0.1, 0.0, 2, 900, 5)
+    r = oracle.decode_frame(fr, trace=True)
+    A = r["alpha"].astype(np.longdouble)
+    B = r["beta"].astype(np.longdouble)
+    ab = (A * B).sum(1)
+    assert float(ab.min()) < 1e-308          # the case this pin is for
+    lam = np.log(ab).astype(np.float64) + r["logA"] + r["logB"]
+    np.testing.assert_allclose(lam, r["logp"], rtol=1e-12, atol=0)
+    lz = r["logZ"] + r["logA"][:-1] + r["logB"][1:]
+    np.testing.assert_allclose(lz, r["logp"], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(r["app"].sum(1), 1.0, rtol=0, atol=1e-12)
+
 
 def test_p6_insertion_cap_and_monotonicity():
     fr = wl.random_frame(3, 4, 5, 20, 0.08, 0.08, 0.02, 2, 12, 3)
