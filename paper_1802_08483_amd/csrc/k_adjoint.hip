@@ -33,7 +33,10 @@ namespace mapdec {
 // W(s, D, delta): lane = start index s; the 64 lanes of a workgroup take
 // consecutive s, so the symbols i whose drift band reaches the wave form one
 // wave-uniform range and every alpha / beta load is a coalesced row segment.
-// Products and sums are FP64 (the metric rows are FP64); W is stored in T.
+// Products and sums are FP64 (the metric rows are FP64), each product
+// alpha_i beta_{i+1} / Z_i formed from mantissas and exponent sums with the
+// APP's per-symbol scale 2^-Zexp[i], which keeps it inside the FP64 range
+// where the plain product of the two rows would not be; W is stored in T.
 // Uniform priors give W independent of D (one [Mn][sp] table, written over
 // Gamma); general priors give [q][Mn][sp] (written over R, which the APP no
 // longer needs), computed in chunks of kWadjDC symbol values.
@@ -53,6 +56,7 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
     const gptr<const double> A = to_global((const double *)f.alpha);
     const gptr<const double> B = to_global((const double *)f.beta);
     const gptr<const double> Zi = to_global((const double *)f.Zinv);
+    const gptr<const int> Ze = to_global((const int *)f.Zexp);
     const size_t sp = (size_t)f.sp;
     // symbols of the segment whose band [n i - M, n i + M] meets [sa, sa + 63]
     const int ilo = max(f.i0, sa - M <= 0 ? 0 : (sa - M + n - 1) / n);
@@ -61,17 +65,22 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
     // Every load is issued (addresses clamped into the row, out-of-band values
     // multiplied by 0), so the compiler cannot turn them into one branch and
     // one wait per load.
-    auto term = [&](int i, double &av, double (&bv)[KW]) {
+    // term = ldexp(av bv[k], ae + be[k]) with av, bv[k] mantissas
+    auto term = [&](int i, double &av, int &ae, double (&bv)[KW], int (&be)[KW]) {
         const int mp = s - n * i;
         const double in = (live && mp >= -M && mp <= M) ? 1.0 : 0.0;
         const int mc = min(max(mp, -M), M);
-        av = A[(size_t)(i - ib) * Mt + mc + M] * Zi[i] * in;
+        int ea;
+        av = frexp(A[(size_t)(i - ib) * Mt + mc + M], &ea) * Zi[i] * in;
+        ae = ea - Ze[i];
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int m = mp + k - MN;
             const int cm = min(max(m, -M), M);
-            const double b = B[(size_t)(i + 1 - ib) * Mt + cm + M];
+            int eb;
+            const double b = frexp(B[(size_t)(i + 1 - ib) * Mt + cm + M], &eb);
             bv[k] = b * ((m >= -M && m <= M) ? 1.0 : 0.0);
+            be[k] = eb;
         }
     };
     if (f.uniform) {
@@ -81,9 +90,10 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
 #pragma unroll 2
         for (int i = ilo; i <= ihi; ++i) {
             double av, bv[KW];
-            term(i, av, bv);
+            int ae, be[KW];
+            term(i, av, ae, bv, be);
 #pragma unroll
-            for (int k = 0; k < KW; ++k) acc[k] += av * bv[k];
+            for (int k = 0; k < KW; ++k) acc[k] += ldexp(av * bv[k], ae + be[k]);
         }
         if (!live) return;
         const gptr<T> W = to_global((T *)f.G);
@@ -101,13 +111,17 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
                 for (int k = 0; k < KW; ++k) acc[c][k] = 0.0;
             for (int i = ilo; i <= ihi; ++i) {
                 double av, bv[KW];
-                term(i, av, bv);
+                int ae, be[KW];
+                term(i, av, ae, bv, be);
+                double pb[KW];
+#pragma unroll
+                for (int k = 0; k < KW; ++k) pb[k] = ldexp(av * bv[k], ae + be[k]);
 #pragma unroll
                 for (int c = 0; c < kWadjDC; ++c) {
                     const int D = min(D0 + c, q - 1);
-                    const double pa = (double)pr[(size_t)i * q + D] * av;
+                    const double pa = (double)pr[(size_t)i * q + D];
 #pragma unroll
-                    for (int k = 0; k < KW; ++k) acc[c][k] += pa * bv[k];
+                    for (int k = 0; k < KW; ++k) acc[c][k] += pa * pb[k];
                 }
             }
             if (!live) continue;

@@ -1,6 +1,8 @@
 // APP kernel (eqs. 1-3).
 #include "device_common.h"
 
+#include <climits>
+
 namespace mapdec {
 
 // ---------------------------------------------------------------------------
@@ -8,6 +10,10 @@ namespace mapdec {
 //   U_i(D) = sum_{m', delta} alpha_i(m') R(n i + m', D, delta) beta_{i+1}(m' + delta)
 //   S_i(D) = prior_i(D) U_i(D),  Z_i = sum_D S_i(D),  APP = S / Z,
 //   d log P / d prior_i(D) = U_i(D) / Z_i.
+// The row products alpha beta are formed from mantissas and exponent sums
+// and scaled by 2^-E_i, E_i the largest exponent sum of the symbol: the
+// two rows can peak at opposite ends of the drift range, with their product
+// at the posterior's drifts below the FP64 range.
 
 constexpr int kAppChunk = 16;
 
@@ -37,6 +43,16 @@ __global__ __launch_bounds__(kAppThreads) void k_app(const FrameDesc *__restrict
         be[mn + Mt + j] = 0.0;
     }
     __syncthreads();
+    // E_i = max over m', delta of the exponent sum of alpha(m') beta(m' + delta)
+    int emax = INT_MIN / 2;
+    for (int mi = tid; mi < Mt; mi += kAppThreads) {
+        if (!(al[mi] > 0.0)) continue;
+        int eb = INT_MIN / 2;
+        for (int k = 0; k < Mn; ++k)
+            if (be[mi + k] > 0.0) eb = max(eb, ilogb(be[mi + k]));
+        if (eb > INT_MIN / 2) emax = max(emax, ilogb(al[mi]) + eb);
+    }
+    for (int off = 32; off >= 1; off >>= 1) emax = max(emax, __shfl_xor(emax, off, 64));
 
     const T *R = (const T *)f.R;
     const size_t sp = (size_t)f.sp;
@@ -48,14 +64,22 @@ __global__ __launch_bounds__(kAppThreads) void k_app(const FrameDesc *__restrict
             const int s = n * i + mi - M;
             if (s < 0 || s > rho) continue;
             const double av = al[mi];
-            if (av == 0.0) continue;
+            if (!(av > 0.0)) continue;
+            // 2^-E alpha(m') beta(m' + delta), delta = k - mn
+            double ab[2 * kMaxMn + 1];
+            const int ea = ilogb(av);
+            const double fa = scalbn(av, -ea);
+            for (int k = 0; k < Mn; ++k) {
+                const double b = be[mi + k];
+                ab[k] = b > 0.0 ? scalbn(fa * scalbn(b, -ilogb(b)), ea + ilogb(b) - emax) : 0.0;
+            }
 #pragma unroll
             for (int e = 0; e < kAppChunk; ++e) {
                 if (dc + e < q) {
                     const T *Rp = R + (size_t)(dc + e) * Mn * sp + (s - s0);
                     double t = 0.0;
-                    for (int k = 0; k < Mn; ++k) t += (double)Rp[(size_t)k * sp] * be[mi + k];
-                    acc[e] += av * t;
+                    for (int k = 0; k < Mn; ++k) t += (double)Rp[(size_t)k * sp] * ab[k];
+                    acc[e] += t;
                 }
             }
         }
@@ -75,7 +99,10 @@ __global__ __launch_bounds__(kAppThreads) void k_app(const FrameDesc *__restrict
         if (f.app) ((T *)f.app)[(size_t)i * q + tid] = (T)(S / Z);
         if (f.dprior) ((T *)f.dprior)[(size_t)i * q + tid] = (T)(u / Z);
     }
-    if (f.Zinv && tid == 0) f.Zinv[i] = 1.0 / Z;
+    if (f.Zinv && tid == 0) {
+        f.Zinv[i] = 1.0 / Z;
+        f.Zexp[i] = emax;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -12,9 +12,10 @@
 //   K_i(s, k) = alpha_i(s - n i) beta_{i+1}(s - n i + k - mn),
 // streaming over k: per k the TI products K_i are formed once (FP64, then
 // the batch precision) and each of the TD loaded R values feeds TI fused
-// multiply-adds.  FP64 alpha and beta rows are staged in LDS with zero padding
-// wide enough that no lane branches on the band edges (states outside the
-// band, and start indices outside [0, rho], have zero metrics).  R is read
+// multiply-adds.  The FP64 alpha and beta rows are staged in LDS as
+// (mantissa, exponent) pairs with zero padding wide enough that no lane
+// branches on the band edges (states outside the band, and start indices
+// outside [0, rho], have zero metrics).  R is read
 // through a buffer descriptor with the D row offset in a scalar register and
 // one vector add per k, so the loads cost almost no vector instructions (and
 // the descriptor's size bounds every access).  The TI x TD accumulators
@@ -58,6 +59,34 @@ struct ReduceScatter {
 template <int V>
 constexpr int log2_of() { return V <= 1 ? 0 : 1 + log2_of<V / 2>(); }
 
+// A metric value as mantissa (in [1/2, 1), batch precision) and binary
+// exponent.  The two normalised rows of a symbol can peak at opposite ends
+// of the drift range, so that their product at the drifts carrying the
+// posterior lies below even the FP64 range while each factor is well
+// inside it; products are therefore formed from mantissas and exponent
+// sums, scaled by the symbol's largest exponent sum.
+template <typename T>
+struct alignas(2 * sizeof(T) > 8 ? 16 : 8) ME {
+    T m;
+    int e;
+};
+constexpr int kZeroExp = -(1 << 20);   // exponent of a zero metric
+template <typename T>
+__device__ __forceinline__ ME<T> to_me(double v) {
+    ME<T> r;
+    if (v > 0.0) {
+        int e;
+        r.m = (T)frexp(v, &e);
+        r.e = e;
+    } else {
+        r.m = T(0);
+        r.e = kZeroExp;
+    }
+    return r;
+}
+__device__ __forceinline__ float scale2(float x, int e) { return ldexpf(x, e); }
+__device__ __forceinline__ double scale2(double x, int e) { return ldexp(x, e); }
+
 template <typename T>
 __device__ __forceinline__ T rload(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
     if constexpr (sizeof(T) == 4) {
@@ -85,41 +114,38 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
     const int WA = Mt + 2 * PAD, WB = Mt + 2 * (PAD + MN);
     const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6;
     const int nwaves = nth >> 6;
-    double *ar = (double *)smem;   // [TI][WA]  sc_i alpha_i(m) at m + M + PAD
-    double *br = ar + TI * WA;     // [TI][WB]  beta_{i+1}(m) at m + M + PAD + mn
-    double *Zsh = br + TI * WB;    // [TI]
-    unsigned long long *smax = (unsigned long long *)(Zsh + TI);   // [TI]
-    T *Ush = (T *)(smax + TI);     // [TI][q]
+    ME<T> *ar = (ME<T> *)smem;     // [TI][WA]  alpha_i(m) at m + M + PAD
+    ME<T> *br = ar + TI * WA;      // [TI][WB]  beta_{i+1}(m) at m + M + PAD + mn
+    double *Zsh = (double *)(br + TI * WB);   // [TI]
+    T *Ush = (T *)(Zsh + TI);      // [TI][q]
     T *part = Ush + TI * q;        // [nwaves][V] per-wave sums
+    int *emax = (int *)(part + nwaves * V);   // [TI]
     const gptr<const double> A = to_global((const double *)f.alpha);
     const gptr<const double> B = to_global((const double *)f.beta);
-    if (tid < TI) smax[tid] = 0ull;
+    if (tid < TI) emax[tid] = 2 * kZeroExp;
     for (int j = tid; j < TI * WA; j += nth) {
         const int ii = j / WA, m = j - ii * WA - PAD, i = i0 + ii;
-        ar[j] = (i < N && m >= 0 && m < Mt) ? A[(size_t)(i - ib) * Mt + m] : 0.0;
+        ar[j] = to_me<T>((i < N && m >= 0 && m < Mt) ? A[(size_t)(i - ib) * Mt + m] : 0.0);
     }
     for (int j = tid; j < TI * WB; j += nth) {
         const int ii = j / WB, m = j - ii * WB - PAD - MN, i = i0 + ii;
-        br[j] = (i < N && m >= 0 && m < Mt) ? B[(size_t)(i + 1 - ib) * Mt + m] : 0.0;
+        br[j] = to_me<T>((i < N && m >= 0 && m < Mt) ? B[(size_t)(i + 1 - ib) * Mt + m] : 0.0);
     }
     __syncthreads();
-    // Two-slice scale: the rows' product alpha_i(m') beta_{i+1}(m'+delta)
-    // spans far less than either row, so dividing it by its maximum brings
-    // it into the FP32 range; the scale is folded into the staged alpha row.
-    // (Max of non-negative doubles through their bit patterns.)
+    // Two-slice scale: the product alpha_i(m') beta_{i+1}(m'+delta) spans
+    // far less than either row; E_i = max over m', delta of the exponent
+    // sum, and every product is taken as 2^-E_i times its true value.
     for (int j = tid; j < TI * Mt; j += nth) {
         const int ii = j / Mt, m = j - ii * Mt;
-        double bm = 0.0;
+        const ME<T> a = ar[ii * WA + PAD + m];
+        if (a.m == T(0)) continue;
+        int eb = 2 * kZeroExp;
 #pragma unroll
-        for (int k = 0; k < Mn; ++k) bm = fmax(bm, br[ii * WB + PAD + m + k]);
-        const double v = ar[ii * WA + PAD + m] * bm;
-        if (v > 0.0) atomicMax(&smax[ii], (unsigned long long)__double_as_longlong(v));
-    }
-    __syncthreads();
-    for (int j = tid; j < TI * WA; j += nth) {
-        const int ii = j / WA;
-        const double mx = __longlong_as_double((long long)smax[ii]);
-        ar[j] = mx > 0.0 ? ar[j] / mx : 0.0;
+        for (int k = 0; k < Mn; ++k) {
+            const ME<T> b = br[ii * WB + PAD + m + k];
+            if (b.m != T(0)) eb = max(eb, b.e);
+        }
+        if (eb > 2 * kZeroExp) atomicMax(&emax[ii], a.e + eb);
     }
     __syncthreads();
 
@@ -160,11 +186,16 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
     for (int j = 0; j < total; ++j) {
         const int c = 64 * (wv + (j % nmy) * nwaves) + lane;
         const int cc = min(c, span - 1);
-        const double live = c < span ? 1.0 : 0.0;
-        double a[TI];
+        const bool live = c < span;
+        T am[TI];
+        int ae[TI];
 #pragma unroll
-        for (int ii = 0; ii < TI; ++ii) a[ii] = live * ar[ii * WA + PAD + cc - n * ii];
-        const double *bb = br + PAD + cc;
+        for (int ii = 0; ii < TI; ++ii) {
+            const ME<T> x = ar[ii * WA + PAD + cc - n * ii];
+            am[ii] = live ? x.m : T(0);
+            ae[ii] = x.e - emax[ii];
+        }
+        const ME<T> *bb = br + PAD + cc;
         const int jn = min(j + 1, total - 1);   // a repeated load past the end is harmless
 #pragma unroll
         for (int k = 0; k < Mn; ++k) {
@@ -175,7 +206,10 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
                 load_k(r[(k + PF) % (PF + 1)], jn, k + PF - Mn);
             T kv[TI];
 #pragma unroll
-            for (int ii = 0; ii < TI; ++ii) kv[ii] = (T)(a[ii] * bb[ii * (WB - n) + k]);
+            for (int ii = 0; ii < TI; ++ii) {
+                const ME<T> b = bb[ii * (WB - n) + k];
+                kv[ii] = scale2(am[ii] * b.m, ae[ii] + b.e);
+            }
 #pragma unroll
             for (int ii = 0; ii < TI; ++ii)
 #pragma unroll
@@ -225,9 +259,11 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
         const T *pr = f.uniform ? nullptr : (const T *)f.prior + (size_t)(i0 + tid) * q;
         for (int D = 0; D < q; ++D) Z += (double)((pr ? pr[D] : up) * Ush[tid * q + D]);
         Zsh[tid] = Z;
-        // 1/Z_i in the units of the unscaled FP64 rows
-        const double mx = __longlong_as_double((long long)smax[tid]);
-        if (f.Zinv) f.Zinv[i0 + tid] = Z > 0.0 ? 1.0 / (Z * mx) : 0.0;
+        // the rows' Z_i is 2^E_i Z: keep 1/Z and E_i
+        if (f.Zinv) {
+            f.Zinv[i0 + tid] = Z > 0.0 ? 1.0 / Z : 0.0;
+            f.Zexp[i0 + tid] = emax[tid];
+        }
     }
     __syncthreads();
     for (int j = tid; j < TI * q; j += nth) {

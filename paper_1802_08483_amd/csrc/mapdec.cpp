@@ -50,7 +50,8 @@ struct FrameLayout {
     bool app_tiled = false;
     std::tuple<int, int, int> app_key;                     // (td, waves, mn) when tiled
     size_t off_cw = 0, off_ybits = 0, off_R = 0, off_G = 0, off_alpha = 0, off_beta = 0,
-           off_logA = 0, off_logB = 0, off_Zinv = 0, off_gacc = 0, off_ck = 0, off_bcarry = 0;
+           off_logA = 0, off_logB = 0, off_Zinv = 0, off_Zexp = 0, off_gacc = 0, off_ck = 0,
+           off_bcarry = 0;
     std::vector<int> gacc_first;   // first [4] partial of each segment
     int gacc_n = 0;
 };
@@ -360,6 +361,8 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         off = align_up(off + sizeof(double) * (fr.N + 1));
         F.off_Zinv = off;
         off = align_up(off + sizeof(double) * fr.N);
+        F.off_Zexp = off;
+        off = align_up(off + sizeof(int) * fr.N);
         F.off_gacc = off;
         off = align_up(off + sizeof(double) * 4 * (size_t)F.gacc_n);
         if (F.nseg > 1) {
@@ -589,6 +592,7 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
             d.logA = reinterpret_cast<double *>(base + F.off_logA);
             d.logB = reinterpret_cast<double *>(base + F.off_logB);
             d.Zinv = L.grad ? reinterpret_cast<double *>(base + F.off_Zinv) : nullptr;
+            d.Zexp = L.grad ? reinterpret_cast<int *>(base + F.off_Zexp) : nullptr;
             d.gacc_all = reinterpret_cast<double *>(base + F.off_gacc);
             d.gacc_n = F.gacc_n;
             const int j = std::min(P.seg, F.nseg - 1);

@@ -44,7 +44,8 @@ struct FrameDesc {
     double *beta;         // [N+1][Mt] backward metric rows (FP64 at every precision)
     double *logA;         // [N+1] log of the product of forward normalisers
     double *logB;         // [N+1] log of the product of backward normalisers
-    double *Zinv;         // [N] 1 / sum_D S_i(D)  (gradient passes)
+    double *Zinv;         // [N] 1 / Z_i' with Z_i = 2^Zexp[i] Z_i' (gradient passes)
+    int *Zexp;            // [N] binary exponent of the APP's row-product scale
     double *gacc;         // [lattice workgroups of this segment][4] partial
                           // d log P / d(a, d, t1, t0)
     double *gacc_all;     // every segment's partials of the frame, contiguous

@@ -181,6 +181,12 @@ class Batch:
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
 
     def decode(self, stream=None):
+        if self.checkpoint_K:
+            # mapdec_decode keeps whole frames; checkpointed runs go through a plan
+            p = Plan(self, graph=False, stream=stream)
+            p.run(stream)
+            p.close()
+            return self
         st = lib().mapdec_decode(self.frames, self.nframes, _ptr(self.logp), _ptr(self.status),
                                  _ptr(self.ws), self.ws_bytes, self.precision,
                                  _stream_handle(stream))

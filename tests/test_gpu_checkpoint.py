@@ -124,3 +124,25 @@ def test_long_frame_workload_shape_reduced():
         ref = oracle.decode_frame(fr, grad=True)
         _compare(b, f, ref["app"], ref["logp"], ref["dparams"], ref["dprior"],
                  ORACLE_TOL[mapdec.FP32], f"long-frame shape frame {f} K={K}")
+
+
+def test_long_frame_workload_full_size():
+    # 16 frames, q=64, n=12, N=10000, M=693, mn=8, K = ceil(sqrt(N)) = 100,
+    # FP32: the checkpointed run against the unsegmented one (which keeps
+    # the whole R table, ~8.4 GB for the batch) and properties that hold at
+    # any size (APP rows sum to 1; with uniform priors sum_D dprior / q = 1)
+    frames = wl.make_workload(5)
+    K = int(np.ceil(np.sqrt(frames[0].N)))
+    assert K == 100
+    ck = _run(frames, mapdec.FP32, K)
+    assert (ck.status.cpu().numpy() == 0).all()
+    for f in range(len(frames)):
+        app = ck.apps[f].double()
+        assert float((app.sum(1) - 1).abs().max()) < 1e-5, f"frame {f}"
+        dps = ck.dpriors[f].double().sum(1) / frames[f].q
+        assert float((dps - 1).abs().max()) < 1e-5, f"frame {f}"
+    full = _run(frames, mapdec.FP32, 0)
+    for f in range(len(frames)):
+        _compare(ck, f, full.apps[f].double().cpu().numpy(), float(full.logp[f]),
+                 full.dparams[f].cpu().numpy(), full.dpriors[f].double().cpu().numpy(),
+                 SELF_TOL[mapdec.FP32], f"long frame {f}")

@@ -123,3 +123,17 @@ def test_autograd_function_logits_and_params():
     refs = [oracle.decode_frame(f, grad=True) for f in frames]
     gp_ref = np.sum([r["dparams"] for r in refs], axis=0)
     assert _rel(params.grad.numpy(), gp_ref) <= 1e-4
+
+
+def test_row_products_below_fp64_range():
+    # q=4, n=4, N=5000, Pi=Pd=0.1, M=900: mid-frame the forward and
+    # backward rows peak at opposite ends of the drift range and their
+    # product at the posterior's drifts lies below 1e-308 (the oracle pins
+    # this case); APP, log P and the gradient must still match the oracle
+    fr = wl.random_frame(913, 4, 4, 5000, 0.1, 0.1, 0.0, 2, 900, 5)
+    ref = oracle.decode_frame(fr, grad=True)
+    for prec in (mapdec.FP64, mapdec.FP32):
+        b = _grad([fr], prec)
+        _check(b, 0, fr, ref, prec, f"underflow case prec={prec}")
+        app = b.apps[0].double().cpu().numpy()
+        assert np.abs(app - ref["app"]).max() <= (1e-12 if prec == mapdec.FP64 else 1e-5)
