@@ -18,12 +18,12 @@ LIB = os.path.join(HERE, "libmapdec.so")
 SOURCES = ["k_misc.hip", "k_lattice.hip", "k_chain.hip", "k_app.hip", "mapdec.cpp"]
 # k_chain_ring.hip is compiled once per (precision, workgroup shape); the
 # shapes (waves, states per thread) match kRingShapes in csrc/kernels.h
-RING_SHAPES = [(1, 1), (2, 1), (4, 1), (4, 2), (8, 2), (16, 2)]
+RING_SHAPES = [(1, 1, 0), (2, 1, 0), (4, 1, 0), (4, 2, 0), (8, 2, 0), (16, 2, 0), (16, 2, 1)]
 VARIANTS = [("k_chain_ring.hip", f"chain_ring_{tag}_{k}",
              [f"-DCHAIN_T={t}", f"-DCHAIN_NW={nw}", f"-DCHAIN_SPL={spl}",
-              f"-DCHAIN_FN=chain_ring_{tag}_{k}"])
+              f"-DCHAIN_ONEROW={one}", f"-DCHAIN_FN=chain_ring_{tag}_{k}"])
             for tag, t in (("f32", "float"), ("f64", "double"))
-            for k, (nw, spl) in enumerate(RING_SHAPES)]
+            for k, (nw, spl, one) in enumerate(RING_SHAPES)]
 # k_adjoint.hip is compiled once per precision
 VARIANTS += [("k_adjoint.hip", f"adj_{tag}", [f"-DADJ_T={t}", f"-DADJ_FN=adj_{tag}"])
              for tag, t in (("f32", "float"), ("f64", "double"))]
@@ -49,6 +49,22 @@ def _compile(job) -> str:
     return obj
 
 
+def _check_unique_kernels(objs) -> None:
+    """Objects built from one source with different -D switches must not
+    define the same kernel: the linker would keep one definition for both
+    launchers.  Every kernel's host stub must come from one object."""
+    seen = {}
+    for obj in objs:
+        r = subprocess.run(["nm", "-g", "--defined-only", obj], capture_output=True, text=True)
+        for line in r.stdout.splitlines():
+            sym = line.split()[-1]
+            if "__device_stub__" not in sym:
+                continue
+            if sym in seen and seen[sym] != obj:
+                raise RuntimeError(f"kernel {sym} defined in {seen[sym]} and {obj}")
+            seen[sym] = obj
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = [(s, s, []) for s in SOURCES] + VARIANTS
@@ -58,6 +74,7 @@ def build(verbose: bool = False) -> str:
     workers = max(1, min(16, os.cpu_count() or 1, len(jobs)))
     with ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(_compile, jobs))
+    _check_unique_kernels(objs)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

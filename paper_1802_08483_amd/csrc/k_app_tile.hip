@@ -112,7 +112,8 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
     const int ib = f.i0;                 // row index base of alpha / beta
     const int PAD = app_tile_pad(n);
     const int WA = Mt + 2 * PAD, WB = Mt + 2 * (PAD + MN);
-    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
     const int nwaves = nth >> 6;
     ME<T> *ar = (ME<T> *)smem;     // [TI][WA]  alpha_i(m) at m + M + PAD
     ME<T> *br = ar + TI * WA;      // [TI][WB]  beta_{i+1}(m) at m + M + PAD + mn

@@ -20,7 +20,7 @@ __device__ __forceinline__ T gamma_at(const FrameDesc &f, const T *G, int i, int
         const int s = f.n * i + mp;
         return (s >= 0 && s <= f.rho) ? G[(size_t)k * f.sp + (s - f.s0)] : T(0);
     }
-    return G[((size_t)(i - f.i0) * f.Mn + k) * f.Mt + (mp + f.M)];
+    return G[(size_t)k * f.gsp + (size_t)(i - f.i0) * f.Mt + (mp + f.M)];
 }
 
 template <typename T>
@@ -155,12 +155,14 @@ MAPDEC_RING_DECL(chain_ring_f32_2)
 MAPDEC_RING_DECL(chain_ring_f32_3)
 MAPDEC_RING_DECL(chain_ring_f32_4)
 MAPDEC_RING_DECL(chain_ring_f32_5)
+MAPDEC_RING_DECL(chain_ring_f32_6)
 MAPDEC_RING_DECL(chain_ring_f64_0)
 MAPDEC_RING_DECL(chain_ring_f64_1)
 MAPDEC_RING_DECL(chain_ring_f64_2)
 MAPDEC_RING_DECL(chain_ring_f64_3)
 MAPDEC_RING_DECL(chain_ring_f64_4)
 MAPDEC_RING_DECL(chain_ring_f64_5)
+MAPDEC_RING_DECL(chain_ring_f64_6)
 #undef MAPDEC_RING_DECL
 
 hipError_t launch_chain_ring(int fp64, int shape, int mn, const FrameDesc *fd, const int *frames,
@@ -169,9 +171,11 @@ hipError_t launch_chain_ring(int fp64, int shape, int mn, const FrameDesc *fd, c
     if (dirs < 1 || dirs > 3) return hipErrorInvalidValue;
     using Fn = hipError_t (*)(int, int, int, size_t, hipStream_t, const FrameDesc *, const int *);
     static const Fn f32[kNumRingShapes] = {chain_ring_f32_0, chain_ring_f32_1, chain_ring_f32_2,
-                                           chain_ring_f32_3, chain_ring_f32_4, chain_ring_f32_5};
+                                           chain_ring_f32_3, chain_ring_f32_4, chain_ring_f32_5,
+                                           chain_ring_f32_6};
     static const Fn f64[kNumRingShapes] = {chain_ring_f64_0, chain_ring_f64_1, chain_ring_f64_2,
-                                           chain_ring_f64_3, chain_ring_f64_4, chain_ring_f64_5};
+                                           chain_ring_f64_3, chain_ring_f64_4, chain_ring_f64_5,
+                                           chain_ring_f64_6};
     if (shape < 0 || shape >= kNumRingShapes) return hipErrorInvalidValue;
     return (fp64 ? f64 : f32)[shape](mn, nchains, dirs, lds, st, fd, frames);
 }

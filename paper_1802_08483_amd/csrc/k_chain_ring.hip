@@ -26,6 +26,11 @@
 // continues the cumulative log of the normalisers, and can copy its last
 // row out (the next checkpoint).
 //
+// With general priors Gamma_i(m', delta) depends on the symbol too; its
+// table holds the states of consecutive symbols one after the other, so
+// "column" Mt i + m' + M plays the part of s and step i reads the Mt columns
+// from Mt i on: the same ring, with Mt columns per step instead of n.
+//
 // Gamma(s, delta) for the start indices a chunk of C steps reads sits in an
 // LDS ring of RING (a power of two) slots of Mn values each, slot-major
 // (threads read with a stride of Mn words, which is odd: no bank conflicts).
@@ -40,30 +45,46 @@
 #if !defined(CHAIN_T) || !defined(CHAIN_NW) || !defined(CHAIN_SPL) || !defined(CHAIN_FN)
 #error "compile with -DCHAIN_T, -DCHAIN_NW, -DCHAIN_SPL and -DCHAIN_FN"
 #endif
+// CHAIN_ONEROW=1: one metric row in LDS, read and then overwritten in place
+// (a second barrier per step), for state spaces whose two rows and ring
+// would not fit in LDS together.
+#ifndef CHAIN_ONEROW
+#define CHAIN_ONEROW 0
+#endif
 
 namespace mapdec {
 
-template <typename T, int NW, int SPL, int MN, int DIR>
+// ONE (one metric row) is a template parameter, not only a macro, so the
+// one-row and two-row objects built from this file never define the same
+// kernel symbol.
+template <typename T, int NW, int SPL, int MN, int DIR, bool ONE>
 __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned char *smem) {
     constexpr int NT = 64 * NW;
     constexpr int Mn = 2 * MN + 1;
     constexpr int ROWW = NT * SPL + 2 * MN;            // padded row
     constexpr bool DUP = ring_duplicates(NT * SPL);
     constexpr int PF = kRingPrefetchRegs;
-    const int Mt = f.Mt, M = f.M, N = f.N, n = f.n;
-    const int i0 = f.i0, i1 = f.i1, s0 = f.s0, s1 = f.s1, NS = i1 - i0;
+    const int Mt = f.Mt, M = f.M, N = f.N;
+    const int i0 = f.i0, i1 = f.i1, NS = i1 - i0;
+    // column of state m at step i: n i + m (uniform priors: the start index)
+    // or Mt i + m + M (general priors); the table holds columns [s0, s1]
+    const bool uni = f.uniform != 0;
+    const int n = uni ? f.n : Mt;
+    const int MC = uni ? M : 0;
+    const int s0 = uni ? f.s0 : Mt * i0;
+    const int s1 = uni ? f.s1 : Mt * i1 - 1;
     const int C = f.ring_chunk, RING = f.ring_cols, mask = RING - 1;
     const int RPHYS = DUP ? RING + NT * SPL + 2 * MN : RING;
     using R = double;                                  // metric rows: FP64 always
     R *row0 = (R *)smem;
-    R *row1 = row0 + ROWW;
+    R *row1 = ONE ? row0 : row0 + ROWW;
     R *part = row1 + ROWW;                             // [2][NW] wave partial sums
     T *ring = (T *)(part + 2 * NW);                    // [RPHYS][Mn], batch precision
     const int tid = threadIdx.x, wv = tid >> 6;
-    const gptr<const T> G = to_global((const T *)f.G);   // [Mn][sp]
-    const size_t sp = (size_t)f.sp;
+    const gptr<const T> G = to_global((const T *)f.G);   // [Mn][gsp]
+    const size_t sp = (size_t)f.gsp;
 
-    for (int j = tid; j < 2 * ROWW + 2 * NW; j += NT) row0[j] = R(0);
+    for (int j = tid; j < (ONE ? 1 : 2) * ROWW + 2 * NW; j += NT) row0[j] = R(0);
     for (int j = tid; j < RPHYS * Mn; j += NT) ring[j] = T(0);
     __syncthreads();
     const int m0 = DIR == 0 ? 0 : f.rho - f.tau;
@@ -80,9 +101,9 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
 
     // chunk k covers steps i0+kC .. i0+kC+C-1 (forward) or i1-1-kC down to
     // i1-C-kC (backward), which read s in [n i_lo - M, n i_hi + M]
-    auto chunk_lo_s = [&](int k) { return n * (DIR == 0 ? i0 + k * C : i1 - C - k * C) - M; };
+    auto chunk_lo_s = [&](int k) { return n * (DIR == 0 ? i0 + k * C : i1 - C - k * C) - MC; };
     auto chunk_hi_s = [&](int k) {
-        return n * (DIR == 0 ? i0 + k * C + C - 1 : i1 - 1 - k * C) + M;
+        return n * (DIR == 0 ? i0 + k * C + C - 1 : i1 - 1 - k * C) - MC + Mt - 1;
     };
     auto new_base = [&](int k) { return DIR == 0 ? chunk_hi_s(k - 1) + 1 : chunk_lo_s(k); };
 
@@ -176,7 +197,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             R csum = R(0);
 #pragma unroll
             for (int w = 0; w < NW; ++w) csum += part[pp * NW + w];
-            const int sb = (n * i - M) & mask;
+            const int sb = (n * i - MC) & mask;
             const R *cb = cur + MN + tid;
             R acc[SPL];
             if (DIR == 0) {
@@ -225,6 +246,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
                 pexp += e;
             }
             const int row = DIR == 0 ? i + 1 : i;
+            if (ONE) __syncthreads();   // every read of the row is done
             R *nb = nxt + MN + tid;
             R p = R(0);
 #pragma unroll
@@ -270,7 +292,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
 }
 
 // dirs: 1 forward only, 2 backward only, 3 both (workgroups 2c, 2c+1)
-template <typename T, int NW, int SPL, int MN>
+template <typename T, int NW, int SPL, int MN, bool ONE>
 __global__ __launch_bounds__(64 * NW) void k_chain_ring(const FrameDesc *__restrict__ fd,
                                                         const int *__restrict__ frames,
                                                         int dirs) {
@@ -280,15 +302,15 @@ __global__ __launch_bounds__(64 * NW) void k_chain_ring(const FrameDesc *__restr
     if (*f.status != kStatusOk) return;
     const int dir = nd == 2 ? (int)(blockIdx.x & 1) : (dirs == 1 ? 0 : 1);
     if (dir)
-        chain_ring_body<T, NW, SPL, MN, 1>(f, smem);
+        chain_ring_body<T, NW, SPL, MN, 1, ONE>(f, smem);
     else
-        chain_ring_body<T, NW, SPL, MN, 0>(f, smem);
+        chain_ring_body<T, NW, SPL, MN, 0, ONE>(f, smem);
 }
 
 template <int MN>
 static hipError_t ring_launch(int nchains, int dirs, size_t lds, hipStream_t st,
                               const FrameDesc *fd, const int *frames) {
-    auto kern = k_chain_ring<CHAIN_T, CHAIN_NW, CHAIN_SPL, MN>;
+    auto kern = k_chain_ring<CHAIN_T, CHAIN_NW, CHAIN_SPL, MN, CHAIN_ONEROW != 0>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

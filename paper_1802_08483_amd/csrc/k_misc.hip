@@ -33,32 +33,55 @@ __global__ __launch_bounds__(256) void k_pack(const FrameDesc *__restrict__ fd,
 
 // ---------------------------------------------------------------------------
 // Gamma_i(m', delta) = sum_D prior_i(D) R(n i + m', D, delta) for general
-// priors; one lane per drift state m', lanes read consecutive s.
+// priors, stored by delta with the states of consecutive symbols in one row
+// (column (i - i0) Mt + m' + M).  One 64-lane workgroup per (symbol i, 64 drift states m'): lanes
+// read consecutive start indices s = n i + m' (coalesced), the priors of
+// symbol i are wave-uniform (scalar loads), and the loads of kGammaDC
+// symbol values (every delta) are issued together: addresses are clamped
+// into the table and out-of-range values multiplied by 0, so no load waits
+// on a branch.
 
-template <typename T>
+constexpr int kGammaDC = 4;
+
+template <typename T, int MN>
 __global__ __launch_bounds__(kGammaLanes) void k_gamma(const FrameDesc *__restrict__ fd,
                                                        const Work *__restrict__ tab) {
+    constexpr int KW = 2 * MN + 1;
     const Work w = tab[blockIdx.x];
     const FrameDesc &f = fd[w.frame];
-    const int per_i = (f.Mt + kGammaLanes - 1) / kGammaLanes;
+    const int Mt = f.Mt, q = f.q;
+    const int per_i = (Mt + kGammaLanes - 1) / kGammaLanes;
     const int i = f.i0 + w.item / per_i;
     const int mi = (w.item % per_i) * kGammaLanes + (int)threadIdx.x;
-    if (mi >= f.Mt) return;
-    const int Mn = f.Mn, Mt = f.Mt, q = f.q;
     const int s = f.n * i + mi - f.M;
-    T *G = (T *)f.G + (size_t)(i - f.i0) * Mn * Mt + mi;
-    if (s < 0 || s > f.rho) {
-        for (int k = 0; k < Mn; ++k) G[(size_t)k * Mt] = T(0);
-        return;
-    }
+    const bool valid = mi < Mt && s >= 0 && s <= f.rho;
+    const T vf = valid ? T(1) : T(0);
+    const int sc = min(max(s, f.s0), f.s1) - f.s0;   // column in the segment's R table
+    const gptr<const T> R = to_global((const T *)f.R);
     const T *pr = (const T *)f.prior + (size_t)i * q;
-    const T *R = (const T *)f.R + (s - f.s0);   // s in [s0, s1] for the segment's symbols
     const size_t sp = (size_t)f.sp;
-    for (int k = 0; k < Mn; ++k) {
-        T acc = T(0);
-        for (int D = 0; D < q; ++D) acc += pr[D] * R[((size_t)D * Mn + k) * sp];
-        G[(size_t)k * Mt] = acc;
+    T acc[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) acc[k] = T(0);
+    for (int D0 = 0; D0 < q; D0 += kGammaDC) {
+        T r[kGammaDC][KW];
+        T p[kGammaDC];
+#pragma unroll
+        for (int c = 0; c < kGammaDC; ++c) {
+            const int D = min(D0 + c, q - 1);
+            p[c] = (D0 + c < q) ? pr[D] : T(0);
+#pragma unroll
+            for (int k = 0; k < KW; ++k) r[c][k] = R[((size_t)D * KW + k) * sp + sc];
+        }
+#pragma unroll
+        for (int c = 0; c < kGammaDC; ++c)
+#pragma unroll
+            for (int k = 0; k < KW; ++k) acc[k] += p[c] * r[c][k];
     }
+    if (mi >= Mt) return;
+    T *G = (T *)f.G + (size_t)(i - f.i0) * Mt + mi;   // [delta][(i - i0) Mt + m' + M]
+#pragma unroll
+    for (int k = 0; k < KW; ++k) G[(size_t)k * f.gsp] = acc[k] * vf;
 }
 
 // ---------------------------------------------------------------------------
@@ -102,14 +125,28 @@ hipError_t launch_pack(const FrameDesc *fd, const Work *tab, int nblocks, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_gamma(int fp64, const FrameDesc *fd, const Work *tab, int nblocks,
+template <typename T>
+static hipError_t gamma_t(int mn, const FrameDesc *fd, const Work *tab, int nblocks,
+                          hipStream_t st) {
+    switch (mn) {
+#define MAPDEC_GAMMA_CASE(K)                                                                \
+    case K:                                                                                 \
+        hipLaunchKernelGGL((k_gamma<T, K>), dim3(nblocks), dim3(kGammaLanes), 0, st, fd, tab); \
+        break;
+        MAPDEC_GAMMA_CASE(0) MAPDEC_GAMMA_CASE(1) MAPDEC_GAMMA_CASE(2) MAPDEC_GAMMA_CASE(3)
+        MAPDEC_GAMMA_CASE(4) MAPDEC_GAMMA_CASE(5) MAPDEC_GAMMA_CASE(6) MAPDEC_GAMMA_CASE(7)
+        MAPDEC_GAMMA_CASE(8)
+#undef MAPDEC_GAMMA_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gamma(int fp64, int mn, const FrameDesc *fd, const Work *tab, int nblocks,
                         hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
-    if (fp64)
-        hipLaunchKernelGGL(k_gamma<double>, dim3(nblocks), dim3(kGammaLanes), 0, st, fd, tab);
-    else
-        hipLaunchKernelGGL(k_gamma<float>, dim3(nblocks), dim3(kGammaLanes), 0, st, fd, tab);
-    return hipGetLastError();
+    return fp64 ? gamma_t<double>(mn, fd, tab, nblocks, st)
+                : gamma_t<float>(mn, fd, tab, nblocks, st);
 }
 
 hipError_t launch_dparams(const FrameDesc *fd, int nframes, hipStream_t st) {

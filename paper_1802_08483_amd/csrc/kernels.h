@@ -26,7 +26,8 @@ hipError_t launch_init(const FrameDesc *fd, int nframes, hipStream_t st);
 hipError_t launch_pack(const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st);
 hipError_t launch_lattice(int fp64, int mn, int imode, const FrameDesc *fd, const Work *tab,
                           int nblocks, hipStream_t st);
-hipError_t launch_gamma(int fp64, const FrameDesc *fd, const Work *tab, int nblocks,
+// Gamma_i for general priors; every frame of the launch has drift limit mn.
+hipError_t launch_gamma(int fp64, int mn, const FrameDesc *fd, const Work *tab, int nblocks,
                         hipStream_t st);
 // Chains over each frame's segment; dirs: 1 forward (alpha) only, 2 backward
 // (beta) only, 3 both (one workgroup per chain).
@@ -39,13 +40,15 @@ hipError_t launch_chain(int fp64, const FrameDesc *fd, const int *frames, int nc
 hipError_t launch_chain_ring(int fp64, int shape, int mn, const FrameDesc *fd, const int *frames,
                              int nchains, int dirs, size_t lds_bytes, hipStream_t st);
 
-// Workgroup shapes of the ring chain kernel: waves per chain and drift
-// states per thread; a frame takes the first shape with 64 nw spl >= 2M+1.
+// Workgroup shapes of the ring chain kernel: waves per chain, drift states
+// per thread, and one metric row in LDS instead of two; a frame takes the
+// first shape with 64 nw spl >= 2M+1 whose LDS fits.
 struct RingShape {
-    int nw, spl;
+    int nw, spl, one_row;
 };
-constexpr RingShape kRingShapes[] = {{1, 1}, {2, 1}, {4, 1}, {4, 2}, {8, 2}, {16, 2}};
-constexpr int kNumRingShapes = 6;
+constexpr RingShape kRingShapes[] = {{1, 1, 0}, {2, 1, 0}, {4, 1, 0}, {4, 2, 0},
+                                     {8, 2, 0}, {16, 2, 0}, {16, 2, 1}};
+constexpr int kNumRingShapes = 7;
 // Rings of at most this many padded states duplicate their edge slots.
 constexpr bool ring_duplicates(int slots) { return slots <= 512; }
 hipError_t launch_app(int fp64, const FrameDesc *fd, const Work *tab, int nblocks,
@@ -80,7 +83,7 @@ hipError_t launch_dparams(const FrameDesc *fd, int nframes, hipStream_t st);
 // Block sizes the host uses to build work tables.
 constexpr int kPackWords = 8;      // packed words per pack workgroup (256 threads)
 constexpr int kLatticeLanes = 64;  // start indices per lattice workgroup
-constexpr int kGammaLanes = 256;   // drift states per Gamma workgroup
+constexpr int kGammaLanes = 64;    // drift states per Gamma workgroup
 constexpr int kChainThreads = 256;
 constexpr int kAppThreads = 64;
 constexpr int kAppTI = 4;   // consecutive symbols per tiled-APP workgroup

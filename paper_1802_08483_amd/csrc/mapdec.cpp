@@ -44,7 +44,7 @@ int validate_code_params(int q, int n, double Pi, double Pd, double Ps, int I, i
 
 // Sizes and places of one frame's workspace pieces.
 struct FrameLayout {
-    int nwords = 0, sp = 0, Mt = 0, Mn = 0, pack_blocks = 0;
+    int nwords = 0, sp = 0, gsp = 0, Mt = 0, Mn = 0, pack_blocks = 0;
     int K = 0, nseg = 1;   // symbols per segment, segments (1 unless checkpointed)
     int ring_shape = -1, ring_chunk = 0, ring_cols = 0;   // ring_shape -1: plain chain
     bool app_tiled = false;
@@ -83,8 +83,8 @@ struct Pass {
     size_t off_fd = 0;
     std::map<std::pair<int, int>, std::vector<Work>> lat;          // (mn, imode)
     std::map<std::pair<int, int>, size_t> off_lat;
-    std::vector<Work> gamma;
-    size_t off_gamma = 0;
+    std::map<int, std::vector<Work>> gamma;                         // mn
+    std::map<int, size_t> off_gamma;
     std::vector<int> chain_plain;
     size_t off_chain = 0;
     std::map<std::pair<int, int>, std::vector<int>> chain_ring;    // (shape, mn)
@@ -126,30 +126,31 @@ std::vector<Work> xcd_order(const std::vector<Work> &items) {
     return out;
 }
 
-// Ring-chain parameters for a uniform-prior frame (workgroup shape, steps
-// per prefetch chunk, ring slots, LDS bytes); false when the frame needs
-// the plain workgroup chain kernel instead.
-bool ring_params(int Mt, int Mn, int n, int mn, size_t tsize, size_t lds_limit, int &shape,
-                 int &chunk, int &cols, size_t &lds) {
+// Ring-chain parameters (workgroup shape, steps per prefetch chunk, ring
+// slots, LDS bytes); false when the frame needs the plain workgroup chain
+// kernel instead.  n = columns per step: the codeword length for uniform
+// priors (the ring then covers at least 8 steps), Mt for general priors
+// (Gamma columns are not shared between steps; one step per chunk).
+bool ring_params(int Mt, int Mn, int n, int mn, bool uniform, size_t tsize, size_t lds_limit,
+                 int &shape, int &chunk, int &cols, size_t &lds) {
+    for (shape = 0; shape < kNumRingShapes; ++shape) {
+        const RingShape &rs = kRingShapes[shape];
+        if (64 * rs.nw * rs.spl < Mt) continue;
+        const int nt = 64 * rs.nw, slots = nt * rs.spl;
+        // ring: a power of two covering the window of at least 8 steps; the
+        // chunk is as long as the ring and the prefetch registers allow
+        cols = 1;
+        while (cols < Mt + (uniform ? n * 7 : 0)) cols *= 2;
+        chunk = std::min({(cols - Mt) / n + 1, (nt * kRingPrefetchRegs) / (n * Mn), 64});
+        if (chunk < 1) continue;
+        const size_t roww = (size_t)slots + 2 * mn;
+        const size_t rphys = ring_duplicates(slots) ? cols + roww : cols;
+        // FP64 rows and wave partials, Gamma ring in the batch precision
+        lds = ((rs.one_row ? 1 : 2) * roww + 2 * rs.nw) * sizeof(double) + rphys * Mn * tsize;
+        if (lds <= lds_limit) return true;
+    }
     shape = -1;
-    for (int k = 0; k < kNumRingShapes; ++k)
-        if (64 * kRingShapes[k].nw * kRingShapes[k].spl >= Mt) {
-            shape = k;
-            break;
-        }
-    if (shape < 0) return false;
-    const int nt = 64 * kRingShapes[shape].nw, slots = nt * kRingShapes[shape].spl;
-    // ring: a power of two covering the window of at least 8 steps; the
-    // chunk is as long as the ring and the prefetch registers allow
-    cols = 1;
-    while (cols < Mt + n * 7) cols *= 2;
-    chunk = std::min({(cols - Mt) / n + 1, (nt * kRingPrefetchRegs) / (n * Mn), 64});
-    if (chunk < 1) return false;
-    const size_t roww = (size_t)slots + 2 * mn;
-    const size_t rphys = ring_duplicates(slots) ? cols + roww : cols;
-    // FP64 rows and wave partials, Gamma ring in the batch precision
-    lds = (2 * roww + 2 * kRingShapes[shape].nw) * sizeof(double) + rphys * Mn * tsize;
-    return lds <= lds_limit;
+    return false;
 }
 
 int frame_imode(const mapdec_code *c) { return c->I <= 2 ? 0 : 1; }
@@ -226,8 +227,8 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         }
         int shape = -1;
         size_t rlds = 0;
-        if (!fr.prior && ring_params(F.Mt, F.Mn, c->n, c->mn, L.tsize, lds_limit, shape,
-                                     F.ring_chunk, F.ring_cols, rlds)) {
+        if (ring_params(F.Mt, F.Mn, fr.prior ? F.Mt : c->n, c->mn, !fr.prior, L.tsize, lds_limit,
+                        shape, F.ring_chunk, F.ring_cols, rlds)) {
             F.ring_shape = shape;
             const auto key = std::make_pair(shape, c->mn);
             L.ring_lds[key] = std::max(L.ring_lds[key], rlds);
@@ -273,7 +274,8 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             for (int b = 0; b < nb; ++b) lv.push_back(Work{f, b * kLatticeLanes});
             if (fr.prior) {
                 const int per_i = (F.Mt + kGammaLanes - 1) / kGammaLanes;
-                for (int b = 0; b < (g.i1 - g.i0) * per_i; ++b) P.gamma.push_back(Work{f, b});
+                auto &gv = P.gamma[c->mn];
+                for (int b = 0; b < (g.i1 - g.i0) * per_i; ++b) gv.push_back(Work{f, b});
             }
             chains.push_back(std::make_pair(g.i1 - g.i0, f));
             if (P.forward) continue;
@@ -302,7 +304,11 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             else
                 P.chain_plain.push_back(f);
         }
+        // neighbouring items share rows (APP, W) or received columns (Gamma):
+        // keep them on one XCD's L2
         for (auto &kv : P.app_tile) kv.second = xcd_order(kv.second);
+        for (auto &kv : P.lat) kv.second = xcd_order(kv.second);
+        for (auto &kv : P.gamma) kv.second = xcd_order(kv.second);
     }
 
     // head: work tables and, per pass, descriptors and work tables
@@ -320,8 +326,10 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             P.off_adj[kv.first] = off;
             off = align_up(off + sizeof(Work) * kv.second.size());
         }
-        P.off_gamma = off;
-        off = align_up(off + sizeof(Work) * P.gamma.size());
+        for (auto &kv : P.gamma) {
+            P.off_gamma[kv.first] = off;
+            off = align_up(off + sizeof(Work) * kv.second.size());
+        }
         P.off_chain = off;
         off = align_up(off + sizeof(int) * P.chain_plain.size());
         for (auto &kv : P.chain_ring) {
@@ -350,7 +358,8 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         F.off_R = off;
         off = align_up(off + T * c->q * F.Mn * (size_t)F.sp);
         F.off_G = off;
-        off = align_up(off + T * (fr.prior ? (size_t)F.K * F.Mn * F.Mt : (size_t)F.Mn * F.sp));
+        F.gsp = fr.prior ? (F.K * F.Mt + 63) / 64 * 64 : F.sp;
+        off = align_up(off + T * (size_t)F.Mn * F.gsp);
         F.off_alpha = off;   // metric rows are FP64 at every precision
         off = align_up(off + sizeof(double) * (size_t)(F.K + 1) * F.Mt);
         F.off_beta = off;
@@ -430,8 +439,11 @@ struct mapdec_plan {
                                    at<Work>(P.off_lat.at(kv.first)), (int)kv.second.size(), st);
             }
             mark(kPhLattice);
-            if (e == hipSuccess)
-                e = launch_gamma(L.fp64, fd, at<Work>(P.off_gamma), (int)P.gamma.size(), st);
+            for (auto &kv : P.gamma) {
+                if (e != hipSuccess) break;
+                e = launch_gamma(L.fp64, kv.first, fd, at<Work>(P.off_gamma.at(kv.first)),
+                                 (int)kv.second.size(), st);
+            }
             mark(kPhGamma);
             const int dirs = P.forward ? kDirFwd : kDirBoth;
             if (e == hipSuccess)
@@ -573,7 +585,7 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
             FrameDesc &d = fd[f];
             d.q = c->q; d.n = c->n; d.N = fr.N; d.rho = fr.rho;
             d.M = c->M; d.mn = c->mn; d.I = c->I; d.tau = c->n * fr.N;
-            d.Mt = F.Mt; d.Mn = F.Mn; d.sp = F.sp; d.uniform = fr.prior ? 0 : 1;
+            d.Mt = F.Mt; d.Mn = F.Mn; d.sp = F.sp; d.gsp = F.gsp; d.uniform = fr.prior ? 0 : 1;
             d.nwords = F.nwords; d.imode = frame_imode(c); d.grad = L.grad; d.ck = F.K;
             d.ring_chunk = F.ring_chunk; d.ring_cols = F.ring_cols;
             const double Pt = 1.0 - c->Pi - c->Pd;
@@ -618,8 +630,9 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
         for (auto &kv : P.adj)
             std::memcpy(stage.data() + P.off_adj.at(kv.first), kv.second.data(),
                         sizeof(Work) * kv.second.size());
-        if (!P.gamma.empty())
-            std::memcpy(stage.data() + P.off_gamma, P.gamma.data(), sizeof(Work) * P.gamma.size());
+        for (auto &kv : P.gamma)
+            std::memcpy(stage.data() + P.off_gamma.at(kv.first), kv.second.data(),
+                        sizeof(Work) * kv.second.size());
         if (!P.chain_plain.empty())
             std::memcpy(stage.data() + P.off_chain, P.chain_plain.data(),
                         sizeof(int) * P.chain_plain.size());

@@ -39,7 +39,9 @@ struct FrameDesc {
     uint32_t *cw;         // [q] codewords; bit (n-1-r) holds C(D)[r]
     uint32_t *ybits;      // [nwords] bit b of word w = y[32w + b]
     void *R;              // [q][Mn][sp] receiver metric R(s, D, delta)
-    void *G;              // uniform: [Mn][sp] sum_D R / q; else [N][Mn][Mt]
+    void *G;              // uniform: [Mn][sp] sum_D R / q at column s - s0; general
+                          // priors: [Mn][gsp] Gamma_i(m', .) at column (i - i0) Mt + m' + M
+    int gsp;              // column stride of G
     double *alpha;        // [N+1][Mt] forward metric rows (FP64 at every precision)
     double *beta;         // [N+1][Mt] backward metric rows (FP64 at every precision)
     double *logA;         // [N+1] log of the product of forward normalisers
