@@ -54,7 +54,8 @@ enum { MAPDEC_FP32 = 0, MAPDEC_FP64 = 1 };
 /* Flags for mapdec_workspace_size / mapdec_plan_create. */
 enum {
     MAPDEC_FLAG_GRAD = 1,    /* the plan will also compute gradients        */
-    MAPDEC_FLAG_GRAPH = 2    /* replay the plan's launches as a HIP graph    */
+    MAPDEC_FLAG_GRAPH = 2,   /* replay the plan's launches as a HIP graph    */
+    MAPDEC_FLAG_SERIAL = 4   /* every launch in order on the run's stream    */
 };
 
 /* Kernel limits of this build: n <= MAPDEC_MAX_N, mn <= MAPDEC_MAX_MN,
@@ -178,6 +179,16 @@ int mapdec_grad(const mapdec_frame *frames, int nframes, double *logp, double *d
  * ws_bytes >= mapdec_workspace_size(frames, nframes, precision, flags,
  * checkpoint_K).  Returns NULL on failure (see mapdec_last_error()).  The
  * descriptor upload is enqueued on stream.
+ *
+ * Batches whose frames differ in shape (q, n, M, mn, priors) need several
+ * launches per phase, one per kernel instance.  A plan without
+ * MAPDEC_FLAG_GRAPH or MAPDEC_FLAG_SERIAL then deals those launches to
+ * three streams of its own (created at plan creation, default priority)
+ * besides the run's stream: each launch waits only for earlier launches
+ * that touched one of its frames, and the run's stream waits for all of
+ * them at the end, so a run is still ordered on the caller's stream as a
+ * whole.  Graph plans record every launch in order on one stream.  Results
+ * do not depend on the order.
  */
 typedef struct mapdec_plan mapdec_plan;
 

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
 #include <tuple>
@@ -388,6 +389,35 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
 // Per-launch phase names, in the order of mapdec_phase_name().
 enum Phase { kPhPack, kPhLattice, kPhGamma, kPhChain, kPhApp, kPhWgrad, kPhAdjoint, kPhDparams };
 
+// One kernel launch (or, for the set-up, two) of a plan, with the frames
+// whose workspace regions it reads or writes.
+struct Op {
+    int phase = 0;
+    bool all = false;          // touches every frame (set-up, parameter sums)
+    std::vector<int> frames;   // sorted, distinct (when !all)
+    int stream = 0;            // 0: the run's stream, k > 0: forked stream k - 1
+    std::function<hipError_t(hipStream_t)> fn;
+};
+
+std::vector<int> frames_of(const std::vector<Work> &items) {
+    std::vector<int> v;
+    v.reserve(items.size());
+    for (const Work &w : items) v.push_back(w.frame);
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    return v;
+}
+std::vector<int> sorted_frames(std::vector<int> v) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    return v;
+}
+
+// Launch groups of one phase that can run side by side: the forked streams
+// besides the run's own.  Kernels of different groups share no workspace
+// region, so only the frames a launch touches order it after earlier ones.
+constexpr int kForkStreams = 3;
+
 }  // namespace
 
 struct mapdec_plan {
@@ -403,14 +433,155 @@ struct mapdec_plan {
     template <typename P>
     P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
 
-    // profiling: an event after each launch group, tagged with its phase
+    std::vector<Op> ops;
+    bool forked = false;                  // some phase has several launch groups
+    hipStream_t side[kForkStreams] = {};
+    std::vector<hipEvent_t> dep;          // one per op, plus the fork
+
+    // profiling: an event after each phase's launches, tagged with the phase
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_phase;
+    size_t nev = 0;
 
-    // Enqueues every launch of one run.  With prof, an event is recorded
-    // first and after each launch group, and ev_phase[k] names the phase of
-    // the group that ends at event k.
-    hipError_t enqueue(hipStream_t st, bool prof = false) {
+    // The plan's launches in dependency order: set-up, then per pass the
+    // lattice, Gamma, chains, APP and (gradients) W and the adjoint sweep,
+    // and the parameter sums.  Launch groups of one phase are dealt to the
+    // streams in order of decreasing size (chains: their longest chain).
+    void build_ops() {
+        const int nf = L.nframes;
+        auto add = [&](int phase, std::vector<int> frames, bool all,
+                       std::function<hipError_t(hipStream_t)> fn) {
+            Op o;
+            o.phase = phase;
+            o.all = all;
+            o.frames = std::move(frames);
+            o.fn = std::move(fn);
+            ops.push_back(std::move(o));
+        };
+        const FrameDesc *fd0 = at<FrameDesc>(L.passes.front().off_fd);
+        const int npack = (int)L.pack.size();
+        const Work *ptab = at<Work>(L.off_pack);
+        add(kPhPack, {}, true, [=](hipStream_t st) {
+            hipError_t e = launch_init(fd0, nf, st);
+            return e == hipSuccess ? launch_pack(fd0, ptab, npack, st) : e;
+        });
+        const int fp64 = L.fp64;
+        for (const Pass &P : L.passes) {
+            const FrameDesc *fd = at<FrameDesc>(P.off_fd);
+            // size of each group, for dealing the groups of a phase to streams
+            std::vector<std::pair<long long, size_t>> group;
+            auto deal = [&]() {
+                std::stable_sort(group.begin(), group.end(),
+                                 [](const std::pair<long long, size_t> &a,
+                                    const std::pair<long long, size_t> &b) {
+                                     return a.first > b.first;
+                                 });
+                for (size_t g = 0; g < group.size(); ++g)
+                    ops[group[g].second].stream = (int)(g % (kForkStreams + 1));
+                if (group.size() > 1) forked = true;
+                group.clear();
+            };
+            auto note = [&](long long size) { group.push_back(std::make_pair(size, ops.size() - 1)); };
+            for (auto &kv : P.lat) {
+                const int mn = kv.first.first, im = kv.first.second, nb = (int)kv.second.size();
+                const Work *tab = at<Work>(P.off_lat.at(kv.first));
+                add(kPhLattice, frames_of(kv.second), false, [=](hipStream_t st) {
+                    return launch_lattice(fp64, mn, im, fd, tab, nb, st);
+                });
+                note(nb);
+            }
+            deal();
+            for (auto &kv : P.gamma) {
+                const int mn = kv.first, nb = (int)kv.second.size();
+                const Work *tab = at<Work>(P.off_gamma.at(kv.first));
+                add(kPhGamma, frames_of(kv.second), false, [=](hipStream_t st) {
+                    return launch_gamma(fp64, mn, fd, tab, nb, st);
+                });
+                note(nb);
+            }
+            deal();
+            const int dirs = P.forward ? kDirFwd : kDirBoth;
+            auto steps = [&](int f) {
+                const Segment g = segment_of(frames_[f], L.fl[f], std::min(P.seg, L.fl[f].nseg - 1));
+                return (long long)(g.i1 - g.i0);
+            };
+            if (!P.chain_plain.empty()) {
+                const int nc = (int)P.chain_plain.size();
+                const int *tab = at<int>(P.off_chain);
+                const size_t lds = L.chain_lds;
+                add(kPhChain, sorted_frames(P.chain_plain), false, [=](hipStream_t st) {
+                    return launch_chain(fp64, fd, tab, nc, dirs, lds, st);
+                });
+                note(steps(P.chain_plain.front()));
+            }
+            for (auto &kv : P.chain_ring) {
+                const int shape = kv.first.first, mn = kv.first.second, nc = (int)kv.second.size();
+                const int *tab = at<int>(P.off_chain_ring.at(kv.first));
+                const size_t lds = L.ring_lds.at(kv.first);
+                add(kPhChain, sorted_frames(kv.second), false, [=](hipStream_t st) {
+                    return launch_chain_ring(fp64, shape, mn, fd, tab, nc, dirs, lds, st);
+                });
+                note(steps(kv.second.front()));
+            }
+            deal();
+            if (P.forward) continue;
+            if (!P.app_plain.empty()) {
+                const int nb = (int)P.app_plain.size();
+                const Work *tab = at<Work>(P.off_app);
+                const size_t lds = L.app_lds;
+                add(kPhApp, frames_of(P.app_plain), false, [=](hipStream_t st) {
+                    return launch_app(fp64, fd, tab, nb, lds, st);
+                });
+                note(nb);
+            }
+            for (auto &kv : P.app_tile) {
+                const int td = std::get<0>(kv.first), nw = std::get<1>(kv.first),
+                          mn = std::get<2>(kv.first), nb = (int)kv.second.size();
+                const Work *tab = at<Work>(P.off_app_tile.at(kv.first));
+                const size_t lds = L.app_tile_lds.at(kv.first);
+                add(kPhApp, frames_of(kv.second), false, [=](hipStream_t st) {
+                    return launch_app_tile(fp64, td, mn, nw, fd, tab, nb, lds, st);
+                });
+                note(nb);
+            }
+            deal();
+            if (!L.grad) continue;
+            for (auto &kv : P.lat) {
+                const int mn = kv.first.first, nb = (int)kv.second.size();
+                const Work *tab = at<Work>(P.off_lat.at(kv.first));
+                add(kPhWgrad, frames_of(kv.second), false, [=](hipStream_t st) {
+                    return fp64 ? adj_f64_w(mn, fd, tab, nb, st) : adj_f32_w(mn, fd, tab, nb, st);
+                });
+                note(nb);
+            }
+            deal();
+            for (auto &kv : P.adj) {
+                const int mn = std::get<0>(kv.first), im = std::get<1>(kv.first),
+                          da = std::get<2>(kv.first), nb = (int)kv.second.size();
+                const Work *tab = at<Work>(P.off_adj.at(kv.first));
+                const size_t lds = L.adj_lds.at(kv.first);
+                add(kPhAdjoint, frames_of(kv.second), false, [=](hipStream_t st) {
+                    return fp64 ? adj_f64_lattice(mn, im, da, fd, tab, nb, lds, st)
+                                : adj_f32_lattice(mn, im, da, fd, tab, nb, lds, st);
+                });
+                note(nb);
+            }
+            deal();
+        }
+        if (L.grad) {
+            const FrameDesc *fdl = at<FrameDesc>(L.passes.back().off_fd);
+            add(kPhDparams, {}, true, [=](hipStream_t st) { return launch_dparams(fdl, nf, st); });
+        }
+        if (flags & MAPDEC_FLAG_SERIAL) forked = false;
+        if (!forked)
+            for (Op &o : ops) o.stream = 0;
+    }
+    std::vector<mapdec_frame> frames_;   // host copy of the frame table (build_ops only)
+
+    // Every launch in order on st; with prof, an event is recorded first and
+    // after the last launch of each phase, and ev_phase[k] names the phase of
+    // the launches that end at event k.
+    hipError_t enqueue_serial(hipStream_t st, bool prof) {
         hipError_t e = hipSuccess;
         size_t k = 0;
         auto mark = [&](int phase) {
@@ -426,77 +597,74 @@ struct mapdec_plan {
             e = hipEventRecord(ev[k], st);
             ++k;
         };
-        const FrameDesc *fd0 = at<FrameDesc>(L.passes.front().off_fd);
         mark(kPhPack);
-        e = launch_init(fd0, L.nframes, st);
-        if (e == hipSuccess) e = launch_pack(fd0, at<Work>(L.off_pack), (int)L.pack.size(), st);
-        mark(kPhPack);
-        for (const Pass &P : L.passes) {
-            const FrameDesc *fd = at<FrameDesc>(P.off_fd);
-            for (auto &kv : P.lat) {
-                if (e != hipSuccess) break;
-                e = launch_lattice(L.fp64, kv.first.first, kv.first.second, fd,
-                                   at<Work>(P.off_lat.at(kv.first)), (int)kv.second.size(), st);
-            }
-            mark(kPhLattice);
-            for (auto &kv : P.gamma) {
-                if (e != hipSuccess) break;
-                e = launch_gamma(L.fp64, kv.first, fd, at<Work>(P.off_gamma.at(kv.first)),
-                                 (int)kv.second.size(), st);
-            }
-            mark(kPhGamma);
-            const int dirs = P.forward ? kDirFwd : kDirBoth;
-            if (e == hipSuccess)
-                e = launch_chain(L.fp64, fd, at<int>(P.off_chain), (int)P.chain_plain.size(), dirs,
-                                 L.chain_lds, st);
-            for (auto &kv : P.chain_ring) {
-                if (e != hipSuccess) break;
-                e = launch_chain_ring(L.fp64, kv.first.first, kv.first.second, fd,
-                                      at<int>(P.off_chain_ring.at(kv.first)),
-                                      (int)kv.second.size(), dirs, L.ring_lds.at(kv.first), st);
-            }
-            mark(kPhChain);
-            if (P.forward) continue;
-            if (e == hipSuccess)
-                e = launch_app(L.fp64, fd, at<Work>(P.off_app), (int)P.app_plain.size(), L.app_lds,
-                               st);
-            for (auto &kv : P.app_tile) {
-                if (e != hipSuccess) break;
-                e = launch_app_tile(L.fp64, std::get<0>(kv.first), std::get<2>(kv.first),
-                                    std::get<1>(kv.first), fd,
-                                    at<Work>(P.off_app_tile.at(kv.first)), (int)kv.second.size(),
-                                    L.app_tile_lds.at(kv.first), st);
-            }
-            mark(kPhApp);
-            if (!L.grad) continue;
-            for (auto &kv : P.lat) {
-                if (e != hipSuccess) break;
-                const Work *tab = at<Work>(P.off_lat.at(kv.first));
-                const int mn = kv.first.first;
-                e = L.fp64 ? adj_f64_w(mn, fd, tab, (int)kv.second.size(), st)
-                           : adj_f32_w(mn, fd, tab, (int)kv.second.size(), st);
-            }
-            mark(kPhWgrad);
-            for (auto &kv : P.adj) {
-                if (e != hipSuccess) break;
-                const Work *tab = at<Work>(P.off_adj.at(kv.first));
-                const int mn = std::get<0>(kv.first), imode = std::get<1>(kv.first),
-                          da = std::get<2>(kv.first);
-                const size_t lds = L.adj_lds.at(kv.first);
-                const int nb = (int)kv.second.size();
-                e = L.fp64 ? adj_f64_lattice(mn, imode, da, fd, tab, nb, lds, st)
-                           : adj_f32_lattice(mn, imode, da, fd, tab, nb, lds, st);
-            }
-            mark(kPhAdjoint);
-        }
-        if (L.grad) {
-            if (e == hipSuccess) e = launch_dparams(at<FrameDesc>(L.passes.back().off_fd), L.nframes, st);
-            mark(kPhDparams);
+        for (size_t j = 0; j < ops.size() && e == hipSuccess; ++j) {
+            e = ops[j].fn(st);
+            if (j + 1 == ops.size() || ops[j + 1].phase != ops[j].phase) mark(ops[j].phase);
         }
         nev = k;
         return e;
     }
-    size_t nev = 0;
+
+    // The launches spread over st and the forked streams: each launch waits
+    // for the last earlier launch that touched any of its frames (event
+    // dep[j + 1] follows op j; dep[0] forks from st), and st finally waits
+    // for every forked stream.
+    hipError_t enqueue_forked(hipStream_t st) {
+        constexpr int NS = kForkStreams + 1;
+        hipStream_t sx[NS] = {st};
+        for (int x = 1; x < NS; ++x) sx[x] = side[x - 1];
+        std::vector<int> last(L.nframes, 0);   // per frame: event of its last launch
+        int tail[NS];                         // per stream: event of its last launch
+        int seen[NS][NS];                     // newest event of stream y that x waited for
+        std::vector<int> ev_stream(ops.size() + 1, 0);
+        for (int x = 0; x < NS; ++x) {
+            tail[x] = x == 0 ? 0 : -1;
+            for (int y = 0; y < NS; ++y) seen[x][y] = -1;
+        }
+        hipError_t e = hipEventRecord(dep[0], st);
+        std::vector<int> need;
+        for (size_t j = 0; j < ops.size() && e == hipSuccess; ++j) {
+            const Op &o = ops[j];
+            const int x = o.stream;
+            need.clear();
+            if (o.all) {
+                for (int y = 0; y < NS; ++y)
+                    if (tail[y] >= 0) need.push_back(tail[y]);
+            } else {
+                for (int f : o.frames) need.push_back(last[f]);
+            }
+            if (tail[x] < 0) need.push_back(0);   // first launch on a forked stream
+            for (int d : need) {
+                const int y = ev_stream[d];
+                if (y == x || seen[x][y] >= d) continue;
+                e = hipStreamWaitEvent(sx[x], dep[d], 0);
+                if (e != hipSuccess) break;
+                seen[x][y] = d;
+            }
+            if (e != hipSuccess) break;
+            e = o.fn(sx[x]);
+            if (e != hipSuccess) break;
+            const int me = (int)j + 1;
+            e = hipEventRecord(dep[me], sx[x]);
+            ev_stream[me] = x;
+            tail[x] = me;
+            if (o.all)
+                std::fill(last.begin(), last.end(), me);
+            else
+                for (int f : o.frames) last[f] = me;
+        }
+        for (int y = 1; y < NS && e == hipSuccess; ++y)
+            if (tail[y] > seen[0][y]) e = hipStreamWaitEvent(st, dep[tail[y]], 0);
+        return e;
+    }
+
+    // Graph capture always takes the one-stream order: a capture that forked
+    // onto the plan's streams ended in a host-side crash inside the runtime
+    // on its first run, so forking is kept to eager runs.
+    hipError_t enqueue(hipStream_t st, bool prof = false, bool capture = false) {
+        return (prof || capture || !forked) ? enqueue_serial(st, prof) : enqueue_forked(st);
+    }
 };
 
 extern "C" {
@@ -653,8 +821,22 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
         e = hipMemcpyAsync(base + L.fl[f].off_cw, frames[f].code->cw.data(),
                            sizeof(uint32_t) * frames[f].code->q, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+        p->frames_.assign(frames, frames + nframes);
+        p->build_ops();
+        p->frames_.clear();
+        if (flags & MAPDEC_FLAG_GRAPH) p->forked = false;
+        for (int x = 0; p->forked && x < kForkStreams && e == hipSuccess; ++x)
+            e = hipStreamCreateWithFlags(&p->side[x], hipStreamNonBlocking);
+        if (p->forked) p->dep.reserve(p->ops.size() + 1);
+        for (size_t k = 0; p->forked && k <= p->ops.size() && e == hipSuccess; ++k) {
+            hipEvent_t x;
+            e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+            if (e == hipSuccess) p->dep.push_back(x);
+        }
+    }
     if (e != hipSuccess) {
-        delete p;
+        mapdec_plan_destroy(p);
         fail(MAPDEC_EDEVICE);
         return nullptr;
     }
@@ -670,7 +852,7 @@ int mapdec_plan_run(mapdec_plan *p, void *stream) {
             if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
             if (e == hipSuccess) e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                hipError_t e2 = p->enqueue(p->cap_stream);
+                hipError_t e2 = p->enqueue(p->cap_stream, false, true);
                 e = hipStreamEndCapture(p->cap_stream, &p->graph);
                 if (e2 != hipSuccess) e = e2;
             }
@@ -711,7 +893,13 @@ const char *mapdec_phase_name(int phase) {
 
 void mapdec_plan_destroy(mapdec_plan *p) {
     if (!p) return;
-    if (!p->ev.empty() || p->exec) hipStreamSynchronize(p->last_stream);
+    if (p->ran || !p->ev.empty()) hipStreamSynchronize(p->last_stream);
+    for (hipStream_t x : p->side)
+        if (x) {
+            hipStreamSynchronize(x);
+            hipStreamDestroy(x);
+        }
+    for (hipEvent_t x : p->dep) hipEventDestroy(x);
     for (hipEvent_t x : p->ev) hipEventDestroy(x);
     if (p->exec) hipGraphExecDestroy(p->exec);
     if (p->graph) hipGraphDestroy(p->graph);

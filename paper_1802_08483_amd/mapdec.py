@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmapdec.so")
 
 OK, EINVAL, EDRIFT, ENOPATH, ENOMEM, ESIZE, EDEVICE, EUNSUPPORTED = range(8)
 FP32, FP64 = 0, 1
-FLAG_GRAD, FLAG_GRAPH = 1, 2
+FLAG_GRAD, FLAG_GRAPH, FLAG_SERIAL = 1, 2, 4
 MAX_N, MAX_MN = 16, 8
 
 # every symbol include/mapdec.h declares
@@ -204,16 +204,17 @@ class Batch:
             raise MapdecError(st, "mapdec_grad")
         return self
 
-    def plan(self, graph: bool = True, stream=None) -> "Plan":
-        return Plan(self, graph=graph, stream=stream)
+    def plan(self, graph: bool = True, stream=None, serial: bool = False) -> "Plan":
+        return Plan(self, graph=graph, stream=stream, serial=serial)
 
 
 class Plan:
     """A ``mapdec_plan``: the batch's launches recorded once, replayed by run()."""
 
-    def __init__(self, batch: Batch, graph: bool = True, stream=None):
+    def __init__(self, batch: Batch, graph: bool = True, stream=None, serial: bool = False):
         self.batch = batch
-        flags = (FLAG_GRAPH if graph else 0) | (FLAG_GRAD if batch.grad else 0)
+        flags = ((FLAG_GRAPH if graph else 0) | (FLAG_GRAD if batch.grad else 0) |
+                 (FLAG_SERIAL if serial else 0))
         self._h = lib().mapdec_plan_create(batch.frames, batch.nframes, _ptr(batch.logp),
                                            _ptr(batch.dparams), _ptr(batch.status),
                                            _ptr(batch.ws), batch.ws_bytes, batch.precision,

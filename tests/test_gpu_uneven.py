@@ -66,3 +66,39 @@ def test_uneven_batch_gradient_slice():
         ref = oracle.decode_frame(frames[f], grad=True)
         assert _rel(b.dparams[f].cpu().numpy(), ref["dparams"]) <= 1e-4, f"frame {f}"
         assert _rel(b.dpriors[f].double().cpu().numpy(), ref["dprior"]) <= 1e-4, f"frame {f}"
+
+
+def _same(a, b, label):
+    assert torch.equal(a.logp, b.logp), label
+    assert torch.equal(a.status, b.status), label
+    for f in range(a.nframes):
+        assert torch.equal(a.apps[f], b.apps[f]), f"{label} frame {f}"
+    if a.grad:
+        assert torch.equal(a.dparams, b.dparams), label
+        for f in range(a.nframes):
+            assert torch.equal(a.dpriors[f], b.dpriors[f]), f"{label} frame {f}"
+
+
+def test_forked_streams_equal_serial_order():
+    # an eager plan deals the launch groups of different kernel instances to
+    # forked streams (per-frame dependencies); it gives the same bits as the
+    # one-stream order of a graph replay and of an eager serial plan, for
+    # decode, gradient and checkpointed passes
+    frames = wl.make_workload(3, nframes=192)
+    for grad, K in ((False, 0), (True, 0), (True, 37)):
+        runs = []
+        for graph, serial in ((True, False), (False, True), (False, False)):
+            b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=grad,
+                                         checkpoint_K=K)
+            p = b.plan(graph=graph, serial=serial)
+            for _ in range(2):
+                b.logp.fill_(0)
+                p.run()
+                torch.cuda.synchronize()
+            p.close()
+            runs.append(b)
+        assert (runs[0].status.cpu().numpy() == 0).all()
+        for r in runs[1:]:
+            _same(runs[0], r, f"grad={grad} K={K}")
+        del runs, b
+        torch.cuda.empty_cache()
