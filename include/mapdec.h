@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MAPDEC_VERSION 101
+#define MAPDEC_VERSION 102
 
 enum {
     MAPDEC_OK = 0,
@@ -55,7 +55,8 @@ enum { MAPDEC_FP32 = 0, MAPDEC_FP64 = 1 };
 enum {
     MAPDEC_FLAG_GRAD = 1,    /* the plan will also compute gradients        */
     MAPDEC_FLAG_GRAPH = 2,   /* replay the plan's launches as a HIP graph    */
-    MAPDEC_FLAG_SERIAL = 4   /* every launch in order on the run's stream    */
+    MAPDEC_FLAG_SERIAL = 4,  /* every launch in order on the run's stream    */
+    MAPDEC_FLAG_TUNE = 8     /* time launch choices first (plan creation)    */
 };
 
 /* Kernel limits of this build: n <= MAPDEC_MAX_N, mn <= MAPDEC_MAX_MN,
@@ -196,6 +197,30 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
                                 double *dparams, int32_t *status, void *ws, size_t ws_bytes,
                                 int precision, int flags, int checkpoint_K, void *stream);
 int mapdec_plan_run(mapdec_plan *plan, void *stream);
+
+/*
+ * Empirical tuning (the run-time choice of kernel configurations, Sec. V,
+ * made by measurement).  With MAPDEC_FLAG_TUNE, mapdec_plan_create first
+ * builds a decode-only plan of the same frames on ws, runs it once, and
+ * times the alternatives of two launch choices on its metric tables:
+ *   - the tiled APP kernel's D tile (2, 4 or 8 symbol values; at most 4 in
+ *     FP64, at most the default for q) and waves per workgroup (the default
+ *     one per 64 start indices, or half of it), per bucket (precision, q, n,
+ *     mn, default waves), on up to 8192 workgroups of the bucket's frames;
+ *   - the ring chain's workgroup shape (the first shape that fits and the
+ *     next two), per bucket (precision, uniform priors, codeword length,
+ *     mn, first shape), on up to 1024 of the bucket's frames.
+ * The fastest choice of each bucket goes into a table shared by every
+ * later plan of the process (buckets already in it are not timed again),
+ * then the plan is laid out with it.  The workspace size does not depend
+ * on these choices.  Tuning writes the frames' outputs (they are written
+ * again by every run) and blocks until its timing runs have finished; it
+ * allocates a small device scratch buffer for the duration.
+ */
+/* Number of buckets in the process's tuned table. */
+int mapdec_tune_entries(void);
+/* Empties the process's tuned table (later plans take the defaults). */
+void mapdec_tune_reset(void);
 /* Waits for the plan's pending work and frees it.  NULL is a no-op. */
 void mapdec_plan_destroy(mapdec_plan *plan);
 

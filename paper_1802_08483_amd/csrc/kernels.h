@@ -104,14 +104,15 @@ constexpr int app_tile_waves(int Mt, int n) {
     const int chunks = ((kAppTI - 1) * n + Mt + 63) / 64;
     return chunks < kAppMaxWaves ? chunks : kAppMaxWaves;
 }
-// LDS bytes of one tiled-APP workgroup: the rows as (mantissa, exponent)
-// pairs (8 bytes in FP32, 16 in FP64), Z and the exponent scale per symbol,
-// the U tile and the per-wave partial sums in the batch precision
-constexpr size_t app_tile_lds(int Mt, int mn, int n, int q, size_t tsize) {
+// LDS bytes of one tiled-APP workgroup of nwaves waves and D tiles of td:
+// the rows as (mantissa, exponent) pairs (8 bytes in FP32, 16 in FP64), Z
+// and the exponent scale per symbol, the U tile and the per-wave partial
+// sums in the batch precision
+constexpr size_t app_tile_lds(int Mt, int mn, int n, int q, size_t tsize, int td, int nwaves) {
     return (size_t)kAppTI * ((size_t)(Mt + 2 * app_tile_pad(n)) +
                              (size_t)(Mt + 2 * (app_tile_pad(n) + mn))) * (tsize == 8 ? 16 : 8) +
            (size_t)kAppTI * (sizeof(double) + sizeof(int)) + (size_t)kAppTI * q * tsize +
-           (size_t)app_tile_waves(Mt, n) * kAppTI * app_tile_td(q, tsize) * tsize;
+           (size_t)nwaves * kAppTI * td * tsize;
 }
 constexpr int kRingPrefetchRegs = 16;   // prefetch registers per thread in k_chain_ring
 

@@ -5,10 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -43,6 +45,22 @@ int validate_code_params(int q, int n, double Pi, double Pd, double Ps, int I, i
     return MAPDEC_OK;
 }
 
+// Tuned launch choices, shared by every plan of the process.  The tiled
+// APP's (D tile, waves) is tuned per (precision, q, n, mn, default waves),
+// the ring chain's workgroup shape per (precision, uniform priors, columns
+// per step, mn, first shape that fits); keys without an entry take the
+// defaults (app_tile_td, app_tile_waves, the first ring shape that fits).
+using TuneKey = std::array<int, 5>;
+struct TuneTable {
+    std::mutex mu;
+    std::map<TuneKey, std::pair<int, int>> app;   // -> (td, waves)
+    std::map<TuneKey, int> ring;                  // -> shape
+};
+TuneTable &tune_table() {
+    static TuneTable t;
+    return t;
+}
+
 // Sizes and places of one frame's workspace pieces.
 struct FrameLayout {
     int nwords = 0, sp = 0, gsp = 0, Mt = 0, Mn = 0, pack_blocks = 0;
@@ -50,6 +68,8 @@ struct FrameLayout {
     int ring_shape = -1, ring_chunk = 0, ring_cols = 0;   // ring_shape -1: plain chain
     bool app_tiled = false;
     std::tuple<int, int, int> app_key;                     // (td, waves, mn) when tiled
+    TuneKey app_bucket{}, ring_bucket{};                   // keys of the tuned choices
+    int ring_first = -1;                                   // first shape that fits
     size_t off_cw = 0, off_ybits = 0, off_R = 0, off_G = 0, off_alpha = 0, off_beta = 0,
            off_logA = 0, off_logB = 0, off_Zinv = 0, off_Zexp = 0, off_gacc = 0, off_ck = 0,
            off_bcarry = 0;
@@ -127,29 +147,36 @@ std::vector<Work> xcd_order(const std::vector<Work> &items) {
     return out;
 }
 
-// Ring-chain parameters (workgroup shape, steps per prefetch chunk, ring
-// slots, LDS bytes); false when the frame needs the plain workgroup chain
-// kernel instead.  n = columns per step: the codeword length for uniform
-// priors (the ring then covers at least 8 steps), Mt for general priors
-// (Gamma columns are not shared between steps; one step per chunk).
+// Ring-chain parameters of one workgroup shape (steps per prefetch chunk,
+// ring slots, LDS bytes); false when the shape does not fit the frame.
+// n = columns per step: the codeword length for uniform priors (the ring
+// then covers at least 8 steps), Mt for general priors (Gamma columns are
+// not shared between steps; one step per chunk).
+bool ring_fit(int shape, int Mt, int Mn, int n, int mn, bool uniform, size_t tsize,
+              size_t lds_limit, int &chunk, int &cols, size_t &lds) {
+    const RingShape &rs = kRingShapes[shape];
+    if (64 * rs.nw * rs.spl < Mt) return false;
+    const int nt = 64 * rs.nw, slots = nt * rs.spl;
+    // ring: a power of two covering the window of at least 8 steps; the
+    // chunk is as long as the ring and the prefetch registers allow
+    cols = 1;
+    while (cols < Mt + (uniform ? n * 7 : 0)) cols *= 2;
+    chunk = std::min({(cols - Mt) / n + 1, (nt * kRingPrefetchRegs) / (n * Mn), 64});
+    if (chunk < 1) return false;
+    const size_t roww = (size_t)slots + 2 * mn;
+    const size_t rphys = ring_duplicates(slots) ? cols + roww : cols;
+    // FP64 rows and wave partials, Gamma ring in the batch precision
+    lds = ((rs.one_row ? 1 : 2) * roww + 2 * rs.nw) * sizeof(double) + rphys * Mn * tsize;
+    return lds <= lds_limit;
+}
+
+// The first ring shape that fits, or false when the frame needs the plain
+// workgroup chain kernel instead.
 bool ring_params(int Mt, int Mn, int n, int mn, bool uniform, size_t tsize, size_t lds_limit,
                  int &shape, int &chunk, int &cols, size_t &lds) {
-    for (shape = 0; shape < kNumRingShapes; ++shape) {
-        const RingShape &rs = kRingShapes[shape];
-        if (64 * rs.nw * rs.spl < Mt) continue;
-        const int nt = 64 * rs.nw, slots = nt * rs.spl;
-        // ring: a power of two covering the window of at least 8 steps; the
-        // chunk is as long as the ring and the prefetch registers allow
-        cols = 1;
-        while (cols < Mt + (uniform ? n * 7 : 0)) cols *= 2;
-        chunk = std::min({(cols - Mt) / n + 1, (nt * kRingPrefetchRegs) / (n * Mn), 64});
-        if (chunk < 1) continue;
-        const size_t roww = (size_t)slots + 2 * mn;
-        const size_t rphys = ring_duplicates(slots) ? cols + roww : cols;
-        // FP64 rows and wave partials, Gamma ring in the batch precision
-        lds = ((rs.one_row ? 1 : 2) * roww + 2 * rs.nw) * sizeof(double) + rphys * Mn * tsize;
-        if (lds <= lds_limit) return true;
-    }
+    for (shape = 0; shape < kNumRingShapes; ++shape)
+        if (ring_fit(shape, Mt, Mn, n, mn, uniform, tsize, lds_limit, chunk, cols, lds))
+            return true;
     shape = -1;
     return false;
 }
@@ -214,22 +241,56 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         F.pack_blocks = (F.nwords + kPackWords - 1) / kPackWords;
         for (int b = 0; b < F.pack_blocks; ++b) L.pack.push_back(Work{f, b * kPackWords});
         {
-            const size_t tl = app_tile_lds(F.Mt, c->mn, c->n, c->q, L.tsize);
+            int td = app_tile_td(c->q, L.tsize), nw = app_tile_waves(F.Mt, c->n);
+            const size_t tl = app_tile_lds(F.Mt, c->mn, c->n, c->q, L.tsize, td, nw);
             // the tile kernel addresses R with 32-bit byte offsets
             const bool fits = (double)c->q * F.Mn * F.sp * L.tsize < 2147483648.0;
             F.app_tiled = fits && tl <= lds_limit;
             if (F.app_tiled) {
-                const int td = app_tile_td(c->q, L.tsize);
-                F.app_key = std::make_tuple(td, app_tile_waves(F.Mt, c->n), c->mn);
-                L.app_tile_lds[F.app_key] = std::max(L.app_tile_lds[F.app_key], tl);
+                F.app_bucket = TuneKey{L.fp64, c->q, c->n, c->mn, nw};
+                size_t lds = tl;
+                {
+                    TuneTable &T = tune_table();
+                    std::lock_guard<std::mutex> g(T.mu);
+                    auto it = T.app.find(F.app_bucket);
+                    if (it != T.app.end()) {
+                        const size_t l2 = app_tile_lds(F.Mt, c->mn, c->n, c->q, L.tsize,
+                                                       it->second.first, it->second.second);
+                        if (l2 <= lds_limit) {
+                            td = it->second.first;
+                            nw = it->second.second;
+                            lds = l2;
+                        }
+                    }
+                }
+                F.app_key = std::make_tuple(td, nw, c->mn);
+                L.app_tile_lds[F.app_key] = std::max(L.app_tile_lds[F.app_key], lds);
             } else {
                 L.app_lds = std::max(L.app_lds, (2 * (size_t)F.Mt + 2 * c->mn + c->q) * sizeof(double));
             }
         }
         int shape = -1;
         size_t rlds = 0;
-        if (ring_params(F.Mt, F.Mn, fr.prior ? F.Mt : c->n, c->mn, !fr.prior, L.tsize, lds_limit,
-                        shape, F.ring_chunk, F.ring_cols, rlds)) {
+        const int ncols = fr.prior ? F.Mt : c->n;
+        if (ring_params(F.Mt, F.Mn, ncols, c->mn, !fr.prior, L.tsize, lds_limit, shape,
+                        F.ring_chunk, F.ring_cols, rlds)) {
+            F.ring_first = shape;
+            F.ring_bucket = TuneKey{L.fp64, fr.prior ? 0 : 1, fr.prior ? 0 : c->n, c->mn, shape};
+            {
+                TuneTable &T = tune_table();
+                std::lock_guard<std::mutex> g(T.mu);
+                auto it = T.ring.find(F.ring_bucket);
+                int ch, co;
+                size_t l2;
+                if (it != T.ring.end() && it->second != shape &&
+                    ring_fit(it->second, F.Mt, F.Mn, ncols, c->mn, !fr.prior, L.tsize, lds_limit,
+                             ch, co, l2)) {
+                    shape = it->second;
+                    F.ring_chunk = ch;
+                    F.ring_cols = co;
+                    rlds = l2;
+                }
+            }
             F.ring_shape = shape;
             const auto key = std::make_pair(shape, c->mn);
             L.ring_lds[key] = std::max(L.ring_lds[key], rlds);
@@ -312,37 +373,35 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         for (auto &kv : P.gamma) kv.second = xcd_order(kv.second);
     }
 
-    // head: work tables and, per pass, descriptors and work tables
+    // head: the pack table and, per pass, the descriptors, the work tables
+    // back to back (8-byte entries) and the chain lists (4-byte entries), so
+    // the head's size depends on the work items only, not on how they are
+    // grouped into launches (tuned choices regroup them)
     size_t off = 0;
     L.off_pack = off;
     off = align_up(off + sizeof(Work) * L.pack.size());
     for (Pass &P : L.passes) {
         P.off_fd = off;
         off = align_up(off + sizeof(FrameDesc) * nframes);
-        for (auto &kv : P.lat) {
-            P.off_lat[kv.first] = off;
-            off = align_up(off + sizeof(Work) * kv.second.size());
-        }
-        for (auto &kv : P.adj) {
-            P.off_adj[kv.first] = off;
-            off = align_up(off + sizeof(Work) * kv.second.size());
-        }
-        for (auto &kv : P.gamma) {
-            P.off_gamma[kv.first] = off;
-            off = align_up(off + sizeof(Work) * kv.second.size());
-        }
+        auto place = [&](auto &groups, auto &offs) {
+            for (auto &kv : groups) {
+                offs[kv.first] = off;
+                off += sizeof(Work) * kv.second.size();
+            }
+        };
+        place(P.lat, P.off_lat);
+        place(P.adj, P.off_adj);
+        place(P.gamma, P.off_gamma);
+        place(P.app_tile, P.off_app_tile);
+        P.off_app = off;
+        off += sizeof(Work) * P.app_plain.size();
         P.off_chain = off;
-        off = align_up(off + sizeof(int) * P.chain_plain.size());
+        off += sizeof(int) * P.chain_plain.size();
         for (auto &kv : P.chain_ring) {
             P.off_chain_ring[kv.first] = off;
-            off = align_up(off + sizeof(int) * kv.second.size());
+            off += sizeof(int) * kv.second.size();
         }
-        for (auto &kv : P.app_tile) {
-            P.off_app_tile[kv.first] = off;
-            off = align_up(off + sizeof(Work) * kv.second.size());
-        }
-        P.off_app = off;
-        off = align_up(off + sizeof(Work) * P.app_plain.size());
+        off = align_up(off);
     }
     L.head = off;
 
@@ -715,9 +774,13 @@ size_t mapdec_workspace_size(const mapdec_frame *frames, int nframes, int precis
     return L.total;
 }
 
-mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double *logp,
-                                double *dparams, int32_t *status, void *ws, size_t ws_bytes,
-                                int precision, int flags, int checkpoint_K, void *stream) {
+}  // extern "C"
+
+namespace {
+
+mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, double *dparams,
+                         int32_t *status, void *ws, size_t ws_bytes, int precision, int flags,
+                         int checkpoint_K, void *stream) {
     if (!logp || !status || !ws || checkpoint_K < 0 ||
         ((flags & MAPDEC_FLAG_GRAD) && !dparams)) {
         fail(MAPDEC_EINVAL);
@@ -841,6 +904,204 @@ mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double 
         return nullptr;
     }
     return p;
+}
+
+// Milliseconds per launch of fn: one launch to warm up, then reps launches
+// between two events.
+hipError_t time_launch(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps,
+                       const std::function<hipError_t(hipStream_t)> &fn, float &ms) {
+    hipError_t e = fn(s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = fn(s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)reps;
+    return e;
+}
+
+// Caps on the work one bucket's candidates are timed on.
+constexpr size_t kTuneAppItems = 8192;   // tiled-APP workgroups
+constexpr size_t kTuneChains = 1024;     // ring chains (frames)
+
+// Fills the tune table for every bucket of plan t's frames that has no
+// entry yet.  t is a decode-only plan on the caller's workspace: one run of
+// it leaves the receiver metric, Gamma and both metric rows of its last
+// pass in place; the candidates then re-run that pass's APP tiles and
+// chains (which only rewrite outputs the final plan writes again).
+int tune_plan(mapdec_plan *t, hipStream_t s) {
+    const Layout &L = t->L;
+    const size_t lds_limit = device_lds_limit();
+    std::map<TuneKey, std::vector<int>> app_b, ring_b;
+    {
+        TuneTable &T = tune_table();
+        std::lock_guard<std::mutex> g(T.mu);
+        for (int f = 0; f < L.nframes; ++f) {
+            const FrameLayout &F = L.fl[f];
+            if (F.app_tiled && !T.app.count(F.app_bucket)) app_b[F.app_bucket].push_back(f);
+            if (F.ring_first >= 0 && !T.ring.count(F.ring_bucket))
+                ring_b[F.ring_bucket].push_back(f);
+        }
+    }
+    if (app_b.empty() && ring_b.empty()) return MAPDEC_OK;
+    hipError_t e = t->enqueue_serial(s, false);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return MAPDEC_EDEVICE;
+
+    const Pass &P = L.passes.back();   // main pass over segment 0
+    const size_t fd_bytes = align_up(sizeof(FrameDesc) * L.nframes);
+    const size_t tab_bytes = std::max(kTuneAppItems * sizeof(Work), kTuneChains * sizeof(int)) +
+                             sizeof(Work) * 4096;
+    unsigned char *scratch = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipMalloc(&scratch, fd_bytes + tab_bytes);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    FrameDesc *fd_tmp = reinterpret_cast<FrameDesc *>(scratch);
+    unsigned char *tab_tmp = scratch + fd_bytes;
+    std::vector<FrameDesc> fd_host(L.nframes);
+    if (e == hipSuccess)
+        e = hipMemcpy(fd_host.data(), t->at<FrameDesc>(P.off_fd), sizeof(FrameDesc) * L.nframes,
+                      hipMemcpyDeviceToHost);
+    const FrameDesc *fd = t->at<FrameDesc>(P.off_fd);
+    const int fp64 = L.fp64;
+
+    for (auto &kv : app_b) {
+        if (e != hipSuccess) break;
+        const TuneKey &key = kv.first;
+        const int q = key[1], n = key[2], mn = key[3], wdef = key[4];
+        std::vector<Work> items;
+        std::vector<int> used;
+        for (int f : kv.second) {
+            const FrameDesc &d = fd_host[f];
+            const int nb = (d.i1 - d.i0 + kAppTI - 1) / kAppTI;
+            if (!items.empty() && items.size() + nb > kTuneAppItems) break;
+            for (int b = 0; b < nb && items.size() < kTuneAppItems; ++b) items.push_back(Work{f, b});
+            used.push_back(f);
+        }
+        e = hipMemcpy(tab_tmp, items.data(), sizeof(Work) * items.size(), hipMemcpyHostToDevice);
+        const Work *tab = reinterpret_cast<const Work *>(tab_tmp);
+        const int nb = (int)items.size();
+        std::pair<int, int> best(app_tile_td(q, L.tsize), wdef);
+        float best_ms = -1.f;
+        for (int td = 2; td <= app_tile_td(q, L.tsize) && e == hipSuccess; td *= 2) {
+            std::vector<int> waves{wdef};
+            if ((wdef + 1) / 2 != wdef) waves.push_back((wdef + 1) / 2);
+            for (int nw : waves) {
+                size_t lds = 0;
+                for (int f : used)
+                    lds = std::max(lds, app_tile_lds(L.fl[f].Mt, mn, n, q, L.tsize, td, nw));
+                if (lds > lds_limit) continue;
+                float ms = 0.f;
+                e = time_launch(s, e0, e1, 3, [&](hipStream_t st) {
+                    return launch_app_tile(fp64, td, mn, nw, fd, tab, nb, lds, st);
+                }, ms);
+                if (e != hipSuccess) break;
+                if (best_ms < 0.f || ms < best_ms) {
+                    best_ms = ms;
+                    best = std::make_pair(td, nw);
+                }
+            }
+        }
+        if (e == hipSuccess) {
+            TuneTable &T = tune_table();
+            std::lock_guard<std::mutex> g(T.mu);
+            T.app[key] = best;
+        }
+    }
+
+    for (auto &kv : ring_b) {
+        if (e != hipSuccess) break;
+        const TuneKey &key = kv.first;
+        const int mn = key[3], first = key[4];
+        std::vector<int> used(kv.second.begin(),
+                              kv.second.begin() + std::min(kv.second.size(), kTuneChains));
+        int best = first;
+        float best_ms = -1.f;
+        for (int shape = first; shape < kNumRingShapes && shape <= first + 2 && e == hipSuccess;
+             ++shape) {
+            std::vector<FrameDesc> patched = fd_host;
+            size_t lds = 0;
+            bool ok = true;
+            for (int f : used) {
+                const FrameLayout &F = L.fl[f];
+                const bool uni = fd_host[f].uniform != 0;
+                int ch, co;
+                size_t l;
+                if (!ring_fit(shape, F.Mt, F.Mn, uni ? fd_host[f].n : F.Mt, mn, uni, L.tsize,
+                              lds_limit, ch, co, l)) {
+                    ok = false;
+                    break;
+                }
+                patched[f].ring_chunk = ch;
+                patched[f].ring_cols = co;
+                lds = std::max(lds, l);
+            }
+            if (!ok) continue;
+            e = hipMemcpy(fd_tmp, patched.data(), sizeof(FrameDesc) * L.nframes,
+                          hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(tab_tmp, used.data(), sizeof(int) * used.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) break;
+            const int *list = reinterpret_cast<const int *>(tab_tmp);
+            const int nc = (int)used.size();
+            float ms = 0.f;
+            e = time_launch(s, e0, e1, 2, [&](hipStream_t st) {
+                return launch_chain_ring(fp64, shape, mn, fd_tmp, list, nc, kDirBoth, lds, st);
+            }, ms);
+            if (e != hipSuccess) break;
+            if (best_ms < 0.f || ms < best_ms) {
+                best_ms = ms;
+                best = shape;
+            }
+        }
+        if (e == hipSuccess) {
+            TuneTable &T = tune_table();
+            std::lock_guard<std::mutex> g(T.mu);
+            T.ring[key] = best;
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (scratch) hipFree(scratch);
+    return e == hipSuccess ? MAPDEC_OK : MAPDEC_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+mapdec_plan *mapdec_plan_create(const mapdec_frame *frames, int nframes, double *logp,
+                                double *dparams, int32_t *status, void *ws, size_t ws_bytes,
+                                int precision, int flags, int checkpoint_K, void *stream) {
+    if (flags & MAPDEC_FLAG_TUNE) {
+        // tune on a decode-only plan, then lay out the real one with the choices
+        mapdec_plan *t = plan_create(frames, nframes, logp, nullptr, status, ws, ws_bytes,
+                                     precision, MAPDEC_FLAG_SERIAL, checkpoint_K, stream);
+        if (!t) return nullptr;
+        const int st = tune_plan(t, static_cast<hipStream_t>(stream));
+        mapdec_plan_destroy(t);
+        if (st != MAPDEC_OK) {
+            fail(st);
+            return nullptr;
+        }
+    }
+    return plan_create(frames, nframes, logp, dparams, status, ws, ws_bytes, precision,
+                       flags & ~MAPDEC_FLAG_TUNE, checkpoint_K, stream);
+}
+
+int mapdec_tune_entries(void) {
+    TuneTable &T = tune_table();
+    std::lock_guard<std::mutex> g(T.mu);
+    return (int)(T.app.size() + T.ring.size());
+}
+
+void mapdec_tune_reset(void) {
+    TuneTable &T = tune_table();
+    std::lock_guard<std::mutex> g(T.mu);
+    T.app.clear();
+    T.ring.clear();
 }
 
 int mapdec_plan_run(mapdec_plan *p, void *stream) {

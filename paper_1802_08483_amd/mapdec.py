@@ -18,13 +18,14 @@ LIB_PATH = os.path.join(HERE, "libmapdec.so")
 
 OK, EINVAL, EDRIFT, ENOPATH, ENOMEM, ESIZE, EDEVICE, EUNSUPPORTED = range(8)
 FP32, FP64 = 0, 1
-FLAG_GRAD, FLAG_GRAPH, FLAG_SERIAL = 1, 2, 4
+FLAG_GRAD, FLAG_GRAPH, FLAG_SERIAL, FLAG_TUNE = 1, 2, 4, 8
 MAX_N, MAX_MN = 16, 8
 
 # every symbol include/mapdec.h declares
 EXPORTS = ["mapdec_create", "mapdec_destroy", "mapdec_workspace_size", "mapdec_decode",
            "mapdec_grad", "mapdec_plan_create", "mapdec_plan_run", "mapdec_plan_destroy",
-           "mapdec_plan_profile", "mapdec_phase_name", "mapdec_last_error",
+           "mapdec_plan_profile", "mapdec_phase_name", "mapdec_tune_entries",
+           "mapdec_tune_reset", "mapdec_last_error",
            "mapdec_strerror", "mapdec_version"]
 
 
@@ -79,8 +80,22 @@ def lib() -> ctypes.CDLL:
         L.mapdec_strerror.restype = ctypes.c_char_p
         L.mapdec_version.argtypes = []
         L.mapdec_version.restype = i32
+        L.mapdec_tune_entries.argtypes = []
+        L.mapdec_tune_entries.restype = i32
+        L.mapdec_tune_reset.argtypes = []
+        L.mapdec_tune_reset.restype = None
         _lib = L
     return _lib
+
+
+def tune_entries() -> int:
+    """Buckets in the process's table of tuned launch choices."""
+    return lib().mapdec_tune_entries()
+
+
+def tune_reset() -> None:
+    """Empties the process's table of tuned launch choices."""
+    lib().mapdec_tune_reset()
 
 
 def strerror(status: int) -> str:
@@ -204,17 +219,19 @@ class Batch:
             raise MapdecError(st, "mapdec_grad")
         return self
 
-    def plan(self, graph: bool = True, stream=None, serial: bool = False) -> "Plan":
-        return Plan(self, graph=graph, stream=stream, serial=serial)
+    def plan(self, graph: bool = True, stream=None, serial: bool = False,
+             tune: bool = False) -> "Plan":
+        return Plan(self, graph=graph, stream=stream, serial=serial, tune=tune)
 
 
 class Plan:
     """A ``mapdec_plan``: the batch's launches recorded once, replayed by run()."""
 
-    def __init__(self, batch: Batch, graph: bool = True, stream=None, serial: bool = False):
+    def __init__(self, batch: Batch, graph: bool = True, stream=None, serial: bool = False,
+                 tune: bool = False):
         self.batch = batch
         flags = ((FLAG_GRAPH if graph else 0) | (FLAG_GRAD if batch.grad else 0) |
-                 (FLAG_SERIAL if serial else 0))
+                 (FLAG_SERIAL if serial else 0) | (FLAG_TUNE if tune else 0))
         self._h = lib().mapdec_plan_create(batch.frames, batch.nframes, _ptr(batch.logp),
                                            _ptr(batch.dparams), _ptr(batch.status),
                                            _ptr(batch.ws), batch.ws_bytes, batch.precision,
