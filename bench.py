@@ -13,7 +13,8 @@ Prints one JSON line: symbols per second, the roofline of the dominant
 kernel (live HIP-event timing per phase), the FP32 decode alone and the
 FP64 plain GPU decode of the same frames, the FP32 errors against the FP64
 CPU oracle, and the oracle's own throughput (decode plus gradient) on a
-bounded sample (host cores).
+bounded sample (host cores).  Beside it, the FP32 decode of the uneven
+4096-frame batch (tuned choices, launch groups on forked streams).
 """
 import argparse
 import json
@@ -119,6 +120,39 @@ def cpu_baseline(frames, budget_s=15.0):
                        f"thread, {wall:.2f} s wall, ~{t1 * nsample:.1f} s CPU)"}, refs)
 
 
+def uneven_batch(mapdec, workloads, torch, steps):
+    """FP32 decode of the uneven batch (4096 frames, q in {2, 8, 16}, n in
+    [4, 10], N in [50, 2000], Pi = Pd log-uniform in [1e-3, 1e-1]): first
+    every launch in order as one HIP graph with the default choices, then
+    an eager plan with tuned choices and launch groups forked over four
+    streams."""
+    frames = workloads.make_workload(3)
+    syms = sum(fr.N for fr in frames)
+    b = mapdec.batch_from_frames(frames, precision=mapdec.FP32)
+    mapdec.tune_reset()
+    p = b.plan(graph=True)
+    ms_graph = time_plan(p, steps, 1, torch)
+    p.close()
+    t0 = time.perf_counter()
+    p = b.plan(graph=False, tune=True)
+    tune_s = time.perf_counter() - t0
+    ms = time_plan(p, steps, 1, torch)
+    p.close()
+    ok = bool((b.status == 0).all())
+    worst = max(float((a.double().sum(1) - 1).abs().max()) for a in b.apps)
+    out = {"workload": workloads.WORKLOAD_NAMES[3], "step": "decode",
+           "value": round(syms / (ms * 1e-3), 1), "unit": "symbols/s",
+           "ms_per_step": round(ms, 4), "schedule": "eager, tuned, launch groups on 4 streams",
+           "tune_s": round(tune_s, 2), "tuned_buckets": mapdec.tune_entries(),
+           "graph_one_stream_default": {"value": round(syms / (ms_graph * 1e-3), 1),
+                                        "ms_per_step": round(ms_graph, 4)},
+           "all_frames_ok": ok, "app_row_sum_max_err": worst}
+    mapdec.tune_reset()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +160,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven 4096-frame batch (reported beside the main line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES bytes device-to-device a few times (a plain copy "
                          "kernel of known size, to calibrate HBM byte counters)")
@@ -190,6 +226,10 @@ def main():
         p64.close()
         del b64
 
+    uneven = None
+    if not args.no_uneven:
+        uneven = uneven_batch(mapdec, workloads, torch, max(3, args.steps // 4))
+
     cpu, refs = (None, {})
     if not args.no_cpu_baseline:
         cpu, refs = cpu_baseline(frames)
@@ -227,6 +267,7 @@ def main():
         "accuracy": {"frames_checked": len(refs), "app_max_abs_err": app_err,
                      "logp_max_rel_err": lp_err, "grad_max_rel_err": g_err},
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "uneven": uneven,
     }
     plan.close()
     print(json.dumps(line))

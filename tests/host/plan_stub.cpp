@@ -1,0 +1,332 @@
+// Host-only stand-ins for the HIP runtime calls and kernel launchers that
+// libmapdec's host code (mapdec.cpp) uses, so its plan logic runs on a CPU
+// under AddressSanitizer.  The "device" workspace is host memory; descriptor
+// and work-table uploads are real copies, and every launch reads its work
+// table to learn which frames it touches.
+//
+// Ordering is checked with vector clocks: each stream carries a clock, an
+// event records a copy, a wait merges it, and a launch ticks its stream.  A
+// launch must be ordered after the previous launch of every frame it
+// touches (same stream, or through waited events), and when the caller's
+// stream is synchronised it must be ordered after every launch so far.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <set>
+#include <vector>
+
+#include "kernels.h"
+#include "mapdec_internal.h"
+
+namespace {
+constexpr int kMaxStreams = 256;
+struct Clock {
+    int t[kMaxStreams] = {};
+};
+struct SStream {
+    int id;
+    Clock vc;
+};
+struct SEvent {
+    bool recorded = false;
+    Clock vc;
+};
+struct SGraph {
+    Clock vc;   // what the captured launches were ordered after, and themselves
+};
+std::set<void *> g_streams, g_events;
+std::map<unsigned char *, size_t> g_allocs;
+SStream g_null{0, {}};   // the legacy stream (handle 0)
+int g_nstreams = 1;
+long g_launches = 0, g_waits = 0;
+unsigned char *g_ws = nullptr;
+size_t g_ws_bytes = 0, g_ws_alloc = 0;
+int g_nframes = 0;
+struct Last {
+    int stream = -1, tick = 0;
+};
+std::vector<Last> g_last;   // per frame: the stream and tick of its last launch
+Last g_any[kMaxStreams];    // per stream: its last launch
+
+[[noreturn]] void die(const char *what) {
+    fprintf(stderr, "plan_stub: %s\n", what);
+    abort();
+}
+SStream *S(hipStream_t s) {
+    if (!s) return &g_null;
+    if (!g_streams.count((void *)s)) die("unknown stream");
+    return (SStream *)s;
+}
+bool in_range(const void *p, size_t n) {
+    const unsigned char *c = (const unsigned char *)p;
+    if (c >= g_ws && c + n <= g_ws + g_ws_bytes) return true;
+    for (auto &kv : g_allocs)
+        if (c >= kv.first && c + n <= kv.first + kv.second) return true;
+    return false;
+}
+bool readable(const void *p, size_t n) {
+    const unsigned char *c = (const unsigned char *)p;
+    if (c >= g_ws && c + n <= g_ws + g_ws_alloc) return true;
+    for (auto &kv : g_allocs)
+        if (c >= kv.first && c + n <= kv.first + kv.second) return true;
+    return false;
+}
+bool happened(const Last &l, const Clock &now) { return l.stream < 0 || now.t[l.stream] >= l.tick; }
+
+// One launch on st touching frames (all frames when all is set).
+void launch(hipStream_t st, const std::vector<int> &frames, bool all) {
+    SStream *x = S(st);
+    for (int f : frames)
+        if (f < 0 || f >= g_nframes) die("work item names a frame out of range");
+    const Clock &now = x->vc;
+    if (all) {
+        for (int y = 0; y < g_nstreams; ++y)
+            if (!happened(g_any[y], now)) die("launch over all frames not ordered after every launch");
+    } else {
+        for (int f : frames)
+            if (!happened(g_last[f], now)) die("launch not ordered after the last launch of its frame");
+    }
+    x->vc.t[x->id] += 1;
+    const Last me{x->id, x->vc.t[x->id]};
+    if (all)
+        for (Last &l : g_last) l = me;
+    else
+        for (int f : frames) g_last[f] = me;
+    g_any[x->id] = me;
+    ++g_launches;
+}
+std::vector<int> work_frames(const mapdec::Work *t, int n) {
+    if (n && !in_range(t, sizeof(mapdec::Work) * n)) die("work table outside the workspace");
+    std::vector<int> v;
+    if (n && !readable(t, sizeof(mapdec::Work) * n)) return v;   // not materialised
+    for (int i = 0; i < n; ++i) v.push_back(t[i].frame);
+    return v;
+}
+std::vector<int> list_frames(const int *t, int n) {
+    if (n && !in_range(t, sizeof(int) * n)) die("chain list outside the workspace");
+    std::vector<int> v;
+    if (n && !readable(t, sizeof(int) * n)) return v;
+    for (int i = 0; i < n; ++i) v.push_back(t[i]);
+    return v;
+}
+void check_fd(const mapdec::FrameDesc *fd) {
+    if (!in_range(fd, sizeof(mapdec::FrameDesc))) die("descriptor table outside the workspace");
+}
+}  // namespace
+
+// test driver hooks
+void stub_set_workspace(void *p, size_t bytes, size_t alloc, int nframes) {
+    g_ws = (unsigned char *)p;
+    g_ws_bytes = bytes;
+    g_ws_alloc = alloc;
+    g_nframes = nframes;
+    g_last.assign(nframes, Last{});
+    for (Last &l : g_any) l = Last{};
+}
+long stub_launches() { return g_launches; }
+long stub_waits() { return g_waits; }
+int stub_live_objects() { return (int)(g_streams.size() + g_events.size() + g_allocs.size()); }
+
+extern "C" {
+hipError_t hipGetDevice(int *d) {
+    *d = 0;
+    return hipSuccess;
+}
+hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t, int) {
+    *v = 160 * 1024;
+    return hipSuccess;
+}
+hipError_t hipEventCreate(hipEvent_t *e) {
+    SEvent *x = new SEvent;
+    g_events.insert(x);
+    *e = (hipEvent_t)x;
+    return hipSuccess;
+}
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { return hipEventCreate(e); }
+hipError_t hipEventDestroy(hipEvent_t e) {
+    if (!g_events.erase((void *)e)) die("destroying an unknown event");
+    delete (SEvent *)e;
+    return hipSuccess;
+}
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
+    if (!g_events.count((void *)e)) die("recording an unknown event");
+    SEvent *x = (SEvent *)e;
+    x->recorded = true;
+    x->vc = S(s)->vc;
+    return hipSuccess;
+}
+hipError_t hipEventSynchronize(hipEvent_t e) {
+    if (!g_events.count((void *)e)) die("unknown event");
+    return hipSuccess;
+}
+hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
+    if (!g_events.count((void *)a) || !g_events.count((void *)b)) die("unknown event");
+    *ms = 1.f;
+    return hipSuccess;
+}
+hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) {
+    if (g_nstreams >= kMaxStreams) die("too many streams");
+    SStream *x = new SStream{g_nstreams++, {}};
+    g_streams.insert(x);
+    *s = (hipStream_t)x;
+    return hipSuccess;
+}
+hipError_t hipStreamDestroy(hipStream_t s) {
+    if (!g_streams.erase((void *)s)) die("destroying an unknown stream");
+    delete (SStream *)s;
+    return hipSuccess;
+}
+hipError_t hipStreamSynchronize(hipStream_t s) {
+    SStream *x = S(s);
+    if (x == &g_null)   // the caller's stream: everything enqueued so far is done
+        for (int y = 0; y < g_nstreams; ++y)
+            if (!happened(g_any[y], x->vc)) die("caller's stream not joined with a forked stream");
+    return hipSuccess;
+}
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
+    if (!g_events.count((void *)e)) die("waiting on an unknown event");
+    SEvent *ev = (SEvent *)e;
+    if (!ev->recorded) die("waiting on an event never recorded");
+    SStream *x = S(s);
+    for (int y = 0; y < kMaxStreams; ++y) x->vc.t[y] = std::max(x->vc.t[y], ev->vc.t[y]);
+    ++g_waits;
+    return hipSuccess;
+}
+hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode) {
+    S(s);
+    return hipSuccess;
+}
+// Launches enqueued during a capture are checked as they are enqueued; a
+// replay orders the capturing stream's clock into the replay stream.
+hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t *g) {
+    SGraph *x = new SGraph;
+    x->vc = S(s)->vc;
+    *g = (hipGraph_t)x;
+    return hipSuccess;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t g, hipGraphNode_t *, char *, size_t) {
+    SGraph *y = new SGraph(*(SGraph *)g);
+    *x = (hipGraphExec_t)y;
+    return hipSuccess;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t g, hipStream_t s) {
+    SStream *x = S(s);
+    const SGraph *y = (const SGraph *)g;
+    for (int k = 0; k < kMaxStreams; ++k) x->vc.t[k] = std::max(x->vc.t[k], y->vc.t[k]);
+    return hipSuccess;
+}
+hipError_t hipGraphExecDestroy(hipGraphExec_t x) {
+    delete (SGraph *)x;
+    return hipSuccess;
+}
+hipError_t hipGraphDestroy(hipGraph_t g) {
+    delete (SGraph *)g;
+    return hipSuccess;
+}
+hipError_t hipMalloc(void **p, size_t n) {
+    *p = malloc(n);
+    g_allocs[(unsigned char *)*p] = n;
+    return hipSuccess;
+}
+hipError_t hipFree(void *p) {
+    if (!g_allocs.erase((unsigned char *)p)) die("freeing an unknown pointer");
+    free(p);
+    return hipSuccess;
+}
+hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind k) {
+    if (k == hipMemcpyHostToDevice) {
+        if (!in_range(d, n)) die("upload outside device memory");
+        if (readable(d, n)) memcpy(d, s, n);
+    } else {
+        if (!in_range(s, n)) die("download outside device memory");
+        if (readable(s, n)) memcpy(d, s, n);
+        else memset(d, 0, n);
+    }
+    return hipSuccess;
+}
+hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hipStream_t st) {
+    S(st);
+    return hipMemcpy(d, s, n, k);
+}
+}  // extern "C"
+
+namespace mapdec {
+hipError_t launch_init(const FrameDesc *fd, int nf, hipStream_t st) {
+    check_fd(fd);
+    launch(st, {}, true);
+    return hipSuccess;
+}
+hipError_t launch_pack(const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
+    check_fd(fd);
+    launch(st, work_frames(t, nb), true);
+    return hipSuccess;
+}
+hipError_t launch_lattice(int, int, int, const FrameDesc *fd, const Work *t, int nb,
+                          hipStream_t st) {
+    check_fd(fd);
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
+hipError_t launch_gamma(int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
+    check_fd(fd);
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
+hipError_t launch_chain(int, const FrameDesc *fd, const int *fr, int nc, int, size_t,
+                        hipStream_t st) {
+    check_fd(fd);
+    launch(st, list_frames(fr, nc), false);
+    return hipSuccess;
+}
+hipError_t launch_chain_ring(int, int shape, int, const FrameDesc *fd, const int *fr, int nc,
+                             int, size_t lds, hipStream_t st) {
+    check_fd(fd);
+    if (shape < 0 || shape >= kNumRingShapes || lds > 160 * 1024) die("bad ring launch");
+    launch(st, list_frames(fr, nc), false);
+    return hipSuccess;
+}
+hipError_t launch_app(int, const FrameDesc *fd, const Work *t, int nb, size_t, hipStream_t st) {
+    check_fd(fd);
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
+hipError_t launch_app_tile(int fp64, int td, int, int nw, const FrameDesc *fd, const Work *t,
+                           int nb, size_t lds, hipStream_t st) {
+    check_fd(fd);
+    if (td != 2 && td != 4 && td != 8) die("bad D tile");
+    if (fp64 && td > 4) die("FP64 D tile above 4");
+    if (nw < 1 || nw > kAppMaxWaves || lds > 160 * 1024) die("bad tiled-APP launch");
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
+hipError_t adj_f32_w(int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
+    check_fd(fd);
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
+hipError_t adj_f64_w(int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
+    check_fd(fd);
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
+hipError_t adj_f32_lattice(int, int, int, const FrameDesc *fd, const Work *t, int nb, size_t,
+                           hipStream_t st) {
+    check_fd(fd);
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
+hipError_t adj_f64_lattice(int, int, int, const FrameDesc *fd, const Work *t, int nb, size_t,
+                           hipStream_t st) {
+    check_fd(fd);
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
+hipError_t launch_dparams(const FrameDesc *fd, int nf, hipStream_t st) {
+    check_fd(fd);
+    launch(st, {}, true);
+    return hipSuccess;
+}
+}  // namespace mapdec
