@@ -110,4 +110,18 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // into one with per-lane selects, so the branch stays a scalar branch.
 __device__ __forceinline__ void keep_branch() { asm volatile(""); }
 
+// c ? a : b on two register values, written as a bitwise blend so that the
+// compiler cannot turn "c ? x[i] : y[i]" over two register arrays into one
+// access through a selected array address (which would move both arrays to
+// scratch memory).  For a wave-uniform c this is one bitfield-insert.
+__device__ __forceinline__ float blend(bool c, float a, float b) {
+    const uint32_t m = 0u - (uint32_t)c;
+    return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
+}
+__device__ __forceinline__ double blend(bool c, double a, double b) {
+    const uint64_t m = 0ull - (uint64_t)c;
+    return __longlong_as_double((long long)(((uint64_t)__double_as_longlong(a) & m) |
+                                            ((uint64_t)__double_as_longlong(b) & ~m)));
+}
+
 }  // namespace mapdec

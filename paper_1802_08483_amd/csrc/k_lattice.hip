@@ -15,17 +15,21 @@ namespace mapdec {
 //   F_n[k] = G_n[k]                                          (last row)
 // with a_t = a^t for t <= I and 0 beyond (at most I insertions in a row).
 // The two possible values of Q for each received position are prepared once
-// per lane (qx0 for a 0 codeword bit, qx1 for a 1), so a node costs one
-// multiply and 1 + IM fused multiply-adds.
+// per lane (qx0 for a 0 codeword bit, qx1 for a 1), so a node costs a select,
+// one multiply and 1 + IM fused multiply-adds.
 
+// G_r from F_{r-1}.  The codeword bit xb is wave-uniform; each node takes its
+// Q by a select on it (one copy of the row code: two copies behind a branch
+// cost a register merge of the whole row at every join).
 template <typename T, int MN, int NB>
 __device__ __forceinline__ void lattice_row_in(T (&G)[2 * MN + 1], const T (&F)[2 * MN + 1],
-                                               const T (&qx)[NB], T d, int r) {
+                                               const T (&qx0)[NB], const T (&qx1)[NB], bool xb,
+                                               T d, int r) {
 #pragma unroll
     for (int k = 0; k < 2 * MN + 1; ++k) {
         T v = (k + 1 < 2 * MN + 1) ? d * F[k + 1] : T(0);
         const int b = r + k - MN - 1;
-        if (b >= 0) v += qx[b] * F[k];
+        if (b >= 0) v += blend(xb, qx1[b], qx0[b]) * F[k];
         G[k] = v;
     }
 }
@@ -83,12 +87,7 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
         for (int r = 1; r <= kMaxN; ++r) {
             if (r > n) continue;   // constant trip count: the loop unrolls
             T G[KW];
-            if ((cw >> (n - r)) & 1u) {
-                lattice_row_in<T, MN, NB>(G, F, qx1, d, r);
-                keep_branch();
-            } else {
-                lattice_row_in<T, MN, NB>(G, F, qx0, d, r);
-            }
+            lattice_row_in<T, MN, NB>(G, F, qx0, qx1, (cw >> (n - r)) & 1u, d, r);
             if (r < n) {
 #pragma unroll
                 for (int k = 0; k < KW; ++k) {
