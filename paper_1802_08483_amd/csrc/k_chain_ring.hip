@@ -11,16 +11,29 @@
 // branches on its state.  One workgroup barrier per step.
 //
 // Rows are FP64 at every precision (their spread within a row can exceed
-// the FP32 range); Gamma stays in the batch precision.  Rows kept are the
-// paper's pre-normalisation metrics: row i+1 is
-// alpha'_{i+1} = sum alpha_i Gamma_i with alpha_i = alpha'_i / c_i and
-// c_i = sum_m alpha'_i(m) (eqs. 11, 12).  Each wave reduces its share of the
-// new row with DPP moves and leaves the partial in LDS; after the barrier
-// every thread adds the partials in the same order, so c_i is known at the
-// start of the next step and scales that step's results.  beta is handled
-// the same way from the other end.  Consumers of the rows are invariant to
-// a per-row scale, and log P(y) = sum_{k<N} log c_k + log alpha'_N(rho -
-// tau); the product of normalisers is carried as mantissa * 2^exponent.
+// the FP32 range); Gamma stays in the batch precision.  Each step scales its
+// new row by a power of two, 2^-e, so that the rows' sums stay near
+// 2^kRowExp (far above 1: the entries that matter on long noisy frames can
+// lie a thousand binary orders below a row's largest, and the FP64 range
+// below the row then holds them; the largest entries keep a margin of
+// hundreds of orders below the FP64 maximum): the
+// normalisation of eqs. 11-12 up to a scale factor, which every consumer of
+// the rows (APP, adjoint) is invariant to, applied exactly (no rounding) and
+// accounted exactly: log P(y) = (sum of the e) ln 2 + log alpha_N(rho - tau)
+// for the stored (scaled) last row.  The sum of the input row is not known
+// when the step starts: only the binary exponent m of the sum of the row
+// before it is (every thread adds that sum's wave partials; the partials of
+// the input row, whose values each thread still holds from writing them,
+// are reduced with DPP moves during the step, so no reduction and no
+// division sits on the path from one barrier to the next).  The step
+// predicts the input row's exponent from m, the exponents it applied to the
+// last two rows and the growth measured between the two rows before, and
+// takes e = prediction + that growth - kRowExp: the stored rows' exponents
+// then stay within the step-to-step change of the growth (a sum of two such
+// differences) of kRowExp, however long the chain; feeding m back alone
+// would let them drift without bound.  beta is handled the same way from the other
+// end.  A zero sum (no path) leaves the rows zero and is reported after the
+// chain.
 // A chain covers the symbols [i0, i1) of its frame's segment: it starts from
 // the row the descriptor gives (a checkpoint) or from the boundary state,
 // continues the cumulative log of the normalisers, and can copy its last
@@ -54,6 +67,8 @@
 
 namespace mapdec {
 
+constexpr int kRowExp = 640;   // binary exponent the stored rows' sums are held near
+
 // ONE (one metric row) is a template parameter, not only a macro, so the
 // one-row and two-row objects built from this file never define the same
 // kernel symbol.
@@ -63,7 +78,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     constexpr int Mn = 2 * MN + 1;
     constexpr int ROWW = NT * SPL + 2 * MN;            // padded row
     constexpr bool DUP = ring_duplicates(NT * SPL);
-    constexpr int PF = kRingPrefetchRegs;
+    constexpr int PF = ring_prefetch_regs(NW, sizeof(T));
     const int Mt = f.Mt, M = f.M, N = f.N;
     const int i0 = f.i0, i1 = f.i1, NS = i1 - i0;
     // column of state m at step i: n i + m (uniform priors: the start index)
@@ -177,12 +192,15 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             p += own[j];
         }
         p = wave_sum_dpp(p);
-        if ((tid & 63) == 0) part[wv] = p;
+        if ((tid & 63) == 0) part[wv] = p;   // stands in for the row before the first
     }
     __syncthreads();
-    int pp = 0;   // partial-sum buffer of the current input row
-    double pmant = 1.0;
-    int pexp = 0;
+    int pp = 0;      // partial-sum buffer read this step (the row before the input row)
+    long long lexp = 0;   // sum of the scale exponents applied so far
+    // exponent of the previous step's measured sum, exponents applied one and
+    // two steps ago; first: the step has no earlier measurement
+    int m2 = 0, u1 = 0, u2 = 0;
+    bool first = true;
     bool dead = false;
     for (int k = 0; k < nchunks && !dead; ++k) {
         if (k >= 1) {
@@ -197,69 +215,81 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             R csum = R(0);
 #pragma unroll
             for (int w = 0; w < NW; ++w) csum += part[pp * NW + w];
+            dead |= !(csum > R(0));
+            int m1;
+            (void)frexp(csum, &m1);   // binary exponent of the sum of the row before the input
+            if (first) m2 = m1;
+            first = false;
+            const int g = m1 - m2 + u2;         // growth measured between those two rows
+            const int rin = m1 + g - u1;        // predicted exponent of the input row's sum
+            // a zero (dead) or denormal sum keeps the scale finite
+            const int e = min(max(rin + g - kRowExp, -1000), 1000);
+            m2 = m1;
+            u2 = u1;
+            u1 = e;
+            const R scl = ldexp(R(1), -e);
+            lexp += e;
             const int sb = (n * i - MC) & mask;
             const R *cb = cur + MN + tid;
+            // Gamma(column, delta) for state mi = tid + NT j and drift change x - MN
+            auto gam = [&](int j, int x) -> R {
+                const int c = DIR == 0 ? sb + tid + NT * j - (x - MN) : sb + tid + NT * j;
+                return (R)(DUP ? ring[(c + MN) * Mn + x] : ring[(c & mask) * Mn + x]);
+            };
+            // the row value that meets it
+            auto rowv = [&](int j, int x) -> R {
+                return DIR == 0 ? cb[NT * j - (x - MN)] : cb[NT * j + x - MN];
+            };
+            auto partial = [&]() {   // partial sum of the input row, for the next step
+                R p = R(0);
+#pragma unroll
+                for (int j = 0; j < SPL; ++j) p += own[j];
+                p = wave_sum_dpp(p);
+                if ((tid & 63) == 0) part[(pp ^ 1) * NW + wv] = p;
+            };
+            // alpha'_{i+1}(m) = sum_delta alpha_i(m - delta) Gamma(n i + m - delta, delta)
+            // beta'_i(m) = sum_delta Gamma(n i + m, delta) beta_{i+1}(m + delta)
+            // (two partial sums over delta halve the dependent FMA chain)
             R acc[SPL];
-            if (DIR == 0) {
-                // alpha'_{i+1}(m) = sum_delta alpha_i(m - delta) Gamma(n i + m - delta, delta)
-                if (DUP) {
-                    const T *rb = ring + (sb + tid + MN) * Mn + MN;
+            if constexpr (SPL == 1) {
+                // operands loaded first, so the partial sum's reduction (a
+                // block of its own: one lane writes) overlaps their latency
+                R rv[Mn], gv[Mn];
 #pragma unroll
-                    for (int j = 0; j < SPL; ++j) {
-                        R a = R(0);
-#pragma unroll
-                        for (int d = -MN; d <= MN; ++d)
-                            a += cb[NT * j - d] * (R)rb[(NT * j - d) * Mn + d];
-                        acc[j] = a;
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < SPL; ++j) {
-                        R a = R(0);
-#pragma unroll
-                        for (int d = -MN; d <= MN; ++d)
-                            a += cb[NT * j - d] *
-                                 (R)ring[((sb + tid + NT * j - d) & mask) * Mn + d + MN];
-                        acc[j] = a;
-                    }
+                for (int x = 0; x < Mn; ++x) {
+                    rv[x] = rowv(0, x);
+                    gv[x] = gam(0, x);
                 }
+                partial();
+                R a0 = R(0), a1 = R(0);
+#pragma unroll
+                for (int x = 0; x < Mn; ++x) {
+                    if (x & 1) a1 += rv[x] * gv[x]; else a0 += rv[x] * gv[x];
+                }
+                acc[0] = a0 + a1;
             } else {
-                // beta'_i(m) = sum_delta Gamma(n i + m, delta) beta_{i+1}(m + delta)
+                partial();
 #pragma unroll
                 for (int j = 0; j < SPL; ++j) {
-                    const T *rb = DUP ? ring + (sb + tid + MN + NT * j) * Mn
-                                      : ring + ((sb + tid + NT * j) & mask) * Mn;
-                    R a = R(0);
+                    R a0 = R(0), a1 = R(0);
 #pragma unroll
-                    for (int kk = 0; kk < Mn; ++kk) a += (R)rb[kk] * cb[NT * j + kk - MN];
-                    acc[j] = a;
+                    for (int x = 0; x < Mn; ++x) {
+                        if (x & 1) a1 += rowv(j, x) * gam(j, x); else a0 += rowv(j, x) * gam(j, x);
+                    }
+                    acc[j] = a0 + a1;
                 }
-            }
-            if (!(csum > R(0))) {
-                dead = true;
-                break;
-            }
-            const R inv = R(1) / csum;
-            if (i != (DIR == 0 ? 0 : N - 1)) {
-                int e;
-                pmant = frexp(pmant * (double)csum, &e);
-                pexp += e;
             }
             const int row = DIR == 0 ? i + 1 : i;
             if (ONE) __syncthreads();   // every read of the row is done
             R *nb = nxt + MN + tid;
-            R p = R(0);
 #pragma unroll
             for (int j = 0; j < SPL; ++j) {
                 const int mi = tid + NT * j;
-                const R v = (mi < Mt) ? acc[j] * inv : R(0);
+                const R v = (mi < Mt) ? acc[j] * scl : R(0);
                 own[j] = v;
-                p += v;
                 nb[NT * j] = v;
                 if (mi < Mt) out[(size_t)(row - i0) * Mt + mi] = v;
             }
-            p = wave_sum_dpp(p);
-            if ((tid & 63) == 0) part[(pp ^ 1) * NW + wv] = p;
             pp ^= 1;
             R *tmp = cur;
             cur = nxt;
@@ -267,7 +297,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             __syncthreads();
         }
     }
-    const double lsum = lbase + log(pmant) + (double)pexp * 0.69314718055994530942;
+    const double lsum = lbase + (double)lexp * 0.69314718055994530942;
     if (dead) {
         if (tid == 0) {
             atomicOr(f.status, kStatusNoPath);

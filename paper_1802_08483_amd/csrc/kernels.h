@@ -114,6 +114,10 @@ constexpr size_t app_tile_lds(int Mt, int mn, int n, int q, size_t tsize, int td
            (size_t)kAppTI * (sizeof(double) + sizeof(int)) + (size_t)kAppTI * q * tsize +
            (size_t)nwaves * kAppTI * td * tsize;
 }
-constexpr int kRingPrefetchRegs = 16;   // prefetch registers per thread in k_chain_ring
+// prefetch registers per thread in k_chain_ring (fewer in the 16-wave shapes,
+// whose threads have 128 VGPRs, and fewer still for 8-byte Gamma there)
+__host__ __device__ constexpr int ring_prefetch_regs(int nw, size_t tsize) {
+    return nw >= 16 ? (tsize == 8 ? 4 : 8) : 16;
+}
 
 }  // namespace mapdec

@@ -161,7 +161,7 @@ bool ring_fit(int shape, int Mt, int Mn, int n, int mn, bool uniform, size_t tsi
     // chunk is as long as the ring and the prefetch registers allow
     cols = 1;
     while (cols < Mt + (uniform ? n * 7 : 0)) cols *= 2;
-    chunk = std::min({(cols - Mt) / n + 1, (nt * kRingPrefetchRegs) / (n * Mn), 64});
+    chunk = std::min({(cols - Mt) / n + 1, (nt * ring_prefetch_regs(rs.nw, tsize)) / (n * Mn), 64});
     if (chunk < 1) return false;
     const size_t roww = (size_t)slots + 2 * mn;
     const size_t rphys = ring_duplicates(slots) ? cols + roww : cols;
