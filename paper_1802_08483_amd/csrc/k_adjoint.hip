@@ -187,7 +187,8 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
     const FrameDesc &f = fd[w.frame];
     if (*f.status != kStatusOk) return;
     const int lane = threadIdx.x;
-    const int s = f.s0 + w.item + lane;   // column s - s0 of W
+    const int chunk = w.item & 63;   // codewords [chunk dq, (chunk + 1) dq)
+    const int s = f.s0 + (w.item & ~63) + lane;   // column s - s0 of W
     const bool live = s <= f.s1;
     const int n = f.n, q = f.q, rho = f.rho;
     const T d = (T)f.d, t1 = (T)f.t1, t0 = (T)f.t0;
@@ -247,7 +248,8 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
         }
     };
 
-    for (int D = 0; D < q; ++D) {
+    const int Dlo = chunk * f.dq, Dhi = min(q, Dlo + f.dq);
+    for (int D = Dlo; D < Dhi; ++D) {
         const uint32_t cw = __builtin_amdgcn_readfirstlane(f.cw[D]);   // wave-uniform
         // output adjoints of this lattice (zero for invalid segments)
         T Fb[KW];
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
     g1 = wave_sum(g1);
     g0 = wave_sum(g0);
     if (lane == 0) {
-        double *o = f.gacc + (size_t)(w.item / 64) * 4;
+        double *o = f.gacc + ((size_t)(w.item >> 6) * f.dsplit + chunk) * 4;
         o[0] = ga;
         o[1] = gd;
         o[2] = g1;

@@ -41,7 +41,8 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
     constexpr int NB = kMaxN + MN;   // received positions a lattice can read
     const Work w = tab[blockIdx.x];
     const FrameDesc &f = fd[w.frame];
-    const int s = f.s0 + w.item + (int)threadIdx.x;   // column s - s0 of the tables
+    const int chunk = w.item & 63;   // codewords [chunk dq, (chunk + 1) dq)
+    const int s = f.s0 + (w.item & ~63) + (int)threadIdx.x;   // column s - s0 of the tables
     if (s > f.s1) return;
     const int n = f.n, q = f.q, rho = f.rho;
     const T d = (T)f.d, t1 = (T)f.t1, t0 = (T)f.t0;
@@ -75,7 +76,8 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
 
     T *R = (T *)f.R;
     const size_t sp = (size_t)f.sp;
-    for (int D = 0; D < q; ++D) {
+    const int Dlo = chunk * f.dq, Dhi = min(q, Dlo + f.dq);
+    for (int D = Dlo; D < Dhi; ++D) {
         const uint32_t cw = __builtin_amdgcn_readfirstlane(f.cw[D]);   // wave-uniform
         T F[KW];
 #pragma unroll
@@ -111,10 +113,16 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
         }
     }
     if (f.uniform) {
-        T *G = (T *)f.G;
-        const T invq = T(1) / T(q);
+        if (f.dsplit == 1) {
+            T *G = (T *)f.G;
+            const T invq = T(1) / T(q);
 #pragma unroll
-        for (int k = 0; k < KW; ++k) G[(size_t)k * sp + (s - f.s0)] = gsum[k] * invq;
+            for (int k = 0; k < KW; ++k) G[(size_t)k * sp + (s - f.s0)] = gsum[k] * invq;
+        } else {   // this chunk's partial sums; k_gsum adds the chunks
+            T *P = (T *)f.Gpart;
+#pragma unroll
+            for (int k = 0; k < KW; ++k) P[((size_t)chunk * KW + k) * sp + (s - f.s0)] = gsum[k];
+        }
     }
 }
 

@@ -90,18 +90,21 @@ __global__ __launch_bounds__(kGammaLanes) void k_gamma(const FrameDesc *__restri
 //   d/dPd = g_d     - (1 - Ps) g_t1 - Ps g_t0
 //   d/dPs = -Pt g_t1 + Pt g_t0
 
-__global__ void k_dparams(const FrameDesc *__restrict__ fd, int nframes) {
-    const int fi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (fi >= nframes) return;
-    const FrameDesc &f = fd[fi];
+// One workgroup per frame: strided FP64 sums over the partials, then a
+// fixed-order reduction across the workgroup.
+__global__ __launch_bounds__(256) void k_dparams(const FrameDesc *__restrict__ fd) {
+    __shared__ double red[4];
+    const FrameDesc &f = fd[blockIdx.x];
     if (!f.dparams) return;
     if (*f.status != kStatusOk) {
-        f.dparams[0] = f.dparams[1] = f.dparams[2] = NAN;
+        if (threadIdx.x == 0) f.dparams[0] = f.dparams[1] = f.dparams[2] = NAN;
         return;
     }
     double g[4] = {0, 0, 0, 0};
-    for (int b = 0; b < f.gacc_n; ++b)
+    for (int b = threadIdx.x; b < f.gacc_n; b += blockDim.x)
         for (int t = 0; t < 4; ++t) g[t] += f.gacc_all[(size_t)b * 4 + t];
+    for (int t = 0; t < 4; ++t) g[t] = block_sum(g[t], red);
+    if (threadIdx.x != 0) return;
     // without the d/da sweep: a g_a - d g_d = rho - tau (every path inserts
     // rho - tau more bits than it deletes)
     if (!f.adj_da) g[0] = ((double)(f.rho - f.tau) + f.d * g[1]) / f.a;
@@ -109,6 +112,33 @@ __global__ void k_dparams(const FrameDesc *__restrict__ fd, int nframes) {
     f.dparams[0] = 0.5 * g[0] - (1.0 - Ps) * g[2] - Ps * g[3];
     f.dparams[1] = g[1] - (1.0 - Ps) * g[2] - Ps * g[3];
     f.dparams[2] = -Pt * g[2] + Pt * g[3];
+}
+
+// Gamma(s, delta) = sum_D R(s, D, delta) / q for uniform priors whose
+// lattice items are split over codeword chunks (the lattice kernel writes it
+// itself otherwise): the sum of the chunks' partial sums, which the lattice
+// items leave in f.Gpart ([dsplit][Mn][sp]).  Lane = start index s; every
+// read is a coalesced row segment.
+template <typename T, int MN>
+__global__ __launch_bounds__(64) void k_gsum(const FrameDesc *__restrict__ fd,
+                                             const Work *__restrict__ tab) {
+    constexpr int KW = 2 * MN + 1;
+    const Work w = tab[blockIdx.x];
+    const FrameDesc &f = fd[w.frame];
+    const int s = f.s0 + w.item + (int)threadIdx.x;
+    if (s > f.s1) return;
+    const size_t sp = (size_t)f.sp, c = (size_t)(s - f.s0);
+    const gptr<const T> P = to_global((const T *)f.Gpart);
+    T acc[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) acc[k] = T(0);
+    for (int x = 0; x < f.dsplit; ++x)
+#pragma unroll
+        for (int k = 0; k < KW; ++k) acc[k] += P[((size_t)x * KW + k) * sp + c];
+    T *G = (T *)f.G;
+    const T invq = T(1) / T(f.q);
+#pragma unroll
+    for (int k = 0; k < KW; ++k) G[(size_t)k * sp + c] = acc[k] * invq;
 }
 
 // ---------------------------------------------------------------------------
@@ -149,8 +179,32 @@ hipError_t launch_gamma(int fp64, int mn, const FrameDesc *fd, const Work *tab, 
                 : gamma_t<float>(mn, fd, tab, nblocks, st);
 }
 
+template <typename T>
+static hipError_t gsum_t(int mn, const FrameDesc *fd, const Work *tab, int nblocks,
+                         hipStream_t st) {
+    switch (mn) {
+#define MAPDEC_GSUM_CASE(K)                                                                \
+    case K:                                                                                \
+        hipLaunchKernelGGL((k_gsum<T, K>), dim3(nblocks), dim3(64), 0, st, fd, tab);       \
+        break;
+        MAPDEC_GSUM_CASE(0) MAPDEC_GSUM_CASE(1) MAPDEC_GSUM_CASE(2) MAPDEC_GSUM_CASE(3)
+        MAPDEC_GSUM_CASE(4) MAPDEC_GSUM_CASE(5) MAPDEC_GSUM_CASE(6) MAPDEC_GSUM_CASE(7)
+        MAPDEC_GSUM_CASE(8)
+#undef MAPDEC_GSUM_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gsum(int fp64, int mn, const FrameDesc *fd, const Work *tab, int nblocks,
+                       hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    return fp64 ? gsum_t<double>(mn, fd, tab, nblocks, st)
+                : gsum_t<float>(mn, fd, tab, nblocks, st);
+}
+
 hipError_t launch_dparams(const FrameDesc *fd, int nframes, hipStream_t st) {
-    hipLaunchKernelGGL(k_dparams, dim3((nframes + 63) / 64), dim3(64), 0, st, fd, nframes);
+    hipLaunchKernelGGL(k_dparams, dim3(nframes), dim3(256), 0, st, fd);
     return hipGetLastError();
 }
 

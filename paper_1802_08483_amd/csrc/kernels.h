@@ -29,6 +29,10 @@ hipError_t launch_lattice(int fp64, int mn, int imode, const FrameDesc *fd, cons
 // Gamma_i for general priors; every frame of the launch has drift limit mn.
 hipError_t launch_gamma(int fp64, int mn, const FrameDesc *fd, const Work *tab, int nblocks,
                         hipStream_t st);
+// Gamma(s, .) = sum_D R / q for uniform-prior frames whose lattice items are
+// split over codeword chunks (items: start-offset blocks of 64).
+hipError_t launch_gsum(int fp64, int mn, const FrameDesc *fd, const Work *tab, int nblocks,
+                       hipStream_t st);
 // Chains over each frame's segment; dirs: 1 forward (alpha) only, 2 backward
 // (beta) only, 3 both (one workgroup per chain).
 constexpr int kDirFwd = 1, kDirBwd = 2, kDirBoth = 3;
@@ -83,6 +87,12 @@ hipError_t launch_dparams(const FrameDesc *fd, int nframes, hipStream_t st);
 // Block sizes the host uses to build work tables.
 constexpr int kPackWords = 8;      // packed words per pack workgroup (256 threads)
 constexpr int kLatticeLanes = 64;  // start indices per lattice workgroup
+// Codeword chunks of lattice / adjoint items: a pass whose lattice has fewer
+// than kLatticeTarget workgroups splits each into up to kLatticeSplitMax
+// items of at least kLatticeMinDq codewords.
+constexpr long long kLatticeTarget = 4096;
+constexpr int kLatticeSplitMax = 16;
+constexpr int kLatticeMinDq = 4;
 constexpr int kGammaLanes = 64;    // drift states per Gamma workgroup
 constexpr int kChainThreads = 256;
 constexpr int kAppThreads = 64;

@@ -72,9 +72,10 @@ struct FrameLayout {
     int ring_first = -1;                                   // first shape that fits
     size_t off_cw = 0, off_ybits = 0, off_R = 0, off_G = 0, off_alpha = 0, off_beta = 0,
            off_logA = 0, off_logB = 0, off_Zinv = 0, off_Zexp = 0, off_gacc = 0, off_ck = 0,
-           off_bcarry = 0;
+           off_bcarry = 0, off_gpart = 0;
     std::vector<int> gacc_first;   // first [4] partial of each segment
     int gacc_n = 0;
+    int dq = 0, dsplit = 1;        // codewords per lattice / adjoint item, items per block
 };
 
 // Segment j of a frame: symbols [i0, i1) and the start indices [s0, s1]
@@ -104,6 +105,10 @@ struct Pass {
     size_t off_fd = 0;
     std::map<std::pair<int, int>, std::vector<Work>> lat;          // (mn, imode)
     std::map<std::pair<int, int>, size_t> off_lat;
+    // per mn: the start-index blocks without codeword chunks (W), and those
+    // of uniform-prior frames whose lattice is split (Gamma from R)
+    std::map<int, std::vector<Work>> wlat, gsum;
+    std::map<int, size_t> off_wlat, off_gsum;
     std::map<int, std::vector<Work>> gamma;                         // mn
     std::map<int, size_t> off_gamma;
     std::vector<int> chain_plain;
@@ -230,12 +235,9 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         F.nseg = (fr.N + F.K - 1) / F.K;
         smax = std::max(smax, F.nseg);
         F.sp = 0;
-        F.gacc_first.resize(F.nseg);
         for (int j = 0; j < F.nseg; ++j) {
             const Segment g = segment_of(fr, F, j);
             F.sp = std::max(F.sp, (g.s1 - g.s0 + 1 + 63) / 64 * 64);
-            F.gacc_first[j] = F.gacc_n;
-            F.gacc_n += lattice_blocks(g);
         }
         F.nwords = (fr.rho + 63) / 32 + 2;
         F.pack_blocks = (F.nwords + kPackWords - 1) / kPackWords;
@@ -309,6 +311,29 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
     }
     if (L.chain_lds > 65536 || L.app_lds > 65536) return MAPDEC_EUNSUPPORTED;
 
+    // Codeword chunks: when one pass's lattice workgroups (one wave each,
+    // looping over every codeword) are too few to fill the device, every
+    // start-index block becomes dsplit items of dq codewords each.
+    {
+        long long blocks = 0;
+        for (int f = 0; f < nframes; ++f)
+            blocks += lattice_blocks(segment_of(frames[f], L.fl[f], 0));
+        const int split = (int)std::min<long long>(
+            kLatticeSplitMax, std::max<long long>(1, (kLatticeTarget + blocks - 1) / blocks));
+        for (int f = 0; f < nframes; ++f) {
+            FrameLayout &F = L.fl[f];
+            const int q = frames[f].code->q;
+            F.dq = split == 1 ? q : std::max(std::min(q, kLatticeMinDq), (q + split - 1) / split);
+            F.dsplit = (q + F.dq - 1) / F.dq;
+            F.gacc_first.assign(F.nseg, 0);
+            F.gacc_n = 0;
+            for (int j = 0; j < F.nseg; ++j) {
+                F.gacc_first[j] = F.gacc_n;
+                F.gacc_n += lattice_blocks(segment_of(frames[f], F, j)) * F.dsplit;
+            }
+        }
+    }
+
     // passes: forward over segments 0 .. S-2, then main passes S-1 .. 0
     for (int j = 0; j + 1 < smax; ++j) {
         Pass P;
@@ -332,8 +357,16 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             if (P.forward ? j + 1 >= F.nseg : j >= F.nseg) continue;
             const Segment g = segment_of(fr, F, j);
             auto &lv = P.lat[std::make_pair(c->mn, frame_imode(c))];
+            auto &wv = P.wlat[c->mn];
             const int nb = lattice_blocks(g);
-            for (int b = 0; b < nb; ++b) lv.push_back(Work{f, b * kLatticeLanes});
+            for (int b = 0; b < nb; ++b) {
+                wv.push_back(Work{f, b * kLatticeLanes});
+                for (int x = 0; x < F.dsplit; ++x) lv.push_back(Work{f, b * kLatticeLanes + x});
+            }
+            if (!fr.prior && F.dsplit > 1) {
+                auto &gs = P.gsum[c->mn];
+                for (int b = 0; b < nb; ++b) gs.push_back(Work{f, b * kLatticeLanes});
+            }
             if (fr.prior) {
                 const int per_i = (F.Mt + kGammaLanes - 1) / kGammaLanes;
                 auto &gv = P.gamma[c->mn];
@@ -350,7 +383,8 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             if (L.grad) {
                 auto &av = P.adj[std::make_tuple(c->mn, frame_imode(c),
                                                  adjoint_needs_da(c->Pi, c->Pd) ? 1 : 0)];
-                for (int b = 0; b < nb; ++b) av.push_back(Work{f, b * kLatticeLanes});
+                for (int b = 0; b < nb; ++b)
+                    for (int x = 0; x < F.dsplit; ++x) av.push_back(Work{f, b * kLatticeLanes + x});
             }
         }
         // longest chains first, so that the longest ones do not start last
@@ -370,6 +404,8 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         // keep them on one XCD's L2
         for (auto &kv : P.app_tile) kv.second = xcd_order(kv.second);
         for (auto &kv : P.lat) kv.second = xcd_order(kv.second);
+        for (auto &kv : P.wlat) kv.second = xcd_order(kv.second);
+        for (auto &kv : P.gsum) kv.second = xcd_order(kv.second);
         for (auto &kv : P.gamma) kv.second = xcd_order(kv.second);
     }
 
@@ -390,6 +426,8 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             }
         };
         place(P.lat, P.off_lat);
+        place(P.wlat, P.off_wlat);
+        place(P.gsum, P.off_gsum);
         place(P.adj, P.off_adj);
         place(P.gamma, P.off_gamma);
         place(P.app_tile, P.off_app_tile);
@@ -420,6 +458,10 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         F.off_G = off;
         F.gsp = fr.prior ? (F.K * F.Mt + 63) / 64 * 64 : F.sp;
         off = align_up(off + T * (size_t)F.Mn * F.gsp);
+        if (!fr.prior && F.dsplit > 1) {
+            F.off_gpart = off;   // per-chunk partial sums of R for Gamma
+            off = align_up(off + T * (size_t)F.dsplit * F.Mn * F.sp);
+        }
         F.off_alpha = off;   // metric rows are FP64 at every precision
         off = align_up(off + sizeof(double) * (size_t)(F.K + 1) * F.Mt);
         F.off_beta = off;
@@ -558,6 +600,14 @@ struct mapdec_plan {
                 });
                 note(nb);
             }
+            for (auto &kv : P.gsum) {
+                const int mn = kv.first, nb = (int)kv.second.size();
+                const Work *tab = at<Work>(P.off_gsum.at(kv.first));
+                add(kPhGamma, frames_of(kv.second), false, [=](hipStream_t st) {
+                    return launch_gsum(fp64, mn, fd, tab, nb, st);
+                });
+                note(nb);
+            }
             deal();
             const int dirs = P.forward ? kDirFwd : kDirBoth;
             auto steps = [&](int f) {
@@ -605,9 +655,9 @@ struct mapdec_plan {
             }
             deal();
             if (!L.grad) continue;
-            for (auto &kv : P.lat) {
-                const int mn = kv.first.first, nb = (int)kv.second.size();
-                const Work *tab = at<Work>(P.off_lat.at(kv.first));
+            for (auto &kv : P.wlat) {
+                const int mn = kv.first, nb = (int)kv.second.size();
+                const Work *tab = at<Work>(P.off_wlat.at(kv.first));
                 add(kPhWgrad, frames_of(kv.second), false, [=](hipStream_t st) {
                     return fp64 ? adj_f64_w(mn, fd, tab, nb, st) : adj_f32_w(mn, fd, tab, nb, st);
                 });
@@ -838,6 +888,9 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
             d.Zexp = L.grad ? reinterpret_cast<int *>(base + F.off_Zexp) : nullptr;
             d.gacc_all = reinterpret_cast<double *>(base + F.off_gacc);
             d.gacc_n = F.gacc_n;
+            d.dq = F.dq;
+            d.dsplit = F.dsplit;
+            d.Gpart = F.off_gpart ? base + F.off_gpart : nullptr;
             const int j = std::min(P.seg, F.nseg - 1);
             const Segment g = segment_of(fr, F, j);
             d.i0 = g.i0; d.i1 = g.i1; d.s0 = g.s0; d.s1 = g.s1;
@@ -855,6 +908,12 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
                 d.b_fin = j > 0 ? bc : nullptr;
             }
         }
+        for (auto &kv : P.wlat)
+            std::memcpy(stage.data() + P.off_wlat.at(kv.first), kv.second.data(),
+                        sizeof(Work) * kv.second.size());
+        for (auto &kv : P.gsum)
+            std::memcpy(stage.data() + P.off_gsum.at(kv.first), kv.second.data(),
+                        sizeof(Work) * kv.second.size());
         for (auto &kv : P.lat)
             std::memcpy(stage.data() + P.off_lat.at(kv.first), kv.second.data(),
                         sizeof(Work) * kv.second.size());

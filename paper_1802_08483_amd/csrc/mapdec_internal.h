@@ -53,6 +53,12 @@ struct FrameDesc {
     double *gacc_all;     // every segment's partials of the frame, contiguous
     int gacc_n;           // number of [4] partials at gacc_all
     int adj_da;           // the adjoint sweep accumulates d/da (else from rho - tau)
+    // Codewords per lattice / adjoint workgroup: dq = q unless a pass has too
+    // few workgroups to fill the device, when each (start-index block) item
+    // is split into dsplit items of dq codewords; the chunk index rides in
+    // the low 6 bits of Work::item (start offsets are multiples of 64).
+    int dq, dsplit;
+    void *Gpart;          // [dsplit][Mn][sp] per-chunk sums of R (uniform priors, dsplit > 1)
     // Segment of the frame that this descriptor's launches cover (the whole
     // frame unless the forward metric is checkpointed): symbols [i0, i1),
     // start indices [s0, s1].  Column c of R and of the uniform Gamma holds
@@ -65,7 +71,9 @@ struct FrameDesc {
     double *b_fin;        // receives beta row i0, or NULL
 };
 
-// Work-table entry: which frame a workgroup serves and where in it.
+// Work-table entry: which frame a workgroup serves and where in it.  For
+// lattice and adjoint items, item = start offset (a multiple of 64) plus the
+// codeword chunk index.
 struct Work {
     int frame;
     int item;

@@ -270,6 +270,11 @@ hipError_t launch_lattice(int, int, int, const FrameDesc *fd, const Work *t, int
     launch(st, work_frames(t, nb), false);
     return hipSuccess;
 }
+hipError_t launch_gsum(int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
+    check_fd(fd);
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
 hipError_t launch_gamma(int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
     launch(st, work_frames(t, nb), false);
