@@ -188,8 +188,13 @@ int mapdec_grad(const mapdec_frame *frames, int nframes, double *logp, double *d
  * besides the run's stream: each launch waits only for earlier launches
  * that touched one of its frames, and the run's stream waits for all of
  * them at the end, so a run is still ordered on the caller's stream as a
- * whole.  Graph plans record every launch in order on one stream.  Results
- * do not depend on the order.
+ * whole.  Gradient plans of at least 32 frames that need one launch per
+ * phase run eagerly as 4 contiguous slices of frames instead, slice k on
+ * stream k, every launch other than the chains also waiting for the same
+ * launch of the slice before: the compute-bound phases then advance slice
+ * by slice while each slice's chains (a latency-bound recursion) run
+ * beside them.  Graph plans record every launch in order on one stream.
+ * Results do not depend on the order.
  */
 typedef struct mapdec_plan mapdec_plan;
 

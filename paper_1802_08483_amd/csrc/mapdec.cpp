@@ -125,6 +125,9 @@ struct Pass {
 
 struct Layout {
     int nframes = 0, fp64 = 0, grad = 0, ckK = 0;
+    // frame slices of an eager forked plan (1: none) and each frame's slice
+    int slices = 1;
+    std::vector<int> fslice;
     size_t tsize = 4;
     size_t off_pack = 0, head = 0, total = 0;
     std::vector<Work> pack;
@@ -135,6 +138,13 @@ struct Layout {
     std::map<std::tuple<int, int, int>, size_t> app_tile_lds, adj_lds;
     std::vector<FrameLayout> fl;
 };
+
+// Frame slices: an eager plan of many frames runs its batch as this many
+// contiguous slices of frames, slice k on stream k, so that one slice's
+// chains (a latency-bound recursion) run beside another slice's
+// compute-bound launches.
+constexpr int kSlices = 4;
+constexpr int kSliceMinFrames = 16;
 
 // Reorders a work list so that the workgroups the dispatcher sends to one
 // XCD (workgroup ids congruent mod 8) take consecutive items: neighbouring
@@ -334,6 +344,32 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         }
     }
 
+    // Slices pay off where every phase is one launch (frames of one kernel
+    // configuration) and the step has enough compute after the chains to
+    // hide them under (gradients); batches with several launch groups per
+    // phase overlap those groups instead.
+    bool one_config = true;
+    {
+        const mapdec_code *c0 = frames[0].code;
+        const FrameLayout &F0 = L.fl[0];
+        for (int f = 1; f < nframes && one_config; ++f) {
+            const mapdec_code *c = frames[f].code;
+            const FrameLayout &F = L.fl[f];
+            one_config = c->mn == c0->mn && frame_imode(c) == frame_imode(c0) &&
+                         (frames[f].prior != nullptr) == (frames[0].prior != nullptr) &&
+                         F.ring_shape == F0.ring_shape && F.app_tiled == F0.app_tiled &&
+                         F.app_key == F0.app_key && F.dsplit == F0.dsplit &&
+                         adjoint_needs_da(c->Pi, c->Pd) == adjoint_needs_da(c0->Pi, c0->Pd);
+        }
+    }
+    L.slices = (L.grad && one_config && !(flags & (MAPDEC_FLAG_GRAPH | MAPDEC_FLAG_SERIAL)) &&
+                nframes >= 2 * kSliceMinFrames)
+                   ? std::min(kSlices, nframes / kSliceMinFrames)
+                   : 1;
+    L.fslice.resize(nframes);
+    for (int f = 0; f < nframes; ++f)
+        L.fslice[f] = (int)((long long)f * L.slices / nframes);
+
     // passes: forward over segments 0 .. S-2, then main passes S-1 .. 0
     for (int j = 0; j + 1 < smax; ++j) {
         Pass P;
@@ -400,13 +436,37 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             else
                 P.chain_plain.push_back(f);
         }
-        // neighbouring items share rows (APP, W) or received columns (Gamma):
-        // keep them on one XCD's L2
-        for (auto &kv : P.app_tile) kv.second = xcd_order(kv.second);
-        for (auto &kv : P.lat) kv.second = xcd_order(kv.second);
-        for (auto &kv : P.wlat) kv.second = xcd_order(kv.second);
-        for (auto &kv : P.gsum) kv.second = xcd_order(kv.second);
-        for (auto &kv : P.gamma) kv.second = xcd_order(kv.second);
+        // items of one slice contiguous (slice order); neighbouring items
+        // share rows (APP, W) or received columns (Gamma): keep them on one
+        // XCD's L2 within each slice
+        auto by_slice = [&](std::vector<Work> &v, bool xcd) {
+            std::stable_sort(v.begin(), v.end(), [&](const Work &a, const Work &b) {
+                return L.fslice[a.frame] < L.fslice[b.frame];
+            });
+            if (!xcd) return;
+            size_t a = 0;
+            while (a < v.size()) {
+                size_t b = a;
+                while (b < v.size() && L.fslice[v[b].frame] == L.fslice[v[a].frame]) ++b;
+                std::vector<Work> part(v.begin() + a, v.begin() + b);
+                part = xcd_order(part);
+                std::copy(part.begin(), part.end(), v.begin() + a);
+                a = b;
+            }
+        };
+        for (auto &kv : P.app_tile) by_slice(kv.second, true);
+        for (auto &kv : P.lat) by_slice(kv.second, true);
+        for (auto &kv : P.wlat) by_slice(kv.second, true);
+        for (auto &kv : P.gsum) by_slice(kv.second, true);
+        for (auto &kv : P.gamma) by_slice(kv.second, true);
+        for (auto &kv : P.adj) by_slice(kv.second, false);
+        by_slice(P.app_plain, false);
+        auto chains_by_slice = [&](std::vector<int> &v) {
+            std::stable_sort(v.begin(), v.end(),
+                             [&](int a, int b) { return L.fslice[a] < L.fslice[b]; });
+        };
+        chains_by_slice(P.chain_plain);
+        for (auto &kv : P.chain_ring) chains_by_slice(kv.second);
     }
 
     // head: the pack table and, per pass, the descriptors, the work tables
@@ -497,6 +557,8 @@ struct Op {
     bool all = false;          // touches every frame (set-up, parameter sums)
     std::vector<int> frames;   // sorted, distinct (when !all)
     int stream = 0;            // 0: the run's stream, k > 0: forked stream k - 1
+    int slice = -1;            // frame slice, or -1
+    int after = -1;            // an earlier op this one also waits for, or -1
     std::function<hipError_t(hipStream_t)> fn;
 };
 
@@ -546,10 +608,16 @@ struct mapdec_plan {
 
     // The plan's launches in dependency order: set-up, then per pass the
     // lattice, Gamma, chains, APP and (gradients) W and the adjoint sweep,
-    // and the parameter sums.  Launch groups of one phase are dealt to the
-    // streams in order of decreasing size (chains: their longest chain).
+    // and the parameter sums.  Without slices, the launch groups of a phase
+    // are dealt to the streams in order of decreasing size (chains: their
+    // longest chain).  With frame slices every group becomes one launch per
+    // slice on the slice's stream, and every launch but the chains also
+    // waits for the same group's launch of the slice before, so that the
+    // compute-bound phases advance slice by slice while each slice's chains
+    // run beside them.
     void build_ops() {
         const int nf = L.nframes;
+        const bool sliced = L.slices > 1;
         auto add = [&](int phase, std::vector<int> frames, bool all,
                        std::function<hipError_t(hipStream_t)> fn) {
             Op o;
@@ -572,6 +640,12 @@ struct mapdec_plan {
             // size of each group, for dealing the groups of a phase to streams
             std::vector<std::pair<long long, size_t>> group;
             auto deal = [&]() {
+                if (sliced) {
+                    for (auto &g : group) ops[g.second].stream = ops[g.second].slice % (kForkStreams + 1);
+                    if (!group.empty()) forked = true;
+                    group.clear();
+                    return;
+                }
                 std::stable_sort(group.begin(), group.end(),
                                  [](const std::pair<long long, size_t> &a,
                                     const std::pair<long long, size_t> &b) {
@@ -582,31 +656,65 @@ struct mapdec_plan {
                 if (group.size() > 1) forked = true;
                 group.clear();
             };
-            auto note = [&](long long size) { group.push_back(std::make_pair(size, ops.size() - 1)); };
+            // one launch per slice range of a work table (the whole table
+            // without slices); launch(stream, table, count)
+            auto add_work = [&](int phase, bool staggered, const std::vector<Work> &items, size_t off,
+                                std::function<hipError_t(hipStream_t, const Work *, int)> launch) {
+                size_t a = 0;
+                int prev = -1;
+                while (a < items.size()) {
+                    size_t b = a;
+                    const int sl = L.fslice[items[a].frame];
+                    while (b < items.size() && L.fslice[items[b].frame] == sl) ++b;
+                    const Work *tab = at<Work>(off) + a;
+                    const int nb = (int)(b - a);
+                    const std::vector<Work> part(items.begin() + a, items.begin() + b);
+                    add(phase, frames_of(part), false,
+                        [=](hipStream_t st) { return launch(st, tab, nb); });
+                    ops.back().slice = sl;
+                    if (sliced && staggered) ops.back().after = prev;
+                    prev = (int)ops.size() - 1;
+                    group.push_back(std::make_pair((long long)nb, ops.size() - 1));
+                    a = b;
+                }
+            };
+            auto add_chains = [&](const std::vector<int> &list, size_t off, long long steps_of_first,
+                                  std::function<hipError_t(hipStream_t, const int *, int)> launch) {
+                size_t a = 0;
+                while (a < list.size()) {
+                    size_t b = a;
+                    const int sl = L.fslice[list[a]];
+                    while (b < list.size() && L.fslice[list[b]] == sl) ++b;
+                    const int *tab = at<int>(off) + a;
+                    const int nc = (int)(b - a);
+                    add(kPhChain, sorted_frames(std::vector<int>(list.begin() + a, list.begin() + b)),
+                        false, [=](hipStream_t st) { return launch(st, tab, nc); });
+                    ops.back().slice = sl;
+                    group.push_back(std::make_pair(steps_of_first, ops.size() - 1));
+                    a = b;
+                }
+            };
             for (auto &kv : P.lat) {
-                const int mn = kv.first.first, im = kv.first.second, nb = (int)kv.second.size();
-                const Work *tab = at<Work>(P.off_lat.at(kv.first));
-                add(kPhLattice, frames_of(kv.second), false, [=](hipStream_t st) {
-                    return launch_lattice(fp64, mn, im, fd, tab, nb, st);
-                });
-                note(nb);
+                const int mn = kv.first.first, im = kv.first.second;
+                add_work(kPhLattice, true, kv.second, P.off_lat.at(kv.first),
+                         [=](hipStream_t st, const Work *tab, int nb) {
+                             return launch_lattice(fp64, mn, im, fd, tab, nb, st);
+                         });
             }
             deal();
             for (auto &kv : P.gamma) {
-                const int mn = kv.first, nb = (int)kv.second.size();
-                const Work *tab = at<Work>(P.off_gamma.at(kv.first));
-                add(kPhGamma, frames_of(kv.second), false, [=](hipStream_t st) {
-                    return launch_gamma(fp64, mn, fd, tab, nb, st);
-                });
-                note(nb);
+                const int mn = kv.first;
+                add_work(kPhGamma, true, kv.second, P.off_gamma.at(kv.first),
+                         [=](hipStream_t st, const Work *tab, int nb) {
+                             return launch_gamma(fp64, mn, fd, tab, nb, st);
+                         });
             }
             for (auto &kv : P.gsum) {
-                const int mn = kv.first, nb = (int)kv.second.size();
-                const Work *tab = at<Work>(P.off_gsum.at(kv.first));
-                add(kPhGamma, frames_of(kv.second), false, [=](hipStream_t st) {
-                    return launch_gsum(fp64, mn, fd, tab, nb, st);
-                });
-                note(nb);
+                const int mn = kv.first;
+                add_work(kPhGamma, true, kv.second, P.off_gsum.at(kv.first),
+                         [=](hipStream_t st, const Work *tab, int nb) {
+                             return launch_gsum(fp64, mn, fd, tab, nb, st);
+                         });
             }
             deal();
             const int dirs = P.forward ? kDirFwd : kDirBoth;
@@ -615,65 +723,58 @@ struct mapdec_plan {
                 return (long long)(g.i1 - g.i0);
             };
             if (!P.chain_plain.empty()) {
-                const int nc = (int)P.chain_plain.size();
-                const int *tab = at<int>(P.off_chain);
                 const size_t lds = L.chain_lds;
-                add(kPhChain, sorted_frames(P.chain_plain), false, [=](hipStream_t st) {
-                    return launch_chain(fp64, fd, tab, nc, dirs, lds, st);
-                });
-                note(steps(P.chain_plain.front()));
+                add_chains(P.chain_plain, P.off_chain, steps(P.chain_plain.front()),
+                           [=](hipStream_t st, const int *tab, int nc) {
+                               return launch_chain(fp64, fd, tab, nc, dirs, lds, st);
+                           });
             }
             for (auto &kv : P.chain_ring) {
-                const int shape = kv.first.first, mn = kv.first.second, nc = (int)kv.second.size();
-                const int *tab = at<int>(P.off_chain_ring.at(kv.first));
+                const int shape = kv.first.first, mn = kv.first.second;
                 const size_t lds = L.ring_lds.at(kv.first);
-                add(kPhChain, sorted_frames(kv.second), false, [=](hipStream_t st) {
-                    return launch_chain_ring(fp64, shape, mn, fd, tab, nc, dirs, lds, st);
-                });
-                note(steps(kv.second.front()));
+                add_chains(kv.second, P.off_chain_ring.at(kv.first), steps(kv.second.front()),
+                           [=](hipStream_t st, const int *tab, int nc) {
+                               return launch_chain_ring(fp64, shape, mn, fd, tab, nc, dirs, lds, st);
+                           });
             }
             deal();
             if (P.forward) continue;
             if (!P.app_plain.empty()) {
-                const int nb = (int)P.app_plain.size();
-                const Work *tab = at<Work>(P.off_app);
                 const size_t lds = L.app_lds;
-                add(kPhApp, frames_of(P.app_plain), false, [=](hipStream_t st) {
-                    return launch_app(fp64, fd, tab, nb, lds, st);
-                });
-                note(nb);
+                add_work(kPhApp, true, P.app_plain, P.off_app,
+                         [=](hipStream_t st, const Work *tab, int nb) {
+                             return launch_app(fp64, fd, tab, nb, lds, st);
+                         });
             }
             for (auto &kv : P.app_tile) {
                 const int td = std::get<0>(kv.first), nw = std::get<1>(kv.first),
-                          mn = std::get<2>(kv.first), nb = (int)kv.second.size();
-                const Work *tab = at<Work>(P.off_app_tile.at(kv.first));
+                          mn = std::get<2>(kv.first);
                 const size_t lds = L.app_tile_lds.at(kv.first);
-                add(kPhApp, frames_of(kv.second), false, [=](hipStream_t st) {
-                    return launch_app_tile(fp64, td, mn, nw, fd, tab, nb, lds, st);
-                });
-                note(nb);
+                add_work(kPhApp, true, kv.second, P.off_app_tile.at(kv.first),
+                         [=](hipStream_t st, const Work *tab, int nb) {
+                             return launch_app_tile(fp64, td, mn, nw, fd, tab, nb, lds, st);
+                         });
             }
             deal();
             if (!L.grad) continue;
             for (auto &kv : P.wlat) {
-                const int mn = kv.first, nb = (int)kv.second.size();
-                const Work *tab = at<Work>(P.off_wlat.at(kv.first));
-                add(kPhWgrad, frames_of(kv.second), false, [=](hipStream_t st) {
-                    return fp64 ? adj_f64_w(mn, fd, tab, nb, st) : adj_f32_w(mn, fd, tab, nb, st);
-                });
-                note(nb);
+                const int mn = kv.first;
+                add_work(kPhWgrad, true, kv.second, P.off_wlat.at(kv.first),
+                         [=](hipStream_t st, const Work *tab, int nb) {
+                             return fp64 ? adj_f64_w(mn, fd, tab, nb, st)
+                                         : adj_f32_w(mn, fd, tab, nb, st);
+                         });
             }
             deal();
             for (auto &kv : P.adj) {
                 const int mn = std::get<0>(kv.first), im = std::get<1>(kv.first),
-                          da = std::get<2>(kv.first), nb = (int)kv.second.size();
-                const Work *tab = at<Work>(P.off_adj.at(kv.first));
+                          da = std::get<2>(kv.first);
                 const size_t lds = L.adj_lds.at(kv.first);
-                add(kPhAdjoint, frames_of(kv.second), false, [=](hipStream_t st) {
-                    return fp64 ? adj_f64_lattice(mn, im, da, fd, tab, nb, lds, st)
-                                : adj_f32_lattice(mn, im, da, fd, tab, nb, lds, st);
-                });
-                note(nb);
+                add_work(kPhAdjoint, true, kv.second, P.off_adj.at(kv.first),
+                         [=](hipStream_t st, const Work *tab, int nb) {
+                             return fp64 ? adj_f64_lattice(mn, im, da, fd, tab, nb, lds, st)
+                                         : adj_f32_lattice(mn, im, da, fd, tab, nb, lds, st);
+                         });
             }
             deal();
         }
@@ -743,6 +844,7 @@ struct mapdec_plan {
             } else {
                 for (int f : o.frames) need.push_back(last[f]);
             }
+            if (o.after >= 0) need.push_back(o.after + 1);
             if (tail[x] < 0) need.push_back(0);   // first launch on a forked stream
             for (int d : need) {
                 const int y = ev_stream[d];

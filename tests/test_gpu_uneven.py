@@ -102,3 +102,26 @@ def test_forked_streams_equal_serial_order():
             _same(runs[0], r, f"grad={grad} K={K}")
         del runs, b
         torch.cuda.empty_cache()
+
+
+def test_frame_slices_equal_graph_order():
+    # an eager gradient plan of frames of one kernel configuration runs in 4
+    # frame slices on 4 streams (compute-bound launches staggered slice by
+    # slice); same bits as the one-stream graph replay, also checkpointed
+    frames = wl.make_workload(2, nframes=96)
+    for K in (0, 61):
+        runs = []
+        for graph in (True, False):
+            b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True,
+                                         checkpoint_K=K)
+            p = b.plan(graph=graph)
+            for _ in range(2):
+                b.logp.fill_(0)
+                p.run()
+                torch.cuda.synchronize()
+            p.close()
+            runs.append(b)
+        assert (runs[0].status.cpu().numpy() == 0).all()
+        _same(runs[0], runs[1], f"slices K={K}")
+        del runs, b
+        torch.cuda.empty_cache()

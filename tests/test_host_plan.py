@@ -5,7 +5,9 @@ g++ against a stub of the HIP runtime calls and kernel launchers
 reads every launch's work table and checks, with vector clocks over
 streams and events, that each launch is ordered after the previous launch
 of every frame it touches and that the caller's stream is joined with
-every forked stream; it aborts otherwise.  No kernel runs.
+every forked stream; it aborts otherwise.  Eager plans of many frames run
+in frame slices (one stream each, compute-bound launches staggered slice
+by slice).  No kernel runs.
 """
 import os
 import shutil
@@ -45,6 +47,8 @@ def driver(tmp_path_factory):
     (160, 0, GRAD | TUNE, 0),          # tuning plan, then the tuned plan
     (32, 0, GRAD | GRAPH, 1),          # uniform batch: one group per phase
     (32, 40, GRAD, 1),
+    (128, 0, GRAD, 1),                 # eager uniform batch in frame slices
+    (128, 0, GRAD | SERIAL, 1),
 ])
 def test_plan_host_logic(driver, nframes, K, flags, uniform):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1")
