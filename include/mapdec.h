@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MAPDEC_VERSION 102
+#define MAPDEC_VERSION 103
 
 enum {
     MAPDEC_OK = 0,
@@ -181,6 +181,10 @@ int mapdec_grad(const mapdec_frame *frames, int nframes, double *logp, double *d
  * checkpoint_K).  Returns NULL on failure (see mapdec_last_error()).  The
  * descriptor upload is enqueued on stream.
  *
+ * Forked runs use 4 streams at once; a process has a limited number of
+ * hardware queues (4 by default), and streams beyond them share one, which
+ * serialises what they share.
+ *
  * Batches whose frames differ in shape (q, n, M, mn, priors) need several
  * launches per phase, one per kernel instance.  A plan without
  * MAPDEC_FLAG_GRAPH or MAPDEC_FLAG_SERIAL then deals those launches to
@@ -231,15 +235,20 @@ void mapdec_plan_destroy(mapdec_plan *plan);
 
 /*
  * mapdec_plan_profile -- per-phase time split of one run (the decoder's
- * time per metric, Sec. VI).  Enqueues the plan's launches once, without
- * the graph, on stream with a HIP event recorded after each group of
- * launches, waits for them, and writes into phase_ms[k] (k < max_phases)
- * the milliseconds of all launch groups of phase k (with checkpoints a
- * phase runs once per segment).  Returns the number of phases, or a
- * negative MAPDEC_* status.  Results land in the plan's outputs as after
- * mapdec_plan_run.
+ * time per metric, Sec. VI).  Runs the plan's launches once, eagerly, in
+ * the plan's own eager schedule (forked streams and frame slices as for a
+ * run without MAPDEC_FLAG_GRAPH; one stream for graph and serial plans),
+ * with a timing event recorded on each launch's stream just before and just
+ * after it; waits for them and writes into phase_ms[k] (k < max_phases)
+ * the sum of the durations of phase k's launches (with checkpoints or
+ * slices a phase has several).  Launches that overlap each count in full.
+ * Returns the number of phases, or a negative MAPDEC_* status.  Results
+ * land in the plan's outputs as after mapdec_plan_run.
  */
 int mapdec_plan_profile(mapdec_plan *plan, void *stream, float *phase_ms, int max_phases);
+/* Number of launches of profile phase k in one run of the plan (a negative
+ * MAPDEC_* status for a NULL plan). */
+int mapdec_plan_launches(const mapdec_plan *plan, int phase);
 /* Static name of profile phase k ("pack", "lattice", "gamma", "chain",
  * "app", ...), or NULL past the last phase. */
 const char *mapdec_phase_name(int phase);

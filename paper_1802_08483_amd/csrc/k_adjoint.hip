@@ -43,7 +43,8 @@ namespace mapdec {
 
 constexpr int kWadjDC = 4;
 
-template <typename T, int MN>
+// UNI: every frame of the launch has uniform priors (else none has).
+template <typename T, int MN, bool UNI>
 __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
                                              const Work *__restrict__ tab) {
     constexpr int KW = 2 * MN + 1;
@@ -83,17 +84,39 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
             be[k] = eb;
         }
     };
-    if (f.uniform) {
+    if constexpr (UNI) {
+        // beta_{i+1} over the wave's window (drifts sa - n i - mn ..
+        // sa + 63 - n i + mn), split into (mantissa, exponent) once per value
+        // and staged in LDS, where each lane reads its 2 mn + 1 neighbours
+        // (one wave: LDS operations stay in program order)
+        constexpr int WIN = 64 + 2 * MN;
+        __shared__ double bm[2][WIN];
+        __shared__ int bx[2][WIN];
+        const int lane = threadIdx.x;
         double acc[KW];
 #pragma unroll
         for (int k = 0; k < KW; ++k) acc[k] = 0.0;
-#pragma unroll 2
         for (int i = ilo; i <= ihi; ++i) {
-            double av, bv[KW];
-            int ae, be[KW];
-            term(i, av, ae, bv, be);
+            const int buf = (i - ilo) & 1;
+            const int base = sa - n * i - MN;   // drift of window slot 0
+            for (int t = lane; t < WIN; t += 64) {
+                const int m = base + t;
+                const int cm = min(max(m, -M), M);
+                int e;
+                const double v = frexp(B[(size_t)(i + 1 - ib) * Mt + cm + M], &e);
+                bm[buf][t] = (m >= -M && m <= M) ? v : 0.0;
+                bx[buf][t] = e;
+            }
+            const int mp = s - n * i;
+            const double in = (live && mp >= -M && mp <= M) ? 1.0 : 0.0;
+            const int mc = min(max(mp, -M), M);
+            int ea;
+            const double av = frexp(A[(size_t)(i - ib) * Mt + mc + M], &ea) * Zi[i] * in;
+            const int ae = ea - Ze[i];
+            lds_wave_sync();
 #pragma unroll
-            for (int k = 0; k < KW; ++k) acc[k] += ldexp(av * bv[k], ae + be[k]);
+            for (int k = 0; k < KW; ++k)
+                acc[k] += ldexp(av * bm[buf][lane + k], ae + bx[buf][lane + k]);
         }
         if (!live) return;
         const gptr<T> W = to_global((T *)f.G);
@@ -424,24 +447,28 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
 #define ADJ_CAT(a, b) ADJ_CAT2(a, b)
 
 template <int MN>
-static hipError_t wadj_mn(const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_wadj<ADJ_T, MN>), dim3(nblocks), dim3(64), 0, st, fd, tab);
+static hipError_t wadj_mn(int uniform, const FrameDesc *fd, const Work *tab, int nblocks,
+                          hipStream_t st) {
+    if (uniform)
+        hipLaunchKernelGGL((k_wadj<ADJ_T, MN, true>), dim3(nblocks), dim3(64), 0, st, fd, tab);
+    else
+        hipLaunchKernelGGL((k_wadj<ADJ_T, MN, false>), dim3(nblocks), dim3(64), 0, st, fd, tab);
     return hipGetLastError();
 }
 
-hipError_t ADJ_CAT(ADJ_FN, _w)(int mn, const FrameDesc *fd, const Work *tab, int nblocks,
-                               hipStream_t st) {
+hipError_t ADJ_CAT(ADJ_FN, _w)(int mn, int uniform, const FrameDesc *fd, const Work *tab,
+                               int nblocks, hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
     switch (mn) {
-        case 0: return wadj_mn<0>(fd, tab, nblocks, st);
-        case 1: return wadj_mn<1>(fd, tab, nblocks, st);
-        case 2: return wadj_mn<2>(fd, tab, nblocks, st);
-        case 3: return wadj_mn<3>(fd, tab, nblocks, st);
-        case 4: return wadj_mn<4>(fd, tab, nblocks, st);
-        case 5: return wadj_mn<5>(fd, tab, nblocks, st);
-        case 6: return wadj_mn<6>(fd, tab, nblocks, st);
-        case 7: return wadj_mn<7>(fd, tab, nblocks, st);
-        case 8: return wadj_mn<8>(fd, tab, nblocks, st);
+        case 0: return wadj_mn<0>(uniform, fd, tab, nblocks, st);
+        case 1: return wadj_mn<1>(uniform, fd, tab, nblocks, st);
+        case 2: return wadj_mn<2>(uniform, fd, tab, nblocks, st);
+        case 3: return wadj_mn<3>(uniform, fd, tab, nblocks, st);
+        case 4: return wadj_mn<4>(uniform, fd, tab, nblocks, st);
+        case 5: return wadj_mn<5>(uniform, fd, tab, nblocks, st);
+        case 6: return wadj_mn<6>(uniform, fd, tab, nblocks, st);
+        case 7: return wadj_mn<7>(uniform, fd, tab, nblocks, st);
+        case 8: return wadj_mn<8>(uniform, fd, tab, nblocks, st);
         default: return hipErrorInvalidValue;
     }
 }

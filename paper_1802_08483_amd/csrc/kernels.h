@@ -67,8 +67,11 @@ hipError_t launch_app_tile(int fp64, int td, int mn, int nwaves, const FrameDesc
 // (per mn group), the backward lattice sweep (per (mn, imode, sa) group, sa =
 // the sweep accumulates d/da itself; LDS from adjoint_lds), and the
 // per-frame reduction with the chain rule (k_misc.hip).
-hipError_t adj_f32_w(int mn, const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st);
-hipError_t adj_f64_w(int mn, const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st);
+// uniform: every frame of the W launch has uniform priors (else none has)
+hipError_t adj_f32_w(int mn, int uniform, const FrameDesc *fd, const Work *tab, int nblocks,
+                     hipStream_t st);
+hipError_t adj_f64_w(int mn, int uniform, const FrameDesc *fd, const Work *tab, int nblocks,
+                     hipStream_t st);
 hipError_t adj_f32_lattice(int mn, int imode, int sa, const FrameDesc *fd, const Work *tab,
                            int nblocks, size_t lds, hipStream_t st);
 hipError_t adj_f64_lattice(int mn, int imode, int sa, const FrameDesc *fd, const Work *tab,

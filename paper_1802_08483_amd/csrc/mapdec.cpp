@@ -107,8 +107,10 @@ struct Pass {
     std::map<std::pair<int, int>, size_t> off_lat;
     // per mn: the start-index blocks without codeword chunks (W), and those
     // of uniform-prior frames whose lattice is split (Gamma from R)
-    std::map<int, std::vector<Work>> wlat, gsum;
-    std::map<int, size_t> off_wlat, off_gsum;
+    std::map<std::pair<int, int>, std::vector<Work>> wlat;   // (mn, uniform priors)
+    std::map<std::pair<int, int>, size_t> off_wlat;
+    std::map<int, std::vector<Work>> gsum;
+    std::map<int, size_t> off_gsum;
     std::map<int, std::vector<Work>> gamma;                         // mn
     std::map<int, size_t> off_gamma;
     std::vector<int> chain_plain;
@@ -138,6 +140,19 @@ struct Layout {
     std::map<std::tuple<int, int, int>, size_t> app_tile_lds, adj_lds;
     std::vector<FrameLayout> fl;
 };
+
+// The plan whose descriptors and work tables the head of a workspace holds.
+// Plans of one batch share its workspace but not always its head layout
+// (slices, tuned choices), so a run first restores its own head when
+// another plan (or a one-shot decode) wrote it last.
+struct HeadOwners {
+    std::mutex mu;
+    std::map<const void *, const void *> owner;   // workspace -> plan
+};
+HeadOwners &head_owners() {
+    static HeadOwners h;
+    return h;
+}
 
 // Frame slices: an eager plan of many frames runs its batch as this many
 // contiguous slices of frames, slice k on stream k, so that one slice's
@@ -393,7 +408,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             if (P.forward ? j + 1 >= F.nseg : j >= F.nseg) continue;
             const Segment g = segment_of(fr, F, j);
             auto &lv = P.lat[std::make_pair(c->mn, frame_imode(c))];
-            auto &wv = P.wlat[c->mn];
+            auto &wv = P.wlat[std::make_pair(c->mn, fr.prior ? 0 : 1)];
             const int nb = lattice_blocks(g);
             for (int b = 0; b < nb; ++b) {
                 wv.push_back(Work{f, b * kLatticeLanes});
@@ -596,15 +611,44 @@ struct mapdec_plan {
     template <typename P>
     P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
 
+    std::vector<unsigned char> head_host;   // this plan's head of the workspace
+    // Restores this plan's head of the workspace (stream-ordered) when
+    // another plan wrote it last.
+    hipError_t own_head(hipStream_t st) {
+        HeadOwners &h = head_owners();
+        std::lock_guard<std::mutex> g(h.mu);
+        auto it = h.owner.find(ws);
+        if (it != h.owner.end() && it->second == this) return hipSuccess;
+        const hipError_t e =
+            hipMemcpyAsync(ws, head_host.data(), head_host.size(), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) h.owner[ws] = this;
+        return e;
+    }
+
     std::vector<Op> ops;
     bool forked = false;                  // some phase has several launch groups
     hipStream_t side[kForkStreams] = {};
     std::vector<hipEvent_t> dep;          // one per op, plus the fork
 
-    // profiling: an event after each phase's launches, tagged with the phase
-    std::vector<hipEvent_t> ev;
-    std::vector<int> ev_phase;
-    size_t nev = 0;
+    // profiling: timing events recorded just before and just after each
+    // launch, on the launch's stream
+    std::vector<hipEvent_t> pb, pa;
+    hipError_t prof_events() {
+        hipError_t e = hipSuccess;
+        while (e == hipSuccess && pb.size() < ops.size()) {
+            hipEvent_t x, y;
+            e = hipEventCreate(&x);
+            if (e != hipSuccess) break;
+            e = hipEventCreate(&y);
+            if (e != hipSuccess) {
+                hipEventDestroy(x);
+                break;
+            }
+            pb.push_back(x);
+            pa.push_back(y);
+        }
+        return e;
+    }
 
     // The plan's launches in dependency order: set-up, then per pass the
     // lattice, Gamma, chains, APP and (gradients) W and the adjoint sweep,
@@ -758,11 +802,11 @@ struct mapdec_plan {
             deal();
             if (!L.grad) continue;
             for (auto &kv : P.wlat) {
-                const int mn = kv.first;
+                const int mn = kv.first.first, uni = kv.first.second;
                 add_work(kPhWgrad, true, kv.second, P.off_wlat.at(kv.first),
                          [=](hipStream_t st, const Work *tab, int nb) {
-                             return fp64 ? adj_f64_w(mn, fd, tab, nb, st)
-                                         : adj_f32_w(mn, fd, tab, nb, st);
+                             return fp64 ? adj_f64_w(mn, uni, fd, tab, nb, st)
+                                         : adj_f32_w(mn, uni, fd, tab, nb, st);
                          });
             }
             deal();
@@ -788,31 +832,15 @@ struct mapdec_plan {
     }
     std::vector<mapdec_frame> frames_;   // host copy of the frame table (build_ops only)
 
-    // Every launch in order on st; with prof, an event is recorded first and
-    // after the last launch of each phase, and ev_phase[k] names the phase of
-    // the launches that end at event k.
+    // Every launch in order on st (with prof, between the events pb[j] and
+    // pa[j]).
     hipError_t enqueue_serial(hipStream_t st, bool prof) {
-        hipError_t e = hipSuccess;
-        size_t k = 0;
-        auto mark = [&](int phase) {
-            if (!prof || e != hipSuccess) return;
-            if (k >= ev.size()) {
-                hipEvent_t x;
-                e = hipEventCreate(&x);
-                if (e != hipSuccess) return;
-                ev.push_back(x);
-                ev_phase.push_back(phase);
-            }
-            ev_phase[k] = phase;
-            e = hipEventRecord(ev[k], st);
-            ++k;
-        };
-        mark(kPhPack);
+        hipError_t e = prof ? prof_events() : hipSuccess;
         for (size_t j = 0; j < ops.size() && e == hipSuccess; ++j) {
-            e = ops[j].fn(st);
-            if (j + 1 == ops.size() || ops[j + 1].phase != ops[j].phase) mark(ops[j].phase);
+            if (prof) e = hipEventRecord(pb[j], st);
+            if (e == hipSuccess) e = ops[j].fn(st);
+            if (prof && e == hipSuccess) e = hipEventRecord(pa[j], st);
         }
-        nev = k;
         return e;
     }
 
@@ -820,8 +848,12 @@ struct mapdec_plan {
     // for the last earlier launch that touched any of its frames (event
     // dep[j + 1] follows op j; dep[0] forks from st), and st finally waits
     // for every forked stream.
-    hipError_t enqueue_forked(hipStream_t st) {
+    hipError_t enqueue_forked(hipStream_t st, bool prof) {
         constexpr int NS = kForkStreams + 1;
+        if (prof) {
+            const hipError_t e0 = prof_events();
+            if (e0 != hipSuccess) return e0;
+        }
         hipStream_t sx[NS] = {st};
         for (int x = 1; x < NS; ++x) sx[x] = side[x - 1];
         std::vector<int> last(L.nframes, 0);   // per frame: event of its last launch
@@ -854,7 +886,9 @@ struct mapdec_plan {
                 seen[x][y] = d;
             }
             if (e != hipSuccess) break;
-            e = o.fn(sx[x]);
+            if (prof) e = hipEventRecord(pb[j], sx[x]);
+            if (e == hipSuccess) e = o.fn(sx[x]);
+            if (prof && e == hipSuccess) e = hipEventRecord(pa[j], sx[x]);
             if (e != hipSuccess) break;
             const int me = (int)j + 1;
             e = hipEventRecord(dep[me], sx[x]);
@@ -874,7 +908,7 @@ struct mapdec_plan {
     // onto the plan's streams ended in a host-side crash inside the runtime
     // on its first run, so forking is kept to eager runs.
     hipError_t enqueue(hipStream_t st, bool prof = false, bool capture = false) {
-        return (prof || capture || !forked) ? enqueue_serial(st, prof) : enqueue_forked(st);
+        return (capture || !forked) ? enqueue_serial(st, prof) : enqueue_forked(st, prof);
     }
 };
 
@@ -1040,6 +1074,12 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(p->ws, stage.data(), L.head, hipMemcpyHostToDevice, s);
+    p->head_host = std::move(stage);
+    {
+        HeadOwners &h = head_owners();
+        std::lock_guard<std::mutex> g(h.mu);
+        h.owner[p->ws] = p;
+    }
     // codewords go straight into each frame's region
     for (int f = 0; f < nframes && e == hipSuccess; ++f)
         e = hipMemcpyAsync(base + L.fl[f].off_cw, frames[f].code->cw.data(),
@@ -1268,7 +1308,7 @@ void mapdec_tune_reset(void) {
 int mapdec_plan_run(mapdec_plan *p, void *stream) {
     if (!p) return MAPDEC_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipSuccess;
+    hipError_t e = p->own_head(s);
     if (p->flags & MAPDEC_FLAG_GRAPH) {
         if (!p->exec) {
             if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
@@ -1292,18 +1332,27 @@ int mapdec_plan_run(mapdec_plan *p, void *stream) {
 int mapdec_plan_profile(mapdec_plan *p, void *stream, float *phase_ms, int max_phases) {
     if (!p || (max_phases > 0 && !phase_ms)) return -MAPDEC_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = p->enqueue(s, true);
+    hipError_t e = p->own_head(s);
+    if (e == hipSuccess) e = p->enqueue(s, true);
     p->last_stream = s;
+    p->ran = true;
     const int nph = p->L.grad ? kPhDparams + 1 : kPhApp + 1;
     for (int k = 0; k < max_phases && k < nph; ++k) phase_ms[k] = 0.f;
-    if (e == hipSuccess && p->nev > 0) e = hipEventSynchronize(p->ev[p->nev - 1]);
-    // the time between consecutive events belongs to the later event's phase
-    for (size_t k = 1; k < p->nev && e == hipSuccess; ++k) {
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // s has joined every forked stream
+    // a phase's time is the sum of its launches' durations
+    for (size_t j = 0; j < p->ops.size() && e == hipSuccess; ++j) {
         float ms = 0.f;
-        e = hipEventElapsedTime(&ms, p->ev[k - 1], p->ev[k]);
-        if (p->ev_phase[k] < max_phases) phase_ms[p->ev_phase[k]] += ms;
+        e = hipEventElapsedTime(&ms, p->pb[j], p->pa[j]);
+        if (p->ops[j].phase < max_phases) phase_ms[p->ops[j].phase] += ms;
     }
     return e == hipSuccess ? nph : -MAPDEC_EDEVICE;
+}
+
+int mapdec_plan_launches(const mapdec_plan *p, int phase) {
+    if (!p) return -MAPDEC_EINVAL;
+    int n = 0;
+    for (const Op &o : p->ops) n += o.phase == phase ? 1 : 0;
+    return n;
 }
 
 const char *mapdec_phase_name(int phase) {
@@ -1315,14 +1364,21 @@ const char *mapdec_phase_name(int phase) {
 
 void mapdec_plan_destroy(mapdec_plan *p) {
     if (!p) return;
-    if (p->ran || !p->ev.empty()) hipStreamSynchronize(p->last_stream);
+    {
+        HeadOwners &h = head_owners();
+        std::lock_guard<std::mutex> g(h.mu);
+        auto it = h.owner.find(p->ws);
+        if (it != h.owner.end() && it->second == p) h.owner.erase(it);
+    }
+    if (p->ran) hipStreamSynchronize(p->last_stream);
     for (hipStream_t x : p->side)
         if (x) {
             hipStreamSynchronize(x);
             hipStreamDestroy(x);
         }
     for (hipEvent_t x : p->dep) hipEventDestroy(x);
-    for (hipEvent_t x : p->ev) hipEventDestroy(x);
+    for (hipEvent_t x : p->pb) hipEventDestroy(x);
+    for (hipEvent_t x : p->pa) hipEventDestroy(x);
     if (p->exec) hipGraphExecDestroy(p->exec);
     if (p->graph) hipGraphDestroy(p->graph);
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);

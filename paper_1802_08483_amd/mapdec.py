@@ -24,7 +24,8 @@ MAX_N, MAX_MN = 16, 8
 # every symbol include/mapdec.h declares
 EXPORTS = ["mapdec_create", "mapdec_destroy", "mapdec_workspace_size", "mapdec_decode",
            "mapdec_grad", "mapdec_plan_create", "mapdec_plan_run", "mapdec_plan_destroy",
-           "mapdec_plan_profile", "mapdec_phase_name", "mapdec_tune_entries",
+           "mapdec_plan_profile", "mapdec_plan_launches", "mapdec_phase_name",
+           "mapdec_tune_entries",
            "mapdec_tune_reset", "mapdec_last_error",
            "mapdec_strerror", "mapdec_version"]
 
@@ -80,6 +81,8 @@ def lib() -> ctypes.CDLL:
         L.mapdec_strerror.restype = ctypes.c_char_p
         L.mapdec_version.argtypes = []
         L.mapdec_version.restype = i32
+        L.mapdec_plan_launches.argtypes = [vp, i32]
+        L.mapdec_plan_launches.restype = i32
         L.mapdec_tune_entries.argtypes = []
         L.mapdec_tune_entries.restype = i32
         L.mapdec_tune_reset.argtypes = []
@@ -245,12 +248,23 @@ class Plan:
             raise MapdecError(st, "mapdec_plan_run")
 
     def profile(self, stream=None) -> dict:
-        """One eager run with a HIP event between phases: {phase: ms}."""
+        """One eager run in the plan's eager schedule with timing events
+        around every launch: {phase: sum of its launches' ms}."""
         buf = (ctypes.c_float * 16)()
         n = lib().mapdec_plan_profile(self._h, _stream_handle(stream), buf, 16)
         if n < 0:
             raise MapdecError(-n, "mapdec_plan_profile")
         return {lib().mapdec_phase_name(k).decode(): float(buf[k]) for k in range(n)}
+
+    def launches(self) -> dict:
+        """{phase: number of launches in one run}."""
+        out, k = {}, 0
+        while True:
+            name = lib().mapdec_phase_name(k)
+            if name is None:
+                return out
+            out[name.decode()] = lib().mapdec_plan_launches(self._h, k)
+            k += 1
 
     def close(self):
         if getattr(self, "_h", None):

@@ -307,12 +307,12 @@ hipError_t launch_app_tile(int fp64, int td, int, int nw, const FrameDesc *fd, c
     launch(st, work_frames(t, nb), false);
     return hipSuccess;
 }
-hipError_t adj_f32_w(int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
+hipError_t adj_f32_w(int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
     launch(st, work_frames(t, nb), false);
     return hipSuccess;
 }
-hipError_t adj_f64_w(int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
+hipError_t adj_f64_w(int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
     launch(st, work_frames(t, nb), false);
     return hipSuccess;

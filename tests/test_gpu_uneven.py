@@ -125,3 +125,26 @@ def test_frame_slices_equal_graph_order():
         _same(runs[0], runs[1], f"slices K={K}")
         del runs, b
         torch.cuda.empty_cache()
+
+
+def test_plans_sharing_one_workspace():
+    # plans of one batch share its workspace; an eager sliced plan and a
+    # graph plan lay out its head differently, so each run restores its own
+    # head when another plan (or a one-shot call) wrote it last
+    frames = wl.make_workload(2, nframes=64)
+    ref = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True)
+    pr = ref.plan(graph=True)
+    pr.run()
+    torch.cuda.synchronize()
+    b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True)
+    pe = b.plan(graph=False)
+    pg = b.plan(graph=True)   # written last: owns the head
+    for step, run in enumerate((pe.run, pg.run, b.run_grad, pe.run, pe.run, pg.run)):
+        b.logp.fill_(0)
+        b.dparams.fill_(0)
+        run()
+        torch.cuda.synchronize()
+        _same(ref, b, f"step {step}")
+    pe.close()
+    pg.close()
+    pr.close()
