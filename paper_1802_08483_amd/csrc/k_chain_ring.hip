@@ -6,7 +6,8 @@
 // -DCHAIN_FN=<launcher name>.
 //
 // One workgroup of NT = 64 NW threads runs one chain; thread t owns
-// drift-state indices t, t + NT, ..., t + NT (SPL - 1).  Rows are padded to
+// drift-state index t (SPL = 1) or SPL of them: the adjacent indices SPL t ..
+// SPL t + SPL - 1 (FP32 Gamma) or t, t + NT, .. (FP64).  Rows are padded to
 // NT SPL states (zero beyond 2M+1) plus mn zeros on each side, so no thread
 // branches on its state.  One workgroup barrier per step.
 //
@@ -96,6 +97,12 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     R *part = row1 + ROWW;                             // [2][NW] wave partial sums
     T *ring = (T *)(part + 2 * NW);                    // [RPHYS][Mn], batch precision
     const int tid = threadIdx.x, wv = tid >> 6;
+    // drift-state index of the thread's j-th state: with several states per
+    // thread (FP32 Gamma) they are adjacent (SPL tid + j), so the row windows
+    // of a thread's states overlap and pair up in LDS reads; FP64 Gamma keeps
+    // them NT apart (fewer live registers)
+    constexpr bool ADJ = SPL > 1 && sizeof(T) == 4;
+    auto state = [&](int j) { return ADJ ? SPL * tid + j : tid + NT * j; };
     const gptr<const T> G = to_global((const T *)f.G);   // [Mn][gsp]
     const size_t sp = (size_t)f.gsp;
 
@@ -188,7 +195,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
         R p = R(0);
 #pragma unroll
         for (int j = 0; j < SPL; ++j) {
-            own[j] = cur[MN + tid + NT * j];
+            own[j] = cur[MN + state(j)];
             p += own[j];
         }
         p = wave_sum_dpp(p);
@@ -230,15 +237,15 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             const R scl = ldexp(R(1), -e);
             lexp += e;
             const int sb = (n * i - MC) & mask;
-            const R *cb = cur + MN + tid;
-            // Gamma(column, delta) for state mi = tid + NT j and drift change x - MN
+            const R *cb = cur + MN;
+            // Gamma(column, delta) for the thread's state j and drift change x - MN
             auto gam = [&](int j, int x) -> R {
-                const int c = DIR == 0 ? sb + tid + NT * j - (x - MN) : sb + tid + NT * j;
+                const int c = DIR == 0 ? sb + state(j) - (x - MN) : sb + state(j);
                 return (R)(DUP ? ring[(c + MN) * Mn + x] : ring[(c & mask) * Mn + x]);
             };
             // the row value that meets it
             auto rowv = [&](int j, int x) -> R {
-                return DIR == 0 ? cb[NT * j - (x - MN)] : cb[NT * j + x - MN];
+                return DIR == 0 ? cb[state(j) - (x - MN)] : cb[state(j) + x - MN];
             };
             auto partial = [&]() {   // partial sum of the input row, for the next step
                 R p = R(0);
@@ -281,13 +288,13 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             }
             const int row = DIR == 0 ? i + 1 : i;
             if (ONE) __syncthreads();   // every read of the row is done
-            R *nb = nxt + MN + tid;
+            R *nb = nxt + MN;
 #pragma unroll
             for (int j = 0; j < SPL; ++j) {
-                const int mi = tid + NT * j;
+                const int mi = state(j);
                 const R v = (mi < Mt) ? acc[j] * scl : R(0);
                 own[j] = v;
-                nb[NT * j] = v;
+                nb[mi] = v;
                 if (mi < Mt) out[(size_t)(row - i0) * Mt + mi] = v;
             }
             pp ^= 1;

@@ -130,7 +130,7 @@ constexpr size_t app_tile_lds(int Mt, int mn, int n, int q, size_t tsize, int td
 // prefetch registers per thread in k_chain_ring (fewer in the 16-wave shapes,
 // whose threads have 128 VGPRs, and fewer still for 8-byte Gamma there)
 __host__ __device__ constexpr int ring_prefetch_regs(int nw, size_t tsize) {
-    return nw >= 16 ? (tsize == 8 ? 4 : 8) : 16;
+    return nw >= 16 ? (tsize == 8 ? 4 : 6) : 16;
 }
 
 }  // namespace mapdec
