@@ -3,11 +3,14 @@
 //
 // One workgroup per (frame, TI = kAppTI consecutive symbols i).  With
 // s_lo = n i0 - M the start indices the block needs are s = s_lo + c,
-// c in [0, span), span = n (TI - 1) + 2M + 1; the waves of the workgroup
-// split c into chunks of 64 (wave w takes chunks w, w + nw, ...) and the 64
-// lanes of a wave walk consecutive s, so every R load is a coalesced row
-// segment.  A lane accumulates, for the TD symbol values of the current
-// D tile and every symbol of the block,
+// c in [0, span), span = n (TI - 1) + 2M + 1, in chunks of 64, and the
+// symbol values D in tiles of TD.  The nw waves of the workgroup form G
+// tile groups of nw / G waves (G the largest divisor of nw that is at most
+// the number of tiles): in round r the waves of group g take tile g + r G,
+// each over its own share of the chunks, so a wave sums its accumulators
+// across lanes once per round.  The 64 lanes of a wave walk consecutive s,
+// so every R load is a coalesced row segment.  A lane accumulates, for the
+// TD symbol values of its tile and every symbol of the block,
 //   U_i(D) += K_i(s, k) R(s, D, k),
 //   K_i(s, k) = alpha_i(s - n i) beta_{i+1}(s - n i + k - mn),
 // streaming over k: per k the TI products K_i are formed once (FP64, then
@@ -15,12 +18,13 @@
 // multiply-adds.  The FP64 alpha and beta rows are staged in LDS as
 // (mantissa, exponent) pairs with zero padding wide enough that no lane
 // branches on the band edges (states outside the band, and start indices
-// outside [0, rho], have zero metrics).  R is read
-// through a buffer descriptor with the D row offset in a scalar register and
-// one vector add per k, so the loads cost almost no vector instructions (and
-// the descriptor's size bounds every access).  The TI x TD accumulators
-// are summed across lanes by a butterfly reduce-scatter and across waves
-// through LDS, then
+// outside [0, rho], have zero metrics).  R is read through a buffer
+// descriptor with the D row offset in a scalar register and the lane's
+// start index plus the k row offset in a vector one (one add per k), so the
+// loads cost almost no vector instructions; every index is clamped into the
+// table (the host keeps the table below 2^31 bytes).  The TI x TD accumulators are summed
+// across lanes by a butterfly reduce-scatter and across the waves of a tile
+// group through LDS, then
 //   S_i(D) = prior_i(D) U_i(D),  Z_i = sum_D S_i(D),  APP = S / Z,
 //   d log P / d prior_i(D) = U_i(D) / Z_i.
 #include "device_common.h"
@@ -124,29 +128,45 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
     const gptr<const double> A = to_global((const double *)f.alpha);
     const gptr<const double> B = to_global((const double *)f.beta);
     if (tid < TI) emax[tid] = 2 * kZeroExp;
-    for (int j = tid; j < TI * WA; j += nth) {
-        const int ii = j / WA, m = j - ii * WA - PAD, i = i0 + ii;
-        ar[j] = to_me<T>((i < N && m >= 0 && m < Mt) ? A[(size_t)(i - ib) * Mt + m] : 0.0);
+    // (ii, x) = divmod(j, W) of a flat loop j = tid, tid + nth, ..
+    auto step = [&](int &ii, int &x, int W) {
+        x += nth;
+        while (x >= W) {
+            x -= W;
+            ++ii;
+        }
+    };
+    {
+        int ii = tid / WA, x = tid - ii * WA;
+        for (int j = tid; j < TI * WA; j += nth, step(ii, x, WA)) {
+            const int m = x - PAD, i = i0 + ii;
+            ar[j] = to_me<T>((i < N && m >= 0 && m < Mt) ? A[(size_t)(i - ib) * Mt + m] : 0.0);
+        }
     }
-    for (int j = tid; j < TI * WB; j += nth) {
-        const int ii = j / WB, m = j - ii * WB - PAD - MN, i = i0 + ii;
-        br[j] = to_me<T>((i < N && m >= 0 && m < Mt) ? B[(size_t)(i + 1 - ib) * Mt + m] : 0.0);
+    {
+        int ii = tid / WB, x = tid - ii * WB;
+        for (int j = tid; j < TI * WB; j += nth, step(ii, x, WB)) {
+            const int m = x - PAD - MN, i = i0 + ii;
+            br[j] = to_me<T>((i < N && m >= 0 && m < Mt) ? B[(size_t)(i + 1 - ib) * Mt + m] : 0.0);
+        }
     }
     __syncthreads();
     // Two-slice scale: the product alpha_i(m') beta_{i+1}(m'+delta) spans
     // far less than either row; E_i = max over m', delta of the exponent
     // sum, and every product is taken as 2^-E_i times its true value.
-    for (int j = tid; j < TI * Mt; j += nth) {
-        const int ii = j / Mt, m = j - ii * Mt;
-        const ME<T> a = ar[ii * WA + PAD + m];
-        if (a.m == T(0)) continue;
-        int eb = 2 * kZeroExp;
+    {
+        int ii = tid / Mt, m = tid - ii * Mt;
+        for (int j = tid; j < TI * Mt; j += nth, step(ii, m, Mt)) {
+            const ME<T> a = ar[ii * WA + PAD + m];
+            if (a.m == T(0)) continue;
+            int eb = 2 * kZeroExp;
 #pragma unroll
-        for (int k = 0; k < Mn; ++k) {
-            const ME<T> b = br[ii * WB + PAD + m + k];
-            if (b.m != T(0)) eb = max(eb, b.e);
+            for (int k = 0; k < Mn; ++k) {
+                const ME<T> b = br[ii * WB + PAD + m + k];
+                if (b.m != T(0)) eb = max(eb, b.e);
+            }
+            if (eb > 2 * kZeroExp) atomicMax(&emax[ii], a.e + eb);
         }
-        if (eb > 2 * kZeroExp) atomicMax(&emax[ii], a.e + eb);
     }
     __syncthreads();
 
@@ -157,35 +177,46 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
     const int s_lo = n * i0 - M;
     const int span = n * (TI - 1) + Mt;   // s in [s_lo, s_lo + span)
     const int nchunks = (span + 63) / 64;
-    const int nmy = (nchunks - wv + nwaves - 1) / nwaves;   // chunks of this wave
     const int ntiles = (q + TD - 1) / TD;
-    // One flat sequence of (tile, chunk) pairs per wave, k unrolled inside;
-    // the R loads run PF steps ahead, across chunk and tile boundaries.
+    int G = min(ntiles, nwaves);
+    while (nwaves % G != 0) --G;
+    const int CG = nwaves / G, tg = wv % G, cg = wv / G;
+    // chunks of this wave (at least one step, so that every wave reaches
+    // the same barriers; a chunk past the span is dead)
+    const int nmy = max(1, (nchunks - cg + CG - 1) / CG);
+    const int nrounds = (ntiles + G - 1) / G;
+    const int total = nrounds * nmy;
+    // One flat sequence of (round, chunk) steps per wave, k unrolled
+    // inside; the R loads run PF steps ahead, across chunk and round
+    // boundaries.
     constexpr int PF = 2;
     T r[PF + 1][TD];
-    auto voff_of = [&](int j) {
-        const int ch = wv + (j % nmy) * nwaves;
+    auto voff_at = [&](int jc) {
+        const int ch = cg + jc * CG;
         return (min(max(s_lo + 64 * ch + lane, s0), s1) - s0) * (int)sizeof(T);
     };
-    auto load_k = [&](T(&dst)[TD], int j, int k) {
-        const int vk = voff_of(j) + k * sp * (int)sizeof(T);
-        const int d0 = (j / nmy) * TD;
+    const int spb = sp * (int)sizeof(T);   // bytes per (D, k) row of R
+    // byte offsets of the rows (D, 0) of a tile starting at d0
+    auto rows_of = [&](int(&ro)[TD], int d0) {
 #pragma unroll
-        for (int d = 0; d < TD; ++d) {
-            const int D = min(d0 + d, q - 1);
-            dst[d] = rload<T>(rs, vk, D * Mn * sp * (int)sizeof(T));
-        }
+        for (int d = 0; d < TD; ++d) ro[d] = min(d0 + d, q - 1) * Mn * spb;
     };
-    const int total = ntiles * nmy;
-    if (total > 0) {
+    auto load_k = [&](T(&dst)[TD], int vo, const int(&ro)[TD], int k) {
 #pragma unroll
-        for (int e = 0; e < PF; ++e) load_k(r[e], 0, e);
+        for (int d = 0; d < TD; ++d) dst[d] = rload<T>(rs, vo + k * spb, ro[d]);
+    };
+    int jr = 0, jc = 0;   // round and chunk index of step j
+    {
+        int ro[TD];
+        rows_of(ro, tg * TD);
+#pragma unroll
+        for (int e = 0; e < PF; ++e) load_k(r[e], voff_at(0), ro, e);
     }
     T acc[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[v] = T(0);
     for (int j = 0; j < total; ++j) {
-        const int c = 64 * (wv + (j % nmy) * nwaves) + lane;
+        const int c = 64 * (cg + jc * CG) + lane;
         const int cc = min(c, span - 1);
         const bool live = c < span;
         T am[TI];
@@ -197,14 +228,21 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
             ae[ii] = x.e - emax[ii];
         }
         const ME<T> *bb = br + PAD + cc;
-        const int jn = min(j + 1, total - 1);   // a repeated load past the end is harmless
+        // the next step (a repeated load past the end is harmless)
+        const bool last_chunk = jc + 1 == nmy;
+        const int jcn = last_chunk ? 0 : jc + 1;
+        const int jrn = last_chunk ? min(jr + 1, nrounds - 1) : jr;
+        const int vo = voff_at(jc), von = voff_at(jcn);
+        int ro[TD], ron[TD];
+        rows_of(ro, (tg + jr * G) * TD);
+        rows_of(ron, (tg + jrn * G) * TD);
 #pragma unroll
         for (int k = 0; k < Mn; ++k) {
-            // issue the loads of step (j, k + PF), or of the next pair's first steps
+            // issue the loads of step (j, k + PF), or of the next step's first k
             if (k + PF < Mn)
-                load_k(r[(k + PF) % (PF + 1)], j, k + PF);
+                load_k(r[(k + PF) % (PF + 1)], vo, ro, k + PF);
             else
-                load_k(r[(k + PF) % (PF + 1)], jn, k + PF - Mn);
+                load_k(r[(k + PF) % (PF + 1)], von, ron, k + PF - Mn);
             T kv[TI];
 #pragma unroll
             for (int ii = 0; ii < TI; ++ii) {
@@ -229,9 +267,9 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
 #pragma unroll
                 for (int d = 0; d < TD; ++d) r[e][d] = tmp[e][d];
         }
-        if ((j + 1) % nmy == 0) {
-            // tile j / nmy complete: sum over lanes, then over waves
-            const int d0 = (j / nmy) * TD;
+        if (last_chunk) {
+            // round jr complete: sum over lanes, then over the waves of
+            // each tile group
             ReduceScatter<T, V, 32>::run(acc, lane);
             if constexpr (V >= 64) {
                 constexpr int m = V / 64;
@@ -242,17 +280,20 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
                 if ((lane & ((1 << SH) - 1)) == 0) part[wv * V + (lane >> SH)] = acc[0];
             }
             __syncthreads();
-            for (int x = tid; x < V; x += nth) {
-                const int ii = x / TD, d = x - ii * TD;
-                if (d0 + d >= q) continue;
+            for (int x = tid; x < G * V; x += nth) {
+                const int g = x / V, xv = x - g * V;
+                const int ii = xv / TD, D = (g + jr * G) * TD + (xv - ii * TD);
+                if (D >= q) continue;
                 T u = T(0);
-                for (int y = 0; y < nwaves; ++y) u += part[y * V + x];
-                Ush[ii * q + d0 + d] = u;
+                for (int y = 0; y < CG; ++y) u += part[(y * G + g) * V + xv];
+                Ush[ii * q + D] = u;
             }
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < V; ++v) acc[v] = T(0);
         }
+        jc = jcn;
+        jr = last_chunk ? jr + 1 : jr;
     }
     const T up = T(1) / T(q);
     if (tid < TI && i0 + tid < N) {
