@@ -110,7 +110,10 @@ def cpu_baseline(frames, budget_s=15.0):
     first = oracle.decode_frame(frames[0], grad=True)
     t1 = time.perf_counter() - t0
     nsample = int(min(len(frames), max(nthreads, round(budget_s / max(t1, 1e-3)))))
-    nsample = max(nthreads, (nsample // nthreads) * nthreads) if nsample >= nthreads else nsample
+    # whole rounds of one frame per thread (rounded up, so the sample holds
+    # about budget_s of CPU work or more)
+    if nsample >= nthreads:
+        nsample = min(len(frames), -(-nsample // nthreads) * nthreads)
     idx = list(range(nsample))
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=nthreads) as ex:

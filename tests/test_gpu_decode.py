@@ -157,3 +157,22 @@ def test_large_drift_ranges(prec):
     b = _decode(frames, prec)
     for f, (fr, ref) in enumerate(zip(frames, refs)):
         _check_frame(b, f, fr, ref, prec, f"M={fr.M}")
+
+
+@pytest.mark.parametrize("prec", [mapdec.FP32, mapdec.FP64])
+def test_app_tile_groups(prec):
+    # Drift range 2M+1 = 341 with n = 6: the tiled APP's span of start
+    # indices takes 6 chunks of 64, so 6 waves.  The alphabets give 1 to 10
+    # D tiles (8 values per tile in FP32, 4 in FP64), so the waves form tile
+    # groups that divide them exactly (2 x 3, 3 x 2), fall back to a smaller
+    # divisor, or run several rounds whose last tiles lie past q; general
+    # priors on two of the frames.
+    specs = [(41, 5, 6, 30, 0.05, 0.05, 0.01, 2, 170, 4, False),
+             (42, 12, 6, 30, 0.05, 0.05, 0.01, 2, 170, 4, True),
+             (43, 24, 6, 30, 0.05, 0.05, 0.01, 2, 170, 4, False),
+             (44, 40, 6, 30, 0.05, 0.05, 0.01, 2, 170, 4, True)]
+    frames = [wl.random_frame(*s[:10], with_prior=s[10]) for s in specs]
+    refs = [oracle.decode_frame(fr) for fr in frames]
+    b = _decode(frames, prec)
+    for f, (fr, ref) in enumerate(zip(frames, refs)):
+        _check_frame(b, f, fr, ref, prec, f"q={fr.q}")
