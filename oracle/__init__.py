@@ -59,6 +59,10 @@ def lib():
                                      ctypes.POINTER(ctypes.c_uint8), _dp, ctypes.c_int,
                                      ctypes.POINTER(_Out)]
         L.mapdec_ref_run.restype = ctypes.c_int
+        L.mapdec_ref_run_drift.argtypes = [ctypes.POINTER(_Code), ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_uint8), _dp, _dp, _dp,
+                                           ctypes.c_int, ctypes.POINTER(_Out)]
+        L.mapdec_ref_run_drift.restype = ctypes.c_int
         L.mapdec_ref_lattice.argtypes = [ctypes.POINTER(_Code), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_uint8), ctypes.c_int,
                                          ctypes.c_int, _dp, _dp]
@@ -90,17 +94,25 @@ def _code(codebook, Pi, Pd, Ps, I, M, mn):
     return c, cb
 
 
-def decode(codebook, y, N, Pi, Pd, Ps, I, M, mn, prior=None, *, grad=False,
-           trace=False, literal=False, check=True):
+def decode(codebook, y, N, Pi, Pd, Ps, I, M, mn, prior=None, *, start=None, end=None,
+           grad=False, trace=False, literal=False, check=True):
     """Run the oracle on one frame.  Returns a dict with ``status``, ``logp``,
     ``app`` (N, q) and, on request, ``dparams`` (3,), ``dprior`` (N, q) and
     the trace arrays ``alpha``, ``beta`` ((N+1), 2M+1), ``logA``, ``logB``,
-    ``logZ``."""
+    ``logZ``.  ``start`` / ``end``: priors of the frame's start and end
+    drift over [-M, M] (entry m + M), or None for the known boundary."""
     c, cb = _code(codebook, Pi, Pd, Ps, I, M, mn)
     q = c.q
     yb = np.ascontiguousarray(y, dtype=np.uint8)
     pr = None if prior is None else np.ascontiguousarray(prior, dtype=np.float64)
     Mt = 2 * M + 1
+    bnd = []
+    for v in (start, end):
+        if v is not None:
+            v = np.ascontiguousarray(v, dtype=np.float64)
+            if v.shape != (Mt,):
+                raise ValueError(f"drift prior must have 2M+1 = {Mt} entries")
+        bnd.append(v)
     res = {"app": np.zeros((N, q)), "logp": np.zeros(1)}
     if grad:
         res["dparams"] = np.zeros(3)
@@ -113,9 +125,11 @@ def decode(codebook, y, N, Pi, Pd, Ps, I, M, mn, prior=None, *, grad=False,
         res["logZ"] = np.zeros(N)
     out = _Out(*[_ptr(res.get(k), ctypes.c_double) for k in
                  ("app", "logp", "dparams", "dprior", "alpha", "beta", "logA", "logB", "logZ")])
-    st = lib().mapdec_ref_run(ctypes.byref(c), int(N), int(yb.shape[0]),
-                              _ptr(yb, ctypes.c_uint8) if yb.size else None,
-                              _ptr(pr, ctypes.c_double), int(bool(literal)), ctypes.byref(out))
+    st = lib().mapdec_ref_run_drift(ctypes.byref(c), int(N), int(yb.shape[0]),
+                                    _ptr(yb, ctypes.c_uint8) if yb.size else None,
+                                    _ptr(pr, ctypes.c_double), _ptr(bnd[0], ctypes.c_double),
+                                    _ptr(bnd[1], ctypes.c_double), int(bool(literal)),
+                                    ctypes.byref(out))
     if st and check:
         raise OracleError(st)
     res["status"] = st
@@ -125,6 +139,8 @@ def decode(codebook, y, N, Pi, Pd, Ps, I, M, mn, prior=None, *, grad=False,
 
 def decode_frame(fr, **kw):
     """Oracle decode of a :class:`paper_1802_08483_amd.workloads.Frame`."""
+    kw.setdefault("start", getattr(fr, "start_drift", None))
+    kw.setdefault("end", getattr(fr, "end_drift", None))
     return decode(fr.codebook, fr.y, fr.N, fr.Pi, fr.Pd, fr.Ps, fr.I, fr.M, fr.mn,
                   prior=fr.prior, **kw)
 

@@ -37,8 +37,13 @@
  *   - The corridor holds every lattice node (r, j) to |j - r| <= mn.
  *   - Frame drift limits [-M, M] hold at codeword boundaries only.
  *   - Segments that start before 0 or end after rho have gamma = 0.
- *   - Frame boundaries are known: alpha_0 = delta(m), beta_N = delta(m -
- *     (rho - tau)).
+ *   - Frame boundaries are known, alpha_0 = delta(m) and beta_N = delta(m -
+ *     (rho - tau)), unless drift priors are given: Sec. II-C makes alpha_0
+ *     and beta_N the prior probabilities of the frame boundaries, so a start
+ *     prior phi_0 and an end prior phi_N over [-M, M] are used as those rows
+ *     (as given, not renormalised), and P(y) = sum_m alpha_N(m) phi_N(m) in
+ *     unnormalised terms.  Received bits before the frame's start or after
+ *     its end are not scored.
  *   - With per-step normalisation the APP row is divided by its own sum Z_i
  *     instead of lambda_N(rho - tau) (equal in exact arithmetic).
  *   - Priors are used as given.
@@ -281,6 +286,13 @@ static double prior_of(const decoder *dc, int i, int D)
 int mapdec_ref_run(const ref_code *c, int N, int rho, const uint8_t *y,
                    const double *prior, int literal, ref_out *out)
 {
+    return mapdec_ref_run_drift(c, N, rho, y, prior, NULL, NULL, literal, out);
+}
+
+int mapdec_ref_run_drift(const ref_code *c, int N, int rho, const uint8_t *y,
+                         const double *prior, const double *start, const double *end,
+                         int literal, ref_out *out)
+{
     int st = mapdec_ref_check(c);
     if (st) return st;
     if (N < 1 || rho < 0 || (!y && rho > 0)) return REF_EINVAL;
@@ -329,11 +341,16 @@ int mapdec_ref_run(const ref_code *c, int N, int rho, const uint8_t *y,
 #define ALPHA(i, m) alpha[(size_t)(i) * Mt + (m) + M]
 #define BETA(i, m) beta[(size_t)(i) * Mt + (m) + M]
 
-    /* step 4: alpha_0 = delta(m); alpha'_{i+1}(m) = sum_{m',D} alpha_i(m')
+    /* step 4: alpha_0 = delta(m) or the start prior; alpha'_{i+1}(m) =
+     * sum_{m',D} alpha_i(m')
      * gamma_i(m', m, D); alpha_{i+1} = alpha' / sum alpha'.
      * gamma_i(m', m, D) = prior_i(D) R(Y[ni+m', n(i+1)+m) | C(D)) (eq. 6),
      * defined for |m - m'| <= mn and m, m' in [-M, M]. */
-    ALPHA(0, 0) = 1.0;
+    if (start) {
+        for (int m = -M; m <= M; m++) ALPHA(0, m) = start[m + M];
+    } else {
+        ALPHA(0, 0) = 1.0;
+    }
     logA[0] = 0.0;
     for (int i = 0; i < N; i++) {
         for (int m = -M; m <= M; m++) acc[m + M] = 0.0;
@@ -357,9 +374,14 @@ int mapdec_ref_run(const ref_code *c, int N, int rho, const uint8_t *y,
         logA[i + 1] = logA[i] + log(csum);
     }
 
-    /* step 5: beta_N = delta(m - (rho - tau)); beta'_i(m') = sum_{m,D}
-     * gamma_i(m', m, D) beta_{i+1}(m); beta_i = beta' / sum beta'. */
-    BETA(N, rho - tau) = 1.0;
+    /* step 5: beta_N = delta(m - (rho - tau)) or the end prior; beta'_i(m')
+     * = sum_{m,D} gamma_i(m', m, D) beta_{i+1}(m); beta_i = beta' / sum
+     * beta'. */
+    if (end) {
+        for (int m = -M; m <= M; m++) BETA(N, m) = end[m + M];
+    } else {
+        BETA(N, rho - tau) = 1.0;
+    }
     logB[N] = 0.0;
     for (int i = N - 1; i >= 0; i--) {
         for (int mp = -M; mp <= M; mp++) {
@@ -384,9 +406,15 @@ int mapdec_ref_run(const ref_code *c, int N, int rho, const uint8_t *y,
         logB[i] = logB[i + 1] + log(esum);
     }
 
-    /* step 6: P(y) = alpha_N(rho - tau) in unnormalised terms (eq. 1) */
+    /* step 6: P(y) = alpha_N(rho - tau) in unnormalised terms (eq. 1), or
+     * sum_m alpha_N(m) phi_N(m) with an end prior */
     {
-        double aN = ALPHA(N, rho - tau);
+        double aN = 0.0;
+        if (end) {
+            for (int m = -M; m <= M; m++) aN += ALPHA(N, m) * end[m + M];
+        } else {
+            aN = ALPHA(N, rho - tau);
+        }
         if (!(aN > 0.0)) { st = REF_ENOPATH; goto done; }
         if (out->logp) *out->logp = logA[N] + log(aN);
     }

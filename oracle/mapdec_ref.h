@@ -66,6 +66,17 @@ int mapdec_ref_run(const ref_code *c, int N, int rho, const uint8_t *y,
                    const double *prior, int literal, ref_out *out);
 
 /*
+ * As mapdec_ref_run with priors of the frame boundaries (Sec. II-C: alpha_0
+ * and beta_N are those priors).  start, end: 2M+1 entries each, [m + M] for
+ * drift m, used as given, or NULL for the known boundary (start drift 0,
+ * end drift rho - tau).  P(y) = sum_m alpha_N(m) end[m + M] in
+ * unnormalised terms; received bits outside the frame are not scored.
+ */
+int mapdec_ref_run_drift(const ref_code *c, int N, int rho, const uint8_t *y,
+                         const double *prior, const double *start, const double *end,
+                         int literal, ref_out *out);
+
+/*
  * Receiver metric of one lattice: R[k] = R(y[s .. s+n+k) | C(D)) for
  * k = delta + mn, delta in [-mn, mn] (0 where the segment is invalid).
  * dR (may be NULL): 4*(2mn+1) forward-mode tangents, [w][k] for

@@ -13,6 +13,9 @@ model, closed forms or exact enumeration, never from the oracle itself.
   P9  gradients: softmax-logit closed form, central differences, and the
       path-count identity linking d/dPi and d/dPd
   P10 per-(i, m') lattices equal the lattices memoised per start index
+  P11 priors of the frame boundaries (Sec. II-C): point priors give the
+      known-boundary decode; general priors give the prior-weighted sum of
+      exact known-boundary decodes of the sub-windows y[m0 : tau + mN]
 """
 import itertools
 import math
@@ -299,3 +302,79 @@ def test_status_codes():
     assert r["status"] == oracle.REF_ENOPATH
     r = oracle.decode(cb, y, 2, 0.0, 0.0, 0.0, 2, 2, 1)
     np.testing.assert_array_equal(r["app"], [[1, 0], [0, 1]])
+
+
+# ---- P11 -------------------------------------------------------------------
+
+def test_p11_point_priors_are_the_known_boundaries():
+    fr = wl.random_frame(61, 4, 3, 12, 0.05, 0.05, 0.02, 2, 8, 3)
+    Mt = 2 * fr.M + 1
+    start = np.zeros(Mt)
+    start[fr.M] = 1.0
+    end = np.zeros(Mt)
+    end[fr.M + fr.rho - fr.tau] = 1.0
+    a = oracle.decode_frame(fr, grad=True)
+    b = oracle.decode_frame(fr, grad=True, start=start, end=end)
+    assert b["status"] == 0
+    assert a["logp"] == b["logp"]
+    np.testing.assert_array_equal(a["app"], b["app"])
+    np.testing.assert_array_equal(a["dparams"], b["dparams"])
+    np.testing.assert_array_equal(a["dprior"], b["dprior"])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_p11_boundary_priors_brute_force(seed):
+    # A frame whose first codeword starts at received bit m0 and whose last
+    # ends before bit tau + mN, the bits outside it unscored, is the
+    # known-boundary frame of the sub-window y[m0 : tau + mN] (end drift
+    # mN - m0).  With M above every reachable drift the limits do not bind
+    # in either form, so P(y) = sum phi_0(m0) phi_N(mN) P(sub-window), and
+    # the APPs and d log P / d(Pi, Pd, Ps) are the same weighted mixtures.
+    rng = np.random.default_rng(700 + seed)
+    n, N, q = 2, 2, 3
+    tau = n * N
+    rho = tau + 2
+    words = rng.choice(1 << n, size=q, replace=False)
+    cb = [[(int(w) >> (n - 1 - r)) & 1 for r in range(n)] for w in words]
+    y = [int(b) for b in rng.integers(0, 2, size=rho)]
+    Pi, Pd, Ps = Fr(1, 10), Fr(3, 20), Fr(1, 20)
+    I, mn = 2, 2
+    M = rho + 1
+    Mt = 2 * M + 1
+    start = [Fr(0)] * Mt
+    end = [Fr(0)] * Mt
+    for m0 in (0, 1, 2):
+        start[M + m0] = Fr(int(rng.integers(1, 9)), 8)
+    for mN in (-1, 0, 1, 2):
+        end[M + mN] = Fr(int(rng.integers(1, 9)), 8)
+    P = Fr(0)
+    num = np.zeros((N, q), dtype=object)
+    num[:] = Fr(0)
+    dP = [Fr(0)] * 3
+    for m0 in range(-M, M + 1):
+        for mN in range(-M, M + 1):
+            w = start[M + m0] * end[M + mN]
+            if w == 0:
+                continue
+            sub = y[m0:tau + mN]
+            Msub = max(tau, len(sub)) + 1
+            b = brute(cb, sub, N, Pi, Pd, Ps, I, Msub, mn)
+            if b["P"] == 0:
+                continue
+            P += w * b["P"]
+            for i in range(N):
+                for D in range(q):
+                    num[i, D] += w * b["P"] * b["app"][i][D]
+            for k in range(3):
+                dP[k] += w * b["P"] * b["dparams"][k]
+    assert P > 0
+    r = _oracle(cb, y, N, Pi, Pd, Ps, I, M, mn, grad=True,
+                start=np.array([float(v) for v in start]),
+                end=np.array([float(v) for v in end]))
+    assert r["status"] == 0
+    lp = math.log(P)
+    assert abs(r["logp"] - lp) <= 1e-12 * max(1.0, abs(lp))
+    app = np.array([[float(num[i, D] / P) for D in range(q)] for i in range(N)])
+    np.testing.assert_allclose(r["app"], app, rtol=0, atol=1e-13)
+    g = np.array([float(v / P) for v in dP])
+    np.testing.assert_allclose(r["dparams"], g, rtol=1e-10, atol=1e-10 * np.abs(g).max())
