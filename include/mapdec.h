@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MAPDEC_VERSION 103
+#define MAPDEC_VERSION 104
 
 enum {
     MAPDEC_OK = 0,
@@ -108,6 +108,18 @@ void mapdec_destroy(mapdec_code *code);
  *   app    device, N*q output APPs [i][D] in the same type as prior, or NULL.
  *   dprior device, N*q output d log P(y) / d prior[i][D] (gradient calls
  *          only), same type, or NULL.
+ *   start_drift, end_drift
+ *          device, 2M+1 doubles each, entry [m + M] the prior probability
+ *          that the frame's first codeword starts at received bit m (start)
+ *          or that its last codeword ends at received bit tau + m (end),
+ *          used as given; NULL means the known boundary (start drift 0, end
+ *          drift rho - tau).  These are the priors of the frame boundaries
+ *          that start the forward and backward metrics (Sec. II-C): alpha_0
+ *          = start, beta_N = end, and P(y) = sum_m alpha_N(m) end[m + M].
+ *          Received bits before the start or after the end are not scored;
+ *          entries whose position (m, or tau + m) lies outside [0, rho]
+ *          carry no path and contribute nothing.  Zero-initialise both when
+ *          they are not used.
  */
 typedef struct {
     const mapdec_code *code;
@@ -117,6 +129,8 @@ typedef struct {
     const void *prior;
     void *app;
     void *dprior;
+    const double *start_drift;
+    const double *end_drift;
 } mapdec_frame;
 
 /*

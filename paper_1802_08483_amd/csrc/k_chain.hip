@@ -48,8 +48,14 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
     const double *init = dir == 0 ? f.a_init : f.b_init;
     const int row0 = dir == 0 ? i0 : i1;
     const double lbase = (dir == 0 ? i0 > 0 : i1 < N) ? logX[row0] : 0.0;
+    // a boundary prior's entries whose received position (m at the start,
+    // tau + m at the end) lies outside [0, rho] carry no path: zero, so that
+    // no later kernel pairs them with a clamped start index
+    const bool prior_row = init && (dir == 0 ? i0 == 0 : i1 == N);
+    const int pos0 = dir == 0 ? 0 : f.tau;
     for (int mi = tid; mi < Mt; mi += nth) {
-        const double v = init ? init[mi] : ((mi == m0 + M) ? 1.0 : 0.0);
+        double v = init ? init[mi] : ((mi == m0 + M) ? 1.0 : 0.0);
+        if (prior_row && (pos0 + mi - M < 0 || pos0 + mi - M > f.rho)) v = 0.0;
         buf0[mn + mi] = v;
         out[(size_t)(row0 - i0) * Mt + mi] = v;
     }
@@ -113,8 +119,14 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
         for (int mi = tid; mi < Mt; mi += nth) fin[mi] = cur[mn + mi];
     if (tid != 0) return;
     if (dir == 0 && i1 == N) {
-        // P(y) = alpha_N(rho - tau) in unnormalised terms
-        const double aN = cur[mn + (f.rho - f.tau) + M];
+        // P(y) = alpha_N(rho - tau), or sum_m alpha_N(m) end_prior(m), in
+        // unnormalised terms
+        double aN = 0.0;
+        if (f.end_prior) {
+            for (int mi = 0; mi < Mt; ++mi) aN += cur[mn + mi] * f.end_prior[mi];
+        } else {
+            aN = cur[mn + (f.rho - f.tau) + M];
+        }
         if (!(aN > 0.0)) {
             atomicOr(f.status, kStatusNoPath);
             *f.logp = -INFINITY;

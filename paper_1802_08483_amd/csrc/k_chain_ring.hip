@@ -113,8 +113,14 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     const double *init = DIR == 0 ? f.a_init : f.b_init;
     const gptr<R> out = to_global(DIR == 0 ? f.alpha : f.beta);
     const int rowA = DIR == 0 ? i0 : i1;
+    // a boundary prior's entries whose received position (m at the start,
+    // tau + m at the end) lies outside [0, rho] carry no path: zero, so that
+    // no later kernel pairs them with a clamped start index
+    const bool prior_row = init && (DIR == 0 ? i0 == 0 : i1 == N);
+    const int pos0 = DIR == 0 ? 0 : f.tau;
     for (int mi = tid; mi < Mt; mi += NT) {
-        const R v = init ? (R)init[mi] : ((mi == m0 + M) ? R(1) : R(0));
+        R v = init ? (R)init[mi] : ((mi == m0 + M) ? R(1) : R(0));
+        if (prior_row && (pos0 + mi - M < 0 || pos0 + mi - M > f.rho)) v = R(0);
         row0[MN + mi] = v;
         out[(size_t)(rowA - i0) * Mt + mi] = v;
     }
@@ -318,7 +324,14 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     if (tid != 0) return;
     logX[DIR == 0 ? i1 : i0] = lsum;
     if (DIR == 0 && i1 == N) {
-        const R aN = cur[MN + (f.rho - f.tau) + M];
+        // P(y) = alpha_N(rho - tau), or sum_m alpha_N(m) end_prior(m), in
+        // the row's scale
+        R aN = R(0);
+        if (f.end_prior) {
+            for (int mi = 0; mi < Mt; ++mi) aN += cur[MN + mi] * (R)f.end_prior[mi];
+        } else {
+            aN = cur[MN + (f.rho - f.tau) + M];
+        }
         if (!(aN > R(0))) {
             atomicOr(f.status, kStatusNoPath);
             *f.logp = -INFINITY;

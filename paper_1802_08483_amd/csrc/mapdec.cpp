@@ -212,6 +212,13 @@ bool ring_params(int Mt, int Mn, int n, int mn, bool uniform, size_t tsize, size
 }
 
 int frame_imode(const mapdec_code *c) { return c->I <= 2 ? 0 : 1; }
+// 1 when the adjoint sweep of the frame accumulates d log P / d a itself:
+// when a g_a from the path-count identity would be a small difference of
+// larger terms, or when boundary priors let the frame's paths differ in
+// their net insertions (the identity then does not hold)
+int frame_da(const mapdec_frame &fr) {
+    return (adjoint_needs_da(fr.code->Pi, fr.code->Pd) || fr.start_drift || fr.end_drift) ? 1 : 0;
+}
 
 // LDS bytes one workgroup may use on the current device (64 KiB when the
 // device cannot be queried, e.g. on a host without a GPU).
@@ -327,8 +334,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             L.chain_lds = std::max(L.chain_lds, (2 * ((size_t)F.Mt + 2 * c->mn) + 16) * sizeof(double));
         }
         if (L.grad) {
-            const auto akey = std::make_tuple(c->mn, frame_imode(c),
-                                              adjoint_needs_da(c->Pi, c->Pd) ? 1 : 0);
+            const auto akey = std::make_tuple(c->mn, frame_imode(c), frame_da(fr));
             const size_t al = adjoint_lds(c->n, c->mn, L.tsize);
             if (al > lds_limit) return MAPDEC_EUNSUPPORTED;
             L.adj_lds[akey] = std::max(L.adj_lds[akey], al);
@@ -374,7 +380,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                          (frames[f].prior != nullptr) == (frames[0].prior != nullptr) &&
                          F.ring_shape == F0.ring_shape && F.app_tiled == F0.app_tiled &&
                          F.app_key == F0.app_key && F.dsplit == F0.dsplit &&
-                         adjoint_needs_da(c->Pi, c->Pd) == adjoint_needs_da(c0->Pi, c0->Pd);
+                         frame_da(frames[f]) == frame_da(frames[0]);
         }
     }
     L.slices = (L.grad && one_config && !(flags & (MAPDEC_FLAG_GRAPH | MAPDEC_FLAG_SERIAL)) &&
@@ -432,8 +438,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                 for (int i = g.i0; i < g.i1; ++i) P.app_plain.push_back(Work{f, i - g.i0});
             }
             if (L.grad) {
-                auto &av = P.adj[std::make_tuple(c->mn, frame_imode(c),
-                                                 adjoint_needs_da(c->Pi, c->Pd) ? 1 : 0)];
+                auto &av = P.adj[std::make_tuple(c->mn, frame_imode(c), frame_da(fr))];
                 for (int b = 0; b < nb; ++b)
                     for (int x = 0; x < F.dsplit; ++x) av.push_back(Work{f, b * kLatticeLanes + x});
             }
@@ -1008,7 +1013,8 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
             const double Pt = 1.0 - c->Pi - c->Pd;
             d.a = 0.5 * c->Pi; d.d = c->Pd; d.t1 = Pt * (1.0 - c->Ps); d.t0 = Pt * c->Ps;
             d.Pi = c->Pi; d.Pd = c->Pd; d.Ps = c->Ps;
-            d.adj_da = adjoint_needs_da(c->Pi, c->Pd) ? 1 : 0;
+            d.adj_da = frame_da(fr);
+            d.end_prior = fr.end_drift;
             d.y = fr.y; d.prior = fr.prior; d.app = fr.app; d.dprior = fr.dprior;
             d.logp = logp + f; d.status = status + f;
             d.dparams = dparams ? dparams + 3 * f : nullptr;
@@ -1033,14 +1039,14 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
             d.gacc = d.gacc_all + 4 * (size_t)F.gacc_first[j];
             double *ck = F.nseg > 1 ? reinterpret_cast<double *>(base + F.off_ck) : nullptr;
             double *bc = F.nseg > 1 ? reinterpret_cast<double *>(base + F.off_bcarry) : nullptr;
-            d.a_init = j > 0 ? ck + (size_t)j * F.Mt : nullptr;
+            d.a_init = j > 0 ? ck + (size_t)j * F.Mt : fr.start_drift;
             if (P.forward) {   // frames without segment P.seg + 1 sit this pass out
                 d.a_fin = P.seg + 1 < F.nseg ? ck + (size_t)(j + 1) * F.Mt : nullptr;
                 d.b_init = nullptr;
                 d.b_fin = nullptr;
             } else {
                 d.a_fin = nullptr;
-                d.b_init = j + 1 < F.nseg ? bc : nullptr;
+                d.b_init = j + 1 < F.nseg ? bc : fr.end_drift;
                 d.b_fin = j > 0 ? bc : nullptr;
             }
         }

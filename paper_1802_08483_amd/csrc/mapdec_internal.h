@@ -69,6 +69,9 @@ struct FrameDesc {
     double *a_fin;        // receives alpha row i1, or NULL
     const double *b_init; // beta row i1 or NULL: the end state (i1 = N)
     double *b_fin;        // receives beta row i0, or NULL
+    const double *end_prior;  // [Mt] prior of the frame's end drift, or NULL
+                              // (known end drift rho - tau): log P(y) takes
+                              // sum_m alpha_N(m) end_prior[m] at i1 = N
 };
 
 // Work-table entry: which frame a workgroup serves and where in it.  For

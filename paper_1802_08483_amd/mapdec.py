@@ -39,7 +39,8 @@ class MapdecError(RuntimeError):
 class _Frame(ctypes.Structure):
     _fields_ = [("code", ctypes.c_void_p), ("N", ctypes.c_int32), ("rho", ctypes.c_int32),
                 ("y", ctypes.c_void_p), ("prior", ctypes.c_void_p), ("app", ctypes.c_void_p),
-                ("dprior", ctypes.c_void_p)]
+                ("dprior", ctypes.c_void_p), ("start_drift", ctypes.c_void_p),
+                ("end_drift", ctypes.c_void_p)]
 
 
 _lib = None
@@ -149,9 +150,11 @@ def _stream_handle(stream) -> Optional[int]:
 class Batch:
     """Device buffers and frame table for a batch of frames.
 
-    ``frames``: sequence of (code, y, N, prior) with ``y`` a uint8 CUDA tensor
-    of 0/1 and ``prior`` an (N, q) CUDA tensor of the batch precision or
-    None (uniform).  Allocates the outputs (APP per frame, log P, status,
+    ``frames``: sequence of (code, y, N, prior) or (code, y, N, prior, start,
+    end) with ``y`` a uint8 CUDA tensor of 0/1, ``prior`` an (N, q) CUDA
+    tensor of the batch precision or None (uniform), and ``start`` / ``end``
+    float64 CUDA tensors of 2M+1 entries, the priors of the frame's start and
+    end drift (Sec. II-C), or None for the known boundary.  Allocates the outputs (APP per frame, log P, status,
     gradient buffers) and the workspace, sized for forward checkpoints every
     ``checkpoint_K`` symbols (0: none), which every run of the batch uses.
     """
@@ -166,8 +169,18 @@ class Batch:
         self.grad = grad
         self.codes = []
         self.ys, self.priors, self.apps, self.dpriors = [], [], [], []
+        self.bounds = []
         arr = (_Frame * len(frames))()
-        for f, (code, y, N, prior) in enumerate(frames):
+        for f, item in enumerate(frames):
+            code, y, N, prior = item[:4]
+            start, end = (item[4], item[5]) if len(item) > 4 else (None, None)
+            for v in (start, end):
+                if v is not None and (v.dtype != torch.float64 or not v.is_cuda
+                                      or tuple(v.shape) != (2 * code.M + 1,)):
+                    raise TypeError("drift priors must be float64 CUDA tensors of 2M+1 entries")
+            start = None if start is None else start.contiguous()
+            end = None if end is None else end.contiguous()
+            self.bounds.append((start, end))
             if y.dtype != torch.uint8 or not y.is_cuda:
                 raise TypeError("y must be a uint8 CUDA tensor")
             y = y.contiguous()
@@ -183,7 +196,7 @@ class Batch:
             self.apps.append(app)
             self.dpriors.append(dpr)
             arr[f] = _Frame(code.handle, int(N), int(y.numel()), _ptr(y), _ptr(prior),
-                            _ptr(app), _ptr(dpr))
+                            _ptr(app), _ptr(dpr), _ptr(start), _ptr(end))
         self.frames = arr
         self.nframes = len(frames)
         self.logp = torch.empty(self.nframes, dtype=torch.float64, device=self.device)
@@ -301,5 +314,8 @@ def batch_from_frames(frames: List, precision: int = FP32, grad: bool = False,
         code = code_for(fr, cache)
         y = torch.from_numpy(fr.y).to(dev)
         prior = None if fr.prior is None else torch.from_numpy(fr.prior).to(dev, dtype)
-        items.append((code, y, fr.N, prior))
+        bnd = [None if getattr(fr, k, None) is None
+               else torch.as_tensor(getattr(fr, k), dtype=torch.float64).contiguous().to(dev)
+               for k in ("start_drift", "end_drift")]
+        items.append((code, y, fr.N, prior, bnd[0], bnd[1]))
     return Batch(items, precision=precision, grad=grad, device=dev, checkpoint_K=checkpoint_K)

@@ -50,6 +50,10 @@ class Frame:
     M: int                        # frame drift limit, states [-M, M]
     mn: int                       # per-codeword drift limit, [-mn, mn]
     prior: Optional[np.ndarray] = None   # (N, q) float64, None = uniform
+    # priors of the frame's start / end drift over [-M, M] (entry m + M),
+    # None = known boundary (start drift 0, end drift rho - tau)
+    start_drift: Optional[np.ndarray] = None
+    end_drift: Optional[np.ndarray] = None
     sim: tuple = ()               # (Pi, Pd, Ps) used to draw y
     redraws: int = 0
 

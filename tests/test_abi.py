@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol(L):
     assert set(declared) == set(mapdec.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
-    assert L.mapdec_version() == 103
+    assert L.mapdec_version() == 104
     for st in range(8):
         assert L.mapdec_strerror(st)
 
