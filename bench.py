@@ -170,6 +170,8 @@ def main():
     ap.add_argument("--graph-only", action="store_true",
                     help="time only the single-stream graph replay (every launch a full-batch "
                          "launch running alone, as in the roofline measurement)")
+    ap.add_argument("--no-boundary", action="store_true",
+                    help="skip the same step with priors of the frame boundaries")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven 4096-frame batch (reported beside the main line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -259,6 +261,22 @@ def main():
         p64.close()
         del b64
 
+    boundary = None
+    if not args.no_boundary and not args.graph_only:
+        # the same decode+adjoint step with priors of every frame's start and
+        # end drift (Sec. II-C), as one HIP graph
+        bframes = workloads.with_boundary_priors(frames)
+        bb = mapdec.batch_from_frames(bframes, precision=mapdec.FP32, grad=True)
+        pbd = bb.plan(graph=True)
+        msb = time_plan(pbd, max(3, args.steps // 2), 1, torch)
+        if not (bb.status == 0).all():
+            raise RuntimeError("a frame with boundary priors reported no path")
+        boundary = {"value": round(total_syms / (msb * 1e-3), 1), "ms_per_step": round(msb, 4),
+                    "schedule": "one HIP graph, every launch in order on one stream",
+                    "priors": "start drift 0..8, end drift rho-tau-4..rho-tau+4, binomial"}
+        pbd.close()
+        del bb
+
     uneven = None
     if not args.no_uneven:
         uneven = uneven_batch(mapdec, workloads, torch, max(3, args.steps // 4))
@@ -302,6 +320,7 @@ def main():
         "accuracy": {"frames_checked": len(refs), "app_max_abs_err": app_err,
                      "logp_max_rel_err": lp_err, "grad_max_rel_err": g_err},
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "boundary_priors": boundary,
         "uneven": uneven,
     }
     print(json.dumps(line))

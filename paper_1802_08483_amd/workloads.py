@@ -221,3 +221,26 @@ def random_frame(seed: int, q: int, n: int, N: int, Pi: float, Pd: float, Ps: fl
     ss = np.random.SeedSequence([SEED_ROOT, 1000, seed])
     return _draw_frame(ss, q, n, N, sim or (Pi, Pd, Ps), (Pi, Pd, Ps), I, M, mn,
                        with_prior=with_prior)
+
+
+def with_boundary_priors(frames: List[Frame], spread: int = 4) -> List[Frame]:
+    """The frames with priors of their start and end drift instead of known
+    boundaries: binomial weights over start drifts 0 .. 2 spread and over end
+    drifts within spread of rho - tau (clipped to [-M, M]), normalised."""
+    from math import comb
+    w = np.array([comb(2 * spread, k) for k in range(2 * spread + 1)], dtype=np.float64)
+    w /= w.sum()
+    out = []
+    for fr in frames:
+        Mt = 2 * fr.M + 1
+        st = np.zeros(Mt)
+        en = np.zeros(Mt)
+        for k in range(2 * spread + 1):
+            m0 = k
+            if m0 <= fr.M:
+                st[fr.M + m0] += w[k]
+            mN = fr.rho - fr.tau + k - spread
+            if abs(mN) <= fr.M:
+                en[fr.M + mN] += w[k]
+        out.append(dataclasses.replace(fr, start_drift=st, end_drift=en))
+    return out
