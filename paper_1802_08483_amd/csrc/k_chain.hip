@@ -118,12 +118,31 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
     if (fin)
         for (int mi = tid; mi < Mt; mi += nth) fin[mi] = cur[mn + mi];
     if (tid != 0) return;
+    if (dir == 1 && i0 == 0 && f.grad && f.start_prior) {
+        // posterior mean of the start drift (prior entries outside [0, rho]
+        // carry no path), for the path-count identity of the adjoint
+        double b0 = 0.0, b0m = 0.0;
+        for (int mi = 0; mi < Mt; ++mi) {
+            if (mi - M < 0 || mi - M > f.rho) continue;
+            const double v = cur[mn + mi] * f.start_prior[mi];
+            b0 += v;
+            b0m += v * (double)(mi - M);
+        }
+        if (b0 > 0.0) f.gacc_all[4 * (size_t)f.gacc_n + 1] = b0m / b0;
+    }
     if (dir == 0 && i1 == N) {
         // P(y) = alpha_N(rho - tau), or sum_m alpha_N(m) end_prior(m), in
         // unnormalised terms
-        double aN = 0.0;
+        double aN = 0.0, aNm = 0.0;
         if (f.end_prior) {
-            for (int mi = 0; mi < Mt; ++mi) aN += cur[mn + mi] * f.end_prior[mi];
+            for (int mi = 0; mi < Mt; ++mi) {
+                const double v = cur[mn + mi] * f.end_prior[mi];
+                aN += v;
+                aNm += v * (double)(mi - M);
+            }
+            // posterior mean of the end drift, for the path-count identity
+            // of the adjoint
+            if (f.grad && aN > 0.0) f.gacc_all[4 * (size_t)f.gacc_n] = aNm / aN;
         } else {
             aN = cur[mn + (f.rho - f.tau) + M];
         }

@@ -323,12 +323,31 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
         for (int mi = tid; mi < Mt; mi += NT) fin[mi] = cur[MN + mi];
     if (tid != 0) return;
     logX[DIR == 0 ? i1 : i0] = lsum;
+    if (DIR == 1 && i0 == 0 && f.grad && f.start_prior) {
+        // posterior mean of the start drift (prior entries outside [0, rho]
+        // carry no path), for the path-count identity of the adjoint
+        R b0 = R(0), b0m = R(0);
+        for (int mi = 0; mi < Mt; ++mi) {
+            if (mi - M < 0 || mi - M > f.rho) continue;
+            const R v = cur[MN + mi] * (R)f.start_prior[mi];
+            b0 += v;
+            b0m += v * (R)(mi - M);
+        }
+        if (b0 > R(0)) f.gacc_all[4 * (size_t)f.gacc_n + 1] = b0m / b0;
+    }
     if (DIR == 0 && i1 == N) {
         // P(y) = alpha_N(rho - tau), or sum_m alpha_N(m) end_prior(m), in
         // the row's scale
-        R aN = R(0);
+        R aN = R(0), aNm = R(0);
         if (f.end_prior) {
-            for (int mi = 0; mi < Mt; ++mi) aN += cur[MN + mi] * (R)f.end_prior[mi];
+            for (int mi = 0; mi < Mt; ++mi) {
+                const R v = cur[MN + mi] * (R)f.end_prior[mi];
+                aN += v;
+                aNm += v * (R)(mi - M);
+            }
+            // posterior mean of the end drift, for the path-count identity
+            // of the adjoint
+            if (f.grad && aN > R(0)) f.gacc_all[4 * (size_t)f.gacc_n] = aNm / aN;
         } else {
             aN = cur[MN + (f.rho - f.tau) + M];
         }

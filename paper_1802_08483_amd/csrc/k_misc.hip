@@ -105,9 +105,16 @@ __global__ __launch_bounds__(256) void k_dparams(const FrameDesc *__restrict__ f
         for (int t = 0; t < 4; ++t) g[t] += f.gacc_all[(size_t)b * 4 + t];
     for (int t = 0; t < 4; ++t) g[t] = block_sum(g[t], red);
     if (threadIdx.x != 0) return;
-    // without the d/da sweep: a g_a - d g_d = rho - tau (every path inserts
-    // rho - tau more bits than it deletes)
-    if (!f.adj_da) g[0] = ((double)(f.rho - f.tau) + f.d * g[1]) / f.a;
+    // without the d/da sweep: a path from start drift m0 to end drift mN
+    // inserts mN - m0 more bits than it deletes, so a g_a - d g_d is the
+    // posterior mean of mN - m0: rho - tau for known boundaries, else the
+    // means the chains left after the partials
+    if (!f.adj_da) {
+        const double *mom = f.gacc_all + 4 * (size_t)f.gacc_n;
+        const double net = (f.end_prior ? mom[0] : (double)(f.rho - f.tau)) -
+                           (f.start_prior ? mom[1] : 0.0);
+        g[0] = (net + f.d * g[1]) / f.a;
+    }
     const double Ps = f.Ps, Pt = 1.0 - f.Pi - f.Pd;
     f.dparams[0] = 0.5 * g[0] - (1.0 - Ps) * g[2] - Ps * g[3];
     f.dparams[1] = g[1] - (1.0 - Ps) * g[2] - Ps * g[3];

@@ -212,13 +212,10 @@ bool ring_params(int Mt, int Mn, int n, int mn, bool uniform, size_t tsize, size
 }
 
 int frame_imode(const mapdec_code *c) { return c->I <= 2 ? 0 : 1; }
-// 1 when the adjoint sweep of the frame accumulates d log P / d a itself:
-// when a g_a from the path-count identity would be a small difference of
-// larger terms, or when boundary priors let the frame's paths differ in
-// their net insertions (the identity then does not hold)
-int frame_da(const mapdec_frame &fr) {
-    return (adjoint_needs_da(fr.code->Pi, fr.code->Pd) || fr.start_drift || fr.end_drift) ? 1 : 0;
-}
+// 1 when the adjoint sweep of the frame accumulates d log P / d a itself,
+// which it does when a g_a from the path-count identity would be a small
+// difference of larger terms
+int frame_da(const mapdec_frame &fr) { return adjoint_needs_da(fr.code->Pi, fr.code->Pd) ? 1 : 0; }
 
 // LDS bytes one workgroup may use on the current device (64 KiB when the
 // device cannot be queried, e.g. on a host without a GPU).
@@ -554,8 +551,8 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         off = align_up(off + sizeof(double) * fr.N);
         F.off_Zexp = off;
         off = align_up(off + sizeof(int) * fr.N);
-        F.off_gacc = off;
-        off = align_up(off + sizeof(double) * 4 * (size_t)F.gacc_n);
+        F.off_gacc = off;   // the partials, then one slot for the boundary-drift means
+        off = align_up(off + sizeof(double) * 4 * ((size_t)F.gacc_n + 1));
         if (F.nseg > 1) {
             F.off_ck = off;      // alpha rows K, 2K, .. (row jK at index j)
             off = align_up(off + sizeof(double) * (size_t)F.nseg * F.Mt);
@@ -1014,6 +1011,7 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
             d.a = 0.5 * c->Pi; d.d = c->Pd; d.t1 = Pt * (1.0 - c->Ps); d.t0 = Pt * c->Ps;
             d.Pi = c->Pi; d.Pd = c->Pd; d.Ps = c->Ps;
             d.adj_da = frame_da(fr);
+            d.start_prior = fr.start_drift;
             d.end_prior = fr.end_drift;
             d.y = fr.y; d.prior = fr.prior; d.app = fr.app; d.dprior = fr.dprior;
             d.logp = logp + f; d.status = status + f;

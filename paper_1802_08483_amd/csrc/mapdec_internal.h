@@ -50,9 +50,12 @@ struct FrameDesc {
     int *Zexp;            // [N] binary exponent of the APP's row-product scale
     double *gacc;         // [lattice workgroups of this segment][4] partial
                           // d log P / d(a, d, t1, t0)
-    double *gacc_all;     // every segment's partials of the frame, contiguous
+    double *gacc_all;     // every segment's partials of the frame, contiguous,
+                          // then [4] more: the posterior means of the end and
+                          // start drift (boundary priors, gradient passes)
     int gacc_n;           // number of [4] partials at gacc_all
-    int adj_da;           // the adjoint sweep accumulates d/da (else from rho - tau)
+    int adj_da;           // the adjoint sweep accumulates d/da (else from the
+                          // path-count identity)
     // Codewords per lattice / adjoint workgroup: dq = q unless a pass has too
     // few workgroups to fill the device, when each (start-index block) item
     // is split into dsplit items of dq codewords; the chunk index rides in
@@ -69,6 +72,7 @@ struct FrameDesc {
     double *a_fin;        // receives alpha row i1, or NULL
     const double *b_init; // beta row i1 or NULL: the end state (i1 = N)
     double *b_fin;        // receives beta row i0, or NULL
+    const double *start_prior;  // [Mt] prior of the frame's start drift, or NULL
     const double *end_prior;  // [Mt] prior of the frame's end drift, or NULL
                               // (known end drift rho - tau): log P(y) takes
                               // sum_m alpha_N(m) end_prior[m] at i1 = N

@@ -125,8 +125,9 @@ def test_point_priors_equal_known_boundary():
         assert torch.equal(a.logp, b.logp)
         assert torch.equal(a.apps[0], b.apps[0])
         assert torch.equal(a.dpriors[0], b.dpriors[0])
-        # d/dPi comes from the path-count identity without priors and from
-        # the sweep's own sum with them: equal up to rounding
+        # d/dPi: a g_a - d g_d is rho - tau without priors and the posterior
+        # mean of mN - m0 (computed from the rows) with them: equal up to
+        # rounding
         assert _rel(b.dparams[0].cpu().numpy(), a.dparams[0].cpu().numpy()) <= TOL_GRAD[prec]
 
 
