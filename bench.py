@@ -320,6 +320,10 @@ def main():
         "accuracy": {"frames_checked": len(refs), "app_max_abs_err": app_err,
                      "logp_max_rel_err": lp_err, "grad_max_rel_err": g_err},
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        # the chain phase is a sequence of N dependent banded steps (forward
+        # and backward chains of every frame run side by side): its latency
+        # per step
+        "chain_step_us": round(phases.get("chain", 0.0) * 1e3 / max(fr.N for fr in frames), 4),
         "boundary_priors": boundary,
         "uneven": uneven,
     }
