@@ -136,3 +136,22 @@ def test_drift_prior_shape_is_checked():
     bad = dataclasses.replace(fr, start_drift=np.ones(2 * fr.M))
     with pytest.raises(TypeError):
         mapdec.batch_from_frames([bad], precision=mapdec.FP64)
+
+
+def test_boundary_priors_full_batch_sampled():
+    # the 256-frame batch (q = 16, n = 10, N = 500) with the boundary priors
+    # the benchmark uses, FP32 decode + adjoint as one HIP graph; sampled
+    # frames against the oracle, APP row sums on all
+    frames = wl.with_boundary_priors(wl.make_workload(2))
+    b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True)
+    p = b.plan(graph=True)
+    p.run()
+    torch.cuda.synchronize()
+    assert (b.status.cpu().numpy() == 0).all()
+    for f in range(len(frames)):
+        s = b.apps[f].double().sum(1).cpu().numpy()
+        assert np.abs(s - 1).max() < 1e-5
+    for f in (0, 255):
+        ref = oracle.decode_frame(frames[f], grad=True)
+        _check(b, f, ref, mapdec.FP32, True, f"full batch frame {f}")
+    p.close()
