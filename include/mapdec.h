@@ -118,8 +118,9 @@ void mapdec_destroy(mapdec_code *code);
  *          = start, beta_N = end, and P(y) = sum_m alpha_N(m) end[m + M].
  *          Received bits before the start or after the end are not scored;
  *          entries whose position (m, or tau + m) lies outside [0, rho]
- *          carry no path and contribute nothing.  Zero-initialise both when
- *          they are not used.
+ *          carry no path and contribute nothing.  The priors are inputs
+ *          only: gradients cover (Pi, Pd, Ps) and the symbol priors, not
+ *          these.  Zero-initialise both when they are not used.
  */
 typedef struct {
     const mapdec_code *code;
