@@ -155,3 +155,29 @@ def test_boundary_priors_full_batch_sampled():
         ref = oracle.decode_frame(frames[f], grad=True)
         _check(b, f, ref, mapdec.FP32, True, f"full batch frame {f}")
     p.close()
+
+
+def test_autograd_with_boundary_priors():
+    # the autograd binding with boundary priors: d log P / d(Pi, Pd, Ps)
+    # summed over the batch against the oracle
+    from paper_1802_08483_amd.autograd import MapDecFn
+    base = [wl.random_frame(95 + k, 8, 5, 40, 0.05, 0.05, 0.02, 2, 14, 4, with_prior=True)
+            for k in range(3)]
+    frames = [_bounded(fr, 95 + k) for k, fr in enumerate(base)]
+    fr0 = frames[0]
+    assert all(f.N == fr0.N for f in frames)
+    # one shared codebook: draw the received bits of every frame with frame 0's
+    frames = [dataclasses.replace(f, codebook=fr0.codebook) for f in frames]
+    prior = torch.from_numpy(np.stack([f.prior for f in frames])).cuda()
+    params = torch.tensor([fr0.Pi, fr0.Pd, fr0.Ps], dtype=torch.float64, requires_grad=True)
+    ys = [torch.from_numpy(f.y).cuda() for f in frames]
+    start = torch.from_numpy(np.stack([f.start_drift for f in frames])).cuda()
+    end = torch.from_numpy(np.stack([f.end_drift for f in frames])).cuda()
+    logp, app = MapDecFn.apply(prior, params, ys, fr0.codebook, fr0.I, fr0.M, fr0.mn,
+                               mapdec.FP64, start, end)
+    logp.sum().backward()
+    refs = [oracle.decode_frame(f, grad=True) for f in frames]
+    np.testing.assert_allclose(logp.detach().cpu().numpy(), [r["logp"] for r in refs],
+                               rtol=1e-12)
+    gp_ref = np.sum([r["dparams"] for r in refs], axis=0)
+    assert _rel(params.grad.numpy(), gp_ref) <= 1e-9
