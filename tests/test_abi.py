@@ -7,6 +7,7 @@ pointers passed to the library in these tests are never dereferenced.
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -120,3 +121,24 @@ def test_unsupported_sizes(L):
     fr2 = _frames([(c2, 10, 30)])
     assert L.mapdec_decode(fr2, 1, dummy, dummy, dummy, 1 << 30, mapdec.FP32, None) \
         == mapdec.EUNSUPPORTED
+
+
+def test_frame_struct_layout_matches_header(tmp_path):
+    # the binding's ctypes mirror of mapdec_frame has the size and field
+    # offsets that a C compiler gives the header's struct
+    fields = [f[0] for f in mapdec._Frame._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "mapdec.h"\n'
+        "int main(void) {\n"
+        '    printf("%zu", sizeof(mapdec_frame));\n'
+        + "".join(f'    printf(" %zu", offsetof(mapdec_frame, {f}));\n' for f in fields)
+        + "    return 0;\n}\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True)
+    vals = [int(v) for v in out.stdout.split()]
+    assert vals[0] == ctypes.sizeof(mapdec._Frame)
+    assert vals[1:] == [getattr(mapdec._Frame, f).offset for f in fields]
