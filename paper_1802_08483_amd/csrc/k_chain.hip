@@ -128,7 +128,8 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
             b0 += v;
             b0m += v * (double)(mi - M);
         }
-        if (b0 > 0.0) f.gacc_all[4 * (size_t)f.gacc_n + 1] = b0m / b0;
+        // written on every run, so that no earlier run's value is read
+        f.gacc_all[4 * (size_t)f.gacc_n + 1] = b0 > 0.0 ? b0m / b0 : 0.0;
     }
     if (dir == 0 && i1 == N) {
         // P(y) = alpha_N(rho - tau), or sum_m alpha_N(m) end_prior(m), in
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
             }
             // posterior mean of the end drift, for the path-count identity
             // of the adjoint
-            if (f.grad && aN > 0.0) f.gacc_all[4 * (size_t)f.gacc_n] = aNm / aN;
+            if (f.grad) f.gacc_all[4 * (size_t)f.gacc_n] = aN > 0.0 ? aNm / aN : 0.0;
         } else {
             aN = cur[mn + (f.rho - f.tau) + M];
         }

@@ -333,7 +333,8 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             b0 += v;
             b0m += v * (R)(mi - M);
         }
-        if (b0 > R(0)) f.gacc_all[4 * (size_t)f.gacc_n + 1] = b0m / b0;
+        // written on every run, so that no earlier run's value is read
+        f.gacc_all[4 * (size_t)f.gacc_n + 1] = b0 > R(0) ? b0m / b0 : R(0);
     }
     if (DIR == 0 && i1 == N) {
         // P(y) = alpha_N(rho - tau), or sum_m alpha_N(m) end_prior(m), in
@@ -347,7 +348,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             }
             // posterior mean of the end drift, for the path-count identity
             // of the adjoint
-            if (f.grad && aN > R(0)) f.gacc_all[4 * (size_t)f.gacc_n] = aNm / aN;
+            if (f.grad) f.gacc_all[4 * (size_t)f.gacc_n] = aN > R(0) ? aNm / aN : R(0);
         } else {
             aN = cur[MN + (f.rho - f.tau) + M];
         }
