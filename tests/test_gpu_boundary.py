@@ -181,3 +181,46 @@ def test_autograd_with_boundary_priors():
                                rtol=1e-12)
     gp_ref = np.sum([r["dparams"] for r in refs], axis=0)
     assert _rel(params.grad.numpy(), gp_ref) <= 1e-9
+
+
+def _random_bounded(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(2, 7))
+    q = int(rng.integers(2, min(16, 1 << n) + 1))
+    N = int(rng.integers(3, 30))
+    M = int(rng.integers(6, 20))
+    mn = int(rng.integers(1, min(M, 5) + 1))
+    fr = wl.random_frame(500 + seed, q, n, N, 0.05, 0.05, 0.02, 2, M, mn,
+                         with_prior=bool(rng.integers(0, 2)))
+    Mt = 2 * M + 1
+    st = en = None
+    if rng.random() < 0.8:   # random support, some entries before the received bits
+        st = np.where(rng.random(Mt) < 0.3, rng.random(Mt), 0.0)
+        st[M] = rng.random() + 0.1
+    if rng.random() < 0.8:   # random support around rho - tau, some past the end
+        en = np.where(rng.random(Mt) < 0.3, rng.random(Mt), 0.0)
+        en[M + fr.rho - fr.tau] = rng.random() + 0.1
+    return dataclasses.replace(fr, start_drift=st, end_drift=en)
+
+
+@pytest.mark.parametrize("prec", [mapdec.FP64, mapdec.FP32])
+def test_boundary_priors_random(prec):
+    # seeded random frames and supports, plus a frame whose end prior lies
+    # wholly past the received bits (no path on either side)
+    frames = [_random_bounded(k) for k in range(12)]
+    nop = wl.random_frame(530, 4, 3, 10, 0.05, 0.05, 0.02, 2, 8, 3)
+    en = np.zeros(2 * nop.M + 1)
+    for m in range(-nop.M, nop.M + 1):
+        if nop.tau + m > nop.rho:
+            en[nop.M + m] = 1.0
+    frames.append(dataclasses.replace(nop, end_drift=en))
+    refs = [oracle.decode_frame(fr, grad=True, check=False) for fr in frames]
+    assert refs[-1]["status"] == oracle.REF_ENOPATH
+    g = mapdec.batch_from_frames(frames, precision=prec, grad=True)
+    g.run_grad()
+    torch.cuda.synchronize()
+    for f, ref in enumerate(refs):
+        if ref["status"] != 0:
+            assert int(g.status[f]) == mapdec.ENOPATH, f"frame {f}"
+            continue
+        _check(g, f, ref, prec, True, f"random frame {f}")
