@@ -281,9 +281,27 @@ def main():
     if not args.no_uneven:
         uneven = uneven_batch(mapdec, workloads, torch, max(3, args.steps // 4))
 
+    # the single small frame (q = 8, n = 6, N = 64, FP64 decode): a launch-
+    # and latency-bound case, one HIP graph
+    small = None
+    if not args.graph_only:
+        sf = workloads.make_workload(1)
+        bs = mapdec.batch_from_frames(sf, precision=mapdec.FP64)
+        ps = bs.plan(graph=True)
+        mss = time_plan(ps, max(10, args.steps), 3, torch)
+        small = {"workload": workloads.WORKLOAD_NAMES[1], "gpu_graph_ms": round(mss, 4)}
+        ps.close()
+        del bs
+
     cpu, refs = (None, {})
     if not args.no_cpu_baseline:
         cpu, refs = cpu_baseline(frames)
+        if small is not None:
+            import oracle
+            t0 = time.perf_counter()
+            for _ in range(5):
+                oracle.decode_frame(sf[0])
+            small["oracle_1core_ms"] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
     else:
         import oracle
         refs = {0: oracle.decode_frame(frames[0], grad=True)}
@@ -325,6 +343,7 @@ def main():
         # per step
         "chain_step_us": round(phases.get("chain", 0.0) * 1e3 / max(fr.N for fr in frames), 4),
         "boundary_priors": boundary,
+        "small_frame": small,
         "uneven": uneven,
     }
     print(json.dumps(line))
