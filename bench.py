@@ -180,8 +180,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the decoder's frames "
-              "are independent and would shard by frame across GPUs, which this build does "
-              "not run.", file=sys.stderr)
+              "are independent and would shard by frame across GPUs, but only the "
+              "single-GPU run is implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -46,7 +46,7 @@ enum {
     MAPDEC_ENOMEM = 4,       /* host or device allocation failed                   */
     MAPDEC_ESIZE = 5,        /* workspace smaller than mapdec_workspace_size()     */
     MAPDEC_EDEVICE = 6,      /* a HIP runtime call failed                          */
-    MAPDEC_EUNSUPPORTED = 7  /* parameters beyond this build's kernel limits       */
+    MAPDEC_EUNSUPPORTED = 7  /* parameters beyond the library's kernel limits     */
 };
 
 enum { MAPDEC_FP32 = 0, MAPDEC_FP64 = 1 };
@@ -59,7 +59,7 @@ enum {
     MAPDEC_FLAG_TUNE = 8     /* time launch choices first (plan creation)    */
 };
 
-/* Kernel limits of this build: n <= MAPDEC_MAX_N, mn <= MAPDEC_MAX_MN,
+/* Kernel limits of the library: n <= MAPDEC_MAX_N, mn <= MAPDEC_MAX_MN,
  * q <= MAPDEC_MAX_Q; beyond them decode calls return MAPDEC_EUNSUPPORTED. */
 #define MAPDEC_MAX_N 16
 #define MAPDEC_MAX_MN 8

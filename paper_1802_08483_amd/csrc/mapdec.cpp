@@ -1421,7 +1421,7 @@ const char *mapdec_strerror(int status) {
         case MAPDEC_ENOMEM: return "MAPDEC_ENOMEM: allocation failed";
         case MAPDEC_ESIZE: return "MAPDEC_ESIZE: workspace too small";
         case MAPDEC_EDEVICE: return "MAPDEC_EDEVICE: HIP runtime error";
-        case MAPDEC_EUNSUPPORTED: return "MAPDEC_EUNSUPPORTED: beyond this build's kernel limits";
+        case MAPDEC_EUNSUPPORTED: return "MAPDEC_EUNSUPPORTED: beyond the library's kernel limits";
         default: return "unknown mapdec status";
     }
 }
