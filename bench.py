@@ -1,30 +1,38 @@
 #!/usr/bin/env python3
 """Throughput of the MAP forward-backward decoder on one MI355X.
 
-Workload: 256 frames, q=16 codewords of n=10 bits, N=500 symbols per frame
-(tau = 5000 bits), BSID channel Pi=Pd=0.05, Ps=0.01, insertion cap I=2,
-drift limits M=98 and mn=6, uniform priors, seeded synthetic frames.  A
-step is one FP32 batched decode plus adjoint of the whole batch
+Headline workload: 16 frames, q=64 codewords of n=12 bits, N=10000 symbols
+per frame (tau = 120000 bits), BSID channel Pi=Pd=0.1, Ps=0, insertion cap
+I=2, drift limits M=693 and mn=8, uniform priors, seeded synthetic frames.
+A step is one FP32 batched decode plus adjoint of the whole batch
 (receiver-metric lattice, forward/backward chains, APPs, log P(y), then
-d log P(y) / d(Pi, Pd, Ps) and d log P(y) / d prior), with every input
-already in HBM, run as an eager plan: 4 slices of 64 frames on 4 HIP
-streams, the compute-bound launches staggered slice by slice so that each
-slice's forward/backward chains run beside the next slice's lattice and the
-previous slice's APP.  The same step replayed as one single-stream HIP
-graph is reported beside it.
+d log P(y) / d(Pi, Pd, Ps) and d log P(y) / d prior) with forward-metric
+checkpoints every K = ceil(sqrt(N)) = 100 symbols and the receiver metric
+recomputed in the backward and adjoint passes, every input already in HBM,
+replayed as one HIP graph.
 
-Prints one JSON line: symbols per second, the roofline of the dominant
-kernel (live HIP-event timing per phase), the FP32 decode alone and the
-FP64 plain GPU decode of the same frames, the FP32 errors against the FP64
-CPU oracle, and the oracle's own throughput (decode plus gradient) on a
-bounded sample (host cores).  Beside it, the FP32 decode of the uneven
-4096-frame batch (tuned choices, launch groups on forked streams).
+Beside it, each with its own roofline figure: the channel-estimation batch
+(128 frames, q=16, n=10, N=1000, softmax priors, decode+adjoint), the
+256-frame batch (q=16, n=10, N=500, decode+adjoint, decode alone and the
+FP64 plain decode), the uneven 4096-frame batch (decode, tuned choices) and
+the single small frame (FP64 decode).
+
+Prints one JSON line.  The roofline of a line is that of its dominant
+kernel: algorithmic flops per launch (the method's work, recomputation
+excluded; FMA = 2 flops) over the kernel's average launch time, measured
+live with HIP events recorded on the launch's own stream around every launch
+(one eager pass of the same plan).  The CPU baseline is the FP64 oracle
+(decode and gradient), built -O3 -march=native on this host, on a bounded
+sample of the headline workload, one frame per host thread.
 """
 import argparse
 import json
 import math
 import os
+import platform
+import subprocess
 import sys
+import tempfile
 import time
 from concurrent.futures import ThreadPoolExecutor
 
@@ -33,7 +41,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed); unpacked issue is half of it
 PEAK_FP64_TFLOPS = 78.6
-WORKLOAD = 2
+HEADLINE = 5
+# host threads a GPU's share of the machine holds (one MI355X: 16)
+HOST_THREADS_CAP = 16
 
 
 def corridor_nodes(n, mn):
@@ -41,38 +51,69 @@ def corridor_nodes(n, mn):
     return sum(r + mn - max(0, r - mn) + 1 for r in range(n + 1))
 
 
-def phase_flops(frames):
-    """Algorithmic flops of each phase for a batch (FMA = 2 flops).
-    lattice: rho q C(n, mn) (3 + 2I); chain: 4 N M_tau M_n (alpha and beta);
-    app: 2 N M_tau M_n (q + 1); wgrad: 3 N M_tau M_n (uniform priors) or
-    4 N M_tau M_n q; adjoint: three lattice passes (forward recompute,
-    adjoint propagation, parameter products)."""
-    out = {"lattice": 0.0, "chain": 0.0, "app": 0.0, "wgrad": 0.0, "adjoint": 0.0}
+def covered_starts(fr, K):
+    """Start indices the lattice / adjoint launches of one run cover: the
+    whole received range without checkpoints; with segments of K symbols,
+    each segment's [n i0 - M, n (i1 - 1) + M] clipped to [0, rho], counted
+    per pass (forward passes over segments 0 .. S-2, main passes over all)."""
+    if not K:
+        return fr.rho + 1, fr.rho + 1
+    S = -(-fr.N // K)
+    tot = 0
+    for j in range(S):
+        i0, i1 = j * K, min(fr.N, (j + 1) * K)
+        s0 = max(0, fr.n * i0 - fr.M)
+        s1 = min(fr.rho, fr.n * (i1 - 1) + fr.M)
+        tot += s1 - s0 + 1
+    fwd = tot - (min(fr.rho, fr.n * (fr.N - 1) + fr.M) - max(0, fr.n * (S - 1) * K - fr.M) + 1)
+    return tot + fwd, tot
+
+
+def phase_flops(frames, K=0):
+    """Algorithmic flops of each phase for a batch (FMA = 2 flops), and the
+    flops the phases execute on top of them (recomputation).
+    lattice: W_R = rho q C(n, mn) (3 + 2I); gamma (general priors):
+    2 N Mt Mn q; chain: 4 N Mt Mn (alpha and beta); app: 2 N Mt Mn (q + 1);
+    wgrad: 3 N Mt Mn (uniform priors) or 4 N Mt Mn q; adjoint: 2 W_R (the
+    reverse sweep's adjoint propagation and parameter products).  Executed
+    on top: the lattice and adjoint over every pass's covered start indices
+    (checkpointed segments overlap by 2M), and the adjoint's recompute of
+    the forward lattice (one more W_R over what it covers)."""
+    alg = {"lattice": 0.0, "gamma": 0.0, "chain": 0.0, "app": 0.0, "wgrad": 0.0,
+           "adjoint": 0.0}
+    extra = {"lattice": 0.0, "adjoint": 0.0}
     for fr in frames:
         Mt, Mn = 2 * fr.M + 1, 2 * fr.mn + 1
-        lat = fr.rho * fr.q * corridor_nodes(fr.n, fr.mn) * (3 + 2 * fr.I)
-        out["lattice"] += lat
-        out["chain"] += 4.0 * fr.N * Mt * Mn
-        out["app"] += 2.0 * fr.N * Mt * Mn * (fr.q + 1)
-        out["wgrad"] += (3.0 if fr.prior is None else 4.0 * fr.q) * fr.N * Mt * Mn
-        out["adjoint"] += 3.0 * lat
-    return out
+        per_s = fr.q * corridor_nodes(fr.n, fr.mn) * (3 + 2 * fr.I)
+        lat = (fr.rho + 1) * per_s
+        lat_cov, adj_cov = covered_starts(fr, K)
+        alg["lattice"] += lat
+        extra["lattice"] += (lat_cov - (fr.rho + 1)) * per_s
+        if fr.prior is not None:
+            alg["gamma"] += 2.0 * fr.N * Mt * Mn * fr.q
+        alg["chain"] += 4.0 * fr.N * Mt * Mn
+        alg["app"] += 2.0 * fr.N * Mt * Mn * (fr.q + 1)
+        alg["wgrad"] += (3.0 if fr.prior is None else 4.0 * fr.q) * fr.N * Mt * Mn
+        alg["adjoint"] += 2.0 * lat
+        extra["adjoint"] += 3.0 * adj_cov * per_s - 2.0 * lat
+    return alg, extra
 
 
-PHASE_KERNEL = {"lattice": "k_lattice", "chain": "k_chain_ring", "app": "k_app_tile",
-                "wgrad": "k_wadj", "adjoint": "k_adjoint"}
+PHASE_KERNEL = {"lattice": "k_lattice", "gamma": "k_gamma", "chain": "k_chain_ring",
+                "app": "k_app_tile", "wgrad": "k_wadj", "adjoint": "k_adjoint"}
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE counters (scaled by a 1 GiB copy's readings), or
-    None when the kernel's sources changed since the counters were taken."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of ``kernel`` on ``workload`` from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE counters (scaled by a plain copy's
+    readings), or None when there are none or the kernel's sources changed
+    since they were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    k = rec["kernels"].get(kernel)
+    k = rec.get("workloads", {}).get(str(workload), {}).get(kernel)
     if not k:
         return None
     h = hashlib.sha256()
@@ -87,6 +128,8 @@ def measured_traffic(kernel):
 
 
 def time_plan(plan, steps, warmup, torch):
+    """Average ms per run over ``steps`` runs after ``warmup`` untimed ones,
+    bracketed by device synchronisation."""
     for _ in range(warmup):
         plan.run()
     torch.cuda.synchronize()
@@ -100,39 +143,175 @@ def time_plan(plan, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps
 
 
-def cpu_baseline(frames, budget_s=15.0):
-    """The FP64 oracle (decode and gradient) on a bounded sample of the
-    batch, one frame per host thread.  Returns (baseline dict, {frame index:
-    oracle result})."""
+def roofline_of(plan, frames, K, steps, workload, precision_peak):
+    """Per-phase launch times (HIP events on each launch's stream, summed
+    per phase, averaged over ``steps`` eager passes of the plan) and the
+    roofline of the phase that takes longest."""
+    acc = {}
+    reps = max(1, steps)
+    for _ in range(reps):
+        for k, v in plan.profile().items():
+            acc[k] = acc.get(k, 0.0) + v
+    phases = {k: v / reps for k, v in acc.items()}
+    nlaunch = plan.launches()
+    alg, extra = phase_flops(frames, K)
+    dom = max((k for k in alg if alg[k] > 0), key=lambda k: phases.get(k, 0.0))
+    nl = max(1, nlaunch.get(dom, 1))
+    ms = phases[dom]
+    achieved = alg[dom] / (ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": precision_peak,
+            "unit": "TFLOP/s", "frac": round(achieved / precision_peak, 4),
+            "traffic": measured_traffic(PHASE_KERNEL[dom], workload),
+            "kernel": PHASE_KERNEL[dom], "launches_per_step": nl,
+            "flops_per_launch": alg[dom] / nl, "launch_ms": round(ms / nl, 5),
+            "recompute_flops_per_launch": extra.get(dom, 0.0) / nl,
+            "measured_in": "HIP events around every launch on its stream, one eager pass "
+                           "of the plan per repeat"}
+    return roof, phases, nlaunch
+
+
+def host_info(nthreads):
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": aff,
+            "threads_used": nthreads}
+
+
+def oracle_native():
+    """The oracle built -O3 -march=native for this host (the committed
+    build is portable -O2); returns (module, flags)."""
     import oracle
-    nthreads = max(1, min(16, os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    first = oracle.decode_frame(frames[0], grad=True)
-    t1 = time.perf_counter() - t0
-    nsample = int(min(len(frames), max(nthreads, round(budget_s / max(t1, 1e-3)))))
-    # whole rounds of one frame per thread (rounded up, so the sample holds
-    # about budget_s of CPU work or more)
-    if nsample >= nthreads:
-        nsample = min(len(frames), -(-nsample // nthreads) * nthreads)
-    idx = list(range(nsample))
-    t0 = time.perf_counter()
+    d = tempfile.mkdtemp(prefix="mapdec_ref_native_")
+    path = os.path.join(d, "libmapdec_ref.so")
+    flags = ["-O3", "-march=native"]
+    try:
+        oracle.load_build(path, flags)
+        return oracle, " ".join(flags)
+    except (subprocess.CalledProcessError, OSError):
+        return oracle, "-O2 (committed portable build; native build failed)"
+
+
+def run_oracle_pool(fn, items, nthreads):
     with ThreadPoolExecutor(max_workers=nthreads) as ex:
-        res = list(ex.map(lambda f: oracle.decode_frame(frames[f], grad=True), idx))
+        return list(ex.map(fn, items))
+
+
+def cpu_baseline(nthreads, sample_N=150):
+    """The FP64 oracle (decode and gradient) on a bounded sample of the
+    headline workload: nthreads frames of sample_N symbols with the
+    workload's code and channel (q=64, n=12, Pi=Pd=0.1, Ps=0, I=2, M=693,
+    mn=8), one frame per host thread."""
+    from paper_1802_08483_amd import workloads as wl
+    orc, flags = oracle_native()
+    full = wl.make_workload(HEADLINE, nframes=1)[0]
+    frames = [wl.random_frame(9000 + k, full.q, full.n, sample_N, full.Pi, full.Pd, full.Ps,
+                              full.I, full.M, full.mn) for k in range(nthreads)]
+    t0 = time.perf_counter()
+    run_oracle_pool(lambda fr: orc.decode_frame(fr, grad=True), frames, nthreads)
     wall = time.perf_counter() - t0
-    syms = sum(frames[f].N for f in idx)
-    refs = dict(zip(idx, res))
-    refs.setdefault(0, first)
-    return ({"value": syms / wall, "unit": "symbols/s", "cores": nthreads, "kind": "oracle",
-             "sample": f"{nsample} of {len(frames)} frames (oracle FP64 decode and gradient, one frame per "
-                       f"thread, {wall:.2f} s wall, ~{t1 * nsample:.1f} s CPU)"}, refs)
+    syms = sum(fr.N for fr in frames)
+    info = host_info(nthreads)
+    return {"value": round(syms / wall, 2), "unit": "symbols/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"{len(frames)} frames of {sample_N} symbols with the workload's code, "
+                      f"channel and drift limits (q=64 n=12 Pi=Pd=0.1 Ps=0 I=2 M={full.M} "
+                      f"mn={full.mn}), FP64 decode and gradient, one frame per thread, "
+                      f"{wall:.2f} s wall; oracle built {flags}",
+            "host": info}
+
+
+def accuracy_vs(batch, f, ref, grad):
+    import numpy as np
+    out = {}
+    app = batch.apps[f].double().cpu().numpy()
+    out["app"] = float(np.abs(app - ref["app"]).max())
+    out["logp"] = abs(float(batch.logp[f]) - ref["logp"]) / abs(ref["logp"])
+    if grad:
+        gp = batch.dparams[f].cpu().numpy()
+        g = float(np.abs(gp - ref["dparams"]).max() / np.abs(ref["dparams"]).max())
+        dpr = batch.dpriors[f].double().cpu().numpy()
+        g = max(g, float(np.abs(dpr - ref["dprior"]).max() / np.abs(ref["dprior"]).max()))
+        out["grad"] = g
+    return out
+
+
+def merge_acc(items):
+    res = {"frames_checked": len(items)}
+    for key, name in (("app", "app_max_abs_err"), ("logp", "logp_max_rel_err"),
+                      ("grad", "grad_max_rel_err")):
+        vals = [a[key] for a in items if key in a]
+        if vals:
+            res[name] = max(vals)
+    return res
+
+
+def golden_accuracy(batch):
+    """The long-frame batch against the oracle's stored values (frames 0 and
+    15: log P, d/d(Pi, Pd, Ps), every 50th row of APP and d/d prior)."""
+    import numpy as np
+    items = []
+    for f in (0, 15):
+        path = os.path.join(ROOT, "tests", "golden", f"long_frame_w5_f{f}.json")
+        if not os.path.exists(path):
+            continue
+        g = json.load(open(path))
+        rows = g["rows"]
+        app = batch.apps[f].double().cpu().numpy()[rows]
+        dpr = batch.dpriors[f].double().cpu().numpy()[rows]
+        ref_dp = np.array([float(v) for v in g["dparams"]])
+        ref_pr = np.array(g["dprior"])
+        gp = batch.dparams[f].cpu().numpy()
+        lp = float(g["logp"])
+        items.append({"app": float(np.abs(app - np.array(g["app"])).max()),
+                      "logp": abs(float(batch.logp[f]) - lp) / abs(lp),
+                      "grad": max(float(np.abs(gp - ref_dp).max() / np.abs(ref_dp).max()),
+                                  float(np.abs(dpr - ref_pr).max() / np.abs(ref_pr).max()))})
+    out = merge_acc(items)
+    out["against"] = "stored oracle values (tests/golden), frames 0 and 15, every 50th row"
+    return out
+
+
+def line_grad(mapdec, workloads, torch, k, K, steps, warmup, graph=True):
+    """FP32 decode + adjoint of workload k as one plan: throughput, phases,
+    roofline."""
+    frames = workloads.make_workload(k)
+    syms = sum(fr.N for fr in frames)
+    b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True, checkpoint_K=K)
+    plan = b.plan(graph=graph)
+    ms = time_plan(plan, steps, warmup, torch)
+    if not (b.status == 0).all():
+        raise RuntimeError(f"workload {k}: a frame reported no path")
+    roof, phases, nl = roofline_of(plan, frames, K, max(1, min(steps, 5)), k, PEAK_FP32_TFLOPS)
+    plan.close()
+    return b, frames, {"workload": workloads.WORKLOAD_NAMES[k],
+                       "value": round(syms / (ms * 1e-3), 1), "unit": "symbols/s",
+                       "ms_per_step": round(ms, 4), "frames": len(frames),
+                       "checkpoint_K": K, "workspace_bytes": b.ws_bytes,
+                       "schedule": "one HIP graph" if graph else "eager plan",
+                       "roofline": roof,
+                       "phases_ms": {p: round(v, 4) for p, v in phases.items()},
+                       "launches": nl,
+                       "chain_step_us": round(phases.get("chain", 0.0) * 1e3 /
+                                              max(1, nl.get("chain", 1)) /
+                                              max(fr.N if not K else min(K, fr.N)
+                                                  for fr in frames), 4)}
 
 
 def uneven_batch(mapdec, workloads, torch, steps):
     """FP32 decode of the uneven batch (4096 frames, q in {2, 8, 16}, n in
-    [4, 10], N in [50, 2000], Pi = Pd log-uniform in [1e-3, 1e-1]): first
-    every launch in order as one HIP graph with the default choices, then
-    an eager plan with tuned choices and launch groups forked over four
-    streams."""
+    [4, 10], N in [50, 2000], Pi = Pd log-uniform in [1e-3, 1e-1]): every
+    launch in order as one HIP graph with the default choices, then an eager
+    plan with tuned choices and launch groups forked over four streams."""
     frames = workloads.make_workload(3)
     syms = sum(fr.N for fr in frames)
     b = mapdec.batch_from_frames(frames, precision=mapdec.FP32)
@@ -165,15 +344,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workloads", default="5,4,2,3,1",
+                    help="comma-separated workloads to run (5 = the headline line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--graph-only", action="store_true",
-                    help="time only the single-stream graph replay (every launch a full-batch "
-                         "launch running alone, as in the roofline measurement)")
-    ap.add_argument("--no-boundary", action="store_true",
-                    help="skip the same step with priors of the frame boundaries")
-    ap.add_argument("--no-uneven", action="store_true",
-                    help="skip the uneven 4096-frame batch (reported beside the main line)")
+    ap.add_argument("--no-oracle", action="store_true",
+                    help="skip every oracle comparison (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES bytes device-to-device a few times (a plain copy "
                          "kernel of known size, to calibrate HBM byte counters)")
@@ -184,7 +359,7 @@ def main():
               "single-GPU run is implemented.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda")
@@ -199,152 +374,125 @@ def main():
 
     if not os.path.exists(libbuild.LIB):
         libbuild.build()
-    frames = workloads.make_workload(WORKLOAD)
-    total_syms = sum(fr.N for fr in frames)
+    wanted = [int(w) for w in args.workloads.split(",") if w]
+    nthreads = max(1, min(HOST_THREADS_CAP, len(os.sched_getaffinity(0))))
+    lines = {}
 
-    b32 = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True)
-    if not args.graph_only:
-        # frame slices on the run's stream and 3 forked ones; timed and closed
-        # before any other plan creates a stream (the device gives a process 4
-        # hardware queues, and streams beyond them share one)
-        plan = b32.plan(graph=False)
-        ms = time_plan(plan, args.steps, args.warmup, torch)
-        if not (b32.status == 0).all():
-            raise RuntimeError("a frame reported no path")
-        plan.close()
-        schedule = "eager, 4 frame slices on 4 streams"
-    pg = b32.plan(graph=True)       # one stream, full-batch launches
-    msg = time_plan(pg, args.steps, args.warmup, torch)
-    graph_line = {"value": round(total_syms / (msg * 1e-3), 1), "ms_per_step": round(msg, 4),
-                  "schedule": "one HIP graph, every launch in order on one stream"}
-    if args.graph_only:
-        ms, schedule = msg, graph_line["schedule"]
-    if not (b32.status == 0).all():
-        raise RuntimeError("a frame reported no path")
+    # headline: the long-frame batch, decode + adjoint, checkpoints every 100
+    head = None
+    if HEADLINE in wanted:
+        fr0 = workloads.make_workload(HEADLINE, nframes=1)[0]
+        K = int(math.ceil(math.sqrt(fr0.N)))
+        b5, frames5, head = line_grad(mapdec, workloads, torch, HEADLINE, K, args.steps,
+                                      args.warmup)
+        if not args.no_oracle:
+            head["accuracy"] = golden_accuracy(b5)
+        # the FP64 plain decode of the same frames (same checkpoints)
+        b64 = mapdec.batch_from_frames(frames5, precision=mapdec.FP64, checkpoint_K=K)
+        p64 = b64.plan(graph=True)
+        ms64 = time_plan(p64, max(2, args.steps // 4), 1, torch)
+        head["fp64_plain"] = {"value": round(sum(f.N for f in frames5) / (ms64 * 1e-3), 1),
+                              "ms_per_step": round(ms64, 4), "step": "decode"}
+        p64.close()
+        del b64, b5
+        torch.cuda.empty_cache()
 
-    bdec = mapdec.batch_from_frames(frames, precision=mapdec.FP32)
-    pdec = bdec.plan(graph=True)
-    msdec = time_plan(pdec, args.steps, 1, torch)
-    decode_only = {"value": round(total_syms / (msdec * 1e-3), 1), "ms_per_step": round(msdec, 4)}
-    pdec.close()
-    del bdec
+    if 4 in wanted:
+        b4, frames4, line = line_grad(mapdec, workloads, torch, 4, 0, args.steps, args.warmup)
+        if not args.no_oracle:
+            import oracle
+            idx = list(range(0, len(frames4), max(1, len(frames4) // nthreads)))[:nthreads]
+            t0 = time.perf_counter()
+            refs = run_oracle_pool(lambda f: oracle.decode_frame(frames4[f], grad=True), idx,
+                                   nthreads)
+            wall = time.perf_counter() - t0
+            line["accuracy"] = merge_acc([accuracy_vs(b4, f, r, True) for f, r in zip(idx, refs)])
+            line["oracle_sample_symbols_per_s"] = round(sum(frames4[f].N for f in idx) / wall, 1)
+        lines["channel_estimation"] = line
+        del b4
+        torch.cuda.empty_cache()
 
-    # Per-phase kernel time of the graph replay's launches (each a full-batch
-    # launch running alone on one stream), from HIP events recorded just
-    # before and after every launch on that stream, averaged over the steps.
-    # The sliced schedule overlaps kernels on purpose, so its launch times
-    # mix several kernels' work and are not a per-kernel roofline measure.
-    acc = {}
-    for _ in range(args.steps):
-        for k, v in pg.profile().items():
-            acc[k] = acc.get(k, 0.0) + v
-    phases = {k: v / args.steps for k, v in acc.items()}
-    nlaunch = pg.launches()
-    pg.close()   # before the uneven batch's plan creates its streams
-    flops = phase_flops(frames)
-    dom = max((k for k in flops), key=lambda k: phases.get(k, 0.0))
-    nl = max(1, nlaunch.get(dom, 1))
-    achieved = flops[dom] / (phases[dom] * 1e-3) / 1e12   # = per-launch flops / launch time
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": measured_traffic(PHASE_KERNEL[dom]), "kernel": PHASE_KERNEL[dom],
-                "launches_per_step": nl, "flops_per_launch": flops[dom] / nl,
-                "launch_ms": round(phases[dom] / nl, 4),
-                "measured_in": "single-stream graph replay (full-batch launches, each alone)"}
-
-    fp64 = None
-    if not args.no_fp64:
-        b64 = mapdec.batch_from_frames(frames, precision=mapdec.FP64)
+    if 2 in wanted:
+        b2, frames2, line = line_grad(mapdec, workloads, torch, 2, 0, args.steps, args.warmup)
+        # the same step as the eager sliced plan (4 frame slices on 4 streams)
+        ps = b2.plan(graph=False)
+        mss = time_plan(ps, args.steps, args.warmup, torch)
+        ps.close()
+        syms2 = sum(fr.N for fr in frames2)
+        line["sliced_eager"] = {"value": round(syms2 / (mss * 1e-3), 1),
+                                "ms_per_step": round(mss, 4),
+                                "schedule": "eager, 4 frame slices on 4 streams"}
+        bdec = mapdec.batch_from_frames(frames2, precision=mapdec.FP32)
+        pdec = bdec.plan(graph=True)
+        msdec = time_plan(pdec, args.steps, 1, torch)
+        line["decode_only"] = {"value": round(syms2 / (msdec * 1e-3), 1),
+                               "ms_per_step": round(msdec, 4)}
+        pdec.close()
+        del bdec
+        b64 = mapdec.batch_from_frames(frames2, precision=mapdec.FP64)
         p64 = b64.plan(graph=True)
         ms64 = time_plan(p64, max(3, args.steps // 2), 1, torch)
-        fp64 = {"value": round(total_syms / (ms64 * 1e-3), 1), "ms_per_step": round(ms64, 4)}
+        line["fp64_plain"] = {"value": round(syms2 / (ms64 * 1e-3), 1),
+                              "ms_per_step": round(ms64, 4), "step": "decode"}
         p64.close()
         del b64
+        if not args.no_oracle:
+            import oracle
+            idx = list(range(0, len(frames2), max(1, len(frames2) // nthreads)))[:nthreads]
+            refs = run_oracle_pool(lambda f: oracle.decode_frame(frames2[f], grad=True), idx,
+                                   nthreads)
+            line["accuracy"] = merge_acc([accuracy_vs(b2, f, r, True) for f, r in zip(idx, refs)])
+        lines["batch256"] = line
+        del b2
+        torch.cuda.empty_cache()
 
-    boundary = None
-    if not args.no_boundary and not args.graph_only:
-        # the same decode+adjoint step with priors of every frame's start and
-        # end drift (Sec. II-C), as one HIP graph
-        bframes = workloads.with_boundary_priors(frames)
-        bb = mapdec.batch_from_frames(bframes, precision=mapdec.FP32, grad=True)
-        pbd = bb.plan(graph=True)
-        msb = time_plan(pbd, max(3, args.steps // 2), 1, torch)
-        if not (bb.status == 0).all():
-            raise RuntimeError("a frame with boundary priors reported no path")
-        boundary = {"value": round(total_syms / (msb * 1e-3), 1), "ms_per_step": round(msb, 4),
-                    "schedule": "one HIP graph, every launch in order on one stream",
-                    "priors": "start drift 0..8, end drift rho-tau-4..rho-tau+4, binomial"}
-        pbd.close()
-        del bb
+    if 3 in wanted:
+        lines["uneven"] = uneven_batch(mapdec, workloads, torch, max(3, args.steps // 4))
 
-    uneven = None
-    if not args.no_uneven:
-        uneven = uneven_batch(mapdec, workloads, torch, max(3, args.steps // 4))
-
-    # the single small frame (q = 8, n = 6, N = 64, FP64 decode): a launch-
-    # and latency-bound case, one HIP graph
-    small = None
-    if not args.graph_only:
+    if 1 in wanted:
         sf = workloads.make_workload(1)
         bs = mapdec.batch_from_frames(sf, precision=mapdec.FP64)
         ps = bs.plan(graph=True)
         mss = time_plan(ps, max(10, args.steps), 3, torch)
         small = {"workload": workloads.WORKLOAD_NAMES[1], "gpu_graph_ms": round(mss, 4)}
         ps.close()
-        del bs
-
-    cpu, refs = (None, {})
-    if not args.no_cpu_baseline:
-        cpu, refs = cpu_baseline(frames)
-        if small is not None:
+        if not args.no_oracle:
             import oracle
             t0 = time.perf_counter()
             for _ in range(5):
                 oracle.decode_frame(sf[0])
             small["oracle_1core_ms"] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
-    else:
-        import oracle
-        refs = {0: oracle.decode_frame(frames[0], grad=True)}
-    app_err, lp_err, g_err = 0.0, 0.0, 0.0
-    for f, ref in refs.items():
-        app = b32.apps[f].double().cpu().numpy()
-        app_err = max(app_err, float(np.abs(app - ref["app"]).max()))
-        lp_err = max(lp_err, abs(float(b32.logp[f]) - ref["logp"]) / abs(ref["logp"]))
-        gp = b32.dparams[f].cpu().numpy()
-        g_err = max(g_err, float(np.abs(gp - ref["dparams"]).max() /
-                                 np.abs(ref["dparams"]).max()))
-        dpr = b32.dpriors[f].double().cpu().numpy()
-        g_err = max(g_err, float(np.abs(dpr - ref["dprior"]).max() /
-                                 np.abs(ref["dprior"]).max()))
+        lines["small_frame"] = small
 
+    cpu = None
+    if head is not None and not args.no_cpu_baseline:
+        cpu = cpu_baseline(nthreads)
+
+    if head is None:
+        # no headline requested (profiling runs): print the lines only
+        print(json.dumps({"lines": lines}))
+        return
     line = {
         "metric": "symbols decoded/sec, FP32 batched+adjoint vs FP64 plain, APP err <=1e-5",
-        "value": round(total_syms / (ms * 1e-3), 1),
+        "value": head["value"],
         "unit": "symbols/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": workloads.WORKLOAD_NAMES[WORKLOAD], "frames": len(frames),
-                   "q": 16, "n": 10, "N": 500, "Pi": 0.05, "Pd": 0.05, "Ps": 0.01, "I": 2,
-                   "M": frames[0].M, "mn": frames[0].mn, "priors": "uniform",
-                   "schedule": schedule,
-                   "step": "decode+adjoint"},
-        "roofline": roofline,
+        "config": {"workload": workloads.WORKLOAD_NAMES[HEADLINE], "frames": 16,
+                   "q": 64, "n": 12, "N": 10000, "Pi": 0.1, "Pd": 0.1, "Ps": 0.0, "I": 2,
+                   "M": 693, "mn": 8, "priors": "uniform", "checkpoint_K": head["checkpoint_K"],
+                   "schedule": head["schedule"], "step": "decode+adjoint"},
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "graph_replay": graph_line,
-        "decode_only": decode_only,
-        "fp64_plain": fp64,
-        "accuracy": {"frames_checked": len(refs), "app_max_abs_err": app_err,
-                     "logp_max_rel_err": lp_err, "grad_max_rel_err": g_err},
-        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
-        # the chain phase is a sequence of N dependent banded steps (forward
-        # and backward chains of every frame run side by side): its latency
-        # per step
-        "chain_step_us": round(phases.get("chain", 0.0) * 1e3 / max(fr.N for fr in frames), 4),
-        "boundary_priors": boundary,
-        "small_frame": small,
-        "uneven": uneven,
+        "accuracy": head.get("accuracy"),
+        "fp64_plain": head["fp64_plain"],
+        "workspace_bytes": head["workspace_bytes"],
+        "phases_ms": head["phases_ms"],
+        "launches": head["launches"],
+        "chain_step_us": head["chain_step_us"],
+        "other_workloads": lines,
     }
     print(json.dumps(line))
 

@@ -22,13 +22,23 @@ SOURCES = [os.path.join(_HERE, "mapdec_ref.c")]
 REF_OK, REF_EINVAL, REF_EDRIFT, REF_ENOPATH, REF_ENOMEM = 0, 1, 2, 3, 4
 
 
-def build() -> str:
-    """Compile the oracle with gcc (portable flags: the library also runs
-    on other hosts)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", LIB_PATH] + SOURCES + ["-lm"]
-    subprocess.run(cmd, check=True)
-    return LIB_PATH
+def build(path: str = LIB_PATH, opt=("-O2",)) -> str:
+    """Compile the oracle with gcc (portable flags by default: the library
+    also runs on other hosts)."""
+    cmd = ["gcc", *opt, "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-o", path] + SOURCES + ["-lm"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return path
+
+
+def load_build(path: str, opt) -> None:
+    """Builds the same sources with other compiler flags (e.g. -O3
+    -march=native for timing on the host that runs them) into ``path`` and
+    makes every later call use that build."""
+    global _lib, LIB_PATH
+    build(path, tuple(opt))
+    _lib = None
+    LIB_PATH = path
 
 
 class _Code(ctypes.Structure):

@@ -1,0 +1,183 @@
+"""Oracle parity at the workloads' full sizes, through the C ABI.
+
+  - the 256-frame batch (q=16, n=10, N=500): every frame's FP32 APP and
+    log P against the FP64 oracle;
+  - the channel-estimation batch (128 frames, q=16, n=10, N=1000, softmax
+    priors, decoded at (0.025, 0.025, 0.015)): every frame's FP32 gradient
+    against the oracle's, and the oracle's own FP64 central differences
+    (step 1e-6) of log P on two frames against both;
+  - the long-frame batch (16 frames, q=64, n=12, N=10000, M=693, mn=8,
+    K = 100 checkpoints, FP32): frames 0 and 15 against the oracle's stored
+    values (tests/golden, written by make_long_frame_goldens.py, which calls
+    only the oracle): log P, d/d(Pi, Pd, Ps) and every 50th row of APP and
+    d/d prior;
+  - tuned plans (other APP tiles, waves and ring shapes) of the uneven batch
+    against the oracle directly on sampled frames.
+
+Bars (the stated targets): APP max abs error <= 1e-5, relative log P error
+<= 1e-6, norm-wise relative gradient error <= 1e-4 per block.  The oracle
+runs on host threads (its calls release the GIL).
+"""
+import json
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1802_08483_amd import mapdec
+from paper_1802_08483_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+T_APP, T_LP, T_G = 1e-5, 1e-6, 1e-4
+NTHREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _pool(fn, items):
+    with ThreadPoolExecutor(max_workers=NTHREADS) as ex:
+        return list(ex.map(fn, items))
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_workload2_every_frame_against_oracle():
+    frames = wl.make_workload(2)
+    b = mapdec.batch_from_frames(frames, precision=mapdec.FP32)
+    b.decode()
+    torch.cuda.synchronize()
+    assert (b.status.cpu().numpy() == 0).all()
+    refs = _pool(lambda fr: oracle.decode_frame(fr), frames)
+    lp = b.logp.cpu().numpy()
+    worst_app = worst_lp = 0.0
+    for f, ref in enumerate(refs):
+        app = b.apps[f].double().cpu().numpy()
+        e_app = float(np.abs(app - ref["app"]).max())
+        e_lp = abs(lp[f] - ref["logp"]) / abs(ref["logp"])
+        assert e_app <= T_APP, f"frame {f}: APP err {e_app}"
+        assert e_lp <= T_LP, f"frame {f}: log P err {e_lp}"
+        worst_app, worst_lp = max(worst_app, e_app), max(worst_lp, e_lp)
+    print(f"workload 2, 256 frames: APP max abs {worst_app:.3e}, log P rel {worst_lp:.3e}")
+
+
+def test_workload4_every_frame_gradient_against_oracle():
+    frames = wl.make_workload(4)
+    b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True)
+    b.run_grad()
+    torch.cuda.synchronize()
+    assert (b.status.cpu().numpy() == 0).all()
+    refs = _pool(lambda fr: oracle.decode_frame(fr, grad=True), frames)
+    worst = 0.0
+    for f, ref in enumerate(refs):
+        gp = b.dparams[f].cpu().numpy()
+        dpr = b.dpriors[f].double().cpu().numpy()
+        e = max(_rel(gp, ref["dparams"]), _rel(dpr, ref["dprior"]))
+        assert e <= T_G, f"frame {f}: gradient err {e} ({gp} vs {ref['dparams']})"
+        app = b.apps[f].double().cpu().numpy()
+        assert float(np.abs(app - ref["app"]).max()) <= T_APP, f"frame {f}: APP"
+        assert abs(float(b.logp[f]) - ref["logp"]) <= T_LP * abs(ref["logp"]), f"frame {f}"
+        worst = max(worst, e)
+    print(f"workload 4, 128 frames: gradient max rel {worst:.3e}")
+
+
+def test_workload4_oracle_central_differences():
+    # FP64 central differences (step 1e-6) of the oracle's log P in
+    # (Pi, Pd, Ps), independent of any gradient code, on two frames
+    frames = wl.make_workload(4)
+    sel = [frames[3], frames[101]]
+    b = mapdec.batch_from_frames(sel, precision=mapdec.FP32, grad=True)
+    b.run_grad()
+    torch.cuda.synchronize()
+    h = 1e-6
+    jobs = []
+    for f, fr in enumerate(sel):
+        for k in range(3):
+            for sgn in (1, -1):
+                p = [fr.Pi, fr.Pd, fr.Ps]
+                p[k] += sgn * h
+                jobs.append((f, k, sgn, p))
+
+    def run(job):
+        f, k, sgn, p = job
+        fr = sel[f]
+        return oracle.decode(fr.codebook, fr.y, fr.N, *p, fr.I, fr.M, fr.mn,
+                             prior=fr.prior)["logp"]
+
+    vals = _pool(run, jobs)
+    refs = _pool(lambda fr: oracle.decode_frame(fr, grad=True), sel)
+    for f in range(len(sel)):
+        fd = np.zeros(3)
+        for (jf, k, sgn, _), v in zip(jobs, vals):
+            if jf == f:
+                fd[k] += sgn * v / (2 * h)
+        gpu = b.dparams[f].cpu().numpy()
+        assert _rel(gpu, fd) <= T_G, f"frame {f}: GPU {gpu} vs FD {fd}"
+        # the oracle's forward-mode gradient against its own differences:
+        # truncation (h^2) and rounding (1e-16 |log P| / h) stay below 1e-6
+        assert _rel(refs[f]["dparams"], fd) <= 1e-6, f"frame {f}: oracle {refs[f]['dparams']}"
+
+
+def _golden(f):
+    path = os.path.join(HERE, "golden", f"long_frame_w5_f{f}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated (tests/golden/make_long_frame_goldens.py)")
+    return json.load(open(path))
+
+
+def test_long_frame_workload_against_stored_oracle_values():
+    frames = wl.make_workload(5)
+    K = 100
+    b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True, checkpoint_K=K)
+    p = b.plan(graph=True)
+    p.run()
+    torch.cuda.synchronize()
+    p.close()
+    assert (b.status.cpu().numpy() == 0).all()
+    for f in (0, 15):
+        g = _golden(f)
+        assert g["N"] == frames[f].N and g["rho"] == frames[f].rho, "inputs changed"
+        rows = g["rows"]
+        app = b.apps[f].double().cpu().numpy()[rows]
+        e_app = float(np.abs(app - np.array(g["app"])).max())
+        assert e_app <= T_APP, f"frame {f}: APP err {e_app}"
+        lp_ref = float(g["logp"])
+        e_lp = abs(float(b.logp[f]) - lp_ref) / abs(lp_ref)
+        assert e_lp <= T_LP, f"frame {f}: log P err {e_lp}"
+        gp = b.dparams[f].cpu().numpy()
+        e_gp = _rel(gp, [float(v) for v in g["dparams"]])
+        assert e_gp <= T_G, f"frame {f}: dparams {gp} vs {g['dparams']}"
+        dpr = b.dpriors[f].double().cpu().numpy()[rows]
+        e_pr = _rel(dpr, g["dprior"])
+        assert e_pr <= T_G, f"frame {f}: dprior err {e_pr}"
+        print(f"long frame {f}: APP {e_app:.3e} logP {e_lp:.3e} dparams {e_gp:.3e} "
+              f"dprior {e_pr:.3e}")
+
+
+@pytest.mark.parametrize("prec", [mapdec.FP32, mapdec.FP64])
+def test_tuned_plans_against_oracle(prec):
+    mapdec.tune_reset()
+    frames = wl.make_workload(3, nframes=160)
+    b = mapdec.batch_from_frames(frames, precision=prec, grad=True)
+    p = b.plan(graph=False, tune=True)
+    p.run()
+    torch.cuda.synchronize()
+    p.close()
+    assert mapdec.tune_entries() > 0
+    assert (b.status.cpu().numpy() == 0).all()
+    # every 8th frame: all q, n and drift ranges of the sample occur
+    idx = list(range(0, len(frames), 8))
+    refs = _pool(lambda f: oracle.decode_frame(frames[f], grad=True), idx)
+    t_app, t_lp, t_g = (T_APP, T_LP, T_G) if prec == mapdec.FP32 else (1e-12, 1e-12, 1e-9)
+    for f, ref in zip(idx, refs):
+        app = b.apps[f].double().cpu().numpy()
+        assert float(np.abs(app - ref["app"]).max()) <= t_app, f"frame {f}: APP"
+        assert abs(float(b.logp[f]) - ref["logp"]) <= t_lp * abs(ref["logp"]), f"frame {f}"
+        assert _rel(b.dparams[f].cpu().numpy(), ref["dparams"]) <= t_g, f"frame {f}: dparams"
+        assert _rel(b.dpriors[f].double().cpu().numpy(), ref["dprior"]) <= t_g, f"frame {f}"
+    mapdec.tune_reset()

@@ -10,12 +10,17 @@ model, closed forms or exact enumeration, never from the oracle itself.
   P6  limits: I >= 2 mn never binds; P(y) nondecreasing in I, M, mn
   P7  hand-derived lattice values for n = 1
   P8  complementing y and every codeword changes nothing
-  P9  gradients: softmax-logit closed form, central differences, and the
-      path-count identity linking d/dPi and d/dPd
-  P10 per-(i, m') lattices equal the lattices memoised per start index
-  P11 priors of the frame boundaries (Sec. II-C): point priors give the
-      known-boundary decode; general priors give the prior-weighted sum of
-      exact known-boundary decodes of the sub-windows y[m0 : tau + mN]
+  P9  gradients: central differences of log P in (Pi, Pd, Ps) and in single
+      prior entries (independent of the gradient code), and the path-count
+      identity linking d/dPi and d/dPd
+  P11 priors of the frame boundaries (below)
+Consistency checks that are not pins (they compare the oracle with a
+restatement of itself; the functions they touch are pinned by P1 and P7):
+the softmax-logit form APP - prior of the prior gradient, and per-(i, m')
+lattices against the lattices memoised per start index.
+      (Sec. II-C): point priors give the known-boundary decode; general
+      priors give the prior-weighted sum of exact known-boundary decodes of
+      the sub-windows y[m0 : tau + mN]
 """
 import itertools
 import math
@@ -236,7 +241,27 @@ def test_p8_complement_symmetry():
 
 # ---- P9 --------------------------------------------------------------------
 
-def test_p9_logit_gradient_closed_form():
+def test_p9_prior_gradient_central_differences():
+    # d log P / d prior[i][D] against central differences of the oracle's
+    # log P (pinned by P1) in that one entry, priors used as given
+    fr = wl.random_frame(12, 8, 6, 25, 0.04, 0.03, 0.02, 2, 14, 4, with_prior=True)
+    r = oracle.decode_frame(fr, grad=True)
+    rng = np.random.default_rng(12)
+    h = 1e-7
+    for _ in range(12):
+        i, D = int(rng.integers(0, fr.N)), int(rng.integers(0, fr.q))
+        vals = []
+        for sgn in (1, -1):
+            pr = fr.prior.copy()
+            pr[i, D] += sgn * h
+            vals.append(oracle.decode(fr.codebook, fr.y, fr.N, fr.Pi, fr.Pd, fr.Ps, fr.I, fr.M,
+                                      fr.mn, prior=pr)["logp"])
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - r["dprior"][i, D]) <= 1e-6 * max(1.0, abs(fd)), (i, D, fd)
+
+
+def test_consistency_logit_gradient_form():
+    # not a pin: the softmax chain rule restated on the oracle's outputs
     fr = wl.random_frame(12, 8, 6, 25, 0.04, 0.03, 0.02, 2, 14, 4, with_prior=True)
     r = oracle.decode_frame(fr, grad=True)
     pi = fr.prior
@@ -274,9 +299,9 @@ def test_p9_count_identity(seed):
     assert 0 <= T1 <= min(fr.tau, fr.rho) + 1e-9
 
 
-# ---- P10 -------------------------------------------------------------------
+# ---- consistency (not a pin) -----------------------------------------------
 
-def test_p10_literal_equals_memoised():
+def test_consistency_literal_equals_memoised():
     fr = wl.random_frame(18, 8, 6, 20, 0.05, 0.05, 0.02, 2, 10, 4, with_prior=True)
     a = oracle.decode_frame(fr, grad=True)
     b = oracle.decode_frame(fr, grad=True, literal=True)
