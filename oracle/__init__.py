@@ -48,6 +48,14 @@ class _Code(ctypes.Structure):
                 ("I", ctypes.c_int), ("M", ctypes.c_int), ("mn", ctypes.c_int)]
 
 
+class _GCode(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int), ("n", ctypes.c_int), ("ncb", ctypes.c_int),
+                ("codebooks", ctypes.POINTER(ctypes.c_uint8)),
+                ("Pi", ctypes.c_double), ("Pd", ctypes.c_double), ("Ps", ctypes.c_double),
+                ("I", ctypes.c_int), ("mt_lo", ctypes.c_int), ("mt_hi", ctypes.c_int),
+                ("mn_lo", ctypes.c_int), ("mn_hi", ctypes.c_int)]
+
+
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
@@ -79,6 +87,16 @@ def lib():
         L.mapdec_ref_lattice.restype = ctypes.c_int
         L.mapdec_ref_check.argtypes = [ctypes.POINTER(_Code)]
         L.mapdec_ref_check.restype = ctypes.c_int
+        L.mapdec_ref_gcheck.argtypes = [ctypes.POINTER(_GCode), ctypes.c_int]
+        L.mapdec_ref_gcheck.restype = ctypes.c_int
+        L.mapdec_ref_run_general.argtypes = [ctypes.POINTER(_GCode), ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_uint8), _dp, _dp, _dp,
+                                             ctypes.c_int, ctypes.POINTER(_Out)]
+        L.mapdec_ref_run_general.restype = ctypes.c_int
+        L.mapdec_ref_glattice.argtypes = [ctypes.POINTER(_GCode), ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_uint8), ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, _dp, _dp]
+        L.mapdec_ref_glattice.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -145,6 +163,80 @@ def decode(codebook, y, N, Pi, Pd, Ps, I, M, mn, prior=None, *, start=None, end=
     res["status"] = st
     res["logp"] = float(res["logp"][0])
     return res
+
+
+def _gcode(codebooks, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi):
+    cb = np.ascontiguousarray(codebooks, dtype=np.uint8)
+    if cb.ndim == 2:
+        cb = cb[None]
+    ncb, q, n = cb.shape
+    c = _GCode(q, n, ncb, _ptr(cb, ctypes.c_uint8), float(Pi), float(Pd), float(Ps), int(I),
+               int(mt_lo), int(mt_hi), int(mn_lo), int(mn_hi))
+    return c, cb
+
+
+def decode_general(codebooks, y, N, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi, prior=None, *,
+                   start=None, end=None, grad=False, trace=False, literal=False, check=True):
+    """Oracle decode under the general scheme: ``codebooks`` is (q, n) (one
+    codebook) or (N, q, n) (C_i per symbol); drift states lie in [mt_lo,
+    mt_hi], drift changes in [mn_lo, mn_hi].  Rows and drift priors have
+    mt_hi - mt_lo + 1 entries, entry m - mt_lo.  Same outputs as decode()."""
+    c, cb = _gcode(codebooks, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi)
+    q = c.q
+    yb = np.ascontiguousarray(y, dtype=np.uint8)
+    pr = None if prior is None else np.ascontiguousarray(prior, dtype=np.float64)
+    Mt = mt_hi - mt_lo + 1
+    bnd = []
+    for v in (start, end):
+        if v is not None:
+            v = np.ascontiguousarray(v, dtype=np.float64)
+            if v.shape != (Mt,):
+                raise ValueError(f"drift prior must have mt_hi - mt_lo + 1 = {Mt} entries")
+        bnd.append(v)
+    res = {"app": np.zeros((N, q)), "logp": np.zeros(1)}
+    if grad:
+        res["dparams"] = np.zeros(3)
+        res["dprior"] = np.zeros((N, q))
+    if trace:
+        res["alpha"] = np.zeros((N + 1, Mt))
+        res["beta"] = np.zeros((N + 1, Mt))
+        res["logA"] = np.zeros(N + 1)
+        res["logB"] = np.zeros(N + 1)
+        res["logZ"] = np.zeros(N)
+    out = _Out(*[_ptr(res.get(k), ctypes.c_double) for k in
+                 ("app", "logp", "dparams", "dprior", "alpha", "beta", "logA", "logB", "logZ")])
+    st = lib().mapdec_ref_run_general(ctypes.byref(c), int(N), int(yb.shape[0]),
+                                      _ptr(yb, ctypes.c_uint8) if yb.size else None,
+                                      _ptr(pr, ctypes.c_double), _ptr(bnd[0], ctypes.c_double),
+                                      _ptr(bnd[1], ctypes.c_double), int(bool(literal)),
+                                      ctypes.byref(out))
+    if st and check:
+        raise OracleError(st)
+    res["status"] = st
+    res["logp"] = float(res["logp"][0])
+    return res
+
+
+def glattice(codebooks, y, N, i, s, D, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi,
+             tangents=False):
+    """R(s, C_i(D), delta) for delta in [mn_lo, mn_hi] under the general
+    scheme (and tangents [w][k])."""
+    c, cb = _gcode(codebooks, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi)
+    yb = np.ascontiguousarray(y, dtype=np.uint8)
+    Mn = mn_hi - mn_lo + 1
+    R = np.zeros(Mn)
+    dR = np.zeros((4, Mn)) if tangents else None
+    st = lib().mapdec_ref_glattice(ctypes.byref(c), int(N), int(yb.shape[0]),
+                                   _ptr(yb, ctypes.c_uint8) if yb.size else None, int(i), int(s),
+                                   int(D), _ptr(R, ctypes.c_double), _ptr(dR, ctypes.c_double))
+    if st:
+        raise OracleError(st)
+    return (R, dR) if tangents else R
+
+
+def check_general(codebooks, N, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi) -> int:
+    c, cb = _gcode(codebooks, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi)
+    return lib().mapdec_ref_gcheck(ctypes.byref(c), int(N))
 
 
 def decode_frame(fr, **kw):

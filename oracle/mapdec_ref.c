@@ -34,8 +34,10 @@
  *     i.e. horizontal moves within one lattice row (the channel stays at the
  *     same time after an insertion, Sec. II-B); kept paths are not
  *     renormalised.
- *   - The corridor holds every lattice node (r, j) to |j - r| <= mn.
- *   - Frame drift limits [-M, M] hold at codeword boundaries only.
+ *   - The corridor holds every lattice node (r, j) to m_n^- <= j - r <=
+ *     m_n^+ ([-mn, mn] for the symmetric limits of a fixed code).
+ *   - Frame drift limits [m_tau^-, m_tau^+] ([-M, M]) hold at codeword
+ *     boundaries only.
  *   - Segments that start before 0 or end after rho have gamma = 0.
  *   - Frame boundaries are known, alpha_0 = delta(m) and beta_N = delta(m -
  *     (rho - tau)), unless drift priors are given: Sec. II-C makes alpha_0
@@ -74,23 +76,54 @@ static weights channel_weights(const ref_code *c)
     return w;
 }
 
-int mapdec_ref_check(const ref_code *c)
+/* The fixed-code, symmetric-limit parameters as an instance of the general
+ * scheme: one codebook, m_tau^-/+ = -/+M, m_n^-/+ = -/+mn. */
+static ref_gcode as_general(const ref_code *c)
 {
-    if (!c || !c->codebook) return REF_EINVAL;
+    ref_gcode g;
+    g.q = c->q; g.n = c->n; g.ncb = 1; g.codebooks = c->codebook;
+    g.Pi = c->Pi; g.Pd = c->Pd; g.Ps = c->Ps; g.I = c->I;
+    g.mt_lo = -c->M; g.mt_hi = c->M; g.mn_lo = -c->mn; g.mn_hi = c->mn;
+    return g;
+}
+
+static int check_codebook(const uint8_t *cb, int q, int n)
+{
+    /* the encoding must be injective (Sec. II-A) */
+    for (int D = 0; D < q; D++) {
+        for (int r = 0; r < n; r++)
+            if (cb[D * n + r] > 1) return REF_EINVAL;
+        for (int E = 0; E < D; E++)
+            if (memcmp(cb + D * n, cb + E * n, (size_t)n) == 0) return REF_EINVAL;
+    }
+    return REF_OK;
+}
+
+int mapdec_ref_gcheck(const ref_gcode *c, int N)
+{
+    if (!c || !c->codebooks || N < 1) return REF_EINVAL;
     if (c->n < 1 || c->n > 30 || c->q < 2 || c->q > (1 << c->n)) return REF_EINVAL;
     if (!(c->Pi >= 0.0) || !(c->Pd >= 0.0) || !(c->Ps >= 0.0) || !(c->Ps <= 1.0))
         return REF_EINVAL;
     if (!(c->Pi + c->Pd < 1.0)) return REF_EINVAL;
-    if (c->I < 0 || c->mn < 0 || c->M < c->mn) return REF_EINVAL;
-    /* the encoding must be injective (Sec. II-A) */
-    for (int D = 0; D < c->q; D++) {
-        for (int r = 0; r < c->n; r++)
-            if (c->codebook[D * c->n + r] > 1) return REF_EINVAL;
-        for (int E = 0; E < D; E++)
-            if (memcmp(c->codebook + D * c->n, c->codebook + E * c->n, (size_t)c->n) == 0)
-                return REF_EINVAL;
+    if (c->I < 0) return REF_EINVAL;
+    /* Sec. III-B: m_n^- <= 0 <= m_n^+, m_tau^- <= m_n^-, m_tau^+ >= m_n^+ */
+    if (c->mn_lo > 0 || c->mn_hi < 0 || c->mt_lo > c->mn_lo || c->mt_hi < c->mn_hi)
+        return REF_EINVAL;
+    if (c->ncb != 1 && c->ncb != N) return REF_EINVAL;
+    for (int i = 0; i < c->ncb; i++) {
+        int st = check_codebook(c->codebooks + (size_t)i * c->q * c->n, c->q, c->n);
+        if (st) return st;
     }
     return REF_OK;
+}
+
+int mapdec_ref_check(const ref_code *c)
+{
+    if (!c || !c->codebook) return REF_EINVAL;
+    if (c->mn < 0 || c->M < c->mn) return REF_EINVAL;
+    ref_gcode g = as_general(c);
+    return mapdec_ref_gcheck(&g, 1);
 }
 
 /* ---- step 2: receiver metric lattice (eqs. 7-10) -------------------------- *
@@ -99,7 +132,8 @@ int mapdec_ref_check(const ref_code *c)
  * segment consumed).  Entering row r from row r-1 is a deletion of x_r
  * (vertical) or a transmission of x_r received as ydot_j (diagonal);
  * moving along a row is an insertion of ydot_j (horizontal), at most I in a
- * row, none along the last row.  Node (r, j) exists iff |j - r| <= mn.
+ * row, none along the last row.  Node (r, j) exists iff j - r lies in the
+ * corridor [m_n^-, m_n^+].
  *
  * G[r][j] collects the paths that enter node (r, j) from row r-1, and
  * F[r][j] adds the up-to-I insertions along row r:
@@ -112,11 +146,16 @@ int mapdec_ref_check(const ref_code *c)
  */
 
 typedef struct {
-    int n, mu, I, mn;
+    int n, mu, I, lo, hi;  /* corridor: lo <= j - r <= hi */
     const uint8_t *ydot;   /* segment, 1-based access ydot[j-1] */
     const uint8_t *x;      /* codeword, 1-based access x[r-1]   */
     weights w;
 } lattice_job;
+
+static int in_corridor(const lattice_job *L, int j, int r)
+{
+    return j - r >= L->lo && j - r <= L->hi;
+}
 
 static double Qdot(const weights *w, uint8_t y, uint8_t x)
 {
@@ -143,7 +182,7 @@ static int run_lattice(const lattice_job *L, double *Fn, double *dFn)
     for (int r = 0; r <= n; r++) {
         /* vertical and diagonal moves into row r */
         for (int j = 0; j <= mu; j++) {
-            if (abs(j - r) > L->mn) continue;          /* outside the corridor */
+            if (!in_corridor(L, j, r)) continue;      /* outside the corridor */
             if (r == 0) {
                 AT(G, 0, j) = (j == 0) ? 1.0 : 0.0;
                 continue;
@@ -167,7 +206,7 @@ static int run_lattice(const lattice_job *L, double *Fn, double *dFn)
         /* horizontal moves along row r: at most I consecutive insertions,
          * none along the last row */
         for (int j = 0; j <= mu; j++) {
-            if (abs(j - r) > L->mn) continue;
+            if (!in_corridor(L, j, r)) continue;
             if (r == n) {
                 AT(F, r, j) = AT(G, r, j);
                 if (dF) for (int t = 0; t < 4; t++) DAT(dF, r, j, t) = DAT(dG, r, j, t);
@@ -176,7 +215,7 @@ static int run_lattice(const lattice_job *L, double *Fn, double *dFn)
             double v = 0.0, ak = 1.0;
             double dv[4] = {0, 0, 0, 0};
             for (int k = 0; k <= L->I && k <= j; k++) {
-                if (abs(j - k - r) <= L->mn) {       /* every node on the run */
+                if (in_corridor(L, j - k, r)) {      /* every node on the run */
                     v += ak * AT(G, r, j - k);
                     if (dF) {
                         for (int t = 0; t < 4; t++) dv[t] += ak * DAT(dG, r, j - k, t);
@@ -202,20 +241,28 @@ static int run_lattice(const lattice_job *L, double *Fn, double *dFn)
     return REF_OK;
 }
 
-/* R(Y[s, s+n+delta) | C(D)) for all delta in [-mn, mn]: one lattice over the
- * longest segment that is needed (Sec. II-C: the last row holds all drift
- * changes).  The segment is extracted from y first (ydot of eq. 6).
- * Invalid segments (s < 0, n + delta < 0, s + n + delta > rho) get 0. */
-static int receiver_metric(const ref_code *c, const weights *w, int rho, const uint8_t *y,
-                           int s, int D, double *R, double *dR)
+/* Codeword C_i(D) of the general scheme. */
+static const uint8_t *codeword(const ref_gcode *c, int i, int D)
 {
-    const int n = c->n, mn = c->mn, Mn = 2 * mn + 1;
+    const int b = c->ncb == 1 ? 0 : i;
+    return c->codebooks + ((size_t)b * c->q + D) * c->n;
+}
+
+/* R(Y[s, s+n+delta) | x) for all delta in [m_n^-, m_n^+]: one lattice over
+ * the longest segment that is needed (Sec. II-C: the last row holds all
+ * drift changes).  The segment is extracted from y first (ydot of eq. 6).
+ * Invalid segments (s < 0, n + delta < 0, s + n + delta > rho) get 0.
+ * R[delta - m_n^-]; dR[t][delta - m_n^-] with M_n columns per tangent. */
+static int receiver_metric(const ref_gcode *c, const weights *w, int rho, const uint8_t *y,
+                           int s, const uint8_t *x, double *R, double *dR)
+{
+    const int n = c->n, lo = c->mn_lo, hi = c->mn_hi, Mn = hi - lo + 1;
     for (int k = 0; k < Mn; k++) {
         R[k] = 0.0;
         if (dR) for (int t = 0; t < 4; t++) dR[t * Mn + k] = 0.0;
     }
     if (s < 0 || s > rho) return REF_OK;
-    int mu = n + mn;
+    int mu = n + hi;
     if (s + mu > rho) mu = rho - s;                 /* longest valid segment */
     if (mu < 0) return REF_OK;
     uint8_t *ydot = malloc((size_t)mu + 1);
@@ -223,18 +270,35 @@ static int receiver_metric(const ref_code *c, const weights *w, int rho, const u
     double *dFn = dR ? malloc(sizeof(double) * 4 * (size_t)(mu + 1)) : NULL;
     if (!ydot || !Fn || (dR && !dFn)) { free(ydot); free(Fn); free(dFn); return REF_ENOMEM; }
     memcpy(ydot, y + s, (size_t)mu);
-    lattice_job L = { n, mu, c->I, mn, ydot, c->codebook + (size_t)D * n, *w };
+    lattice_job L = { n, mu, c->I, lo, hi, ydot, x, *w };
     int st = run_lattice(&L, Fn, dFn);
     if (st == REF_OK) {
-        for (int delta = -mn; delta <= mn; delta++) {
+        for (int delta = lo; delta <= hi; delta++) {
             int len = n + delta;
             if (len < 0 || len > mu) continue;
-            R[delta + mn] = Fn[len];
-            if (dR) for (int t = 0; t < 4; t++) dR[t * Mn + delta + mn] = dFn[(size_t)len * 4 + t];
+            R[delta - lo] = Fn[len];
+            if (dR) for (int t = 0; t < 4; t++) dR[t * Mn + delta - lo] = dFn[(size_t)len * 4 + t];
         }
     }
     free(ydot); free(Fn); free(dFn);
     return st;
+}
+
+static weights channel_weights_g(const ref_gcode *c)
+{
+    ref_code k = {0};
+    k.Pi = c->Pi; k.Pd = c->Pd; k.Ps = c->Ps;
+    return channel_weights(&k);
+}
+
+int mapdec_ref_glattice(const ref_gcode *c, int N, int rho, const uint8_t *y, int i, int s,
+                        int D, double *R, double *dR)
+{
+    int st = mapdec_ref_gcheck(c, N);
+    if (st) return st;
+    if (D < 0 || D >= c->q || rho < 0 || i < 0 || i >= N) return REF_EINVAL;
+    weights w = channel_weights_g(c);
+    return receiver_metric(c, &w, rho, y, s, codeword(c, i, D), R, dR);
 }
 
 int mapdec_ref_lattice(const ref_code *c, int rho, const uint8_t *y, int s, int D,
@@ -242,37 +306,38 @@ int mapdec_ref_lattice(const ref_code *c, int rho, const uint8_t *y, int s, int 
 {
     int st = mapdec_ref_check(c);
     if (st) return st;
-    if (D < 0 || D >= c->q || rho < 0) return REF_EINVAL;
-    weights w = channel_weights(c);
-    return receiver_metric(c, &w, rho, y, s, D, R, dR);
+    ref_gcode g = as_general(c);
+    return mapdec_ref_glattice(&g, 1, rho, y, 0, s, D, R, dR);
 }
 
 /* ---- steps 3-8 ------------------------------------------------------------ */
 
 typedef struct {
-    const ref_code *c;
+    const ref_gcode *c;
     weights w;
     int N, rho, literal, tangents;
     const uint8_t *y;
     const double *prior;
-    /* memo: R for every start s in [0, rho], [s][D][k] (k = delta + mn) */
+    /* memo (one codebook): R for every start s in [0, rho], [s][D][k] with
+     * k = delta - m_n^- */
     double *Rtab, *dRtab;
     double *Rbuf, *dRbuf;   /* literal mode scratch */
     int status;
 } decoder;
 
-/* Receiver metric row R(s, D, .) (and tangents [w][k]) -- memoised or
- * recomputed for this (i, m', D).  Returns NULL for s outside [0, rho]. */
-static const double *R_row(decoder *dc, int s, int D, const double **dRrow)
+/* Receiver metric row R(s, C_i(D), .) (and tangents [w][k]) -- memoised
+ * per s (one codebook) or recomputed for this (i, m', D).  Returns NULL for
+ * s outside [0, rho]. */
+static const double *R_row(decoder *dc, int i, int s, int D, const double **dRrow)
 {
-    const int Mn = 2 * dc->c->mn + 1, q = dc->c->q;
+    const int Mn = dc->c->mn_hi - dc->c->mn_lo + 1, q = dc->c->q;
     if (s < 0 || s > dc->rho) return NULL;
     if (!dc->literal) {
         if (dRrow) *dRrow = dc->dRtab ? dc->dRtab + ((size_t)s * q + D) * 4 * Mn : NULL;
         return dc->Rtab + ((size_t)s * q + D) * Mn;
     }
-    int st = receiver_metric(dc->c, &dc->w, dc->rho, dc->y, s, D, dc->Rbuf,
-                             dc->tangents ? dc->dRbuf : NULL);
+    int st = receiver_metric(dc->c, &dc->w, dc->rho, dc->y, s, codeword(dc->c, i, D),
+                             dc->Rbuf, dc->tangents ? dc->dRbuf : NULL);
     if (st) dc->status = st;
     if (dRrow) *dRrow = dc->tangents ? dc->dRbuf : NULL;
     return dc->Rbuf;
@@ -295,17 +360,29 @@ int mapdec_ref_run_drift(const ref_code *c, int N, int rho, const uint8_t *y,
 {
     int st = mapdec_ref_check(c);
     if (st) return st;
-    if (N < 1 || rho < 0 || (!y && rho > 0)) return REF_EINVAL;
-    const int n = c->n, q = c->q, M = c->M, mn = c->mn;
-    const int Mt = 2 * M + 1, Mn = 2 * mn + 1;
+    ref_gcode g = as_general(c);
+    return mapdec_ref_run_general(&g, N, rho, y, prior, start, end, literal, out);
+}
+
+int mapdec_ref_run_general(const ref_gcode *c, int N, int rho, const uint8_t *y,
+                           const double *prior, const double *start, const double *end,
+                           int literal, ref_out *out)
+{
+    int st = mapdec_ref_gcheck(c, N);
+    if (st) return st;
+    if (rho < 0 || (!y && rho > 0)) return REF_EINVAL;
+    const int n = c->n, q = c->q;
+    const int mlo = c->mt_lo, mhi = c->mt_hi, dlo = c->mn_lo, dhi = c->mn_hi;
+    const int Mt = mhi - mlo + 1, Mn = dhi - dlo + 1;
     const int tau = n * N;
-    if (abs(rho - tau) > M) return REF_EDRIFT;      /* end drift out of range */
+    if (rho - tau < mlo || rho - tau > mhi) return REF_EDRIFT;   /* end drift out of range */
     ref_out none = {0};
     if (!out) out = &none;
     const int tangents = out->dparams != NULL;
+    if (c->ncb > 1) literal = 1;   /* R depends on i as well as on s */
 
     decoder dc = {0};
-    dc.c = c; dc.w = channel_weights(c); dc.N = N; dc.rho = rho; dc.literal = literal;
+    dc.c = c; dc.w = channel_weights_g(c); dc.N = N; dc.rho = rho; dc.literal = literal;
     dc.tangents = tangents; dc.y = y; dc.prior = prior;
 
     double *alpha = calloc((size_t)(N + 1) * Mt, sizeof(double));
@@ -317,7 +394,8 @@ int mapdec_ref_run_drift(const ref_code *c, int N, int rho, const uint8_t *y,
     double *acc = calloc((size_t)Mt, sizeof(double));
     if (!alpha || !beta || !logA || !logB || !S || !U || !acc) { st = REF_ENOMEM; goto done; }
 
-    /* step 2, memoised: one lattice per start s (R depends on s, D only) */
+    /* step 2, memoised: one lattice per start s (with one codebook R
+     * depends on s and D only) */
     if (!literal) {
         dc.Rtab = malloc(sizeof(double) * (size_t)(rho + 1) * q * Mn);
         if (!dc.Rtab) { st = REF_ENOMEM; goto done; }
@@ -327,7 +405,7 @@ int mapdec_ref_run_drift(const ref_code *c, int N, int rho, const uint8_t *y,
         }
         for (int s = 0; s <= rho; s++)
             for (int D = 0; D < q; D++) {
-                st = receiver_metric(c, &dc.w, rho, y, s, D,
+                st = receiver_metric(c, &dc.w, rho, y, s, codeword(c, 0, D),
                                      dc.Rtab + ((size_t)s * q + D) * Mn,
                                      tangents ? dc.dRtab + ((size_t)s * q + D) * 4 * Mn : NULL);
                 if (st) goto done;
@@ -338,39 +416,39 @@ int mapdec_ref_run_drift(const ref_code *c, int N, int rho, const uint8_t *y,
         if (!dc.Rbuf || !dc.dRbuf) { st = REF_ENOMEM; goto done; }
     }
 
-#define ALPHA(i, m) alpha[(size_t)(i) * Mt + (m) + M]
-#define BETA(i, m) beta[(size_t)(i) * Mt + (m) + M]
+#define ALPHA(i, m) alpha[(size_t)(i) * Mt + (m) - mlo]
+#define BETA(i, m) beta[(size_t)(i) * Mt + (m) - mlo]
 
     /* step 4: alpha_0 = delta(m) or the start prior; alpha'_{i+1}(m) =
-     * sum_{m',D} alpha_i(m')
-     * gamma_i(m', m, D); alpha_{i+1} = alpha' / sum alpha'.
-     * gamma_i(m', m, D) = prior_i(D) R(Y[ni+m', n(i+1)+m) | C(D)) (eq. 6),
-     * defined for |m - m'| <= mn and m, m' in [-M, M]. */
+     * sum_{m',D} alpha_i(m') gamma_i(m', m, D); alpha_{i+1} = alpha' / sum
+     * alpha'.  gamma_i(m', m, D) = prior_i(D) R(Y[ni+m', n(i+1)+m) |
+     * C_i(D)) (eq. 6), defined for m - m' in [m_n^-, m_n^+] and m, m' in
+     * [m_tau^-, m_tau^+]. */
     if (start) {
-        for (int m = -M; m <= M; m++) ALPHA(0, m) = start[m + M];
+        for (int m = mlo; m <= mhi; m++) ALPHA(0, m) = start[m - mlo];
     } else {
         ALPHA(0, 0) = 1.0;
     }
     logA[0] = 0.0;
     for (int i = 0; i < N; i++) {
-        for (int m = -M; m <= M; m++) acc[m + M] = 0.0;
-        for (int mp = -M; mp <= M; mp++) {
+        for (int m = mlo; m <= mhi; m++) acc[m - mlo] = 0.0;
+        for (int mp = mlo; mp <= mhi; mp++) {
             for (int D = 0; D < q; D++) {
-                const double *R = R_row(&dc, n * i + mp, D, NULL);
+                const double *R = R_row(&dc, i, n * i + mp, D, NULL);
                 if (dc.status) { st = dc.status; goto done; }
                 if (!R) continue;
-                for (int delta = -mn; delta <= mn; delta++) {
+                for (int delta = dlo; delta <= dhi; delta++) {
                     int m = mp + delta;
-                    if (m < -M || m > M) continue;
-                    double gamma = prior_of(&dc, i, D) * R[delta + mn];
-                    acc[m + M] += ALPHA(i, mp) * gamma;
+                    if (m < mlo || m > mhi) continue;
+                    double gamma = prior_of(&dc, i, D) * R[delta - dlo];
+                    acc[m - mlo] += ALPHA(i, mp) * gamma;
                 }
             }
         }
         double csum = 0.0;
-        for (int m = -M; m <= M; m++) csum += acc[m + M];
+        for (int m = mlo; m <= mhi; m++) csum += acc[m - mlo];
         if (!(csum > 0.0)) { st = REF_ENOPATH; goto done; }
-        for (int m = -M; m <= M; m++) ALPHA(i + 1, m) = acc[m + M] / csum;
+        for (int m = mlo; m <= mhi; m++) ALPHA(i + 1, m) = acc[m - mlo] / csum;
         logA[i + 1] = logA[i] + log(csum);
     }
 
@@ -378,31 +456,31 @@ int mapdec_ref_run_drift(const ref_code *c, int N, int rho, const uint8_t *y,
      * = sum_{m,D} gamma_i(m', m, D) beta_{i+1}(m); beta_i = beta' / sum
      * beta'. */
     if (end) {
-        for (int m = -M; m <= M; m++) BETA(N, m) = end[m + M];
+        for (int m = mlo; m <= mhi; m++) BETA(N, m) = end[m - mlo];
     } else {
         BETA(N, rho - tau) = 1.0;
     }
     logB[N] = 0.0;
     for (int i = N - 1; i >= 0; i--) {
-        for (int mp = -M; mp <= M; mp++) {
+        for (int mp = mlo; mp <= mhi; mp++) {
             double v = 0.0;
             for (int D = 0; D < q; D++) {
-                const double *R = R_row(&dc, n * i + mp, D, NULL);
+                const double *R = R_row(&dc, i, n * i + mp, D, NULL);
                 if (dc.status) { st = dc.status; goto done; }
                 if (!R) continue;
-                for (int delta = -mn; delta <= mn; delta++) {
+                for (int delta = dlo; delta <= dhi; delta++) {
                     int m = mp + delta;
-                    if (m < -M || m > M) continue;
-                    double gamma = prior_of(&dc, i, D) * R[delta + mn];
+                    if (m < mlo || m > mhi) continue;
+                    double gamma = prior_of(&dc, i, D) * R[delta - dlo];
                     v += gamma * BETA(i + 1, m);
                 }
             }
-            acc[mp + M] = v;
+            acc[mp - mlo] = v;
         }
         double esum = 0.0;
-        for (int m = -M; m <= M; m++) esum += acc[m + M];
+        for (int m = mlo; m <= mhi; m++) esum += acc[m - mlo];
         if (!(esum > 0.0)) { st = REF_ENOPATH; goto done; }
-        for (int m = -M; m <= M; m++) BETA(i, m) = acc[m + M] / esum;
+        for (int m = mlo; m <= mhi; m++) BETA(i, m) = acc[m - mlo] / esum;
         logB[i] = logB[i + 1] + log(esum);
     }
 
@@ -411,7 +489,7 @@ int mapdec_ref_run_drift(const ref_code *c, int N, int rho, const uint8_t *y,
     {
         double aN = 0.0;
         if (end) {
-            for (int m = -M; m <= M; m++) aN += ALPHA(N, m) * end[m + M];
+            for (int m = mlo; m <= mhi; m++) aN += ALPHA(N, m) * end[m - mlo];
         } else {
             aN = ALPHA(N, rho - tau);
         }
@@ -428,22 +506,22 @@ int mapdec_ref_run_drift(const ref_code *c, int N, int rho, const uint8_t *y,
         for (int i = 0; i < N; i++) {
             long double gi[4] = {0, 0, 0, 0};
             for (int D = 0; D < q; D++) { S[D] = 0.0; U[D] = 0.0; }
-            for (int mp = -M; mp <= M; mp++) {
+            for (int mp = mlo; mp <= mhi; mp++) {
                 for (int D = 0; D < q; D++) {
                     const double *dR = NULL;
-                    const double *R = R_row(&dc, n * i + mp, D, tangents ? &dR : NULL);
+                    const double *R = R_row(&dc, i, n * i + mp, D, tangents ? &dR : NULL);
                     if (dc.status) { st = dc.status; goto done; }
                     if (!R) continue;
-                    for (int delta = -mn; delta <= mn; delta++) {
+                    for (int delta = dlo; delta <= dhi; delta++) {
                         int m = mp + delta;
-                        if (m < -M || m > M) continue;
+                        if (m < mlo || m > mhi) continue;
                         long double ab = (long double)ALPHA(i, mp) * BETA(i + 1, m);
-                        double gamma = prior_of(&dc, i, D) * R[delta + mn];
+                        double gamma = prior_of(&dc, i, D) * R[delta - dlo];
                         S[D] += ab * gamma;
-                        U[D] += ab * R[delta + mn];
+                        U[D] += ab * R[delta - dlo];
                         if (tangents)
                             for (int t = 0; t < 4; t++)
-                                gi[t] += ab * prior_of(&dc, i, D) * dR[t * Mn + delta + mn];
+                                gi[t] += ab * prior_of(&dc, i, D) * dR[t * Mn + delta - dlo];
                     }
                 }
             }

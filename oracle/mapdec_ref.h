@@ -38,7 +38,28 @@ typedef struct {
     int mn;                   /* per-codeword drift change limit [-mn, mn]   */
 } ref_code;
 
-/* Requested outputs; any pointer may be NULL. */
+/*
+ * The general scheme (Sec. II-A: a constituent encoding C_i per symbol
+ * position; Sec. III-B: arbitrary state-space limits m_n^- <= 0 <= m_n^+,
+ * m_tau^- <= m_n^-, m_tau^+ >= m_n^+).  Drift states m at codeword
+ * boundaries lie in [mt_lo, mt_hi] (M_tau = mt_hi - mt_lo + 1 of them);
+ * every lattice node (r, j) keeps j - r in [mn_lo, mn_hi] (the corridor,
+ * M_n = mn_hi - mn_lo + 1 drift changes).  ncb = 1: one codebook for every
+ * position; ncb = N: codebook i serves symbol i.  Codebook i occupies bytes
+ * [i q n, (i+1) q n), row D of it is C_i(D).
+ */
+typedef struct {
+    int q, n;
+    int ncb;                   /* 1 or N                                      */
+    const uint8_t *codebooks;  /* ncb*q*n bytes of 0/1                        */
+    double Pi, Pd, Ps;
+    int I;
+    int mt_lo, mt_hi;          /* frame drift limits m_tau^-, m_tau^+         */
+    int mn_lo, mn_hi;          /* per-codeword drift change limits m_n^-, m_n^+ */
+} ref_gcode;
+
+/* Requested outputs; any pointer may be NULL.  With a ref_gcode the rows
+ * alpha/beta (and the drift priors) have M_tau entries, [i][m - mt_lo]. */
 typedef struct {
     double *app;      /* N*q   APP L_i(D), row-major [i][D]                  */
     double *logp;     /* 1     natural log of P(y)                           */
@@ -75,6 +96,29 @@ int mapdec_ref_run(const ref_code *c, int N, int rho, const uint8_t *y,
 int mapdec_ref_run_drift(const ref_code *c, int N, int rho, const uint8_t *y,
                          const double *prior, const double *start, const double *end,
                          int literal, ref_out *out);
+
+/* Check general-scheme parameters for frames of N symbols; REF_OK or
+ * REF_EINVAL (ncb must be 1 or N, every C_i injective, limits ordered as
+ * above). */
+int mapdec_ref_gcheck(const ref_gcode *c, int N);
+
+/*
+ * Decode one frame under the general scheme.  As mapdec_ref_run_drift,
+ * with start / end of M_tau entries ([m - mt_lo]) or NULL for the known
+ * boundary; REF_EDRIFT unless mt_lo <= rho - tau <= mt_hi.  With ncb = N
+ * every lattice is recomputed per (i, m', D) (literal is then implied).
+ */
+int mapdec_ref_run_general(const ref_gcode *c, int N, int rho, const uint8_t *y,
+                           const double *prior, const double *start, const double *end,
+                           int literal, ref_out *out);
+
+/*
+ * Receiver metric R(y[s .. s+n+delta) | C_i(D)) for delta in [mn_lo,
+ * mn_hi] (R[delta - mn_lo]) under the general scheme; dR as below with
+ * M_n columns per tangent.
+ */
+int mapdec_ref_glattice(const ref_gcode *c, int N, int rho, const uint8_t *y, int i, int s,
+                        int D, double *R, double *dR);
 
 /*
  * Receiver metric of one lattice: R[k] = R(y[s .. s+n+k) | C(D)) for

@@ -8,9 +8,11 @@ event, and applies the decoder's truncation as constraints on the walk:
 
   (i)   at most I consecutive insertions at one channel time step;
   (ii)  inside codeword c (started at received index s = c n + m'), every
-        visited node keeps |(p - t) - m'| <= mn, where t counts input bits
-        and p received bits;
-  (iii) at every codeword boundary the drift p - t lies in [-M, M];
+        visited node keeps (p - t) - m' in [mn_lo, mn_hi] ([-mn, mn] for a
+        fixed code's symmetric limits), where t counts input bits and p
+        received bits;
+  (iii) at every codeword boundary the drift p - t lies in [mt_lo, mt_hi]
+        ([-M, M]);
   plus start drift 0, all of y consumed, and no insertion after the last
   input bit.
 
@@ -46,6 +48,13 @@ def _add(x, y):
 def channel_sum(X: Sequence[int], y: Sequence[int], n: int, Pi, Pd, Ps, I: int, M: int, mn: int):
     """Sum of the weights of all admissible event sequences X -> y, and its
     derivatives with respect to (Pi, Pd, Ps).  Returns a 4-tuple."""
+    return channel_sum_limits(X, y, n, Pi, Pd, Ps, I, -M, M, -mn, mn)
+
+
+def channel_sum_limits(X: Sequence[int], y: Sequence[int], n: int, Pi, Pd, Ps, I: int,
+                       mt_lo: int, mt_hi: int, mn_lo: int, mn_hi: int):
+    """channel_sum with drift limits [mt_lo, mt_hi] at codeword boundaries
+    and a corridor [mn_lo, mn_hi] inside codewords."""
     Pi, Pd, Ps = Fraction(Pi), Fraction(Pd), Fraction(Ps)
     Pt = 1 - Pi - Pd
     a, d, t1, t0 = Pi / 2, Pd, Pt * (1 - Ps), Pt * Ps
@@ -65,16 +74,16 @@ def channel_sum(X: Sequence[int], y: Sequence[int], n: int, Pi, Pd, Ps, I: int, 
             return (Fraction(1), F0, F0, F0) if p == rho else zero
         total = zero
         # insertion: emit y[p], stay at time t
-        if k < I and p < rho and abs((p + 1 - t) - mp) <= mn:
+        if k < I and p < rho and mn_lo <= (p + 1 - t) - mp <= mn_hi:
             total = _add(total, _edge(a, da, go(t, p + 1, k + 1, mp)))
 
         def advance(np_):
             nt = t + 1
-            if abs((np_ - nt) - mp) > mn:
+            if not mn_lo <= (np_ - nt) - mp <= mn_hi:
                 return None
             if nt % n == 0:
                 drift = np_ - nt
-                if abs(drift) > M:
+                if not mt_lo <= drift <= mt_hi:
                     return None
                 return go(nt, np_, 0, drift)
             return go(nt, np_, 0, mp)
@@ -100,8 +109,16 @@ def brute(codebook, y, N: int, Pi, Pd, Ps, I: int, M: int, mn: int,
 
     ``codebook``: q rows of n bits; ``prior``: N x q (Fractions or ints/
     floats converted exactly), default 1/q."""
-    q = len(codebook)
-    n = len(codebook[0])
+    return brute_general([codebook] * N, y, N, Pi, Pd, Ps, I, -M, M, -mn, mn, prior)
+
+
+def brute_general(codebooks, y, N: int, Pi, Pd, Ps, I: int, mt_lo: int, mt_hi: int,
+                  mn_lo: int, mn_hi: int, prior: Optional[Sequence[Sequence]] = None):
+    """brute() under the general scheme: ``codebooks[i]`` (q rows of n bits)
+    encodes symbol i (Sec. II-A, C_i), drift limits [mt_lo, mt_hi] and
+    corridor [mn_lo, mn_hi]."""
+    q = len(codebooks[0])
+    n = len(codebooks[0][0])
     if prior is None:
         prior = [[Fraction(1, q)] * q for _ in range(N)]
     else:
@@ -111,8 +128,9 @@ def brute(codebook, y, N: int, Pi, Pd, Ps, I: int, M: int, mn: int,
     num = [[F0] * q for _ in range(N)]          # sum over messages with D_i = D
     dpr = [[F0] * q for _ in range(N)]          # d P / d prior_i(D)
     for msg in itertools.product(range(q), repeat=N):
-        X = [b for D in msg for b in codebook[D]]
-        V, dPi, dPd, dPs = channel_sum(X, y, n, Pi, Pd, Ps, I, M, mn)
+        X = [b for i, D in enumerate(msg) for b in codebooks[i][D]]
+        V, dPi, dPd, dPs = channel_sum_limits(X, y, n, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo,
+                                              mn_hi)
         if V == 0 and dPi == 0 and dPd == 0 and dPs == 0:
             continue
         pw = Fraction(1)
