@@ -208,7 +208,8 @@ int mapdec_grad(const mapdec_frame *frames, int nframes, double *logp, double *d
  * that touched one of its frames, and the run's stream waits for all of
  * them at the end, so a run is still ordered on the caller's stream as a
  * whole.  Gradient plans of at least 32 frames that need one launch per
- * phase run eagerly as 4 contiguous slices of frames instead, slice k on
+ * phase run eagerly as min(4, nframes / 16) contiguous slices of frames
+ * instead (2 slices for 32-47 frames, 3 for 48-63, 4 from 64), slice k on
  * stream k, every launch other than the chains also waiting for the same
  * launch of the slice before: the compute-bound phases then advance slice
  * by slice while each slice's chains (a latency-bound recursion) run
