@@ -269,6 +269,27 @@ int mapdec_plan_launches(const mapdec_plan *plan, int phase);
  * "app", ...), or NULL past the last phase. */
 const char *mapdec_phase_name(int phase);
 
+/*
+ * mapdec_decode_noalloc -- mapdec_decode for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same frames, outputs, status codes and
+ * asynchronous semantics as mapdec_decode, with no workspace argument: the
+ * workspace is a fixed device array of mapdec_noalloc_limit() bytes
+ * (64 MiB) inside the library, one per device, held until the process
+ * ends.  Returns MAPDEC_ESIZE when mapdec_workspace_size(frames, nframes,
+ * precision, 0, 0) exceeds that limit.  No hipMalloc / hipFree or other
+ * device allocation, no stream or event creation; the frame descriptors are
+ * copied from host memory into the array's head on stream.  Every call on a
+ * device shares that device's array, which keeps the last call's contents:
+ * calls that overlap on one device (other streams, other threads, before
+ * the previous call's work has finished on a different stream) race and
+ * give undefined results.  Calls in order on one stream are safe.
+ */
+int mapdec_decode_noalloc(const mapdec_frame *frames, int nframes, double *logp,
+                          int32_t *status, int precision, void *stream);
+/* Bytes of the device array behind mapdec_decode_noalloc. */
+size_t mapdec_noalloc_limit(void);
+
 /* Status of the calling thread's last failed mapdec_create / plan_create. */
 int mapdec_last_error(void);
 /* Static string naming a status code. */

@@ -87,6 +87,11 @@ constexpr size_t adjoint_lds(int nmax, int mn, size_t tsize) {
 inline bool adjoint_needs_da(double Pi, double Pd) { return !(Pi > 0.0) || 4.0 * Pi < Pd; }
 hipError_t launch_dparams(const FrameDesc *fd, int nframes, hipStream_t st);
 
+// The fixed device array of the allocation-free decode (scratch.hip): its
+// size, and its address on the current device (taken once per device).
+size_t scratch_bytes();
+hipError_t scratch_address(void **out);
+
 // Block sizes the host uses to build work tables.
 constexpr int kPackWords = 8;      // packed words per pack workgroup (256 threads)
 constexpr int kLatticeLanes = 64;  // start indices per lattice workgroup

@@ -1157,13 +1157,13 @@ int tune_plan(mapdec_plan *t, hipStream_t s) {
     const size_t fd_bytes = align_up(sizeof(FrameDesc) * L.nframes);
     const size_t tab_bytes = std::max(kTuneAppItems * sizeof(Work), kTuneChains * sizeof(int)) +
                              sizeof(Work) * 4096;
-    unsigned char *scratch = nullptr;
+    unsigned char *tbuf = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    e = hipMalloc(&scratch, fd_bytes + tab_bytes);
+    e = hipMalloc(&tbuf, fd_bytes + tab_bytes);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    FrameDesc *fd_tmp = reinterpret_cast<FrameDesc *>(scratch);
-    unsigned char *tab_tmp = scratch + fd_bytes;
+    FrameDesc *fd_tmp = reinterpret_cast<FrameDesc *>(tbuf);
+    unsigned char *tab_tmp = tbuf + fd_bytes;
     std::vector<FrameDesc> fd_host(L.nframes);
     if (e == hipSuccess)
         e = hipMemcpy(fd_host.data(), t->at<FrameDesc>(P.off_fd), sizeof(FrameDesc) * L.nframes,
@@ -1269,7 +1269,7 @@ int tune_plan(mapdec_plan *t, hipStream_t s) {
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
-    if (scratch) hipFree(scratch);
+    if (tbuf) hipFree(tbuf);
     return e == hipSuccess ? MAPDEC_OK : MAPDEC_EDEVICE;
 }
 
@@ -1409,6 +1409,26 @@ int mapdec_grad(const mapdec_frame *frames, int nframes, double *logp, double *d
     mapdec_plan_destroy(p);
     return st;
 }
+
+int mapdec_decode_noalloc(const mapdec_frame *frames, int nframes, double *logp,
+                          int32_t *status, int precision, void *stream) {
+    Layout L;
+    const int v = build_layout(frames, nframes, precision, MAPDEC_FLAG_SERIAL, 0, L);
+    if (v != MAPDEC_OK) return v;
+    if (L.total > scratch_bytes()) return MAPDEC_ESIZE;
+    void *ws = nullptr;
+    if (scratch_address(&ws) != hipSuccess) return MAPDEC_EDEVICE;
+    // the plan's only device memory is the scratch array; a serial plan
+    // creates no streams or events either
+    mapdec_plan *p = mapdec_plan_create(frames, nframes, logp, nullptr, status, ws,
+                                        scratch_bytes(), precision, MAPDEC_FLAG_SERIAL, 0, stream);
+    if (!p) return g_last_error;
+    int st = mapdec_plan_run(p, stream);
+    mapdec_plan_destroy(p);
+    return st;
+}
+
+size_t mapdec_noalloc_limit(void) { return scratch_bytes(); }
 
 int mapdec_last_error(void) { return g_last_error; }
 

@@ -27,7 +27,8 @@ EXPORTS = ["mapdec_create", "mapdec_destroy", "mapdec_workspace_size", "mapdec_d
            "mapdec_plan_profile", "mapdec_plan_launches", "mapdec_phase_name",
            "mapdec_tune_entries",
            "mapdec_tune_reset", "mapdec_last_error",
-           "mapdec_strerror", "mapdec_version"]
+           "mapdec_strerror", "mapdec_version", "mapdec_decode_noalloc",
+           "mapdec_noalloc_limit"]
 
 
 class MapdecError(RuntimeError):
@@ -88,6 +89,10 @@ def lib() -> ctypes.CDLL:
         L.mapdec_tune_entries.restype = i32
         L.mapdec_tune_reset.argtypes = []
         L.mapdec_tune_reset.restype = None
+        L.mapdec_decode_noalloc.argtypes = [fp, i32, vp, vp, i32, vp]
+        L.mapdec_decode_noalloc.restype = i32
+        L.mapdec_noalloc_limit.argtypes = []
+        L.mapdec_noalloc_limit.restype = sz
         _lib = L
     return _lib
 
@@ -95,6 +100,11 @@ def lib() -> ctypes.CDLL:
 def tune_entries() -> int:
     """Buckets in the process's table of tuned launch choices."""
     return lib().mapdec_tune_entries()
+
+
+def noalloc_limit() -> int:
+    """Bytes of the device array behind mapdec_decode_noalloc."""
+    return int(lib().mapdec_noalloc_limit())
 
 
 def tune_reset() -> None:
@@ -160,7 +170,7 @@ class Batch:
     """
 
     def __init__(self, frames: Sequence, precision: int = FP32, grad: bool = False,
-                 device=None, checkpoint_K: int = 0):
+                 device=None, checkpoint_K: int = 0, workspace: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("libmapdec needs a GPU; no device is visible")
         self.device = torch.device(device or "cuda")
@@ -209,7 +219,9 @@ class Batch:
                                                     self.checkpoint_K)
         if self.ws_bytes == 0:
             raise MapdecError(EINVAL, "mapdec_workspace_size")
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        # workspace=False: the batch is decoded only by decode_noalloc()
+        self.ws = (torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+                   if workspace else None)
 
     def decode(self, stream=None):
         if self.checkpoint_K:
@@ -223,6 +235,17 @@ class Batch:
                                  _stream_handle(stream))
         if st:
             raise MapdecError(st, "mapdec_decode")
+        return self
+
+    def decode_noalloc(self, stream=None):
+        """mapdec_decode_noalloc: the decode in the library's fixed device
+        array instead of the batch's workspace (at most noalloc_limit()
+        bytes)."""
+        st = lib().mapdec_decode_noalloc(self.frames, self.nframes, _ptr(self.logp),
+                                         _ptr(self.status), self.precision,
+                                         _stream_handle(stream))
+        if st:
+            raise MapdecError(st, "mapdec_decode_noalloc")
         return self
 
     def run_grad(self, stream=None):
@@ -304,7 +327,7 @@ def code_for(frame, cache: Optional[dict] = None) -> Code:
 
 
 def batch_from_frames(frames: List, precision: int = FP32, grad: bool = False,
-                      device=None, checkpoint_K: int = 0) -> Batch:
+                      device=None, checkpoint_K: int = 0, workspace: bool = True) -> Batch:
     """Uploads workloads.Frame objects and builds a :class:`Batch`."""
     dev = torch.device(device or "cuda")
     dtype = torch.float64 if precision == FP64 else torch.float32
@@ -318,4 +341,5 @@ def batch_from_frames(frames: List, precision: int = FP32, grad: bool = False,
                else torch.as_tensor(getattr(fr, k), dtype=torch.float64).contiguous().to(dev)
                for k in ("start_drift", "end_drift")]
         items.append((code, y, fr.N, prior, bnd[0], bnd[1]))
-    return Batch(items, precision=precision, grad=grad, device=dev, checkpoint_K=checkpoint_K)
+    return Batch(items, precision=precision, grad=grad, device=dev, checkpoint_K=checkpoint_K,
+                 workspace=workspace)

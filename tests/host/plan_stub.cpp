@@ -334,4 +334,11 @@ hipError_t launch_dparams(const FrameDesc *fd, int nf, hipStream_t st) {
     launch(st, {}, true);
     return hipSuccess;
 }
+// the allocation-free decode's array: host memory here (no kernel runs)
+size_t scratch_bytes() { return (size_t)64 << 20; }
+hipError_t scratch_address(void **out) {
+    static std::vector<unsigned char> buf(scratch_bytes());
+    *out = buf.data();
+    return hipSuccess;
+}
 }  // namespace mapdec

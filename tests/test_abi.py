@@ -97,6 +97,22 @@ def test_workspace_size_and_validation(L):
     assert L.mapdec_decode(noy, 1, dummy, dummy, dummy, ws32, mapdec.FP32, None) == mapdec.EINVAL
 
 
+def test_noalloc_limit_and_size_check(L):
+    # the allocation-free decode validates like mapdec_decode and rejects a
+    # layout beyond its fixed array before any device call
+    assert L.mapdec_noalloc_limit() == 64 << 20
+    c = _code(q=16, n=10, M=98, mn=6, cb=np.array(
+        [[(w >> (9 - r)) & 1 for r in range(10)] for w in range(16)], np.uint8))
+    big = _frames([(c, 500, 5000)] * 32)
+    need = L.mapdec_workspace_size(big, 32, mapdec.FP32, 0, 0)
+    assert need > L.mapdec_noalloc_limit()
+    dummy = ctypes.c_void_p(0x1000)
+    assert L.mapdec_decode_noalloc(big, 32, dummy, dummy, mapdec.FP32, None) == mapdec.ESIZE
+    bad = _frames([(c, 500, 5000 + 99)])
+    assert L.mapdec_decode_noalloc(bad, 1, dummy, dummy, mapdec.FP32, None) == mapdec.EDRIFT
+    assert L.mapdec_decode_noalloc(big, 0, dummy, dummy, mapdec.FP32, None) == mapdec.EINVAL
+
+
 def test_checkpointed_workspace_is_smaller(L):
     # a long frame: segments of K symbols keep O(K) metric rows and one
     # segment's receiver metric instead of the whole frame's
