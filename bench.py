@@ -6,10 +6,10 @@ per frame (tau = 120000 bits), BSID channel Pi=Pd=0.1, Ps=0, insertion cap
 I=2, drift limits M=693 and mn=8, uniform priors, seeded synthetic frames.
 A step is one FP32 batched decode plus adjoint of the whole batch
 (receiver-metric lattice, forward/backward chains, APPs, log P(y), then
-d log P(y) / d(Pi, Pd, Ps) and d log P(y) / d prior) with forward-metric
-checkpoints every K = ceil(sqrt(N)) = 100 symbols and the receiver metric
-recomputed in the backward and adjoint passes, every input already in HBM,
-replayed as one HIP graph.
+d log P(y) / d(Pi, Pd, Ps) and d log P(y) / d prior) with forward (and
+backward) metric checkpoints every K = ceil(sqrt(N)) = 100 symbols and the
+receiver metric recomputed for the APP and adjoint passes, every input
+already in HBM, replayed as one HIP graph.
 
 Beside it, each with its own roofline figure: the channel-estimation batch
 (128 frames, q=16, n=10, N=1000, softmax priors, decode+adjoint), the
@@ -51,22 +51,35 @@ def corridor_nodes(n, mn):
     return sum(r + mn - max(0, r - mn) + 1 for r in range(n + 1))
 
 
+GROUP_SPAN = 4   # groups of checkpoint segments reach at most 1/4 more start indices
+
+
+def group_symbols(fr, K):
+    """Symbols per main pass of a checkpointed frame: whole segments of K,
+    enough that the group's n K_G received bits are at least 4 x 2M."""
+    nck = -(-fr.N // K)
+    per = max(1, -(-(GROUP_SPAN * 2 * fr.M) // (fr.n * K)))
+    return min(fr.N, min(nck, per) * K)
+
+
 def covered_starts(fr, K):
-    """Start indices the lattice / adjoint launches of one run cover: the
-    whole received range without checkpoints; with segments of K symbols,
-    each segment's [n i0 - M, n (i1 - 1) + M] clipped to [0, rho], counted
-    per pass (forward passes over segments 0 .. S-2, main passes over all)."""
-    if not K:
+    """Start indices the lattice and adjoint launches of one run cover.
+    Without checkpoints: the whole received range once each.  With
+    checkpoints every K symbols: the lattice once over the whole frame for
+    Gamma (uniform priors; per group with general priors) and once per
+    group in the main passes, each group reaching [n i0 - M, n (i1 - 1) + M]
+    clipped to [0, rho]; the adjoint once per group."""
+    if not K or K >= fr.N:
         return fr.rho + 1, fr.rho + 1
-    S = -(-fr.N // K)
+    KG = group_symbols(fr, K)
     tot = 0
-    for j in range(S):
-        i0, i1 = j * K, min(fr.N, (j + 1) * K)
+    for i0 in range(0, fr.N, KG):
+        i1 = min(fr.N, i0 + KG)
         s0 = max(0, fr.n * i0 - fr.M)
         s1 = min(fr.rho, fr.n * (i1 - 1) + fr.M)
         tot += s1 - s0 + 1
-    fwd = tot - (min(fr.rho, fr.n * (fr.N - 1) + fr.M) - max(0, fr.n * (S - 1) * K - fr.M) + 1)
-    return tot + fwd, tot
+    pre = fr.rho + 1 if fr.prior is None else tot
+    return pre + tot, tot
 
 
 def phase_flops(frames, K=0):
@@ -77,11 +90,12 @@ def phase_flops(frames, K=0):
     wgrad: 3 N Mt Mn (uniform priors) or 4 N Mt Mn q; adjoint: 2 W_R (the
     reverse sweep's adjoint propagation and parameter products).  Executed
     on top: the lattice and adjoint over every pass's covered start indices
-    (checkpointed segments overlap by 2M), and the adjoint's recompute of
-    the forward lattice (one more W_R over what it covers)."""
+    (checkpointed groups overlap by 2M), the forward and backward
+    recursions recomputed from the checkpoints, and the adjoint's recompute
+    of the forward lattice (one more W_R over what it covers)."""
     alg = {"lattice": 0.0, "gamma": 0.0, "chain": 0.0, "app": 0.0, "wgrad": 0.0,
            "adjoint": 0.0}
-    extra = {"lattice": 0.0, "adjoint": 0.0}
+    extra = {"lattice": 0.0, "adjoint": 0.0, "rechain": 0.0}
     for fr in frames:
         Mt, Mn = 2 * fr.M + 1, 2 * fr.mn + 1
         per_s = fr.q * corridor_nodes(fr.n, fr.mn) * (3 + 2 * fr.I)
@@ -92,6 +106,8 @@ def phase_flops(frames, K=0):
         if fr.prior is not None:
             alg["gamma"] += 2.0 * fr.N * Mt * Mn * fr.q
         alg["chain"] += 4.0 * fr.N * Mt * Mn
+        if K and K < fr.N:   # both recursions again from the checkpoints
+            extra["rechain"] += 4.0 * fr.N * Mt * Mn
         alg["app"] += 2.0 * fr.N * Mt * Mn * (fr.q + 1)
         alg["wgrad"] += (3.0 if fr.prior is None else 4.0 * fr.q) * fr.N * Mt * Mn
         alg["adjoint"] += 2.0 * lat
@@ -155,7 +171,10 @@ def roofline_of(plan, frames, K, steps, workload, precision_peak):
     phases = {k: v / reps for k, v in acc.items()}
     nlaunch = plan.launches()
     alg, extra = phase_flops(frames, K)
-    dom = max((k for k in alg if alg[k] > 0), key=lambda k: phases.get(k, 0.0))
+    # the chains are bound by the latency of their N dependent steps, not by
+    # an ALU or HBM roofline: they are reported as time per step instead
+    dom = max((k for k in alg if alg[k] > 0 and k != "chain"),
+              key=lambda k: phases.get(k, 0.0))
     nl = max(1, nlaunch.get(dom, 1))
     ms = phases[dom]
     achieved = alg[dom] / (ms * 1e-3) / 1e12
@@ -301,10 +320,11 @@ def line_grad(mapdec, workloads, torch, k, K, steps, warmup, graph=True):
                        "roofline": roof,
                        "phases_ms": {p: round(v, 4) for p, v in phases.items()},
                        "launches": nl,
+                       # one launch runs the whole frame's recursions (the
+                       # sweep when checkpointed): its time per step
                        "chain_step_us": round(phases.get("chain", 0.0) * 1e3 /
                                               max(1, nl.get("chain", 1)) /
-                                              max(fr.N if not K else min(K, fr.N)
-                                                  for fr in frames), 4)}
+                                              max(fr.N for fr in frames), 4)}
 
 
 def uneven_batch(mapdec, workloads, torch, steps):

@@ -166,16 +166,20 @@ int mapdec_decode(const mapdec_frame *frames, int nframes, double *logp, int32_t
  *   dparams  device, 3*nframes doubles: d log P / d(Pi, Pd, Ps) per frame.
  *   frames[f].dprior receives d log P / d prior[i][D] when non-NULL.
  * checkpoint_K: 0 keeps the receiver metric, Gamma and every forward and
- * backward metric row of the whole frame in the workspace.  K > 0 splits
- * each frame into segments of K symbols (the last may be shorter): a
- * forward pass computes each segment's receiver metric and forward rows and
- * keeps only the forward row at every segment boundary (a checkpoint); the
- * backward pass then recomputes, segment by segment from the last, the
- * receiver metric, Gamma and the forward rows from the checkpoint, and runs
- * the backward rows, APPs and gradient terms of that segment.  The
- * workspace then holds one segment's tables (O(K) rows instead of O(N))
- * plus N/K checkpoint rows; K = ceil(sqrt(N)) balances the two.  Results
- * equal those of K = 0 up to rounding.
+ * backward metric row of the whole frame in the workspace.  K > 0 (K < N)
+ * keeps the forward and backward rows only at every K-th symbol (the
+ * checkpoints) and recomputes the receiver metric: a first pass computes
+ * Gamma for the whole frame (2 mn + 1 values per received bit) and runs the
+ * forward and backward recursions over the whole frame side by side,
+ * storing the checkpoints of both; main passes then take consecutive
+ * segments of K symbols a group at a time (enough segments that the
+ * received bits a group reaches exceed its own by a quarter at most): the
+ * group's receiver metric is recomputed, every segment's forward and
+ * backward rows are recomputed from its two checkpoints (all segments at
+ * once), then the APPs and gradient terms of the group follow.  The
+ * workspace then holds one group's tables plus O(N) checkpoints and Gamma
+ * instead of O(N) rows and receiver metric; K = ceil(sqrt(N)) balances the
+ * two.  Results equal those of K = 0 up to rounding.
  * Workspace from mapdec_workspace_size(..., flags | MAPDEC_FLAG_GRAD,
  * checkpoint_K).
  */
@@ -266,7 +270,8 @@ int mapdec_plan_profile(mapdec_plan *plan, void *stream, float *phase_ms, int ma
  * MAPDEC_* status for a NULL plan). */
 int mapdec_plan_launches(const mapdec_plan *plan, int phase);
 /* Static name of profile phase k ("pack", "lattice", "gamma", "chain",
- * "app", ...), or NULL past the last phase. */
+ * "app", "wgrad", "adjoint", "dparams", "rechain": the forward and backward
+ * rows recomputed from checkpoints), or NULL past the last phase. */
 const char *mapdec_phase_name(int phase);
 
 /*

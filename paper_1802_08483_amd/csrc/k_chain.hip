@@ -18,7 +18,7 @@ __device__ __forceinline__ T gamma_at(const FrameDesc &f, const T *G, int i, int
     if (mp < -f.M || mp > f.M) return T(0);
     if (f.uniform) {
         const int s = f.n * i + mp;
-        return (s >= 0 && s <= f.rho) ? G[(size_t)k * f.sp + (s - f.s0)] : T(0);
+        return (s >= 0 && s <= f.rho) ? G[(size_t)k * f.gsp + (s - f.s0)] : T(0);
     }
     return G[(size_t)k * f.gsp + (size_t)(i - f.i0) * f.Mt + (mp + f.M)];
 }
@@ -47,7 +47,14 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
     double *logX = dir == 0 ? f.logA : f.logB;
     const double *init = dir == 0 ? f.a_init : f.b_init;
     const int row0 = dir == 0 ? i0 : i1;
-    const double lbase = (dir == 0 ? i0 > 0 : i1 < N) ? logX[row0] : 0.0;
+    // where row r goes (sweep: checkpoints only), whether the starting row
+    // is stored, and whether the cumulative logs are written
+    const int mode = f.chain_mode, cks = f.ck_stride;
+    auto stored = [&](int r) { return mode != kChainSweep || r % cks == 0; };
+    auto slot = [&](int r) { return (size_t)(mode == kChainSweep ? r / cks : r - i0) * Mt; };
+    const bool put_init = mode == kChainSub ? ((f.wr_init >> dir) & 1) != 0 : stored(row0);
+    const bool logs = mode != kChainSub;
+    const double lbase = (logs && (dir == 0 ? i0 > 0 : i1 < N)) ? logX[row0] : 0.0;
     // a boundary prior's entries whose received position (m at the start,
     // tau + m at the end) lies outside [0, rho] carry no path: zero, so that
     // no later kernel pairs them with a clamped start index
@@ -57,9 +64,9 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
         double v = init ? init[mi] : ((mi == m0 + M) ? 1.0 : 0.0);
         if (prior_row && (pos0 + mi - M < 0 || pos0 + mi - M > f.rho)) v = 0.0;
         buf0[mn + mi] = v;
-        out[(size_t)(row0 - i0) * Mt + mi] = v;
+        if (put_init) out[slot(row0) + mi] = v;
     }
-    if (tid == 0) logX[row0] = lbase;
+    if (tid == 0 && logs) logX[row0] = lbase;
     __syncthreads();
 
     const T *G = (const T *)f.G;
@@ -95,13 +102,15 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
         }
         const double inv = 1.0 / c;
         const int row = dir == 0 ? i + 1 : i;
+        const bool st_row = stored(row);
+        const size_t ro = slot(row);
         for (int mi = tid; mi < Mt; mi += nth) {
             const double v = nxt[mn + mi] * inv;
             nxt[mn + mi] = v;
-            out[(size_t)(row - i0) * Mt + mi] = v;
+            if (st_row) out[ro + mi] = v;
         }
         lsum += log(c);
-        if (tid == 0) logX[row] = lsum;
+        if (tid == 0 && logs && st_row) logX[row] = lsum;
         double *t = cur;
         cur = nxt;
         nxt = t;
@@ -117,7 +126,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
     double *fin = dir == 0 ? f.a_fin : f.b_fin;
     if (fin)
         for (int mi = tid; mi < Mt; mi += nth) fin[mi] = cur[mn + mi];
-    if (tid != 0) return;
+    if (tid != 0 || !logs) return;
     if (dir == 1 && i0 == 0 && f.grad && f.start_prior) {
         // posterior mean of the start drift (prior entries outside [0, rho]
         // carry no path), for the path-count identity of the adjoint

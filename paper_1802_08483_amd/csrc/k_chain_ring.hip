@@ -118,14 +118,21 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     // no later kernel pairs them with a clamped start index
     const bool prior_row = init && (DIR == 0 ? i0 == 0 : i1 == N);
     const int pos0 = DIR == 0 ? 0 : f.tau;
+    // where row r goes (sweep: checkpoints only), and whether the starting
+    // row is stored
+    const int mode = f.chain_mode, cks = f.ck_stride;
+    auto stored = [&](int r) { return mode != kChainSweep || r % cks == 0; };
+    auto slot = [&](int r) { return (size_t)(mode == kChainSweep ? r / cks : r - i0) * Mt; };
+    const bool put_init = mode == kChainSub ? ((f.wr_init >> DIR) & 1) != 0 : stored(rowA);
     for (int mi = tid; mi < Mt; mi += NT) {
         R v = init ? (R)init[mi] : ((mi == m0 + M) ? R(1) : R(0));
         if (prior_row && (pos0 + mi - M < 0 || pos0 + mi - M > f.rho)) v = R(0);
         row0[MN + mi] = v;
-        out[(size_t)(rowA - i0) * Mt + mi] = v;
+        if (put_init) out[slot(rowA) + mi] = v;
     }
     double *logX = DIR == 0 ? f.logA : f.logB;
-    const double lbase = (DIR == 0 ? i0 > 0 : i1 < N) ? logX[rowA] : 0.0;
+    const double lbase =
+        (mode != kChainSub && (DIR == 0 ? i0 > 0 : i1 < N)) ? logX[rowA] : 0.0;
 
     // chunk k covers steps i0+kC .. i0+kC+C-1 (forward) or i1-1-kC down to
     // i1-C-kC (backward), which read s in [n i_lo - M, n i_hi + M]
@@ -295,14 +302,20 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             const int row = DIR == 0 ? i + 1 : i;
             if (ONE) __syncthreads();   // every read of the row is done
             R *nb = nxt + MN;
+            const bool st_row = stored(row);
+            const size_t ro = slot(row);
 #pragma unroll
             for (int j = 0; j < SPL; ++j) {
                 const int mi = state(j);
                 const R v = (mi < Mt) ? acc[j] * scl : R(0);
                 own[j] = v;
                 nb[mi] = v;
-                if (mi < Mt) out[(size_t)(row - i0) * Mt + mi] = v;
+                if (mi < Mt && st_row) out[ro + mi] = v;
             }
+            // the sweep keeps each checkpoint's cumulative log for the
+            // recomputations that start from it
+            if (mode == kChainSweep && st_row && tid == 0)
+                logX[row] = lbase + (double)lexp * 0.69314718055994530942;
             pp ^= 1;
             R *tmp = cur;
             cur = nxt;
@@ -321,7 +334,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     double *fin = DIR == 0 ? f.a_fin : f.b_fin;
     if (fin)
         for (int mi = tid; mi < Mt; mi += NT) fin[mi] = cur[MN + mi];
-    if (tid != 0) return;
+    if (tid != 0 || mode == kChainSub) return;
     logX[DIR == 0 ? i1 : i0] = lsum;
     if (DIR == 1 && i0 == 0 && f.grad && f.start_prior) {
         // posterior mean of the start drift (prior entries outside [0, rho]

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
 #pragma unroll
     for (int k = 0; k < KW; ++k) gsum[k] = T(0);
 
-    T *R = (T *)f.R;
+    T *R = (T *)f.R;   // NULL: only Gamma is wanted (uniform priors)
     const size_t sp = (size_t)f.sp;
     const int Dlo = chunk * f.dq, Dhi = min(q, Dlo + f.dq);
     for (int D = Dlo; D < Dhi; ++D) {
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
         for (int k = 0; k < KW; ++k) {
             const int len = n + k - MN;   // segment length n + delta
             const T v = (len >= 0 && s + len <= rho) ? F[k] : T(0);
-            R[((size_t)D * KW + k) * sp + (s - f.s0)] = v;
+            if (R) R[((size_t)D * KW + k) * sp + (s - f.s0)] = v;
             gsum[k] += v;
         }
     }
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kLatticeLanes) void k_lattice(const FrameDesc *__re
             T *G = (T *)f.G;
             const T invq = T(1) / T(q);
 #pragma unroll
-            for (int k = 0; k < KW; ++k) G[(size_t)k * sp + (s - f.s0)] = gsum[k] * invq;
+            for (int k = 0; k < KW; ++k) G[(size_t)k * f.gsp + (s - f.s0)] = gsum[k] * invq;
         } else {   // this chunk's partial sums; k_gsum adds the chunks
             T *P = (T *)f.Gpart;
 #pragma unroll

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(64) void k_gsum(const FrameDesc *__restrict__ fd,
     T *G = (T *)f.G;
     const T invq = T(1) / T(f.q);
 #pragma unroll
-    for (int k = 0; k < KW; ++k) G[(size_t)k * sp + c] = acc[k] * invq;
+    for (int k = 0; k < KW; ++k) G[(size_t)k * f.gsp + c] = acc[k] * invq;
 }
 
 // ---------------------------------------------------------------------------

@@ -62,9 +62,24 @@ TuneTable &tune_table() {
 }
 
 // Sizes and places of one frame's workspace pieces.
+//
+// Checkpointed frames (checkpoint spacing ck < N) run in three kinds of
+// pass: pre-passes compute Gamma for the whole frame into its own table
+// (uniform priors: one lattice pass over every start index, no R stored;
+// general priors: lattice and Gamma per group of segments); one sweep pass
+// runs the forward and backward chains over the whole frame side by side,
+// keeping only the rows at multiples of ck (the checkpoints of both
+// directions); main passes then take the frame a group of consecutive
+// checkpoint segments at a time: the group's receiver metric, every
+// segment's forward and backward rows recomputed from its own two
+// checkpoints (all at once), the APPs and the gradient terms.  Groups hold
+// enough segments that the start indices the group's symbols reach (nK +
+// 2M for K symbols) exceed the group's own nK by a quarter at most.
 struct FrameLayout {
     int nwords = 0, sp = 0, gsp = 0, Mt = 0, Mn = 0, pack_blocks = 0;
-    int K = 0, nseg = 1;   // symbols per segment, segments (1 unless checkpointed)
+    int K = 0, nseg = 1;   // symbols per main pass (group) and groups (1 unless checkpointed)
+    int ck = 0, nck = 1;   // checkpoint spacing (0: none) and checkpoint segments
+    int spw = 0, gspw = 0; // column strides of the whole-frame Gamma (checkpointed frames)
     int ring_shape = -1, ring_chunk = 0, ring_cols = 0;   // ring_shape -1: plain chain
     bool app_tiled = false;
     std::tuple<int, int, int> app_key;                     // (td, waves, mn) when tiled
@@ -72,14 +87,15 @@ struct FrameLayout {
     int ring_first = -1;                                   // first shape that fits
     size_t off_cw = 0, off_ybits = 0, off_R = 0, off_G = 0, off_alpha = 0, off_beta = 0,
            off_logA = 0, off_logB = 0, off_Zinv = 0, off_Zexp = 0, off_gacc = 0, off_ck = 0,
-           off_bcarry = 0, off_gpart = 0;
-    std::vector<int> gacc_first;   // first [4] partial of each segment
+           off_ckb = 0, off_Gw = 0, off_gpart = 0;
+    std::vector<int> gacc_first;   // first [4] partial of each group
     int gacc_n = 0;
     int dq = 0, dsplit = 1;        // codewords per lattice / adjoint item, items per block
 };
 
-// Segment j of a frame: symbols [i0, i1) and the start indices [s0, s1]
-// their drift bands reach (s0 <= s1 whenever |rho - tau| <= M).
+// Group j of a frame (the symbols of one main pass): symbols [i0, i1) and
+// the start indices [s0, s1] their drift bands reach (s0 <= s1 whenever
+// |rho - tau| <= M).
 struct Segment {
     int i0, i1, s0, s1;
 };
@@ -92,17 +108,26 @@ Segment segment_of(const mapdec_frame &fr, const FrameLayout &F, int j) {
     g.s1 = std::min(fr.rho, c->n * (g.i1 - 1) + c->M);
     return g;
 }
+// Groups span at least this many times 2M received bits, so that the
+// start indices a group's symbols reach exceed its own by 1/kGroupSpan.
+constexpr int kGroupSpan = 4;
 int lattice_blocks(const Segment &g) { return (g.s1 - g.s0 + 1 + kLatticeLanes - 1) / kLatticeLanes; }
 
-// The launches of one pass over segment j of every frame that has one.  A
-// forward pass (checkpointed frames only) runs the lattice, Gamma and the
-// forward chain, which leaves the next checkpoint; a main pass runs the
-// lattice, Gamma, both chains, the APP and, for gradients, W and the
-// adjoint sweep.
+// The launches of one pass.  Pre-pass j (checkpointed frames): the
+// lattice and Gamma of group j into the whole-frame Gamma (uniform priors:
+// every start index in pass 0).  Sweep (checkpointed frames): both chains
+// over the whole frame, keeping the checkpoints.  Main pass j, over group
+// j of every frame that has one: the lattice, the chains (unsegmented
+// frames: Gamma and both chains over the frame; checkpointed frames: each
+// segment's chains from its checkpoints, through extra descriptors after
+// the frames'), the APP and, for gradients, W and the adjoint sweep.
+enum PassKind { kPassPre, kPassSweep, kPassMain };
 struct Pass {
-    bool forward = false;
+    int kind = kPassMain;
     int seg = 0;
     size_t off_fd = 0;
+    std::vector<int> sub_frame;   // frame of descriptor nframes + k
+    std::vector<int> sub_seg;     // its checkpoint segment
     std::map<std::pair<int, int>, std::vector<Work>> lat;          // (mn, imode)
     std::map<std::pair<int, int>, size_t> off_lat;
     // per mn: the start-index blocks without codeword chunks (W), and those
@@ -260,7 +285,20 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         FrameLayout &F = L.fl[f];
         F.Mt = 2 * c->M + 1;
         F.Mn = 2 * c->mn + 1;
-        F.K = ckK > 0 ? std::min(ckK, fr.N) : fr.N;
+        if (ckK > 0 && ckK < fr.N) {
+            F.ck = ckK;
+            F.nck = (fr.N + ckK - 1) / ckK;
+            const long long span = (long long)kGroupSpan * 2 * c->M;
+            const long long per = std::max<long long>(1, (span + (long long)c->n * ckK - 1) /
+                                                             ((long long)c->n * ckK));
+            F.K = (int)std::min<long long>((long long)F.nck, per) * ckK;
+            F.K = std::min(F.K, fr.N);
+            F.spw = (fr.rho + 1 + 63) / 64 * 64;
+            F.gspw = (int)(((long long)fr.N * F.Mt + 63) / 64 * 64);
+            if ((long long)fr.N * F.Mt + 64 > (1LL << 31)) return MAPDEC_EUNSUPPORTED;
+        } else {
+            F.K = fr.N;
+        }
         F.nseg = (fr.N + F.K - 1) / F.K;
         smax = std::max(smax, F.nseg);
         F.sp = 0;
@@ -388,27 +426,62 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
     for (int f = 0; f < nframes; ++f)
         L.fslice[f] = (int)((long long)f * L.slices / nframes);
 
-    // passes: forward over segments 0 .. S-2, then main passes S-1 .. 0
-    for (int j = 0; j + 1 < smax; ++j) {
+    // passes: pre-passes and the sweep (checkpointed frames), then main
+    // passes over groups S-1 .. 0 (the last pass covers group 0)
+    int npre = 0;
+    bool any_ck = false;
+    for (int f = 0; f < nframes; ++f) {
+        const FrameLayout &F = L.fl[f];
+        if (!F.ck) continue;
+        any_ck = true;
+        npre = std::max(npre, frames[f].prior ? F.nseg : 1);
+    }
+    for (int j = 0; j < npre; ++j) {
         Pass P;
-        P.forward = true;
+        P.kind = kPassPre;
         P.seg = j;
+        L.passes.push_back(P);
+    }
+    if (any_ck) {
+        Pass P;
+        P.kind = kPassSweep;
         L.passes.push_back(P);
     }
     for (int j = smax - 1; j >= 0; --j) {
         Pass P;
-        P.forward = false;
+        P.kind = kPassMain;
         P.seg = j;
         L.passes.push_back(P);
     }
     for (Pass &P : L.passes) {
         const int j = P.seg;
-        std::vector<std::pair<int, int>> chains;   // (steps, frame)
+        std::vector<std::pair<int, int>> chains;   // (steps, descriptor)
         for (int f = 0; f < nframes; ++f) {
             const mapdec_frame &fr = frames[f];
             const mapdec_code *c = fr.code;
             const FrameLayout &F = L.fl[f];
-            if (P.forward ? j + 1 >= F.nseg : j >= F.nseg) continue;
+            if (P.kind == kPassSweep) {
+                if (F.ck) chains.push_back(std::make_pair(fr.N, f));
+                continue;
+            }
+            if (P.kind == kPassPre) {
+                if (!F.ck || j >= (fr.prior ? F.nseg : 1)) continue;
+                auto &lv = P.lat[std::make_pair(c->mn, frame_imode(c))];
+                if (!fr.prior) {   // every start index, Gamma only
+                    const int nb = (fr.rho + kLatticeLanes) / kLatticeLanes;
+                    for (int b = 0; b < nb; ++b) lv.push_back(Work{f, b * kLatticeLanes});
+                    continue;
+                }
+                const Segment g = segment_of(fr, F, j);
+                const int nb = lattice_blocks(g);
+                for (int b = 0; b < nb; ++b)
+                    for (int x = 0; x < F.dsplit; ++x) lv.push_back(Work{f, b * kLatticeLanes + x});
+                const int per_i = (F.Mt + kGammaLanes - 1) / kGammaLanes;
+                auto &gv = P.gamma[c->mn];
+                for (int b = 0; b < (g.i1 - g.i0) * per_i; ++b) gv.push_back(Work{f, b});
+                continue;
+            }
+            if (j >= F.nseg) continue;
             const Segment g = segment_of(fr, F, j);
             auto &lv = P.lat[std::make_pair(c->mn, frame_imode(c))];
             auto &wv = P.wlat[std::make_pair(c->mn, fr.prior ? 0 : 1)];
@@ -417,17 +490,26 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                 wv.push_back(Work{f, b * kLatticeLanes});
                 for (int x = 0; x < F.dsplit; ++x) lv.push_back(Work{f, b * kLatticeLanes + x});
             }
-            if (!fr.prior && F.dsplit > 1) {
-                auto &gs = P.gsum[c->mn];
-                for (int b = 0; b < nb; ++b) gs.push_back(Work{f, b * kLatticeLanes});
+            if (F.ck) {
+                // each checkpoint segment of the group: its own chains
+                for (int k = g.i0 / F.ck; k * F.ck < g.i1; ++k) {
+                    const int d = nframes + (int)P.sub_frame.size();
+                    P.sub_frame.push_back(f);
+                    P.sub_seg.push_back(k);
+                    chains.push_back(std::make_pair(std::min(fr.N, (k + 1) * F.ck) - k * F.ck, d));
+                }
+            } else {
+                if (!fr.prior && F.dsplit > 1) {
+                    auto &gs = P.gsum[c->mn];
+                    for (int b = 0; b < nb; ++b) gs.push_back(Work{f, b * kLatticeLanes});
+                }
+                if (fr.prior) {
+                    const int per_i = (F.Mt + kGammaLanes - 1) / kGammaLanes;
+                    auto &gv = P.gamma[c->mn];
+                    for (int b = 0; b < (g.i1 - g.i0) * per_i; ++b) gv.push_back(Work{f, b});
+                }
+                chains.push_back(std::make_pair(g.i1 - g.i0, f));
             }
-            if (fr.prior) {
-                const int per_i = (F.Mt + kGammaLanes - 1) / kGammaLanes;
-                auto &gv = P.gamma[c->mn];
-                for (int b = 0; b < (g.i1 - g.i0) * per_i; ++b) gv.push_back(Work{f, b});
-            }
-            chains.push_back(std::make_pair(g.i1 - g.i0, f));
-            if (P.forward) continue;
             if (F.app_tiled) {
                 auto &v = P.app_tile[F.app_key];
                 for (int b = 0; b * kAppTI < g.i1 - g.i0; ++b) v.push_back(Work{f, b});
@@ -446,12 +528,13 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                              return a.first > b.first;
                          });
         for (const auto &ch : chains) {
-            const int f = ch.second;
+            const int d = ch.second;   // descriptor
+            const int f = d < nframes ? d : P.sub_frame[d - nframes];
             const FrameLayout &F = L.fl[f];
             if (F.ring_shape >= 0)
-                P.chain_ring[std::make_pair(F.ring_shape, frames[f].code->mn)].push_back(f);
+                P.chain_ring[std::make_pair(F.ring_shape, frames[f].code->mn)].push_back(d);
             else
-                P.chain_plain.push_back(f);
+                P.chain_plain.push_back(d);
         }
         // items of one slice contiguous (slice order); neighbouring items
         // share rows (APP, W) or received columns (Gamma): keep them on one
@@ -478,9 +561,14 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         for (auto &kv : P.gamma) by_slice(kv.second, true);
         for (auto &kv : P.adj) by_slice(kv.second, false);
         by_slice(P.app_plain, false);
+        // by slice, and within a slice whole-frame chains before the
+        // recomputations of checkpoint segments (separate launches)
         auto chains_by_slice = [&](std::vector<int> &v) {
-            std::stable_sort(v.begin(), v.end(),
-                             [&](int a, int b) { return L.fslice[a] < L.fslice[b]; });
+            auto fr_of = [&](int d) { return d < nframes ? d : P.sub_frame[d - nframes]; };
+            std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
+                const int sa = L.fslice[fr_of(a)], sb = L.fslice[fr_of(b)];
+                return sa != sb ? sa < sb : (a >= nframes) < (b >= nframes);
+            });
         };
         chains_by_slice(P.chain_plain);
         for (auto &kv : P.chain_ring) chains_by_slice(kv.second);
@@ -495,7 +583,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
     off = align_up(off + sizeof(Work) * L.pack.size());
     for (Pass &P : L.passes) {
         P.off_fd = off;
-        off = align_up(off + sizeof(FrameDesc) * nframes);
+        off = align_up(off + sizeof(FrameDesc) * (nframes + P.sub_frame.size()));
         auto place = [&](auto &groups, auto &offs) {
             for (auto &kv : groups) {
                 offs[kv.first] = off;
@@ -534,7 +622,13 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         off = align_up(off + T * c->q * F.Mn * (size_t)F.sp);
         F.off_G = off;
         F.gsp = fr.prior ? (F.K * F.Mt + 63) / 64 * 64 : F.sp;
-        off = align_up(off + T * (size_t)F.Mn * F.gsp);
+        // checkpointed frames with general priors keep Gamma in the
+        // whole-frame table only
+        if (!(F.ck && fr.prior)) off = align_up(off + T * (size_t)F.Mn * F.gsp);
+        if (F.ck) {
+            F.off_Gw = off;
+            off = align_up(off + T * (size_t)F.Mn * (fr.prior ? F.gspw : F.spw));
+        }
         if (!fr.prior && F.dsplit > 1) {
             F.off_gpart = off;   // per-chunk partial sums of R for Gamma
             off = align_up(off + T * (size_t)F.dsplit * F.Mn * F.sp);
@@ -553,11 +647,11 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         off = align_up(off + sizeof(int) * fr.N);
         F.off_gacc = off;   // the partials, then one slot for the boundary-drift means
         off = align_up(off + sizeof(double) * 4 * ((size_t)F.gacc_n + 1));
-        if (F.nseg > 1) {
-            F.off_ck = off;      // alpha rows K, 2K, .. (row jK at index j)
-            off = align_up(off + sizeof(double) * (size_t)F.nseg * F.Mt);
-            F.off_bcarry = off;  // beta row at the current segment's end
-            off = align_up(off + sizeof(double) * (size_t)F.Mt);
+        if (F.ck) {
+            F.off_ck = off;      // alpha rows 0, ck, 2 ck, .. (row j ck at index j)
+            off = align_up(off + sizeof(double) * (size_t)(F.nck + 1) * F.Mt);
+            F.off_ckb = off;     // beta rows at the same places
+            off = align_up(off + sizeof(double) * (size_t)(F.nck + 1) * F.Mt);
         }
     }
     L.total = off;
@@ -565,7 +659,11 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
 }
 
 // Per-launch phase names, in the order of mapdec_phase_name().
-enum Phase { kPhPack, kPhLattice, kPhGamma, kPhChain, kPhApp, kPhWgrad, kPhAdjoint, kPhDparams };
+// kPhRechain: the chains of checkpoint segments recomputed in main passes.
+enum Phase {
+    kPhPack, kPhLattice, kPhGamma, kPhChain, kPhApp, kPhWgrad, kPhAdjoint, kPhDparams,
+    kPhRechain, kNumPhases
+};
 
 // One kernel launch (or, for the set-up, two) of a plan, with the frames
 // whose workspace regions it reads or writes.
@@ -724,16 +822,24 @@ struct mapdec_plan {
                     a = b;
                 }
             };
+            // chain lists hold descriptors: frames, or a checkpoint
+            // segment's descriptor after them
+            auto frame_of = [&](int d) { return d < nf ? d : P.sub_frame[d - nf]; };
             auto add_chains = [&](const std::vector<int> &list, size_t off, long long steps_of_first,
                                   std::function<hipError_t(hipStream_t, const int *, int)> launch) {
                 size_t a = 0;
                 while (a < list.size()) {
                     size_t b = a;
-                    const int sl = L.fslice[list[a]];
-                    while (b < list.size() && L.fslice[list[b]] == sl) ++b;
+                    const int sl = L.fslice[frame_of(list[a])];
+                    const bool sub = list[a] >= nf;
+                    while (b < list.size() && L.fslice[frame_of(list[b])] == sl &&
+                           (list[b] >= nf) == sub)
+                        ++b;
                     const int *tab = at<int>(off) + a;
                     const int nc = (int)(b - a);
-                    add(kPhChain, sorted_frames(std::vector<int>(list.begin() + a, list.begin() + b)),
+                    std::vector<int> fl;
+                    for (size_t k = a; k < b; ++k) fl.push_back(frame_of(list[k]));
+                    add(sub ? kPhRechain : kPhChain, sorted_frames(fl),
                         false, [=](hipStream_t st) { return launch(st, tab, nc); });
                     ops.back().slice = sl;
                     group.push_back(std::make_pair(steps_of_first, ops.size() - 1));
@@ -763,9 +869,16 @@ struct mapdec_plan {
                          });
             }
             deal();
-            const int dirs = P.forward ? kDirFwd : kDirBoth;
-            auto steps = [&](int f) {
-                const Segment g = segment_of(frames_[f], L.fl[f], std::min(P.seg, L.fl[f].nseg - 1));
+            const int dirs = kDirBoth;
+            auto steps = [&](int d) {
+                const int f = frame_of(d);
+                const FrameLayout &F = L.fl[f];
+                if (d >= nf) {
+                    const int j = P.sub_seg[d - nf];
+                    return (long long)(std::min(frames_[f].N, (j + 1) * F.ck) - j * F.ck);
+                }
+                if (P.kind == kPassSweep) return (long long)frames_[f].N;
+                const Segment g = segment_of(frames_[f], F, std::min(P.seg, F.nseg - 1));
                 return (long long)(g.i1 - g.i0);
             };
             if (!P.chain_plain.empty()) {
@@ -784,7 +897,7 @@ struct mapdec_plan {
                            });
             }
             deal();
-            if (P.forward) continue;
+            if (P.kind != kPassMain) continue;
             if (!P.app_plain.empty()) {
                 const size_t lds = L.app_lds;
                 add_work(kPhApp, true, P.app_plain, P.off_app,
@@ -1035,18 +1148,70 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
             const Segment g = segment_of(fr, F, j);
             d.i0 = g.i0; d.i1 = g.i1; d.s0 = g.s0; d.s1 = g.s1;
             d.gacc = d.gacc_all + 4 * (size_t)F.gacc_first[j];
-            double *ck = F.nseg > 1 ? reinterpret_cast<double *>(base + F.off_ck) : nullptr;
-            double *bc = F.nseg > 1 ? reinterpret_cast<double *>(base + F.off_bcarry) : nullptr;
-            d.a_init = j > 0 ? ck + (size_t)j * F.Mt : fr.start_drift;
-            if (P.forward) {   // frames without segment P.seg + 1 sit this pass out
-                d.a_fin = P.seg + 1 < F.nseg ? ck + (size_t)(j + 1) * F.Mt : nullptr;
-                d.b_init = nullptr;
-                d.b_fin = nullptr;
-            } else {
-                d.a_fin = nullptr;
-                d.b_init = j + 1 < F.nseg ? bc : fr.end_drift;
-                d.b_fin = j > 0 ? bc : nullptr;
+            d.a_init = fr.start_drift;
+            d.b_init = fr.end_drift;
+            d.a_fin = d.b_fin = nullptr;
+            d.chain_mode = kChainRows;
+            d.ck_stride = 0;
+            d.wr_init = 3;
+            if (!F.ck) continue;
+            const size_t T = L.tsize;
+            unsigned char *Gw = base + F.off_Gw;
+            double *cka = reinterpret_cast<double *>(base + F.off_ck);
+            double *ckb = reinterpret_cast<double *>(base + F.off_ckb);
+            if (P.kind == kPassPre) {
+                if (!fr.prior) {   // the whole frame, Gamma only
+                    d.i0 = 0; d.i1 = fr.N; d.s0 = 0; d.s1 = fr.rho;
+                    d.R = nullptr;
+                    d.G = Gw;
+                    d.gsp = F.spw;
+                    d.dq = c->q;
+                    d.dsplit = 1;
+                } else {           // group j's Gamma into the whole-frame table
+                    d.G = Gw + T * (size_t)g.i0 * F.Mt;
+                    d.gsp = F.gspw;
+                }
+            } else if (P.kind == kPassSweep) {
+                d.i0 = 0; d.i1 = fr.N; d.s0 = 0; d.s1 = fr.rho;
+                d.G = Gw;
+                d.gsp = fr.prior ? F.gspw : F.spw;
+                d.alpha = cka;
+                d.beta = ckb;
+                d.chain_mode = kChainSweep;
+                d.ck_stride = F.ck;
+            } else if (fr.prior) {
+                // main pass: Gamma stays in the whole-frame table
+                d.G = Gw + T * (size_t)g.i0 * F.Mt;
+                d.gsp = F.gspw;
             }
+        }
+        // the chains of each checkpoint segment of a main pass's groups
+        for (size_t k = 0; k < P.sub_frame.size(); ++k) {
+            const int f = P.sub_frame[k], j = P.sub_seg[k];
+            const mapdec_frame &fr = frames[f];
+            const FrameLayout &F = L.fl[f];
+            FrameDesc &d = fd[nframes + k];
+            d = fd[f];
+            const Segment g = segment_of(fr, F, P.seg);
+            d.i0 = j * F.ck;
+            d.i1 = std::min(fr.N, d.i0 + F.ck);
+            d.s0 = 0;
+            d.s1 = fr.rho;
+            unsigned char *Gw = base + F.off_Gw;
+            d.G = fr.prior ? Gw + L.tsize * (size_t)d.i0 * F.Mt : Gw;
+            d.gsp = fr.prior ? F.gspw : F.spw;
+            d.alpha = fd[f].alpha + (size_t)(d.i0 - g.i0) * F.Mt;
+            d.beta = fd[f].beta + (size_t)(d.i0 - g.i0) * F.Mt;
+            double *cka = reinterpret_cast<double *>(base + F.off_ck);
+            double *ckb = reinterpret_cast<double *>(base + F.off_ckb);
+            d.a_init = j > 0 ? cka + (size_t)j * F.Mt : fr.start_drift;
+            d.b_init = j + 1 < F.nck ? ckb + (size_t)(j + 1) * F.Mt : fr.end_drift;
+            d.a_fin = d.b_fin = nullptr;
+            d.chain_mode = kChainSub;
+            // rows shared with the neighbouring segment are written by the
+            // chain that computes them; each starting row only at the
+            // group's ends
+            d.wr_init = (d.i0 == g.i0 ? 1 : 0) | (d.i1 == g.i1 ? 2 : 0);
         }
         for (auto &kv : P.wlat)
             std::memcpy(stage.data() + P.off_wlat.at(kv.first), kv.second.data(),
@@ -1144,7 +1309,8 @@ int tune_plan(mapdec_plan *t, hipStream_t s) {
         for (int f = 0; f < L.nframes; ++f) {
             const FrameLayout &F = L.fl[f];
             if (F.app_tiled && !T.app.count(F.app_bucket)) app_b[F.app_bucket].push_back(f);
-            if (F.ring_first >= 0 && !T.ring.count(F.ring_bucket))
+            // (checkpointed frames' main-pass descriptors hold no whole chain)
+            if (F.ring_first >= 0 && !F.ck && !T.ring.count(F.ring_bucket))
                 ring_b[F.ring_bucket].push_back(f);
         }
     }
@@ -1340,7 +1506,7 @@ int mapdec_plan_profile(mapdec_plan *p, void *stream, float *phase_ms, int max_p
     if (e == hipSuccess) e = p->enqueue(s, true);
     p->last_stream = s;
     p->ran = true;
-    const int nph = p->L.grad ? kPhDparams + 1 : kPhApp + 1;
+    const int nph = kNumPhases;
     for (int k = 0; k < max_phases && k < nph; ++k) phase_ms[k] = 0.f;
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // s has joined every forked stream
     // a phase's time is the sum of its launches' durations
@@ -1361,7 +1527,7 @@ int mapdec_plan_launches(const mapdec_plan *p, int phase) {
 
 const char *mapdec_phase_name(int phase) {
     static const char *names[] = {"pack", "lattice", "gamma", "chain", "app",
-                                  "wgrad", "adjoint", "dparams"};
+                                  "wgrad", "adjoint", "dparams", "rechain"};
     return (phase >= 0 && phase < (int)(sizeof(names) / sizeof(names[0]))) ? names[phase]
                                                                            : nullptr;
 }

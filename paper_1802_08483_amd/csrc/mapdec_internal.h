@@ -38,8 +38,9 @@ struct FrameDesc {
     // workspace (device)
     uint32_t *cw;         // [q] codewords; bit (n-1-r) holds C(D)[r]
     uint32_t *ybits;      // [nwords] bit b of word w = y[32w + b]
-    void *R;              // [q][Mn][sp] receiver metric R(s, D, delta)
-    void *G;              // uniform: [Mn][sp] sum_D R / q at column s - s0; general
+    void *R;              // [q][Mn][sp] receiver metric R(s, D, delta), or NULL
+                          // (a pass that only wants Gamma, uniform priors)
+    void *G;              // uniform: [Mn][gsp] sum_D R / q at column s - s0; general
                           // priors: [Mn][gsp] Gamma_i(m', .) at column (i - i0) Mt + m' + M
     int gsp;              // column stride of G
     double *alpha;        // [N+1][Mt] forward metric rows (FP64 at every precision)
@@ -72,6 +73,17 @@ struct FrameDesc {
     double *a_fin;        // receives alpha row i1, or NULL
     const double *b_init; // beta row i1 or NULL: the end state (i1 = N)
     double *b_fin;        // receives beta row i0, or NULL
+    // How a chain over this descriptor stores its results:
+    //   kChainRows  every row of [i0, i1] at index row - i0, the cumulative
+    //               logs at i0 / i1, log P at i1 = N;
+    //   kChainSweep only rows at multiples of ck_stride, at index
+    //               row / ck_stride, with the cumulative log of each such row
+    //               (the checkpoints of both directions), log P at i1 = N;
+    //   kChainSub   a recomputation from checkpoints: rows of [i0, i1] at
+    //               index row - i0 except the starting row unless wr_init
+    //               asks for it (bit 0 forward, bit 1 backward), and no logs,
+    //               log P or drift means (the sweep wrote them).
+    int chain_mode, ck_stride, wr_init;
     const double *start_prior;  // [Mt] prior of the frame's start drift, or NULL
     const double *end_prior;  // [Mt] prior of the frame's end drift, or NULL
                               // (known end drift rho - tau): log P(y) takes
@@ -87,5 +99,6 @@ struct Work {
 };
 
 enum : int { kStatusOk = 0, kStatusNoPath = 3 };
+enum : int { kChainRows = 0, kChainSweep = 1, kChainSub = 2 };
 
 }  // namespace mapdec

@@ -115,6 +115,19 @@ std::vector<int> list_frames(const int *t, int n) {
 void check_fd(const mapdec::FrameDesc *fd) {
     if (!in_range(fd, sizeof(mapdec::FrameDesc))) die("descriptor table outside the workspace");
 }
+// Chain lists name descriptors: a frame's own, or (checkpoint segments)
+// one after the frames' whose status pointer gives its frame.
+std::vector<int> chain_frames(const mapdec::FrameDesc *fd, const int *t, int n) {
+    std::vector<int> v = list_frames(t, n);
+    for (int &d : v) {
+        if (d < g_nframes) continue;
+        if (!in_range(fd + d, sizeof(mapdec::FrameDesc))) die("chain descriptor outside the workspace");
+        if (!readable(fd + d, sizeof(mapdec::FrameDesc)) || !readable(fd, sizeof(mapdec::FrameDesc)))
+            die("chain descriptor not materialised");
+        d = (int)(fd[d].status - fd[0].status);
+    }
+    return v;
+}
 }  // namespace
 
 // test driver hooks
@@ -283,14 +296,14 @@ hipError_t launch_gamma(int, int, const FrameDesc *fd, const Work *t, int nb, hi
 hipError_t launch_chain(int, const FrameDesc *fd, const int *fr, int nc, int, size_t,
                         hipStream_t st) {
     check_fd(fd);
-    launch(st, list_frames(fr, nc), false);
+    launch(st, chain_frames(fd, fr, nc), false);
     return hipSuccess;
 }
 hipError_t launch_chain_ring(int, int shape, int, const FrameDesc *fd, const int *fr, int nc,
                              int, size_t lds, hipStream_t st) {
     check_fd(fd);
     if (shape < 0 || shape >= kNumRingShapes || lds > 160 * 1024) die("bad ring launch");
-    launch(st, list_frames(fr, nc), false);
+    launch(st, chain_frames(fd, fr, nc), false);
     return hipSuccess;
 }
 hipError_t launch_app(int, const FrameDesc *fd, const Work *t, int nb, size_t, hipStream_t st) {

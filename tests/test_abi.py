@@ -114,13 +114,15 @@ def test_noalloc_limit_and_size_check(L):
 
 
 def test_checkpointed_workspace_is_smaller(L):
-    # a long frame: segments of K symbols keep O(K) metric rows and one
-    # segment's receiver metric instead of the whole frame's
+    # a long frame: groups of checkpoint segments keep O(K) metric rows and
+    # one group's receiver metric instead of the whole frame's; what stays
+    # O(N) is Gamma (2mn+1 values per received bit, the chains' input), the
+    # checkpoints and the per-symbol logs
     c = _code()
     fr = _frames([(c, 2000, 6000)])
     full = L.mapdec_workspace_size(fr, 1, mapdec.FP32, mapdec.FLAG_GRAD, 0)
     ck = L.mapdec_workspace_size(fr, 1, mapdec.FP32, mapdec.FLAG_GRAD, 45)
-    assert 0 < ck < full / 4
+    assert 0 < ck < full / 3
     # K >= N is a single segment: the same layout as K = 0
     assert L.mapdec_workspace_size(fr, 1, mapdec.FP32, mapdec.FLAG_GRAD, 2000) == full
 
