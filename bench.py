@@ -14,7 +14,9 @@ already in HBM, replayed as one HIP graph.
 Beside it, each with its own roofline figure: the channel-estimation batch
 (128 frames, q=16, n=10, N=1000, softmax priors, decode+adjoint), the
 256-frame batch (q=16, n=10, N=500, decode+adjoint, decode alone and the
-FP64 plain decode), the uneven 4096-frame batch (decode, tuned choices) and
+FP64 plain decode), the general scheme (64 frames of that batch's shape with
+a codebook per symbol position and a narrower corridor, decode+adjoint),
+the uneven 4096-frame batch (decode, tuned choices) and
 the single small frame (FP64 decode).
 
 Prints one JSON line.  The roofline of a line is that of its dominant
@@ -46,9 +48,11 @@ HEADLINE = 5
 HOST_THREADS_CAP = 16
 
 
-def corridor_nodes(n, mn):
-    """Lattice nodes (r, j), 0 <= r <= n, max(0, r - mn) <= j <= r + mn."""
-    return sum(r + mn - max(0, r - mn) + 1 for r in range(n + 1))
+def corridor_nodes(n, mn, lo=None):
+    """Lattice nodes (r, j), 0 <= r <= n, max(0, r + lo) <= j <= r + mn
+    (lo = -mn unless given: the corridor [lo, mn])."""
+    lo = -mn if lo is None else lo
+    return sum(r + mn - max(0, r + lo) + 1 for r in range(n + 1))
 
 
 GROUP_SPAN = 4   # groups of checkpoint segments reach at most 1/4 more start indices
@@ -97,12 +101,22 @@ def phase_flops(frames, K=0):
            "adjoint": 0.0}
     extra = {"lattice": 0.0, "adjoint": 0.0, "rechain": 0.0}
     for fr in frames:
-        Mt, Mn = 2 * fr.M + 1, 2 * fr.mn + 1
-        per_s = fr.q * corridor_nodes(fr.n, fr.mn) * (3 + 2 * fr.I)
-        lat = (fr.rho + 1) * per_s
-        lat_cov, adj_cov = covered_starts(fr, K)
+        lim = getattr(fr, "limits", None) or (-fr.M, fr.M, -fr.mn, fr.mn)
+        Mt, Mn = lim[1] - lim[0] + 1, lim[3] - lim[2] + 1
+        # the method's lattice work: nodes of the corridor [lo, hi]; the
+        # kernels run the symmetric corridor that contains it
+        per_s = fr.q * corridor_nodes(fr.n, lim[3], lim[2]) * (3 + 2 * fr.I)
+        per_x = fr.q * corridor_nodes(fr.n, fr.mn) * (3 + 2 * fr.I)
+        if getattr(fr, "codebooks", None) is not None:
+            # a codebook per symbol: one lattice per (symbol, drift state, D)
+            lat = fr.N * Mt * per_s
+            lat_cov = adj_cov = fr.N * (2 * fr.M + 1)
+        else:
+            lat = (fr.rho + 1) * per_s
+            lat_cov, adj_cov = covered_starts(fr, K)
+        per_s = per_x
         alg["lattice"] += lat
-        extra["lattice"] += (lat_cov - (fr.rho + 1)) * per_s
+        extra["lattice"] += lat_cov * per_x - lat
         if fr.prior is not None:
             alg["gamma"] += 2.0 * fr.N * Mt * Mn * fr.q
         alg["chain"] += 4.0 * fr.N * Mt * Mn
@@ -327,6 +341,28 @@ def line_grad(mapdec, workloads, torch, k, K, steps, warmup, graph=True):
                                               max(fr.N for fr in frames), 4)}
 
 
+def line_general(mapdec, workloads, torch, steps, warmup):
+    """The general scheme (a codebook per symbol position, a narrower
+    corridor): FP32 decode + adjoint as one HIP graph, with its roofline."""
+    frames = workloads.make_general_workload()
+    syms = sum(fr.N for fr in frames)
+    b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True)
+    plan = b.plan(graph=True)
+    ms = time_plan(plan, steps, warmup, torch)
+    if not (b.status == 0).all():
+        raise RuntimeError("general scheme: a frame reported no path")
+    roof, phases, nl = roofline_of(plan, frames, 0, max(1, min(steps, 5)), "general",
+                                   PEAK_FP32_TFLOPS)
+    plan.close()
+    return b, frames, {"workload": workloads.GENERAL_NAME,
+                       "value": round(syms / (ms * 1e-3), 1), "unit": "symbols/s",
+                       "ms_per_step": round(ms, 4), "frames": len(frames),
+                       "step": "decode+adjoint", "schedule": "one HIP graph",
+                       "workspace_bytes": b.ws_bytes, "roofline": roof,
+                       "phases_ms": {p: round(v, 4) for p, v in phases.items()},
+                       "launches": nl}
+
+
 def uneven_batch(mapdec, workloads, torch, steps):
     """FP32 decode of the uneven batch (4096 frames, q in {2, 8, 16}, n in
     [4, 10], N in [50, 2000], Pi = Pd log-uniform in [1e-3, 1e-1]): every
@@ -364,8 +400,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workloads", default="5,4,2,3,1",
-                    help="comma-separated workloads to run (5 = the headline line)")
+    ap.add_argument("--workloads", default="5,4,2,6,3,1",
+                    help="comma-separated workloads to run (5 = the headline line; 6 = the "
+                         "general scheme: a codebook per symbol, a narrower corridor)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip every oracle comparison (profiling runs)")
@@ -464,6 +501,18 @@ def main():
             line["accuracy"] = merge_acc([accuracy_vs(b2, f, r, True) for f, r in zip(idx, refs)])
         lines["batch256"] = line
         del b2
+        torch.cuda.empty_cache()
+
+    if 6 in wanted:
+        bg, framesg, line = line_general(mapdec, workloads, torch, args.steps, args.warmup)
+        if not args.no_oracle:
+            import oracle
+            idx = list(range(0, len(framesg), max(1, len(framesg) // nthreads)))[:nthreads]
+            refs = run_oracle_pool(lambda f: oracle.decode_frame(framesg[f], grad=True), idx,
+                                   nthreads)
+            line["accuracy"] = merge_acc([accuracy_vs(bg, f, r, True) for f, r in zip(idx, refs)])
+        lines["general"] = line
+        del bg
         torch.cuda.empty_cache()
 
     if 3 in wanted:

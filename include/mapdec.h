@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MAPDEC_VERSION 104
+#define MAPDEC_VERSION 105
 
 enum {
     MAPDEC_OK = 0,
@@ -92,6 +92,34 @@ typedef struct mapdec_code mapdec_code;
  */
 mapdec_code *mapdec_create(int q, int n, const uint8_t *codebook, double Pi, double Pd,
                            double Ps, int I, int M, int mn);
+
+/*
+ * mapdec_create_general -- the general scheme (Sec. II-A: a constituent
+ * encoding C_i for every symbol position; Sec. III-B: arbitrary state-space
+ * limits m_n^- <= 0 <= m_n^+, m_tau^- <= m_n^-, m_tau^+ >= m_n^+).
+ * ncb        1 (one codebook for every position, as mapdec_create) or the
+ *            number of symbols N of every frame that uses the handle
+ *            (codebook i encodes symbol i).
+ * codebooks  host, ncb*q*n bytes of 0/1; codebook i occupies bytes
+ *            [i q n, (i+1) q n), row D of it is C_i(D).  Each codebook must
+ *            be injective.  The bytes are copied.
+ * mt_lo, mt_hi  frame drift limits m_tau^-, m_tau^+: drift states at
+ *            codeword boundaries lie in [mt_lo, mt_hi].
+ * mn_lo, mn_hi  per-codeword drift change limits m_n^-, m_n^+: every
+ *            lattice node (r, j) keeps j - r in [mn_lo, mn_hi].
+ * Other arguments as mapdec_create.  Frames of such a code give their
+ * boundary drift priors (if any) as 2M+1 entries [m + M] with M =
+ * max(-mt_lo, mt_hi); entries outside [mt_lo, mt_hi] are ignored.  A frame
+ * reports MAPDEC_EDRIFT unless mt_lo <= rho - tau <= mt_hi, and
+ * MAPDEC_EINVAL if ncb > 1 and its N differs from ncb.  The kernel limits
+ * apply to max(-mn_lo, mn_hi).  Returns NULL on failure (mapdec_last_error()
+ * gives MAPDEC_EINVAL or MAPDEC_ENOMEM).  With ncb > 1 the receiver metric
+ * is computed per (symbol, drift state) instead of being shared by the
+ * start index (the lattices of Sec. IV-A): about M_tau / n times the work.
+ */
+mapdec_code *mapdec_create_general(int q, int n, int ncb, const uint8_t *codebooks, double Pi,
+                                   double Pd, double Ps, int I, int mt_lo, int mt_hi, int mn_lo,
+                                   int mn_hi);
 
 /* Frees a handle.  NULL is a no-op.  Plans that use it must be destroyed first. */
 void mapdec_destroy(mapdec_code *code);

@@ -240,11 +240,30 @@ def check_general(codebooks, N, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi) -> in
 
 
 def decode_frame(fr, **kw):
-    """Oracle decode of a :class:`paper_1802_08483_amd.workloads.Frame`."""
-    kw.setdefault("start", getattr(fr, "start_drift", None))
-    kw.setdefault("end", getattr(fr, "end_drift", None))
-    return decode(fr.codebook, fr.y, fr.N, fr.Pi, fr.Pd, fr.Ps, fr.I, fr.M, fr.mn,
-                  prior=fr.prior, **kw)
+    """Oracle decode of a :class:`paper_1802_08483_amd.workloads.Frame`.
+    Frames of the general scheme (``codebooks`` or ``limits`` set) go
+    through decode_general; their drift priors, given over [-M, M], are cut
+    to [mt_lo, mt_hi] (the entries outside are ignored by definition)."""
+    cbs = getattr(fr, "codebooks", None)
+    lim = getattr(fr, "limits", None)
+    if cbs is None and lim is None:
+        kw.setdefault("start", getattr(fr, "start_drift", None))
+        kw.setdefault("end", getattr(fr, "end_drift", None))
+        return decode(fr.codebook, fr.y, fr.N, fr.Pi, fr.Pd, fr.Ps, fr.I, fr.M, fr.mn,
+                      prior=fr.prior, **kw)
+    lim = lim if lim is not None else (-fr.M, fr.M, -fr.mn, fr.mn)
+    for key, attr in (("start", "start_drift"), ("end", "end_drift")):
+        v = getattr(fr, attr, None)
+        if key not in kw and v is not None:
+            kw[key] = np.asarray(v, dtype=np.float64)[lim[0] + fr.M: lim[1] + fr.M + 1]
+    res = decode_general(cbs if cbs is not None else fr.codebook, fr.y, fr.N, fr.Pi, fr.Pd,
+                         fr.Ps, fr.I, *lim, prior=fr.prior, **kw)
+    if "alpha" in res:   # rows over [-M, M] like decode()
+        for k in ("alpha", "beta"):
+            full = np.zeros((fr.N + 1, 2 * fr.M + 1))
+            full[:, lim[0] + fr.M: lim[1] + fr.M + 1] = res[k]
+            res[k] = full
+    return res
 
 
 def lattice(codebook, y, s, D, Pi, Pd, Ps, I, M, mn, tangents=False):

@@ -159,6 +159,53 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
     }
 }
 
+// W with a codebook per symbol position: R has one column per (symbol i,
+// drift state m') (column c = (i - i0) Mt + m' + M), so each column meets
+// one symbol only and W needs no sum over i:
+//   W(c, D, delta) = prior_i(D) alpha_i(m') beta_{i+1}(m' + delta) / Z_i,
+// formed from mantissas and exponent sums as above.  Lane = column.
+template <typename T, int MN, bool UNI>
+__global__ __launch_bounds__(64) void k_wadj_col(const FrameDesc *__restrict__ fd,
+                                                 const Work *__restrict__ tab) {
+    constexpr int KW = 2 * MN + 1;
+    const Work w = tab[blockIdx.x];
+    const FrameDesc &f = fd[w.frame];
+    if (*f.status != kStatusOk) return;
+    const int c = w.item + (int)threadIdx.x;
+    const int Mt = f.Mt, M = f.M, q = f.q, ib = f.i0;
+    if (c >= (f.i1 - f.i0) * Mt) return;
+    const int di = c / Mt, i = ib + di, mi = c - di * Mt, mp = mi - M;
+    const gptr<const double> A = to_global((const double *)f.alpha);
+    const gptr<const double> B = to_global((const double *)f.beta);
+    int ea;
+    const double av = frexp(A[(size_t)di * Mt + mi], &ea) * f.Zinv[i];
+    const int ae = ea - f.Zexp[i];
+    double pb[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+        const int m = mp + k - MN;
+        const int cm = min(max(m, -M), M);
+        int eb;
+        const double b = frexp(B[(size_t)(di + 1) * Mt + cm + M], &eb);
+        pb[k] = (m >= -M && m <= M) ? ldexp(av * b, ae + eb) : 0.0;
+    }
+    const size_t sp = (size_t)f.sp;
+    if constexpr (UNI) {
+        const gptr<T> W = to_global((T *)f.G);
+        const double invq = 1.0 / q;
+#pragma unroll
+        for (int k = 0; k < KW; ++k) W[(size_t)k * sp + c] = (T)(pb[k] * invq);
+    } else {
+        const gptr<T> W = to_global((T *)f.R);
+        const T *pr = (const T *)f.prior + (size_t)i * q;
+        for (int D = 0; D < q; ++D) {
+            const double pa = (double)pr[D];
+#pragma unroll
+            for (int k = 0; k < KW; ++k) W[((size_t)D * KW + k) * sp + c] = (T)(pa * pb[k]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Backward sweep through the lattices.  Lane = start index s, loop over D
 // (codeword bits are wave-uniform).  The even forward rows F_2, F_4, .. below
@@ -198,7 +245,21 @@ struct alignas(16) Slot {
     T v[E];
 };
 
-template <typename T, int MN, int IM, bool SA>
+// Zeroes corridor coordinates outside the frame's corridor (asymmetric
+// limits: the lattice zeroed those nodes, so their adjoints are zero too);
+// frames with the full corridor skip it on one scalar compare.
+template <typename T, int KW>
+__device__ __forceinline__ void adj_mask(T (&F)[KW], uint32_t cmask) {
+    if (cmask != (1u << KW) - 1u) {
+#pragma unroll
+        for (int k = 0; k < KW; ++k) F[k] = ((cmask >> k) & 1u) ? F[k] : T(0);
+    }
+}
+
+// GEN: the general scheme's instance (a codebook per symbol or a narrower
+// corridor).  With f.percol, lane = column (symbol i, drift state m') with
+// codeword C_i(D), as in the lattice kernel; else lane = start index s.
+template <typename T, int MN, int IM, bool SA, bool GEN>
 __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd,
                                                 const Work *__restrict__ tab) {
     constexpr int KW = 2 * MN + 1;
@@ -211,9 +272,23 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
     if (*f.status != kStatusOk) return;
     const int lane = threadIdx.x;
     const int chunk = w.item & 63;   // codewords [chunk dq, (chunk + 1) dq)
-    const int s = f.s0 + (w.item & ~63) + lane;   // column s - s0 of W
-    const bool live = s <= f.s1;
+    const int col = (w.item & ~63) + lane;   // column of W
     const int n = f.n, q = f.q, rho = f.rho;
+    const bool PERCOL = GEN && f.percol;
+    int s, sym = 0;
+    bool live;
+    if (PERCOL) {
+        const bool in = col < (f.i1 - f.i0) * f.Mt;
+        const int cc = in ? col : 0;
+        const int di = cc / f.Mt;
+        sym = f.i0 + di;
+        s = n * sym + (cc - di * f.Mt) - f.M;
+        live = in && s >= 0 && s <= rho;
+    } else {
+        s = f.s0 + col;
+        live = s <= f.s1;
+    }
+    const uint32_t cmask = GEN ? f.cmask : 0xffffffffu;
     const T d = (T)f.d, t1 = (T)f.t1, t0 = (T)f.t0;
     Slot<T> *rows = (Slot<T> *)smem;   // [(n - 1) / 2][KV][64]: F_2, F_4, ..
 
@@ -235,7 +310,9 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
         const int dl = k - MN;   // row 0: dl insertions before the first bit
         F0[k] = (dl >= 0 && dl <= IM) ? apow[dl] : T(0);
     }
-    const int sl = live ? s : f.s0;
+    if (GEN) adj_mask<T, KW>(F0, cmask);
+    const int sl = live ? s : (PERCOL ? 0 : f.s0);
+    const int wc = PERCOL ? (live ? col : 0) : sl - f.s0;   // W column
     const int wi = sl >> 5, sh = sl & 31;
     const uint32_t lo = f.ybits[wi], hi = f.ybits[wi + 1];
     const uint32_t win = sh ? ((lo >> sh) | (hi << (32 - sh))) : lo;
@@ -273,15 +350,16 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
 
     const int Dlo = chunk * f.dq, Dhi = min(q, Dlo + f.dq);
     for (int D = Dlo; D < Dhi; ++D) {
-        const uint32_t cw = __builtin_amdgcn_readfirstlane(f.cw[D]);   // wave-uniform
+        // wave-uniform with one codebook, the lane's symbol's otherwise
+        const uint32_t cw = GEN ? f.cw[(size_t)sym * f.cwi + D]
+                                : __builtin_amdgcn_readfirstlane(f.cw[D]);
         // output adjoints of this lattice (zero for invalid segments)
         T Fb[KW];
         const size_t wbase = (size_t)(f.uniform ? 0 : D) * KW * sp;
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int len = n + k - MN;
-            Fb[k] = (live && len >= 0 && s + len <= rho) ? Wt[wbase + (size_t)k * sp + (sl - f.s0)]
-                                                         : T(0);
+            Fb[k] = (live && len >= 0 && s + len <= rho) ? Wt[wbase + (size_t)k * sp + wc] : T(0);
         }
         // forward rows F_1 .. F_{n-1}; the even ones to LDS
         {
@@ -298,6 +376,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
                 } else {
                     adj_row_in<T, MN, NB>(G, F, qx0, d, r);
                 }
+                if (GEN) adj_mask<T, KW>(G, cmask);
 #pragma unroll
                 for (int k = 0; k < KW; ++k) {
                     T v = G[k];
@@ -306,6 +385,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
                         if (t <= k) v += apow[t] * G[k - t];
                     F[k] = v;
                 }
+                if (GEN) adj_mask<T, KW>(F, cmask);
                 if ((r & 1) == 0) park(r, F);
             }
         }
@@ -340,6 +420,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
                 } else {
                     adj_row_in<T, MN, NB>(G, E, qx0, d, r - 1);
                 }
+                if (GEN) adj_mask<T, KW>(G, cmask);
 #pragma unroll
                 for (int k = 0; k < KW; ++k) {
                     T v = G[k];
@@ -348,8 +429,11 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
                         if (t <= k) v += apow[t] * G[k - t];
                     Fp[k] = v;
                 }
+                if (GEN) adj_mask<T, KW>(Fp, cmask);
             }
             const bool xb = (cw >> (n - r)) & 1u;
+            // the adjoint of the row before its corridor mask
+            if (GEN) adj_mask<T, KW>(Fb, cmask);
             T Gb[KW];
             if (r == n) {
 #pragma unroll
@@ -363,6 +447,8 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
                         if (k + t < KW) v += apow[t] * Fb[k + t];
                     Gb[k] = v;
                 }
+                // G_r was masked before its insertion runs
+                if (GEN) adj_mask<T, KW>(Gb, cmask);
                 if constexpr (SA) {
                     // G_r recomputed from F_{r-1} for the insertion-weight term
                     T G[KW];
@@ -372,6 +458,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
                     } else {
                         adj_row_in<T, MN, NB>(G, Fp, qx0, d, r);
                     }
+                    if (GEN) adj_mask<T, KW>(G, cmask);
 #pragma unroll
                     for (int k = 0; k < KW; ++k) {
                         T u = T(0);
@@ -408,6 +495,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
         }
         if constexpr (SA) {
             // row 0: F_0[k] = a^(k - MN) for 1 <= k - MN <= I
+            if (GEN) adj_mask<T, KW>(Fb, cmask);
 #pragma unroll
             for (int k = 0; k < KW; ++k) {
                 const int dl = k - MN;
@@ -447,36 +535,44 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
 #define ADJ_CAT(a, b) ADJ_CAT2(a, b)
 
 template <int MN>
-static hipError_t wadj_mn(int uniform, const FrameDesc *fd, const Work *tab, int nblocks,
-                          hipStream_t st) {
-    if (uniform)
+static hipError_t wadj_mn(int uniform, int percol, const FrameDesc *fd, const Work *tab,
+                          int nblocks, hipStream_t st) {
+    if (percol) {
+        if (uniform)
+            hipLaunchKernelGGL((k_wadj_col<ADJ_T, MN, true>), dim3(nblocks), dim3(64), 0, st, fd,
+                               tab);
+        else
+            hipLaunchKernelGGL((k_wadj_col<ADJ_T, MN, false>), dim3(nblocks), dim3(64), 0, st,
+                               fd, tab);
+    } else if (uniform) {
         hipLaunchKernelGGL((k_wadj<ADJ_T, MN, true>), dim3(nblocks), dim3(64), 0, st, fd, tab);
-    else
+    } else {
         hipLaunchKernelGGL((k_wadj<ADJ_T, MN, false>), dim3(nblocks), dim3(64), 0, st, fd, tab);
+    }
     return hipGetLastError();
 }
 
-hipError_t ADJ_CAT(ADJ_FN, _w)(int mn, int uniform, const FrameDesc *fd, const Work *tab,
-                               int nblocks, hipStream_t st) {
+hipError_t ADJ_CAT(ADJ_FN, _w)(int mn, int uniform, int percol, const FrameDesc *fd,
+                               const Work *tab, int nblocks, hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
     switch (mn) {
-        case 0: return wadj_mn<0>(uniform, fd, tab, nblocks, st);
-        case 1: return wadj_mn<1>(uniform, fd, tab, nblocks, st);
-        case 2: return wadj_mn<2>(uniform, fd, tab, nblocks, st);
-        case 3: return wadj_mn<3>(uniform, fd, tab, nblocks, st);
-        case 4: return wadj_mn<4>(uniform, fd, tab, nblocks, st);
-        case 5: return wadj_mn<5>(uniform, fd, tab, nblocks, st);
-        case 6: return wadj_mn<6>(uniform, fd, tab, nblocks, st);
-        case 7: return wadj_mn<7>(uniform, fd, tab, nblocks, st);
-        case 8: return wadj_mn<8>(uniform, fd, tab, nblocks, st);
+        case 0: return wadj_mn<0>(uniform, percol, fd, tab, nblocks, st);
+        case 1: return wadj_mn<1>(uniform, percol, fd, tab, nblocks, st);
+        case 2: return wadj_mn<2>(uniform, percol, fd, tab, nblocks, st);
+        case 3: return wadj_mn<3>(uniform, percol, fd, tab, nblocks, st);
+        case 4: return wadj_mn<4>(uniform, percol, fd, tab, nblocks, st);
+        case 5: return wadj_mn<5>(uniform, percol, fd, tab, nblocks, st);
+        case 6: return wadj_mn<6>(uniform, percol, fd, tab, nblocks, st);
+        case 7: return wadj_mn<7>(uniform, percol, fd, tab, nblocks, st);
+        case 8: return wadj_mn<8>(uniform, percol, fd, tab, nblocks, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int MN, int IM, bool SA>
+template <int MN, int IM, bool SA, bool PC>
 static hipError_t adj_launch(const FrameDesc *fd, const Work *tab, int nblocks, size_t lds,
                              hipStream_t st) {
-    auto kern = k_adjoint<ADJ_T, MN, IM, SA>;
+    auto kern = k_adjoint<ADJ_T, MN, IM, SA, PC>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -486,32 +582,39 @@ static hipError_t adj_launch(const FrameDesc *fd, const Work *tab, int nblocks, 
     return hipGetLastError();
 }
 
-template <int MN>
+template <int MN, bool PC>
 static hipError_t adj_mn(int imode, int sa, const FrameDesc *fd, const Work *tab, int nblocks,
                          size_t lds, hipStream_t st) {
     constexpr int IM2 = (2 < 2 * MN) ? 2 : 2 * MN;
     if (imode == 0)
-        return sa ? adj_launch<MN, IM2, true>(fd, tab, nblocks, lds, st)
-                  : adj_launch<MN, IM2, false>(fd, tab, nblocks, lds, st);
-    return sa ? adj_launch<MN, 2 * MN, true>(fd, tab, nblocks, lds, st)
-              : adj_launch<MN, 2 * MN, false>(fd, tab, nblocks, lds, st);
+        return sa ? adj_launch<MN, IM2, true, PC>(fd, tab, nblocks, lds, st)
+                  : adj_launch<MN, IM2, false, PC>(fd, tab, nblocks, lds, st);
+    return sa ? adj_launch<MN, 2 * MN, true, PC>(fd, tab, nblocks, lds, st)
+              : adj_launch<MN, 2 * MN, false, PC>(fd, tab, nblocks, lds, st);
 }
 
-hipError_t ADJ_CAT(ADJ_FN, _lattice)(int mn, int imode, int sa, const FrameDesc *fd,
-                                     const Work *tab, int nblocks, size_t lds, hipStream_t st) {
-    if (nblocks == 0) return hipSuccess;
+template <bool PC>
+static hipError_t adj_pc(int mn, int imode, int sa, const FrameDesc *fd, const Work *tab,
+                         int nblocks, size_t lds, hipStream_t st) {
     switch (mn) {
-        case 0: return adj_mn<0>(imode, sa, fd, tab, nblocks, lds, st);
-        case 1: return adj_mn<1>(imode, sa, fd, tab, nblocks, lds, st);
-        case 2: return adj_mn<2>(imode, sa, fd, tab, nblocks, lds, st);
-        case 3: return adj_mn<3>(imode, sa, fd, tab, nblocks, lds, st);
-        case 4: return adj_mn<4>(imode, sa, fd, tab, nblocks, lds, st);
-        case 5: return adj_mn<5>(imode, sa, fd, tab, nblocks, lds, st);
-        case 6: return adj_mn<6>(imode, sa, fd, tab, nblocks, lds, st);
-        case 7: return adj_mn<7>(imode, sa, fd, tab, nblocks, lds, st);
-        case 8: return adj_mn<8>(imode, sa, fd, tab, nblocks, lds, st);
+        case 0: return adj_mn<0, PC>(imode, sa, fd, tab, nblocks, lds, st);
+        case 1: return adj_mn<1, PC>(imode, sa, fd, tab, nblocks, lds, st);
+        case 2: return adj_mn<2, PC>(imode, sa, fd, tab, nblocks, lds, st);
+        case 3: return adj_mn<3, PC>(imode, sa, fd, tab, nblocks, lds, st);
+        case 4: return adj_mn<4, PC>(imode, sa, fd, tab, nblocks, lds, st);
+        case 5: return adj_mn<5, PC>(imode, sa, fd, tab, nblocks, lds, st);
+        case 6: return adj_mn<6, PC>(imode, sa, fd, tab, nblocks, lds, st);
+        case 7: return adj_mn<7, PC>(imode, sa, fd, tab, nblocks, lds, st);
+        case 8: return adj_mn<8, PC>(imode, sa, fd, tab, nblocks, lds, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t ADJ_CAT(ADJ_FN, _lattice)(int mn, int imode, int sa, int gen, const FrameDesc *fd,
+                                     const Work *tab, int nblocks, size_t lds, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    return gen ? adj_pc<true>(mn, imode, sa, fd, tab, nblocks, lds, st)
+                  : adj_pc<false>(mn, imode, sa, fd, tab, nblocks, lds, st);
 }
 
 }  // namespace mapdec

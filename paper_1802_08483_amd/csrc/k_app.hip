@@ -63,6 +63,9 @@ __global__ __launch_bounds__(kAppThreads) void k_app(const FrameDesc *__restrict
         for (int mi = tid; mi < Mt; mi += kAppThreads) {
             const int s = n * i + mi - M;
             if (s < 0 || s > rho) continue;
+            // R's column: the start index's, or (a codebook per symbol) the
+            // symbol's and drift state's
+            const int col = f.percol ? (i - f.i0) * Mt + mi : s - s0;
             const double av = al[mi];
             if (!(av > 0.0)) continue;
             // 2^-E alpha(m') beta(m' + delta), delta = k - mn
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(kAppThreads) void k_app(const FrameDesc *__restrict
 #pragma unroll
             for (int e = 0; e < kAppChunk; ++e) {
                 if (dc + e < q) {
-                    const T *Rp = R + (size_t)(dc + e) * Mn * sp + (s - s0);
+                    const T *Rp = R + (size_t)(dc + e) * Mn * sp + col;
                     double t = 0.0;
                     for (int k = 0; k < Mn; ++k) t += (double)Rp[(size_t)k * sp] * ab[k];
                     acc[e] += t;

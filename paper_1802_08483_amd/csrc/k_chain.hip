@@ -16,7 +16,7 @@ namespace mapdec {
 template <typename T>
 __device__ __forceinline__ T gamma_at(const FrameDesc &f, const T *G, int i, int mp, int k) {
     if (mp < -f.M || mp > f.M) return T(0);
-    if (f.uniform) {
+    if (f.uniform && !f.percol) {
         const int s = f.n * i + mp;
         return (s >= 0 && s <= f.rho) ? G[(size_t)k * f.gsp + (s - f.s0)] : T(0);
     }
@@ -60,9 +60,12 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
     // no later kernel pairs them with a clamped start index
     const bool prior_row = init && (dir == 0 ? i0 == 0 : i1 == N);
     const int pos0 = dir == 0 ? 0 : f.tau;
+    // drift states kept (asymmetric limits): indices [lo_i, hi_i]
+    const int lo_i = f.lim_lo + M, hi_i = f.lim_hi + M;
     for (int mi = tid; mi < Mt; mi += nth) {
         double v = init ? init[mi] : ((mi == m0 + M) ? 1.0 : 0.0);
         if (prior_row && (pos0 + mi - M < 0 || pos0 + mi - M > f.rho)) v = 0.0;
+        if (mi < lo_i || mi > hi_i) v = 0.0;
         buf0[mn + mi] = v;
         if (put_init) out[slot(row0) + mi] = v;
     }
@@ -92,6 +95,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
                     acc += (double)gamma_at(f, G, i, m, k) * cur[mn + mi + dl];
                 }
             }
+            if (mi < lo_i || mi > hi_i) acc = 0.0;
             nxt[mn + mi] = acc;
             part += acc;
         }

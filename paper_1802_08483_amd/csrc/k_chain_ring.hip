@@ -84,7 +84,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     const int i0 = f.i0, i1 = f.i1, NS = i1 - i0;
     // column of state m at step i: n i + m (uniform priors: the start index)
     // or Mt i + m + M (general priors); the table holds columns [s0, s1]
-    const bool uni = f.uniform != 0;
+    const bool uni = f.uniform != 0 && !f.percol;
     const int n = uni ? f.n : Mt;
     const int MC = uni ? M : 0;
     const int s0 = uni ? f.s0 : Mt * i0;
@@ -124,9 +124,12 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     auto stored = [&](int r) { return mode != kChainSweep || r % cks == 0; };
     auto slot = [&](int r) { return (size_t)(mode == kChainSweep ? r / cks : r - i0) * Mt; };
     const bool put_init = mode == kChainSub ? ((f.wr_init >> DIR) & 1) != 0 : stored(rowA);
+    // drift states kept (asymmetric limits): indices [lo_i, hi_i]
+    const int lo_i = f.lim_lo + M, hi_i = f.lim_hi + M;
     for (int mi = tid; mi < Mt; mi += NT) {
         R v = init ? (R)init[mi] : ((mi == m0 + M) ? R(1) : R(0));
         if (prior_row && (pos0 + mi - M < 0 || pos0 + mi - M > f.rho)) v = R(0);
+        if (mi < lo_i || mi > hi_i) v = R(0);
         row0[MN + mi] = v;
         if (put_init) out[slot(rowA) + mi] = v;
     }
@@ -307,7 +310,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
 #pragma unroll
             for (int j = 0; j < SPL; ++j) {
                 const int mi = state(j);
-                const R v = (mi < Mt) ? acc[j] * scl : R(0);
+                const R v = (mi >= lo_i && mi <= hi_i) ? acc[j] * scl : R(0);
                 own[j] = v;
                 nb[mi] = v;
                 if (mi < Mt && st_row) out[ro + mi] = v;

@@ -56,7 +56,10 @@ __global__ __launch_bounds__(kGammaLanes) void k_gamma(const FrameDesc *__restri
     const int s = f.n * i + mi - f.M;
     const bool valid = mi < Mt && s >= 0 && s <= f.rho;
     const T vf = valid ? T(1) : T(0);
-    const int sc = min(max(s, f.s0), f.s1) - f.s0;   // column in the segment's R table
+    // column in the segment's R table: the start index's, or (a codebook
+    // per symbol) the symbol's and drift state's
+    const int sc = f.percol ? (i - f.i0) * Mt + min(mi, Mt - 1)
+                            : min(max(s, f.s0), f.s1) - f.s0;
     const gptr<const T> R = to_global((const T *)f.R);
     const T *pr = (const T *)f.prior + (size_t)i * q;
     const size_t sp = (size_t)f.sp;

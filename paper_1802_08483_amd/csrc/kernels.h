@@ -24,8 +24,10 @@ namespace mapdec {
 // fp64 != 0 selects the double-precision instantiation of each kernel.
 hipError_t launch_init(const FrameDesc *fd, int nframes, hipStream_t st);
 hipError_t launch_pack(const FrameDesc *fd, const Work *tab, int nblocks, hipStream_t st);
-hipError_t launch_lattice(int fp64, int mn, int imode, const FrameDesc *fd, const Work *tab,
-                          int nblocks, hipStream_t st);
+// gen: the general-scheme instance (frames with a codebook per symbol or a
+// corridor narrower than [-mn, mn]); else every frame has neither
+hipError_t launch_lattice(int fp64, int mn, int imode, int gen, const FrameDesc *fd,
+                          const Work *tab, int nblocks, hipStream_t st);
 // Gamma_i for general priors; every frame of the launch has drift limit mn.
 hipError_t launch_gamma(int fp64, int mn, const FrameDesc *fd, const Work *tab, int nblocks,
                         hipStream_t st);
@@ -68,14 +70,17 @@ hipError_t launch_app_tile(int fp64, int td, int mn, int nwaves, const FrameDesc
 // the sweep accumulates d/da itself; LDS from adjoint_lds), and the
 // per-frame reduction with the chain rule (k_misc.hip).
 // uniform: every frame of the W launch has uniform priors (else none has)
-hipError_t adj_f32_w(int mn, int uniform, const FrameDesc *fd, const Work *tab, int nblocks,
-                     hipStream_t st);
-hipError_t adj_f64_w(int mn, int uniform, const FrameDesc *fd, const Work *tab, int nblocks,
-                     hipStream_t st);
-hipError_t adj_f32_lattice(int mn, int imode, int sa, const FrameDesc *fd, const Work *tab,
-                           int nblocks, size_t lds, hipStream_t st);
-hipError_t adj_f64_lattice(int mn, int imode, int sa, const FrameDesc *fd, const Work *tab,
-                           int nblocks, size_t lds, hipStream_t st);
+// W: percol, the launch's frames have a codebook per symbol (R by symbol
+// and drift state), else every one has one codebook; the sweep: gen as for
+// the lattice
+hipError_t adj_f32_w(int mn, int uniform, int percol, const FrameDesc *fd, const Work *tab,
+                     int nblocks, hipStream_t st);
+hipError_t adj_f64_w(int mn, int uniform, int percol, const FrameDesc *fd, const Work *tab,
+                     int nblocks, hipStream_t st);
+hipError_t adj_f32_lattice(int mn, int imode, int sa, int gen, const FrameDesc *fd,
+                           const Work *tab, int nblocks, size_t lds, hipStream_t st);
+hipError_t adj_f64_lattice(int mn, int imode, int sa, int gen, const FrameDesc *fd,
+                           const Work *tab, int nblocks, size_t lds, hipStream_t st);
 // LDS bytes of one adjoint workgroup: the even rows F_2, F_4, .. below row
 // n of 64 lattices, each row in 16-byte slots
 constexpr size_t adjoint_lds(int nmax, int mn, size_t tsize) {

@@ -22,7 +22,13 @@ using namespace mapdec;
 struct mapdec_code {
     int q, n, I, M, mn;
     double Pi, Pd, Ps;
-    std::vector<uint32_t> cw;   // codeword D: bit (n-1-r) = C(D)[r]
+    // ncb codebooks of q codewords (ncb = 1, or N: codebook i for symbol i);
+    // codeword D of codebook b at cw[b q + D]: bit (n-1-r) = C_b(D)[r]
+    int ncb = 1;
+    std::vector<uint32_t> cw;
+    // drift state limits [mt_lo, mt_hi] and corridor [mn_lo, mn_hi]; M and
+    // mn above are the symmetric limits that contain them
+    int mt_lo = 0, mt_hi = 0, mn_lo = 0, mn_hi = 0;
 };
 
 namespace {
@@ -79,6 +85,11 @@ struct FrameLayout {
     int nwords = 0, sp = 0, gsp = 0, Mt = 0, Mn = 0, pack_blocks = 0;
     int K = 0, nseg = 1;   // symbols per main pass (group) and groups (1 unless checkpointed)
     int ck = 0, nck = 1;   // checkpoint spacing (0: none) and checkpoint segments
+    // percol: a codebook per symbol, R by (symbol, drift state); gcol: Gamma
+    // by (symbol, drift state) (general priors, or percol); gen: the lattice
+    // and adjoint kernels' general-scheme instance (percol, or a corridor
+    // narrower than [-mn, mn])
+    bool percol = false, gcol = false, gen = false;
     int spw = 0, gspw = 0; // column strides of the whole-frame Gamma (checkpointed frames)
     int ring_shape = -1, ring_chunk = 0, ring_cols = 0;   // ring_shape -1: plain chain
     bool app_tiled = false;
@@ -112,6 +123,12 @@ Segment segment_of(const mapdec_frame &fr, const FrameLayout &F, int j) {
 // start indices a group's symbols reach exceed its own by 1/kGroupSpan.
 constexpr int kGroupSpan = 4;
 int lattice_blocks(const Segment &g) { return (g.s1 - g.s0 + 1 + kLatticeLanes - 1) / kLatticeLanes; }
+// Lattice workgroups of a group: 64 start indices each, or (a codebook per
+// symbol) 64 (symbol, drift state) columns.
+int blocks_of(const FrameLayout &F, const Segment &g) {
+    return F.percol ? ((g.i1 - g.i0) * F.Mt + kLatticeLanes - 1) / kLatticeLanes
+                    : lattice_blocks(g);
+}
 
 // The launches of one pass.  Pre-pass j (checkpointed frames): the
 // lattice and Gamma of group j into the whole-frame Gamma (uniform priors:
@@ -128,12 +145,12 @@ struct Pass {
     size_t off_fd = 0;
     std::vector<int> sub_frame;   // frame of descriptor nframes + k
     std::vector<int> sub_seg;     // its checkpoint segment
-    std::map<std::pair<int, int>, std::vector<Work>> lat;          // (mn, imode)
-    std::map<std::pair<int, int>, size_t> off_lat;
+    std::map<std::tuple<int, int, int>, std::vector<Work>> lat;   // (mn, imode, gen)
+    std::map<std::tuple<int, int, int>, size_t> off_lat;
     // per mn: the start-index blocks without codeword chunks (W), and those
     // of uniform-prior frames whose lattice is split (Gamma from R)
-    std::map<std::pair<int, int>, std::vector<Work>> wlat;   // (mn, uniform priors)
-    std::map<std::pair<int, int>, size_t> off_wlat;
+    std::map<std::tuple<int, int, int>, std::vector<Work>> wlat;   // (mn, uniform priors, percol)
+    std::map<std::tuple<int, int, int>, size_t> off_wlat;
     std::map<int, std::vector<Work>> gsum;
     std::map<int, size_t> off_gsum;
     std::map<int, std::vector<Work>> gamma;                         // mn
@@ -146,8 +163,8 @@ struct Pass {
     std::map<std::tuple<int, int, int>, size_t> off_app_tile;
     std::vector<Work> app_plain;
     size_t off_app = 0;
-    std::map<std::tuple<int, int, int>, std::vector<Work>> adj;    // (mn, imode, d/da)
-    std::map<std::tuple<int, int, int>, size_t> off_adj;
+    std::map<std::tuple<int, int, int, int>, std::vector<Work>> adj;   // (mn, imode, d/da, gen)
+    std::map<std::tuple<int, int, int, int>, size_t> off_adj;
 };
 
 struct Layout {
@@ -162,7 +179,8 @@ struct Layout {
     // LDS bytes of each kernel instance (maxima over its launches)
     size_t chain_lds = 0, app_lds = 0;
     std::map<std::pair<int, int>, size_t> ring_lds;
-    std::map<std::tuple<int, int, int>, size_t> app_tile_lds, adj_lds;
+    std::map<std::tuple<int, int, int>, size_t> app_tile_lds;
+    std::map<std::tuple<int, int, int, int>, size_t> adj_lds;
     std::vector<FrameLayout> fl;
 };
 
@@ -280,11 +298,17 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         if (!c || fr.N < 1 || fr.rho < 0 || (fr.rho > 0 && !fr.y)) return MAPDEC_EINVAL;
         const long long tau = (long long)c->n * fr.N;
         if (tau > (1LL << 30) || fr.rho > (1 << 30)) return MAPDEC_EUNSUPPORTED;
-        if (std::llabs((long long)fr.rho - tau) > c->M) return MAPDEC_EDRIFT;
+        if ((long long)fr.rho - tau < c->mt_lo || (long long)fr.rho - tau > c->mt_hi)
+            return MAPDEC_EDRIFT;
+        if (c->ncb > 1 && c->ncb != fr.N) return MAPDEC_EINVAL;   // a codebook per symbol
         if (c->n > kMaxN || c->mn > kMaxMn || c->q > kMaxQ) return MAPDEC_EUNSUPPORTED;
         FrameLayout &F = L.fl[f];
         F.Mt = 2 * c->M + 1;
         F.Mn = 2 * c->mn + 1;
+        F.percol = c->ncb > 1;
+        F.gcol = F.percol || fr.prior != nullptr;
+        F.gen = F.percol || c->mn_lo != -c->mn || c->mn_hi != c->mn;
+        if (F.percol && (long long)fr.N * F.Mt + 64 > (1LL << 31)) return MAPDEC_EUNSUPPORTED;
         if (ckK > 0 && ckK < fr.N) {
             F.ck = ckK;
             F.nck = (fr.N + ckK - 1) / ckK;
@@ -304,7 +328,8 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         F.sp = 0;
         for (int j = 0; j < F.nseg; ++j) {
             const Segment g = segment_of(fr, F, j);
-            F.sp = std::max(F.sp, (g.s1 - g.s0 + 1 + 63) / 64 * 64);
+            const int cols = F.percol ? (g.i1 - g.i0) * F.Mt : g.s1 - g.s0 + 1;
+            F.sp = std::max(F.sp, (cols + 63) / 64 * 64);
         }
         F.nwords = (fr.rho + 63) / 32 + 2;
         F.pack_blocks = (F.nwords + kPackWords - 1) / kPackWords;
@@ -312,9 +337,10 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         {
             int td = app_tile_td(c->q, L.tsize), nw = app_tile_waves(F.Mt, c->n);
             const size_t tl = app_tile_lds(F.Mt, c->mn, c->n, c->q, L.tsize, td, nw);
-            // the tile kernel addresses R with 32-bit byte offsets
+            // the tile kernel addresses R with 32-bit byte offsets, and
+            // shares each R column among the symbols of a tile (one codebook)
             const bool fits = (double)c->q * F.Mn * F.sp * L.tsize < 2147483648.0;
-            F.app_tiled = fits && tl <= lds_limit;
+            F.app_tiled = fits && tl <= lds_limit && !F.percol;
             if (F.app_tiled) {
                 F.app_bucket = TuneKey{L.fp64, c->q, c->n, c->mn, nw};
                 size_t lds = tl;
@@ -340,11 +366,11 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         }
         int shape = -1;
         size_t rlds = 0;
-        const int ncols = fr.prior ? F.Mt : c->n;
-        if (ring_params(F.Mt, F.Mn, ncols, c->mn, !fr.prior, L.tsize, lds_limit, shape,
+        const int ncols = F.gcol ? F.Mt : c->n;
+        if (ring_params(F.Mt, F.Mn, ncols, c->mn, !F.gcol, L.tsize, lds_limit, shape,
                         F.ring_chunk, F.ring_cols, rlds)) {
             F.ring_first = shape;
-            F.ring_bucket = TuneKey{L.fp64, fr.prior ? 0 : 1, fr.prior ? 0 : c->n, c->mn, shape};
+            F.ring_bucket = TuneKey{L.fp64, F.gcol ? 0 : 1, F.gcol ? 0 : c->n, c->mn, shape};
             {
                 TuneTable &T = tune_table();
                 std::lock_guard<std::mutex> g(T.mu);
@@ -352,7 +378,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                 int ch, co;
                 size_t l2;
                 if (it != T.ring.end() && it->second != shape &&
-                    ring_fit(it->second, F.Mt, F.Mn, ncols, c->mn, !fr.prior, L.tsize, lds_limit,
+                    ring_fit(it->second, F.Mt, F.Mn, ncols, c->mn, !F.gcol, L.tsize, lds_limit,
                              ch, co, l2)) {
                     shape = it->second;
                     F.ring_chunk = ch;
@@ -369,7 +395,8 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             L.chain_lds = std::max(L.chain_lds, (2 * ((size_t)F.Mt + 2 * c->mn) + 16) * sizeof(double));
         }
         if (L.grad) {
-            const auto akey = std::make_tuple(c->mn, frame_imode(c), frame_da(fr));
+            const auto akey = std::make_tuple(c->mn, frame_imode(c), frame_da(fr),
+                                              F.gen ? 1 : 0);
             const size_t al = adjoint_lds(c->n, c->mn, L.tsize);
             if (al > lds_limit) return MAPDEC_EUNSUPPORTED;
             L.adj_lds[akey] = std::max(L.adj_lds[akey], al);
@@ -383,19 +410,21 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
     {
         long long blocks = 0;
         for (int f = 0; f < nframes; ++f)
-            blocks += lattice_blocks(segment_of(frames[f], L.fl[f], 0));
+            blocks += blocks_of(L.fl[f], segment_of(frames[f], L.fl[f], 0));
         const int split = (int)std::min<long long>(
             kLatticeSplitMax, std::max<long long>(1, (kLatticeTarget + blocks - 1) / blocks));
         for (int f = 0; f < nframes; ++f) {
             FrameLayout &F = L.fl[f];
             const int q = frames[f].code->q;
-            F.dq = split == 1 ? q : std::max(std::min(q, kLatticeMinDq), (q + split - 1) / split);
+            // per-symbol lattices are never short of workgroups
+            F.dq = (split == 1 || F.percol)
+                       ? q : std::max(std::min(q, kLatticeMinDq), (q + split - 1) / split);
             F.dsplit = (q + F.dq - 1) / F.dq;
             F.gacc_first.assign(F.nseg, 0);
             F.gacc_n = 0;
             for (int j = 0; j < F.nseg; ++j) {
                 F.gacc_first[j] = F.gacc_n;
-                F.gacc_n += lattice_blocks(segment_of(frames[f], F, j)) * F.dsplit;
+                F.gacc_n += blocks_of(F, segment_of(frames[f], F, j)) * F.dsplit;
             }
         }
     }
@@ -412,6 +441,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             const mapdec_code *c = frames[f].code;
             const FrameLayout &F = L.fl[f];
             one_config = c->mn == c0->mn && frame_imode(c) == frame_imode(c0) &&
+                         F.percol == F0.percol && F.gen == F0.gen &&
                          (frames[f].prior != nullptr) == (frames[0].prior != nullptr) &&
                          F.ring_shape == F0.ring_shape && F.app_tiled == F0.app_tiled &&
                          F.app_key == F0.app_key && F.dsplit == F0.dsplit &&
@@ -434,7 +464,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         const FrameLayout &F = L.fl[f];
         if (!F.ck) continue;
         any_ck = true;
-        npre = std::max(npre, frames[f].prior ? F.nseg : 1);
+        npre = std::max(npre, F.gcol ? F.nseg : 1);
     }
     for (int j = 0; j < npre; ++j) {
         Pass P;
@@ -465,27 +495,29 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                 continue;
             }
             if (P.kind == kPassPre) {
-                if (!F.ck || j >= (fr.prior ? F.nseg : 1)) continue;
-                auto &lv = P.lat[std::make_pair(c->mn, frame_imode(c))];
-                if (!fr.prior) {   // every start index, Gamma only
+                if (!F.ck || j >= (F.gcol ? F.nseg : 1)) continue;
+                auto &lv = P.lat[std::make_tuple(c->mn, frame_imode(c), F.gen ? 1 : 0)];
+                if (!F.gcol) {   // every start index, Gamma only
                     const int nb = (fr.rho + kLatticeLanes) / kLatticeLanes;
                     for (int b = 0; b < nb; ++b) lv.push_back(Work{f, b * kLatticeLanes});
                     continue;
                 }
                 const Segment g = segment_of(fr, F, j);
-                const int nb = lattice_blocks(g);
+                const int nb = blocks_of(F, g);
                 for (int b = 0; b < nb; ++b)
                     for (int x = 0; x < F.dsplit; ++x) lv.push_back(Work{f, b * kLatticeLanes + x});
-                const int per_i = (F.Mt + kGammaLanes - 1) / kGammaLanes;
-                auto &gv = P.gamma[c->mn];
-                for (int b = 0; b < (g.i1 - g.i0) * per_i; ++b) gv.push_back(Work{f, b});
+                if (fr.prior) {   // (uniform priors: the lattice writes Gamma)
+                    const int per_i = (F.Mt + kGammaLanes - 1) / kGammaLanes;
+                    auto &gv = P.gamma[c->mn];
+                    for (int b = 0; b < (g.i1 - g.i0) * per_i; ++b) gv.push_back(Work{f, b});
+                }
                 continue;
             }
             if (j >= F.nseg) continue;
             const Segment g = segment_of(fr, F, j);
-            auto &lv = P.lat[std::make_pair(c->mn, frame_imode(c))];
-            auto &wv = P.wlat[std::make_pair(c->mn, fr.prior ? 0 : 1)];
-            const int nb = lattice_blocks(g);
+            auto &lv = P.lat[std::make_tuple(c->mn, frame_imode(c), F.gen ? 1 : 0)];
+            auto &wv = P.wlat[std::make_tuple(c->mn, fr.prior ? 0 : 1, F.percol ? 1 : 0)];
+            const int nb = blocks_of(F, g);
             for (int b = 0; b < nb; ++b) {
                 wv.push_back(Work{f, b * kLatticeLanes});
                 for (int x = 0; x < F.dsplit; ++x) lv.push_back(Work{f, b * kLatticeLanes + x});
@@ -517,7 +549,8 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                 for (int i = g.i0; i < g.i1; ++i) P.app_plain.push_back(Work{f, i - g.i0});
             }
             if (L.grad) {
-                auto &av = P.adj[std::make_tuple(c->mn, frame_imode(c), frame_da(fr))];
+                auto &av = P.adj[std::make_tuple(c->mn, frame_imode(c), frame_da(fr),
+                                                 F.gen ? 1 : 0)];
                 for (int b = 0; b < nb; ++b)
                     for (int x = 0; x < F.dsplit; ++x) av.push_back(Work{f, b * kLatticeLanes + x});
             }
@@ -615,19 +648,20 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         FrameLayout &F = L.fl[f];
         const size_t T = L.tsize;
         F.off_cw = off;
-        off = align_up(off + sizeof(uint32_t) * c->q);
+        off = align_up(off + sizeof(uint32_t) * c->q * c->ncb);
         F.off_ybits = off;
         off = align_up(off + sizeof(uint32_t) * F.nwords);
         F.off_R = off;
         off = align_up(off + T * c->q * F.Mn * (size_t)F.sp);
         F.off_G = off;
-        F.gsp = fr.prior ? (F.K * F.Mt + 63) / 64 * 64 : F.sp;
-        // checkpointed frames with general priors keep Gamma in the
-        // whole-frame table only
+        F.gsp = F.gcol ? std::max(F.sp, (F.K * F.Mt + 63) / 64 * 64) : F.sp;
+        // checkpointed frames with Gamma by symbol keep Gamma in the
+        // whole-frame table only (uniform priors with a codebook per symbol
+        // need the group's buffer for W)
         if (!(F.ck && fr.prior)) off = align_up(off + T * (size_t)F.Mn * F.gsp);
         if (F.ck) {
             F.off_Gw = off;
-            off = align_up(off + T * (size_t)F.Mn * (fr.prior ? F.gspw : F.spw));
+            off = align_up(off + T * (size_t)F.Mn * (F.gcol ? F.gspw : F.spw));
         }
         if (!fr.prior && F.dsplit > 1) {
             F.off_gpart = off;   // per-chunk partial sums of R for Gamma
@@ -847,10 +881,11 @@ struct mapdec_plan {
                 }
             };
             for (auto &kv : P.lat) {
-                const int mn = kv.first.first, im = kv.first.second;
+                const int mn = std::get<0>(kv.first), im = std::get<1>(kv.first),
+                          pc = std::get<2>(kv.first);
                 add_work(kPhLattice, true, kv.second, P.off_lat.at(kv.first),
                          [=](hipStream_t st, const Work *tab, int nb) {
-                             return launch_lattice(fp64, mn, im, fd, tab, nb, st);
+                             return launch_lattice(fp64, mn, im, pc, fd, tab, nb, st);
                          });
             }
             deal();
@@ -917,22 +952,23 @@ struct mapdec_plan {
             deal();
             if (!L.grad) continue;
             for (auto &kv : P.wlat) {
-                const int mn = kv.first.first, uni = kv.first.second;
+                const int mn = std::get<0>(kv.first), uni = std::get<1>(kv.first),
+                          pc = std::get<2>(kv.first);
                 add_work(kPhWgrad, true, kv.second, P.off_wlat.at(kv.first),
                          [=](hipStream_t st, const Work *tab, int nb) {
-                             return fp64 ? adj_f64_w(mn, uni, fd, tab, nb, st)
-                                         : adj_f32_w(mn, uni, fd, tab, nb, st);
+                             return fp64 ? adj_f64_w(mn, uni, pc, fd, tab, nb, st)
+                                         : adj_f32_w(mn, uni, pc, fd, tab, nb, st);
                          });
             }
             deal();
             for (auto &kv : P.adj) {
                 const int mn = std::get<0>(kv.first), im = std::get<1>(kv.first),
-                          da = std::get<2>(kv.first);
+                          da = std::get<2>(kv.first), pc = std::get<3>(kv.first);
                 const size_t lds = L.adj_lds.at(kv.first);
                 add_work(kPhAdjoint, true, kv.second, P.off_adj.at(kv.first),
                          [=](hipStream_t st, const Work *tab, int nb) {
-                             return fp64 ? adj_f64_lattice(mn, im, da, fd, tab, nb, lds, st)
-                                         : adj_f32_lattice(mn, im, da, fd, tab, nb, lds, st);
+                             return fp64 ? adj_f64_lattice(mn, im, da, pc, fd, tab, nb, lds, st)
+                                         : adj_f32_lattice(mn, im, da, pc, fd, tab, nb, lds, st);
                          });
             }
             deal();
@@ -1027,6 +1063,35 @@ struct mapdec_plan {
     }
 };
 
+namespace {
+
+// Packs ncb codebooks of q codewords (q n bytes of 0/1 each) into c->cw;
+// false if a byte is not 0/1 or a codebook repeats a codeword (each
+// encoding must be injective, Sec. II-A).
+bool pack_codebooks(mapdec_code *c, int ncb, const uint8_t *bytes) {
+    const int q = c->q, n = c->n;
+    c->ncb = ncb;
+    c->cw.assign((size_t)ncb * q, 0u);
+    for (int b = 0; b < ncb; ++b) {
+        for (int D = 0; D < q; ++D) {
+            uint32_t w = 0;
+            for (int r = 0; r < n; ++r) {
+                const uint8_t x = bytes[((size_t)b * q + D) * n + r];
+                if (x > 1) return false;
+                w |= (uint32_t)x << (n - 1 - r);
+            }
+            c->cw[(size_t)b * q + D] = w;
+        }
+        std::vector<uint32_t> sorted(c->cw.begin() + (size_t)b * q,
+                                     c->cw.begin() + (size_t)(b + 1) * q);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
 extern "C" {
 
 mapdec_code *mapdec_create(int q, int n, const uint8_t *codebook, double Pi, double Pd,
@@ -1042,25 +1107,37 @@ mapdec_code *mapdec_create(int q, int n, const uint8_t *codebook, double Pi, dou
     }
     c->q = q; c->n = n; c->I = I; c->M = M; c->mn = mn;
     c->Pi = Pi; c->Pd = Pd; c->Ps = Ps;
-    c->cw.resize(q);
-    for (int D = 0; D < q; ++D) {
-        uint32_t w = 0;
-        for (int r = 0; r < n; ++r) {
-            const uint8_t b = codebook[(size_t)D * n + r];
-            if (b > 1) {
-                delete c;
-                fail(MAPDEC_EINVAL);
-                return nullptr;
-            }
-            w |= (uint32_t)b << (n - 1 - r);
-        }
-        c->cw[D] = w;
-    }
-    std::vector<uint32_t> sorted = c->cw;
-    std::sort(sorted.begin(), sorted.end());
-    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) {
+    c->mt_lo = -M; c->mt_hi = M; c->mn_lo = -mn; c->mn_hi = mn;
+    if (!pack_codebooks(c, 1, codebook)) {
         delete c;
-        fail(MAPDEC_EINVAL);   // the encoding must be injective
+        fail(MAPDEC_EINVAL);
+        return nullptr;
+    }
+    return c;
+}
+
+mapdec_code *mapdec_create_general(int q, int n, int ncb, const uint8_t *codebooks, double Pi,
+                                   double Pd, double Ps, int I, int mt_lo, int mt_hi, int mn_lo,
+                                   int mn_hi) {
+    // Sec. III-B: m_n^- <= 0 <= m_n^+, m_tau^- <= m_n^-, m_tau^+ >= m_n^+
+    const bool limits = mn_lo <= 0 && mn_hi >= 0 && mt_lo <= mn_lo && mt_hi >= mn_hi;
+    const int M = std::max(-mt_lo, mt_hi), mn = std::max(-mn_lo, mn_hi);
+    if (!codebooks || ncb < 1 || !limits ||
+        validate_code_params(q, n, Pi, Pd, Ps, I, M, mn) != MAPDEC_OK) {
+        fail(MAPDEC_EINVAL);
+        return nullptr;
+    }
+    mapdec_code *c = new (std::nothrow) mapdec_code;
+    if (!c) {
+        fail(MAPDEC_ENOMEM);
+        return nullptr;
+    }
+    c->q = q; c->n = n; c->I = I; c->M = M; c->mn = mn;
+    c->Pi = Pi; c->Pd = Pd; c->Ps = Ps;
+    c->mt_lo = mt_lo; c->mt_hi = mt_hi; c->mn_lo = mn_lo; c->mn_hi = mn_hi;
+    if (!pack_codebooks(c, ncb, codebooks)) {
+        delete c;
+        fail(MAPDEC_EINVAL);
         return nullptr;
     }
     return c;
@@ -1154,13 +1231,20 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
             d.chain_mode = kChainRows;
             d.ck_stride = 0;
             d.wr_init = 3;
+            d.percol = F.percol ? 1 : 0;
+            d.cwi = F.percol ? c->q : 0;
+            d.lim_lo = c->mt_lo;
+            d.lim_hi = c->mt_hi;
+            d.cmask = 0;
+            for (int k = 0; k < F.Mn; ++k)
+                if (k - c->mn >= c->mn_lo && k - c->mn <= c->mn_hi) d.cmask |= 1u << k;
             if (!F.ck) continue;
             const size_t T = L.tsize;
             unsigned char *Gw = base + F.off_Gw;
             double *cka = reinterpret_cast<double *>(base + F.off_ck);
             double *ckb = reinterpret_cast<double *>(base + F.off_ckb);
             if (P.kind == kPassPre) {
-                if (!fr.prior) {   // the whole frame, Gamma only
+                if (!F.gcol) {   // the whole frame, Gamma only
                     d.i0 = 0; d.i1 = fr.N; d.s0 = 0; d.s1 = fr.rho;
                     d.R = nullptr;
                     d.G = Gw;
@@ -1174,7 +1258,7 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
             } else if (P.kind == kPassSweep) {
                 d.i0 = 0; d.i1 = fr.N; d.s0 = 0; d.s1 = fr.rho;
                 d.G = Gw;
-                d.gsp = fr.prior ? F.gspw : F.spw;
+                d.gsp = F.gcol ? F.gspw : F.spw;
                 d.alpha = cka;
                 d.beta = ckb;
                 d.chain_mode = kChainSweep;
@@ -1198,8 +1282,8 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
             d.s0 = 0;
             d.s1 = fr.rho;
             unsigned char *Gw = base + F.off_Gw;
-            d.G = fr.prior ? Gw + L.tsize * (size_t)d.i0 * F.Mt : Gw;
-            d.gsp = fr.prior ? F.gspw : F.spw;
+            d.G = F.gcol ? Gw + L.tsize * (size_t)d.i0 * F.Mt : Gw;
+            d.gsp = F.gcol ? F.gspw : F.spw;
             d.alpha = fd[f].alpha + (size_t)(d.i0 - g.i0) * F.Mt;
             d.beta = fd[f].beta + (size_t)(d.i0 - g.i0) * F.Mt;
             double *cka = reinterpret_cast<double *>(base + F.off_ck);
@@ -1252,7 +1336,7 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
     // codewords go straight into each frame's region
     for (int f = 0; f < nframes && e == hipSuccess; ++f)
         e = hipMemcpyAsync(base + L.fl[f].off_cw, frames[f].code->cw.data(),
-                           sizeof(uint32_t) * frames[f].code->q, hipMemcpyHostToDevice, s);
+                           sizeof(uint32_t) * frames[f].code->cw.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) {
         p->frames_.assign(frames, frames + nframes);

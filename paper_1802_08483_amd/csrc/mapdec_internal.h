@@ -84,6 +84,16 @@ struct FrameDesc {
     //               asks for it (bit 0 forward, bit 1 backward), and no logs,
     //               log P or drift means (the sweep wrote them).
     int chain_mode, ck_stride, wr_init;
+    // The general scheme (Sec. II-A: a codebook C_i per symbol position;
+    // Sec. III-B: asymmetric limits).  percol: R holds one column per
+    // (symbol i, drift state m'), column (i - i0) Mt + m' + M, computed with
+    // codeword cw[i cwi + D]; else column s - s0 of the start index (one
+    // codebook: R depends on s only).  Drift states outside [lim_lo, lim_hi]
+    // (within [-M, M]) are zero in every metric row; a lattice keeps node
+    // (r, j) only if bit j - r + mn of cmask is set (the corridor
+    // [m_n^-, m_n^+] inside [-mn, mn]).
+    int percol, cwi, lim_lo, lim_hi;
+    uint32_t cmask;
     const double *start_prior;  // [Mt] prior of the frame's start drift, or NULL
     const double *end_prior;  // [Mt] prior of the frame's end drift, or NULL
                               // (known end drift rho - tau): log P(y) takes

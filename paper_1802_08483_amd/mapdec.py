@@ -28,7 +28,7 @@ EXPORTS = ["mapdec_create", "mapdec_destroy", "mapdec_workspace_size", "mapdec_d
            "mapdec_tune_entries",
            "mapdec_tune_reset", "mapdec_last_error",
            "mapdec_strerror", "mapdec_version", "mapdec_decode_noalloc",
-           "mapdec_noalloc_limit"]
+           "mapdec_noalloc_limit", "mapdec_create_general"]
 
 
 class MapdecError(RuntimeError):
@@ -59,6 +59,9 @@ def lib() -> ctypes.CDLL:
         fp = ctypes.POINTER(_Frame)
         L.mapdec_create.argtypes = [i32, i32, vp, dbl, dbl, dbl, i32, i32, i32]
         L.mapdec_create.restype = vp
+        L.mapdec_create_general.argtypes = [i32, i32, i32, vp, dbl, dbl, dbl, i32, i32, i32,
+                                            i32, i32]
+        L.mapdec_create_general.restype = vp
         L.mapdec_destroy.argtypes = [vp]
         L.mapdec_destroy.restype = None
         L.mapdec_workspace_size.argtypes = [fp, i32, i32, i32, i32]
@@ -117,20 +120,38 @@ def strerror(status: int) -> str:
 
 
 class Code:
-    """Owns a ``mapdec_code`` handle (host-only, immutable)."""
+    """Owns a ``mapdec_code`` handle (host-only, immutable).
 
-    def __init__(self, codebook, Pi: float, Pd: float, Ps: float, I: int, M: int, mn: int):
+    ``limits`` = (mt_lo, mt_hi, mn_lo, mn_hi) and/or a codebook array of
+    shape (N, q, n) (codebook i for symbol i) select the general scheme
+    (mapdec_create_general); ``M`` and ``mn`` are then ignored and become
+    max(-mt_lo, mt_hi) and max(-mn_lo, mn_hi)."""
+
+    def __init__(self, codebook, Pi: float, Pd: float, Ps: float, I: int, M: int = 0,
+                 mn: int = 0, limits=None):
         import numpy as np
         cb = np.ascontiguousarray(np.asarray(codebook, dtype=np.uint8))
-        if cb.ndim != 2:
-            raise ValueError("codebook must be (q, n)")
-        self.q, self.n = int(cb.shape[0]), int(cb.shape[1])
+        if cb.ndim not in (2, 3):
+            raise ValueError("codebook must be (q, n) or (N, q, n)")
+        self.q, self.n = int(cb.shape[-2]), int(cb.shape[-1])
+        self.ncb = int(cb.shape[0]) if cb.ndim == 3 else 1
         self.Pi, self.Pd, self.Ps = float(Pi), float(Pd), float(Ps)
-        self.I, self.M, self.mn = int(I), int(M), int(mn)
-        self._h = lib().mapdec_create(self.q, self.n, cb.ctypes.data, self.Pi, self.Pd,
-                                      self.Ps, self.I, self.M, self.mn)
+        self.I = int(I)
+        if limits is None and cb.ndim == 2:
+            self.M, self.mn = int(M), int(mn)
+            self.limits = (-self.M, self.M, -self.mn, self.mn)
+            self._h = lib().mapdec_create(self.q, self.n, cb.ctypes.data, self.Pi, self.Pd,
+                                          self.Ps, self.I, self.M, self.mn)
+            what = "mapdec_create"
+        else:
+            lim = tuple(int(v) for v in (limits if limits is not None else (-M, M, -mn, mn)))
+            self.limits = lim
+            self.M, self.mn = max(-lim[0], lim[1]), max(-lim[2], lim[3])
+            self._h = lib().mapdec_create_general(self.q, self.n, self.ncb, cb.ctypes.data,
+                                                  self.Pi, self.Pd, self.Ps, self.I, *lim)
+            what = "mapdec_create_general"
         if not self._h:
-            raise MapdecError(lib().mapdec_last_error(), "mapdec_create")
+            raise MapdecError(lib().mapdec_last_error(), what)
 
     @property
     def handle(self) -> int:
@@ -316,11 +337,14 @@ class Plan:
 
 def code_for(frame, cache: Optional[dict] = None) -> Code:
     """A :class:`Code` for a workloads.Frame (shared when the parameters match)."""
-    key = (frame.codebook.tobytes(), frame.codebook.shape, frame.Pi, frame.Pd, frame.Ps,
-           frame.I, frame.M, frame.mn)
+    cbs = getattr(frame, "codebooks", None)
+    cb = frame.codebook if cbs is None else cbs
+    lim = getattr(frame, "limits", None)
+    key = (cb.tobytes(), cb.shape, frame.Pi, frame.Pd, frame.Ps, frame.I, frame.M, frame.mn,
+           lim)
     if cache is not None and key in cache:
         return cache[key]
-    c = Code(frame.codebook, frame.Pi, frame.Pd, frame.Ps, frame.I, frame.M, frame.mn)
+    c = Code(cb, frame.Pi, frame.Pd, frame.Ps, frame.I, frame.M, frame.mn, limits=lim)
     if cache is not None:
         cache[key] = c
     return c

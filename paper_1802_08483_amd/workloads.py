@@ -56,6 +56,12 @@ class Frame:
     end_drift: Optional[np.ndarray] = None
     sim: tuple = ()               # (Pi, Pd, Ps) used to draw y
     redraws: int = 0
+    # the general scheme (Sec. II-A / III-B): codebooks (N, q, n), codebook
+    # i for symbol i (None: ``codebook`` for every symbol), and the limits
+    # (mt_lo, mt_hi, mn_lo, mn_hi) (None: [-M, M] and [-mn, mn]); M and mn
+    # are then max(-mt_lo, mt_hi) and max(-mn_lo, mn_hi)
+    codebooks: Optional[np.ndarray] = None
+    limits: Optional[tuple] = None
 
     @property
     def tau(self) -> int:
@@ -212,6 +218,59 @@ def make_workload(k: int, nframes: Optional[int] = None, first: int = 0) -> List
         else:
             raise ValueError(f"unknown workload {k}")
     return frames
+
+
+def general_frame(seed: int, q: int, n: int, N: int, Pi: float, Pd: float, Ps: float, I: int,
+                  mt_lo: int, mt_hi: int, mn_lo: int, mn_hi: int, per_symbol: bool = True,
+                  with_prior: bool = False, sim: Optional[tuple] = None) -> Frame:
+    """A seeded frame of the general scheme: with ``per_symbol`` a random
+    codebook C_i for every symbol position (else one for all), drift limits
+    [mt_lo, mt_hi] and corridor [mn_lo, mn_hi]; the channel draw is
+    repeated (from child seeds) until the end drift rho - tau lies in
+    [mt_lo, mt_hi]."""
+    ss = np.random.SeedSequence([SEED_ROOT, 2000, seed])
+    rng = np.random.Generator(np.random.PCG64(ss))
+    if per_symbol:
+        codebooks = np.stack([random_codebook(rng, q, n) for _ in range(N)])
+    else:
+        codebooks = random_codebook(rng, q, n)[None]
+    message = rng.integers(0, q, size=N)
+    prior = None
+    if with_prior:
+        logits = rng.standard_normal((N, q))
+        e = np.exp(logits - logits.max(axis=1, keepdims=True))
+        prior = e / e.sum(axis=1, keepdims=True)
+    cbs = codebooks if per_symbol else np.repeat(codebooks, N, axis=0)
+    x = cbs[np.arange(N), message].reshape(-1).astype(np.uint8)
+    tau = n * N
+    sim = sim or (Pi, Pd, Ps)
+    redraws = 0
+    child = ss
+    while True:
+        y = bsid_channel(rng, x, *sim, I)
+        if mt_lo <= y.shape[0] - tau <= mt_hi:
+            break
+        redraws += 1
+        child = child.spawn(1)[0]
+        rng = np.random.Generator(np.random.PCG64(child))
+    M, mn = max(-mt_lo, mt_hi), max(-mn_lo, mn_hi)
+    return Frame(q=q, n=n, N=N, codebook=codebooks[0], message=message, y=y, Pi=Pi, Pd=Pd,
+                 Ps=Ps, I=I, M=M, mn=mn, prior=prior, sim=tuple(sim), redraws=redraws,
+                 codebooks=codebooks if per_symbol else None,
+                 limits=(mt_lo, mt_hi, mn_lo, mn_hi))
+
+
+GENERAL_NAME = ("64 frames q16 n10 N500 Pi=Pd=0.05 Ps=0.01, a codebook per symbol, "
+                "drift limits [-98, 98], corridor [-5, 6]")
+
+
+def make_general_workload(nframes: int = 64) -> List[Frame]:
+    """The general scheme at the 256-frame batch's operating point: 64 frames
+    of q=16, n=10, N=500 at Pi=Pd=0.05, Ps=0.01, I=2, each with a random
+    codebook per symbol position, drift limits [-98, 98] and the corridor
+    [-5, 6] (one drift change narrower on the deletion side)."""
+    return [general_frame(10_000 + f, 16, 10, 500, 0.05, 0.05, 0.01, 2, -98, 98, -5, 6)
+            for f in range(nframes)]
 
 
 def random_frame(seed: int, q: int, n: int, N: int, Pi: float, Pd: float, Ps: float,

@@ -2,7 +2,7 @@
 // creation, runs, profiling, tuning and destruction on uneven and uniform
 // batches; the stub aborts on any out-of-range table, unknown handle or
 // launch not ordered after an earlier launch of one of its frames.
-//   plan_driver <frames> <checkpoint_K> <flags> <uniform 0/1>
+//   plan_driver <frames> <checkpoint_K> <flags> <mode: 0 uneven, 1 uniform, 2 general>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -19,7 +19,9 @@ int stub_live_objects();
 int main(int argc, char **argv) {
     if (argc < 5) return 2;
     const int nf = atoi(argv[1]), K = atoi(argv[2]), flags = atoi(argv[3]);
-    const bool uniform = atoi(argv[4]) != 0;
+    // mode: 0 uneven batch, 1 uniform batch, 2 uneven with general-scheme frames
+    const int mode = atoi(argv[4]);
+    const bool uniform = mode == 1;
     std::mt19937 rng(1802);
     std::vector<mapdec_code *> codes;
     std::vector<mapdec_frame> fr(nf);
@@ -43,13 +45,27 @@ int main(int argc, char **argv) {
             for (int r = 0; r < n; ++r) cb[(size_t)D * n + r] = (uint8_t)((D >> (r % 5)) & 1);
         for (int D = 0; D < q; ++D)   // distinct: the low bits of D in the first 5 positions
             for (int r = 0; r < 5 && r < n; ++r) cb[(size_t)D * n + r] = (uint8_t)((D >> r) & 1);
-        mapdec_code *c = mapdec_create(q, n, cb.data(), p, p, 0.01, 2, M, mn);
+        mapdec_code *c = nullptr;
+        if (mode == 2 && f % 3 == 0) {
+            // the general scheme: a codebook per symbol (the same words,
+            // rotated per position) and asymmetric limits
+            std::vector<uint8_t> cbs((size_t)N * q * n);
+            for (int i = 0; i < N; ++i)
+                for (int D = 0; D < q; ++D)
+                    for (int r = 0; r < n; ++r)
+                        cbs[((size_t)i * q + D) * n + r] = cb[(size_t)((D + i) % q) * n + r];
+            c = mapdec_create_general(q, n, N, cbs.data(), p, p, 0.01, 2, -M, M / 2 + mn,
+                                      -mn, mn / 2);
+        } else {
+            c = mapdec_create(q, n, cb.data(), p, p, 0.01, 2, M, mn);
+        }
         if (!c) {
             printf("create failed: %s\n", mapdec_strerror(mapdec_last_error()));
             return 1;
         }
         codes.push_back(c);
-        const int drift = (int)(rng() % (2 * M + 1)) - M;
+        int drift = (int)(rng() % (2 * M + 1)) - M;
+        if (mode == 2 && f % 3 == 0) drift = drift / 2 > M / 2 + mn ? M / 2 + mn : drift / 2;
         fr[f] = mapdec_frame{c, N, n * N + drift, dev, (!uniform && f % 5 == 0) ? dev : nullptr,
                              dev, dev};
     }

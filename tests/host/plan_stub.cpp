@@ -277,7 +277,7 @@ hipError_t launch_pack(const FrameDesc *fd, const Work *t, int nb, hipStream_t s
     launch(st, work_frames(t, nb), true);
     return hipSuccess;
 }
-hipError_t launch_lattice(int, int, int, const FrameDesc *fd, const Work *t, int nb,
+hipError_t launch_lattice(int, int, int, int, const FrameDesc *fd, const Work *t, int nb,
                           hipStream_t st) {
     check_fd(fd);
     launch(st, work_frames(t, nb), false);
@@ -320,23 +320,23 @@ hipError_t launch_app_tile(int fp64, int td, int, int nw, const FrameDesc *fd, c
     launch(st, work_frames(t, nb), false);
     return hipSuccess;
 }
-hipError_t adj_f32_w(int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
+hipError_t adj_f32_w(int, int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
     launch(st, work_frames(t, nb), false);
     return hipSuccess;
 }
-hipError_t adj_f64_w(int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
+hipError_t adj_f64_w(int, int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
     launch(st, work_frames(t, nb), false);
     return hipSuccess;
 }
-hipError_t adj_f32_lattice(int, int, int, const FrameDesc *fd, const Work *t, int nb, size_t,
+hipError_t adj_f32_lattice(int, int, int, int, const FrameDesc *fd, const Work *t, int nb, size_t,
                            hipStream_t st) {
     check_fd(fd);
     launch(st, work_frames(t, nb), false);
     return hipSuccess;
 }
-hipError_t adj_f64_lattice(int, int, int, const FrameDesc *fd, const Work *t, int nb, size_t,
+hipError_t adj_f64_lattice(int, int, int, int, const FrameDesc *fd, const Work *t, int nb, size_t,
                            hipStream_t st) {
     check_fd(fd);
     launch(st, work_frames(t, nb), false);

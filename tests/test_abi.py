@@ -40,7 +40,7 @@ def test_exports_every_declared_symbol(L):
     assert set(declared) == set(mapdec.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
-    assert L.mapdec_version() == 104
+    assert L.mapdec_version() == 105
     for st in range(8):
         assert L.mapdec_strerror(st)
 
@@ -95,6 +95,32 @@ def test_workspace_size_and_validation(L):
     noy = (mapdec._Frame * 1)()
     noy[0] = mapdec._Frame(c.handle, 10, 30, None, None, None, None)
     assert L.mapdec_decode(noy, 1, dummy, dummy, dummy, ws32, mapdec.FP32, None) == mapdec.EINVAL
+
+
+def test_general_code_validation(L):
+    cb = np.array([[[(w >> (3 - r)) & 1 for r in range(4)] for w in range(4)]] * 5, np.uint8)
+    # limits must satisfy m_n^- <= 0 <= m_n^+, m_tau^- <= m_n^-, m_tau^+ >= m_n^+
+    for lim in [(-4, 4, 1, 2), (-4, 4, -2, -1), (-1, 4, -2, 2), (-4, 1, -2, 2)]:
+        with pytest.raises(mapdec.MapdecError) as e:
+            mapdec.Code(cb, 0.05, 0.05, 0.0, 2, limits=lim)
+        assert e.value.status == mapdec.EINVAL
+    bad = cb.copy()
+    bad[2, 1] = bad[2, 0]   # codebook 2 not injective
+    with pytest.raises(mapdec.MapdecError):
+        mapdec.Code(bad, 0.05, 0.05, 0.0, 2, limits=(-4, 4, -2, 2))
+    c = mapdec.Code(cb, 0.05, 0.05, 0.0, 2, limits=(-3, 6, -1, 2))
+    assert (c.M, c.mn) == (6, 2)
+    dummy = ctypes.c_void_p(0x1000)
+    # N must equal the number of codebooks
+    fr = _frames([(c, 4, 16)])
+    assert L.mapdec_decode(fr, 1, dummy, dummy, dummy, 1 << 30, mapdec.FP32, None) \
+        == mapdec.EINVAL
+    # end drift inside [-M, M] but outside [mt_lo, mt_hi]
+    fr = _frames([(c, 5, 20 - 5)])
+    assert L.mapdec_decode(fr, 1, dummy, dummy, dummy, 1 << 30, mapdec.FP32, None) \
+        == mapdec.EDRIFT
+    fr = _frames([(c, 5, 20 + 6)])
+    assert L.mapdec_workspace_size(fr, 1, mapdec.FP32, 0, 0) > 0
 
 
 def test_noalloc_limit_and_size_check(L):

@@ -49,6 +49,9 @@ def driver(tmp_path_factory):
     (32, 40, GRAD, 1),
     (128, 0, GRAD, 1),                 # eager uniform batch in frame slices
     (128, 0, GRAD | SERIAL, 1),
+    (60, 0, GRAD, 2),                  # with general-scheme frames
+    (60, 11, GRAD, 2),
+    (60, 0, GRAPH, 2),
 ])
 def test_plan_host_logic(driver, nframes, K, flags, uniform):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1")
