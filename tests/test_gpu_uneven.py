@@ -148,3 +148,31 @@ def test_plans_sharing_one_workspace():
     pe.close()
     pg.close()
     pr.close()
+
+
+def test_graph_replays_equal_eager_serial():
+    # three replays of a graph plan of an uneven batch, with eager runs of
+    # another batch of the same frames between them, each equal the eager
+    # one-stream order
+    frames = wl.make_workload(3, nframes=256)
+    for grad in (False, True):
+        ref = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=grad)
+        pr = ref.plan(graph=False, serial=True)
+        pr.run()
+        torch.cuda.synchronize()
+        b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=grad)
+        pg = b.plan(graph=True)
+        other = mapdec.batch_from_frames(frames[:64], precision=mapdec.FP32, grad=grad)
+        for rep in range(3):
+            b.logp.fill_(0)
+            for a in b.apps:
+                a.fill_(0)
+            pg.run()
+            torch.cuda.synchronize()
+            _same(ref, b, f"grad={grad} replay {rep}")
+            other.run_grad() if grad else other.decode()
+            torch.cuda.synchronize()
+        pg.close()
+        pr.close()
+        del ref, b, other
+        torch.cuda.empty_cache()
