@@ -97,6 +97,10 @@ def lib():
                                           ctypes.POINTER(ctypes.c_uint8), ctypes.c_int,
                                           ctypes.c_int, ctypes.c_int, _dp, _dp]
         L.mapdec_ref_glattice.restype = ctypes.c_int
+        L.mapdec_ref_run_pruned.argtypes = [ctypes.POINTER(_GCode), ctypes.c_int, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_uint8), _dp, _dp, _dp,
+                                            ctypes.c_double, ctypes.POINTER(_Out)]
+        L.mapdec_ref_run_pruned.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -176,11 +180,13 @@ def _gcode(codebooks, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi):
 
 
 def decode_general(codebooks, y, N, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi, prior=None, *,
-                   start=None, end=None, grad=False, trace=False, literal=False, check=True):
+                   start=None, end=None, grad=False, trace=False, literal=False, check=True,
+                   theta=0.0):
     """Oracle decode under the general scheme: ``codebooks`` is (q, n) (one
     codebook) or (N, q, n) (C_i per symbol); drift states lie in [mt_lo,
     mt_hi], drift changes in [mn_lo, mn_hi].  Rows and drift priors have
-    mt_hi - mt_lo + 1 entries, entry m - mt_lo.  Same outputs as decode()."""
+    mt_hi - mt_lo + 1 entries, entry m - mt_lo.  Same outputs as decode().
+    ``theta`` > 0: path thresholds (mapdec_ref_run_pruned)."""
     c, cb = _gcode(codebooks, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi)
     q = c.q
     yb = np.ascontiguousarray(y, dtype=np.uint8)
@@ -205,11 +211,20 @@ def decode_general(codebooks, y, N, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi, p
         res["logZ"] = np.zeros(N)
     out = _Out(*[_ptr(res.get(k), ctypes.c_double) for k in
                  ("app", "logp", "dparams", "dprior", "alpha", "beta", "logA", "logB", "logZ")])
-    st = lib().mapdec_ref_run_general(ctypes.byref(c), int(N), int(yb.shape[0]),
-                                      _ptr(yb, ctypes.c_uint8) if yb.size else None,
-                                      _ptr(pr, ctypes.c_double), _ptr(bnd[0], ctypes.c_double),
-                                      _ptr(bnd[1], ctypes.c_double), int(bool(literal)),
-                                      ctypes.byref(out))
+    if theta:
+        st = lib().mapdec_ref_run_pruned(ctypes.byref(c), int(N), int(yb.shape[0]),
+                                         _ptr(yb, ctypes.c_uint8) if yb.size else None,
+                                         _ptr(pr, ctypes.c_double),
+                                         _ptr(bnd[0], ctypes.c_double),
+                                         _ptr(bnd[1], ctypes.c_double), float(theta),
+                                         ctypes.byref(out))
+    else:
+        st = lib().mapdec_ref_run_general(ctypes.byref(c), int(N), int(yb.shape[0]),
+                                          _ptr(yb, ctypes.c_uint8) if yb.size else None,
+                                          _ptr(pr, ctypes.c_double),
+                                          _ptr(bnd[0], ctypes.c_double),
+                                          _ptr(bnd[1], ctypes.c_double), int(bool(literal)),
+                                          ctypes.byref(out))
     if st and check:
         raise OracleError(st)
     res["status"] = st
@@ -241,12 +256,16 @@ def check_general(codebooks, N, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi) -> in
 
 def decode_frame(fr, **kw):
     """Oracle decode of a :class:`paper_1802_08483_amd.workloads.Frame`.
-    Frames of the general scheme (``codebooks`` or ``limits`` set) go
-    through decode_general; their drift priors, given over [-M, M], are cut
-    to [mt_lo, mt_hi] (the entries outside are ignored by definition)."""
+    Frames of the general scheme (``codebooks`` or ``limits`` set) or with
+    path thresholds (``theta`` > 0) go through decode_general; their drift
+    priors, given over [-M, M], are cut to [mt_lo, mt_hi] (the entries
+    outside are ignored by definition)."""
     cbs = getattr(fr, "codebooks", None)
     lim = getattr(fr, "limits", None)
-    if cbs is None and lim is None:
+    theta = getattr(fr, "theta", 0.0) or 0.0
+    if theta:
+        kw.setdefault("theta", theta)
+    if cbs is None and lim is None and not theta:
         kw.setdefault("start", getattr(fr, "start_drift", None))
         kw.setdefault("end", getattr(fr, "end_drift", None))
         return decode(fr.codebook, fr.y, fr.N, fr.Pi, fr.Pd, fr.Ps, fr.I, fr.M, fr.mn,

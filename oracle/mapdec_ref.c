@@ -364,9 +364,33 @@ int mapdec_ref_run_drift(const ref_code *c, int N, int rho, const uint8_t *y,
     return mapdec_ref_run_general(&g, N, rho, y, prior, start, end, literal, out);
 }
 
+static int run_core(const ref_gcode *c, int N, int rho, const uint8_t *y,
+                    const double *prior, const double *start, const double *end,
+                    int literal, double theta, ref_out *out);
+
 int mapdec_ref_run_general(const ref_gcode *c, int N, int rho, const uint8_t *y,
                            const double *prior, const double *start, const double *end,
                            int literal, ref_out *out)
+{
+    return run_core(c, N, rho, y, prior, start, end, literal, 0.0, out);
+}
+
+int mapdec_ref_run_pruned(const ref_gcode *c, int N, int rho, const uint8_t *y,
+                          const double *prior, const double *start, const double *end,
+                          double theta, ref_out *out)
+{
+    if (!(theta >= 0.0) || !(theta < 1.0)) return REF_EINVAL;
+    return run_core(c, N, rho, y, prior, start, end, 0, theta, out);
+}
+
+/* The decoder's steps (Sec. II-C) under the general scheme.  theta > 0
+ * adds path thresholds (the flexibility list of Sec. III-B): a state whose
+ * normalised forward metric is below theta is not pursued (its metric is
+ * set to zero), and the backward recursion runs on the states the forward
+ * recursion kept, so every result is that of the kept paths. */
+static int run_core(const ref_gcode *c, int N, int rho, const uint8_t *y,
+                    const double *prior, const double *start, const double *end,
+                    int literal, double theta, ref_out *out)
 {
     int st = mapdec_ref_gcheck(c, N);
     if (st) return st;
@@ -430,6 +454,13 @@ int mapdec_ref_run_general(const ref_gcode *c, int N, int rho, const uint8_t *y,
         ALPHA(0, 0) = 1.0;
     }
     logA[0] = 0.0;
+    /* thresholds: row 0 like every other row, against its own sum */
+    if (theta > 0.0) {
+        double s0 = 0.0;
+        for (int m = mlo; m <= mhi; m++) s0 += ALPHA(0, m);
+        for (int m = mlo; m <= mhi; m++)
+            if (ALPHA(0, m) < theta * s0) ALPHA(0, m) = 0.0;
+    }
     for (int i = 0; i < N; i++) {
         for (int m = mlo; m <= mhi; m++) acc[m - mlo] = 0.0;
         for (int mp = mlo; mp <= mhi; mp++) {
@@ -448,7 +479,11 @@ int mapdec_ref_run_general(const ref_gcode *c, int N, int rho, const uint8_t *y,
         double csum = 0.0;
         for (int m = mlo; m <= mhi; m++) csum += acc[m - mlo];
         if (!(csum > 0.0)) { st = REF_ENOPATH; goto done; }
-        for (int m = mlo; m <= mhi; m++) ALPHA(i + 1, m) = acc[m - mlo] / csum;
+        for (int m = mlo; m <= mhi; m++) {
+            /* not pursued: a normalised metric below theta */
+            const double v = acc[m - mlo] / csum;
+            ALPHA(i + 1, m) = v < theta ? 0.0 : v;
+        }
         logA[i + 1] = logA[i] + log(csum);
     }
 
@@ -460,6 +495,10 @@ int mapdec_ref_run_general(const ref_gcode *c, int N, int rho, const uint8_t *y,
     } else {
         BETA(N, rho - tau) = 1.0;
     }
+    /* with thresholds, only the states the forward recursion kept */
+    if (theta > 0.0)
+        for (int m = mlo; m <= mhi; m++)
+            if (!(ALPHA(N, m) > 0.0)) BETA(N, m) = 0.0;
     logB[N] = 0.0;
     for (int i = N - 1; i >= 0; i--) {
         for (int mp = mlo; mp <= mhi; mp++) {
@@ -475,7 +514,7 @@ int mapdec_ref_run_general(const ref_gcode *c, int N, int rho, const uint8_t *y,
                     v += gamma * BETA(i + 1, m);
                 }
             }
-            acc[mp - mlo] = v;
+            acc[mp - mlo] = (theta > 0.0 && !(ALPHA(i, mp) > 0.0)) ? 0.0 : v;
         }
         double esum = 0.0;
         for (int m = mlo; m <= mhi; m++) esum += acc[m - mlo];

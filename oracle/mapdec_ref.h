@@ -113,6 +113,21 @@ int mapdec_ref_run_general(const ref_gcode *c, int N, int rho, const uint8_t *y,
                            int literal, ref_out *out);
 
 /*
+ * mapdec_ref_run_general with path thresholds (Sec. III-B, flexibility
+ * item h): after every forward step (and at the start row) a drift state
+ * whose forward metric, normalised to sum 1 over the row, is below theta is
+ * not pursued (set to zero); the backward recursion is computed on the
+ * states the forward recursion kept (beta_i(m) = 0 where alpha_i(m) = 0).
+ * log P(y), APPs and gradients are then those of the kept paths (the kept
+ * states held fixed).  theta = 0 gives mapdec_ref_run_general.  0 <= theta
+ * < 1, else REF_EINVAL.  Every lattice is memoised per start index (ncb = 1)
+ * or recomputed per (i, m', D).
+ */
+int mapdec_ref_run_pruned(const ref_gcode *c, int N, int rho, const uint8_t *y,
+                          const double *prior, const double *start, const double *end,
+                          double theta, ref_out *out);
+
+/*
  * Receiver metric R(y[s .. s+n+delta) | C_i(D)) for delta in [mn_lo,
  * mn_hi] (R[delta - mn_lo]) under the general scheme; dR as below with
  * M_n columns per tangent.

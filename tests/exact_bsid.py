@@ -52,9 +52,11 @@ def channel_sum(X: Sequence[int], y: Sequence[int], n: int, Pi, Pd, Ps, I: int, 
 
 
 def channel_sum_limits(X: Sequence[int], y: Sequence[int], n: int, Pi, Pd, Ps, I: int,
-                       mt_lo: int, mt_hi: int, mn_lo: int, mn_hi: int):
+                       mt_lo: int, mt_hi: int, mn_lo: int, mn_hi: int, allowed=None):
     """channel_sum with drift limits [mt_lo, mt_hi] at codeword boundaries
-    and a corridor [mn_lo, mn_hi] inside codewords."""
+    and a corridor [mn_lo, mn_hi] inside codewords.  ``allowed``: optional
+    per-boundary sets of drifts (allowed[b] for boundary b = 1 .. len(X)/n)
+    that a path must also keep to."""
     Pi, Pd, Ps = Fraction(Pi), Fraction(Pd), Fraction(Ps)
     Pt = 1 - Pi - Pd
     a, d, t1, t0 = Pi / 2, Pd, Pt * (1 - Ps), Pt * Ps
@@ -84,6 +86,8 @@ def channel_sum_limits(X: Sequence[int], y: Sequence[int], n: int, Pi, Pd, Ps, I
             if nt % n == 0:
                 drift = np_ - nt
                 if not mt_lo <= drift <= mt_hi:
+                    return None
+                if allowed is not None and drift not in allowed[nt // n]:
                     return None
                 return go(nt, np_, 0, drift)
             return go(nt, np_, 0, mp)
@@ -155,3 +159,70 @@ def brute_general(codebooks, y, N: int, Pi, Pd, Ps, I: int, mt_lo: int, mt_hi: i
         "dparams": [g / P for g in dP],
         "dprior": [[dpr[i][D] / P for D in range(q)] for i in range(N)],
     }
+
+
+def brute_pruned(codebooks, y, N: int, Pi, Pd, Ps, I: int, mt_lo: int, mt_hi: int,
+                 mn_lo: int, mn_hi: int, theta, prior: Optional[Sequence[Sequence]] = None):
+    """Exact results of the decoder with path thresholds: the drifts kept at
+    boundary i are those whose forward mass (the summed weight of all path
+    prefixes through the first i codewords, with their priors, that end at
+    that drift after consuming exactly the received bits up to it and keep
+    to the drifts kept at every earlier boundary) is at least ``theta``
+    times the total over drifts; then every result is that of the paths
+    that keep to the kept drifts at every boundary.  Returns brute()'s
+    dict plus ``kept`` (the kept drift sets, boundaries 1 .. N)."""
+    q = len(codebooks[0])
+    n = len(codebooks[0][0])
+    pr = ([[Fraction(1, q)] * q for _ in range(N)] if prior is None
+          else [[Fraction(v) for v in row] for row in prior])
+    theta = Fraction(theta)
+    kept = [None]   # boundary 0: start drift 0
+    for i in range(1, N + 1):
+        mass = {}
+        for m in range(mt_lo, mt_hi + 1):
+            end = n * i + m
+            if end < 0 or end > len(y):
+                continue
+            tot = F0
+            for msg in itertools.product(range(q), repeat=i):
+                X = [b for j, D in enumerate(msg) for b in codebooks[j][D]]
+                allowed = kept + [{m}]
+                V = channel_sum_limits(X, y[:end], n, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo, mn_hi,
+                                       allowed=allowed)[0]
+                if V:
+                    w = Fraction(1)
+                    for j, D in enumerate(msg):
+                        w *= pr[j][D]
+                    tot += w * V
+            mass[m] = tot
+        total = sum(mass.values(), F0)
+        kept.append({m for m, v in mass.items() if v > 0 and v >= theta * total})
+    P = F0
+    dP = [F0, F0, F0]
+    num = [[F0] * q for _ in range(N)]
+    dpr = [[F0] * q for _ in range(N)]
+    for msg in itertools.product(range(q), repeat=N):
+        X = [b for i, D in enumerate(msg) for b in codebooks[i][D]]
+        V, dPi, dPd, dPs = channel_sum_limits(X, y, n, Pi, Pd, Ps, I, mt_lo, mt_hi, mn_lo,
+                                              mn_hi, allowed=kept)
+        if V == 0 and dPi == 0 and dPd == 0 and dPs == 0:
+            continue
+        pw = Fraction(1)
+        for i, D in enumerate(msg):
+            pw *= pr[i][D]
+        P += pw * V
+        for k, g in enumerate((dPi, dPd, dPs)):
+            dP[k] += pw * g
+        for i, D in enumerate(msg):
+            num[i][D] += pw * V
+            rest = Fraction(1)
+            for j, E in enumerate(msg):
+                if j != i:
+                    rest *= pr[j][E]
+            dpr[i][D] += rest * V
+    out = {"P": P, "kept": kept[1:]}
+    if P:
+        out.update({"app": [[num[i][D] / P for D in range(q)] for i in range(N)],
+                    "dparams": [g / P for g in dP],
+                    "dprior": [[dpr[i][D] / P for D in range(q)] for i in range(N)]})
+    return out
