@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MAPDEC_VERSION 105
+#define MAPDEC_VERSION 106
 
 enum {
     MAPDEC_OK = 0,
@@ -120,6 +120,23 @@ mapdec_code *mapdec_create(int q, int n, const uint8_t *codebook, double Pi, dou
 mapdec_code *mapdec_create_general(int q, int n, int ncb, const uint8_t *codebooks, double Pi,
                                    double Pd, double Ps, int I, int mt_lo, int mt_hi, int mn_lo,
                                    int mn_hi);
+
+/*
+ * mapdec_with_threshold -- a new handle: code with path thresholds (the
+ * flexibility list of Sec. III-B: thresholds that avoid pursuing
+ * low-probability trellis paths).  After every forward step (and at the
+ * start row) a drift state whose forward metric is below theta times the
+ * sum of its row is not pursued (its metric becomes zero); the backward
+ * recursion runs on the states the forward recursion kept.  log P(y), the
+ * APPs and the gradient are then those of the kept paths (with the kept
+ * states held fixed); MAPDEC_ENOPATH when the thresholds drop every path.
+ * 0 <= theta < 1 (theta = 0: the exact decoder).  The forward chain of a
+ * frame then runs before its backward chain, and the workspace holds a byte
+ * per (symbol boundary, drift state).  code is not changed; the new handle
+ * is destroyed with mapdec_destroy.  NULL on failure (MAPDEC_EINVAL for a
+ * theta outside [0, 1), MAPDEC_ENOMEM).
+ */
+mapdec_code *mapdec_with_threshold(const mapdec_code *code, double theta);
 
 /* Frees a handle.  NULL is a no-op.  Plans that use it must be destroyed first. */
 void mapdec_destroy(mapdec_code *code);

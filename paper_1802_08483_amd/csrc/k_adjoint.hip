@@ -356,11 +356,17 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
         // output adjoints of this lattice (zero for invalid segments)
         T Fb[KW];
         const size_t wbase = (size_t)(f.uniform ? 0 : D) * KW * sp;
+        bool nz = false;
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int len = n + k - MN;
             Fb[k] = (live && len >= 0 && s + len <= rho) ? Wt[wbase + (size_t)k * sp + wc] : T(0);
+            nz |= Fb[k] != T(0);
         }
+        // lattices whose output adjoints are all zero (no path through
+        // them: metric rows zero there, e.g. states the path thresholds
+        // dropped) contribute nothing: the wave skips them together
+        if (__ballot(nz) == 0) continue;
         // forward rows F_1 .. F_{n-1}; the even ones to LDS
         {
             T F[KW];

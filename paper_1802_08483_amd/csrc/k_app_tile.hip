@@ -228,6 +228,14 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
             ae[ii] = x.e - emax[ii];
         }
         const ME<T> *bb = br + PAD + cc;
+        // a chunk where no symbol of the block has a forward metric (states
+        // the path thresholds dropped, or none reachable) adds nothing: the
+        // wave skips its products (the R loads still run, they feed the
+        // prefetch of the next step)
+        bool anz = false;
+#pragma unroll
+        for (int ii = 0; ii < TI; ++ii) anz |= am[ii] != T(0);
+        const bool act = __ballot(anz) != 0;
         // the next step (a repeated load past the end is harmless)
         const bool last_chunk = jc + 1 == nmy;
         const int jcn = last_chunk ? 0 : jc + 1;
@@ -243,17 +251,19 @@ __global__ __launch_bounds__(512) void k_app_tile(const FrameDesc *__restrict__ 
                 load_k(r[(k + PF) % (PF + 1)], vo, ro, k + PF);
             else
                 load_k(r[(k + PF) % (PF + 1)], von, ron, k + PF - Mn);
-            T kv[TI];
+            if (act) {
+                T kv[TI];
 #pragma unroll
-            for (int ii = 0; ii < TI; ++ii) {
-                const ME<T> b = bb[ii * (WB - n) + k];
-                kv[ii] = scale2(am[ii] * b.m, ae[ii] + b.e);
+                for (int ii = 0; ii < TI; ++ii) {
+                    const ME<T> b = bb[ii * (WB - n) + k];
+                    kv[ii] = scale2(am[ii] * b.m, ae[ii] + b.e);
+                }
+#pragma unroll
+                for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+                    for (int d = 0; d < TD; ++d)
+                        acc[ii * TD + d] += kv[ii] * r[k % (PF + 1)][d];
             }
-#pragma unroll
-            for (int ii = 0; ii < TI; ++ii)
-#pragma unroll
-                for (int d = 0; d < TD; ++d)
-                    acc[ii * TD + d] += kv[ii] * r[k % (PF + 1)][d];
         }
         // the ring position of step (j + 1, 0) must be slot 0
         if constexpr (Mn % (PF + 1) != 0) {

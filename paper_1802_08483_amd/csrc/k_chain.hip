@@ -62,13 +62,31 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
     const int pos0 = dir == 0 ? 0 : f.tau;
     // drift states kept (asymmetric limits): indices [lo_i, hi_i]
     const int lo_i = f.lim_lo + M, hi_i = f.lim_hi + M;
+    // path thresholds: the forward chain over the frame decides which
+    // states are kept, every other chain applies its decisions
+    const bool pr = f.theta > 0.0;
+    const bool decide = pr && dir == 0 && mode != kChainSub;
+    uint8_t *kept = f.kept;
+    double s0 = 0.0;
     for (int mi = tid; mi < Mt; mi += nth) {
         double v = init ? init[mi] : ((mi == m0 + M) ? 1.0 : 0.0);
         if (prior_row && (pos0 + mi - M < 0 || pos0 + mi - M > f.rho)) v = 0.0;
         if (mi < lo_i || mi > hi_i) v = 0.0;
+        if (pr && !decide && !kept[(size_t)row0 * Mt + mi]) v = 0.0;
         buf0[mn + mi] = v;
-        if (put_init) out[slot(row0) + mi] = v;
+        s0 += v;
     }
+    if (decide) {   // the start row against its own sum
+        const double cut = f.theta * block_sum(s0, red);
+        for (int mi = tid; mi < Mt; mi += nth) {
+            const double v = buf0[mn + mi];
+            const bool k = v > 0.0 && !(v < cut);
+            buf0[mn + mi] = k ? v : 0.0;
+            kept[(size_t)row0 * Mt + mi] = k ? 1 : 0;
+        }
+    }
+    if (put_init)
+        for (int mi = tid; mi < Mt; mi += nth) out[slot(row0) + mi] = buf0[mn + mi];
     if (tid == 0 && logs) logX[row0] = lbase;
     __syncthreads();
 
@@ -109,7 +127,14 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
         const bool st_row = stored(row);
         const size_t ro = slot(row);
         for (int mi = tid; mi < Mt; mi += nth) {
-            const double v = nxt[mn + mi] * inv;
+            double v = nxt[mn + mi] * inv;
+            if (decide) {   // not pursued: a normalised metric below theta
+                const bool k = v > 0.0 && !(v < f.theta);
+                v = k ? v : 0.0;
+                kept[(size_t)row * Mt + mi] = k ? 1 : 0;
+            } else if (pr && !kept[(size_t)row * Mt + mi]) {
+                v = 0.0;
+            }
             nxt[mn + mi] = v;
             if (st_row) out[ro + mi] = v;
         }

@@ -95,7 +95,8 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     R *row0 = (R *)smem;
     R *row1 = ONE ? row0 : row0 + ROWW;
     R *part = row1 + ROWW;                             // [2][NW] wave partial sums
-    T *ring = (T *)(part + 2 * NW);                    // [RPHYS][Mn], batch precision
+    R *red = part + 2 * NW;                            // [NW] partial sums of a new row
+    T *ring = (T *)(part + 3 * NW);                    // [RPHYS][Mn], batch precision
     const int tid = threadIdx.x, wv = tid >> 6;
     // drift-state index of the thread's j-th state: with several states per
     // thread (FP32 Gamma) they are adjacent (SPL tid + j), so the row windows
@@ -106,7 +107,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     const gptr<const T> G = to_global((const T *)f.G);   // [Mn][gsp]
     const size_t sp = (size_t)f.gsp;
 
-    for (int j = tid; j < (ONE ? 1 : 2) * ROWW + 2 * NW; j += NT) row0[j] = R(0);
+    for (int j = tid; j < (ONE ? 1 : 2) * ROWW + 3 * NW; j += NT) row0[j] = R(0);
     for (int j = tid; j < RPHYS * Mn; j += NT) ring[j] = T(0);
     __syncthreads();
     const int m0 = DIR == 0 ? 0 : f.rho - f.tau;
@@ -126,13 +127,37 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     const bool put_init = mode == kChainSub ? ((f.wr_init >> DIR) & 1) != 0 : stored(rowA);
     // drift states kept (asymmetric limits): indices [lo_i, hi_i]
     const int lo_i = f.lim_lo + M, hi_i = f.lim_hi + M;
+    // path thresholds: the forward chain over the frame decides which
+    // states are kept (decide), every other chain applies its decisions
+    const bool pr = f.theta > 0.0;
+    const bool decide = pr && DIR == 0 && mode != kChainSub;
+    const gptr<uint8_t> kept = to_global(f.kept);
     for (int mi = tid; mi < Mt; mi += NT) {
         R v = init ? (R)init[mi] : ((mi == m0 + M) ? R(1) : R(0));
         if (prior_row && (pos0 + mi - M < 0 || pos0 + mi - M > f.rho)) v = R(0);
         if (mi < lo_i || mi > hi_i) v = R(0);
+        if (pr && !decide && !kept[(size_t)rowA * Mt + mi]) v = R(0);
         row0[MN + mi] = v;
-        if (put_init) out[slot(rowA) + mi] = v;
     }
+    if (decide) {   // the start row against its own sum
+        __syncthreads();
+        R t = R(0);
+        for (int mi = tid; mi < Mt; mi += NT) t += row0[MN + mi];
+        t = wave_sum_dpp(t);
+        if ((tid & 63) == 0) red[wv] = t;
+        __syncthreads();
+        R sum = R(0);
+        for (int w = 0; w < NW; ++w) sum += red[w];
+        const R cut = (R)f.theta * sum;
+        for (int mi = tid; mi < Mt; mi += NT) {
+            const R v = row0[MN + mi];
+            const bool k = v > R(0) && !(v < cut);
+            row0[MN + mi] = k ? v : R(0);
+            kept[(size_t)rowA * Mt + mi] = k ? 1 : 0;
+        }
+    }
+    if (put_init)
+        for (int mi = tid; mi < Mt; mi += NT) out[slot(rowA) + mi] = row0[MN + mi];
     double *logX = DIR == 0 ? f.logA : f.logB;
     const double lbase =
         (mode != kChainSub && (DIR == 0 ? i0 > 0 : i1 < N)) ? logX[rowA] : 0.0;
@@ -225,6 +250,25 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     int m2 = 0, u1 = 0, u2 = 0;
     bool first = true;
     bool dead = false;
+    // applied decisions of the rows KPF steps ahead, loaded that early so
+    // that their latency stays off the step (kq[0] is this step's row)
+    constexpr int KPF = 4;
+    uint32_t kq[KPF][SPL];
+    auto krow = [&](int g) { return DIR == 0 ? i0 + g + 1 : i1 - 1 - g; };   // row of step g
+    auto kload = [&](uint32_t(&dst)[SPL], int g) {
+        const int r = krow(g);
+        const bool in = g < NS;
+#pragma unroll
+        for (int j = 0; j < SPL; ++j) {
+            const int mi = min(state(j), Mt - 1);
+            dst[j] = in ? kept[(size_t)(in ? r : 0) * Mt + mi] : 0u;
+        }
+    };
+    if (pr && !decide) {
+#pragma unroll
+        for (int d = 0; d < KPF; ++d) kload(kq[d], d);
+    }
+    int gs = 0;   // steps done
     for (int k = 0; k < nchunks && !dead; ++k) {
         if (k >= 1) {
             const int b = new_base(k);
@@ -303,6 +347,39 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
                 }
             }
             const int row = DIR == 0 ? i + 1 : i;
+            if (decide) {
+                // the new row's sum (its scale is that of acc), then the
+                // states below theta times it are not pursued
+                R t = R(0);
+#pragma unroll
+                for (int j = 0; j < SPL; ++j) {
+                    const int mi = state(j);
+                    t += (mi >= lo_i && mi <= hi_i) ? acc[j] : R(0);
+                }
+                t = wave_sum_dpp(t);
+                if ((tid & 63) == 0) red[wv] = t;
+                __syncthreads();
+                R sum = R(0);
+#pragma unroll
+                for (int w = 0; w < NW; ++w) sum += red[w];
+                const R cut = (R)f.theta * sum;
+#pragma unroll
+                for (int j = 0; j < SPL; ++j) {
+                    const int mi = state(j);
+                    const bool k = mi >= lo_i && mi <= hi_i && acc[j] > R(0) && !(acc[j] < cut);
+                    acc[j] = k ? acc[j] : R(0);
+                    if (mi < Mt) kept[(size_t)row * Mt + mi] = k ? 1 : 0;
+                }
+            } else if (pr) {
+#pragma unroll
+                for (int j = 0; j < SPL; ++j) acc[j] = kq[0][j] ? acc[j] : R(0);
+#pragma unroll
+                for (int d = 0; d + 1 < KPF; ++d)
+#pragma unroll
+                    for (int j = 0; j < SPL; ++j) kq[d][j] = kq[d + 1][j];
+                kload(kq[KPF - 1], gs + KPF);
+            }
+            ++gs;
             if (ONE) __syncthreads();   // every read of the row is done
             R *nb = nxt + MN;
             const bool st_row = stored(row);

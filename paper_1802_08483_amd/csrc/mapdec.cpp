@@ -29,6 +29,7 @@ struct mapdec_code {
     // drift state limits [mt_lo, mt_hi] and corridor [mn_lo, mn_hi]; M and
     // mn above are the symmetric limits that contain them
     int mt_lo = 0, mt_hi = 0, mn_lo = 0, mn_hi = 0;
+    double theta = 0.0;   // path thresholds (0: none)
 };
 
 namespace {
@@ -90,6 +91,7 @@ struct FrameLayout {
     // and adjoint kernels' general-scheme instance (percol, or a corridor
     // narrower than [-mn, mn])
     bool percol = false, gcol = false, gen = false;
+    bool pruned = false;   // path thresholds (theta > 0)
     int spw = 0, gspw = 0; // column strides of the whole-frame Gamma (checkpointed frames)
     int ring_shape = -1, ring_chunk = 0, ring_cols = 0;   // ring_shape -1: plain chain
     bool app_tiled = false;
@@ -98,7 +100,7 @@ struct FrameLayout {
     int ring_first = -1;                                   // first shape that fits
     size_t off_cw = 0, off_ybits = 0, off_R = 0, off_G = 0, off_alpha = 0, off_beta = 0,
            off_logA = 0, off_logB = 0, off_Zinv = 0, off_Zexp = 0, off_gacc = 0, off_ck = 0,
-           off_ckb = 0, off_Gw = 0, off_gpart = 0;
+           off_ckb = 0, off_Gw = 0, off_gpart = 0, off_kept = 0;
     std::vector<int> gacc_first;   // first [4] partial of each group
     int gacc_n = 0;
     int dq = 0, dsplit = 1;        // codewords per lattice / adjoint item, items per block
@@ -155,10 +157,12 @@ struct Pass {
     std::map<int, size_t> off_gsum;
     std::map<int, std::vector<Work>> gamma;                         // mn
     std::map<int, size_t> off_gamma;
-    std::vector<int> chain_plain;
-    size_t off_chain = 0;
-    std::map<std::pair<int, int>, std::vector<int>> chain_ring;    // (shape, mn)
-    std::map<std::pair<int, int>, size_t> off_chain_ring;
+    // chain lists by (the frames' path thresholds are decided here, so the
+    // forward chains run before the backward ones: 1, else both at once: 0)
+    std::map<int, std::vector<int>> chain_plain;
+    std::map<int, size_t> off_chain;
+    std::map<std::tuple<int, int, int>, std::vector<int>> chain_ring;   // (shape, mn, fwd first)
+    std::map<std::tuple<int, int, int>, size_t> off_chain_ring;
     std::map<std::tuple<int, int, int>, std::vector<Work>> app_tile;   // (td, waves, mn)
     std::map<std::tuple<int, int, int>, size_t> off_app_tile;
     std::vector<Work> app_plain;
@@ -239,7 +243,7 @@ bool ring_fit(int shape, int Mt, int Mn, int n, int mn, bool uniform, size_t tsi
     const size_t roww = (size_t)slots + 2 * mn;
     const size_t rphys = ring_duplicates(slots) ? cols + roww : cols;
     // FP64 rows and wave partials, Gamma ring in the batch precision
-    lds = ((rs.one_row ? 1 : 2) * roww + 2 * rs.nw) * sizeof(double) + rphys * Mn * tsize;
+    lds = ((rs.one_row ? 1 : 2) * roww + 3 * rs.nw) * sizeof(double) + rphys * Mn * tsize;
     return lds <= lds_limit;
 }
 
@@ -308,6 +312,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         F.percol = c->ncb > 1;
         F.gcol = F.percol || fr.prior != nullptr;
         F.gen = F.percol || c->mn_lo != -c->mn || c->mn_hi != c->mn;
+        F.pruned = c->theta > 0.0;
         if (F.percol && (long long)fr.N * F.Mt + 64 > (1LL << 31)) return MAPDEC_EUNSUPPORTED;
         if (ckK > 0 && ckK < fr.N) {
             F.ck = ckK;
@@ -564,10 +569,13 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             const int d = ch.second;   // descriptor
             const int f = d < nframes ? d : P.sub_frame[d - nframes];
             const FrameLayout &F = L.fl[f];
+            // a forward chain over the frame decides the path thresholds
+            // that the backward chain applies
+            const int seq = (frames[f].code->theta > 0.0 && d < nframes) ? 1 : 0;
             if (F.ring_shape >= 0)
-                P.chain_ring[std::make_pair(F.ring_shape, frames[f].code->mn)].push_back(d);
+                P.chain_ring[std::make_tuple(F.ring_shape, frames[f].code->mn, seq)].push_back(d);
             else
-                P.chain_plain.push_back(d);
+                P.chain_plain[seq].push_back(d);
         }
         // items of one slice contiguous (slice order); neighbouring items
         // share rows (APP, W) or received columns (Gamma): keep them on one
@@ -603,7 +611,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                 return sa != sb ? sa < sb : (a >= nframes) < (b >= nframes);
             });
         };
-        chains_by_slice(P.chain_plain);
+        for (auto &kv : P.chain_plain) chains_by_slice(kv.second);
         for (auto &kv : P.chain_ring) chains_by_slice(kv.second);
     }
 
@@ -631,8 +639,10 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         place(P.app_tile, P.off_app_tile);
         P.off_app = off;
         off += sizeof(Work) * P.app_plain.size();
-        P.off_chain = off;
-        off += sizeof(int) * P.chain_plain.size();
+        for (auto &kv : P.chain_plain) {
+            P.off_chain[kv.first] = off;
+            off += sizeof(int) * kv.second.size();
+        }
         for (auto &kv : P.chain_ring) {
             P.off_chain_ring[kv.first] = off;
             off += sizeof(int) * kv.second.size();
@@ -681,6 +691,10 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         off = align_up(off + sizeof(int) * fr.N);
         F.off_gacc = off;   // the partials, then one slot for the boundary-drift means
         off = align_up(off + sizeof(double) * 4 * ((size_t)F.gacc_n + 1));
+        if (F.pruned) {
+            F.off_kept = off;    // the states the thresholds kept, a byte per (row, state)
+            off = align_up(off + (size_t)(fr.N + 1) * F.Mt);
+        }
         if (F.ck) {
             F.off_ck = off;      // alpha rows 0, ck, 2 ck, .. (row j ck at index j)
             off = align_up(off + sizeof(double) * (size_t)(F.nck + 1) * F.Mt);
@@ -916,20 +930,26 @@ struct mapdec_plan {
                 const Segment g = segment_of(frames_[f], F, std::min(P.seg, F.nseg - 1));
                 return (long long)(g.i1 - g.i0);
             };
-            if (!P.chain_plain.empty()) {
+            // lists whose forward chains decide path thresholds: the forward
+            // launch, then the backward one (ordered through their frames)
+            for (auto &kv : P.chain_plain) {
                 const size_t lds = L.chain_lds;
-                add_chains(P.chain_plain, P.off_chain, steps(P.chain_plain.front()),
-                           [=](hipStream_t st, const int *tab, int nc) {
-                               return launch_chain(fp64, fd, tab, nc, dirs, lds, st);
-                           });
+                for (int dd : kv.first ? std::vector<int>{kDirFwd, kDirBwd} : std::vector<int>{dirs})
+                    add_chains(kv.second, P.off_chain.at(kv.first), steps(kv.second.front()),
+                               [=](hipStream_t st, const int *tab, int nc) {
+                                   return launch_chain(fp64, fd, tab, nc, dd, lds, st);
+                               });
             }
             for (auto &kv : P.chain_ring) {
-                const int shape = kv.first.first, mn = kv.first.second;
-                const size_t lds = L.ring_lds.at(kv.first);
-                add_chains(kv.second, P.off_chain_ring.at(kv.first), steps(kv.second.front()),
-                           [=](hipStream_t st, const int *tab, int nc) {
-                               return launch_chain_ring(fp64, shape, mn, fd, tab, nc, dirs, lds, st);
-                           });
+                const int shape = std::get<0>(kv.first), mn = std::get<1>(kv.first);
+                const size_t lds = L.ring_lds.at(std::make_pair(shape, mn));
+                for (int dd : std::get<2>(kv.first) ? std::vector<int>{kDirFwd, kDirBwd}
+                                                   : std::vector<int>{dirs})
+                    add_chains(kv.second, P.off_chain_ring.at(kv.first), steps(kv.second.front()),
+                               [=](hipStream_t st, const int *tab, int nc) {
+                                   return launch_chain_ring(fp64, shape, mn, fd, tab, nc, dd, lds,
+                                                            st);
+                               });
             }
             deal();
             if (P.kind != kPassMain) continue;
@@ -1143,6 +1163,20 @@ mapdec_code *mapdec_create_general(int q, int n, int ncb, const uint8_t *codeboo
     return c;
 }
 
+mapdec_code *mapdec_with_threshold(const mapdec_code *code, double theta) {
+    if (!code || !(theta >= 0.0) || !(theta < 1.0)) {
+        fail(MAPDEC_EINVAL);
+        return nullptr;
+    }
+    mapdec_code *c = new (std::nothrow) mapdec_code(*code);
+    if (!c) {
+        fail(MAPDEC_ENOMEM);
+        return nullptr;
+    }
+    c->theta = theta;
+    return c;
+}
+
 void mapdec_destroy(mapdec_code *code) { delete code; }
 
 size_t mapdec_workspace_size(const mapdec_frame *frames, int nframes, int precision, int flags,
@@ -1235,6 +1269,8 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
             d.cwi = F.percol ? c->q : 0;
             d.lim_lo = c->mt_lo;
             d.lim_hi = c->mt_hi;
+            d.theta = c->theta;
+            d.kept = F.pruned ? base + F.off_kept : nullptr;
             d.cmask = 0;
             for (int k = 0; k < F.Mn; ++k)
                 if (k - c->mn >= c->mn_lo && k - c->mn <= c->mn_hi) d.cmask |= 1u << k;
@@ -1312,9 +1348,9 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
         for (auto &kv : P.gamma)
             std::memcpy(stage.data() + P.off_gamma.at(kv.first), kv.second.data(),
                         sizeof(Work) * kv.second.size());
-        if (!P.chain_plain.empty())
-            std::memcpy(stage.data() + P.off_chain, P.chain_plain.data(),
-                        sizeof(int) * P.chain_plain.size());
+        for (auto &kv : P.chain_plain)
+            std::memcpy(stage.data() + P.off_chain.at(kv.first), kv.second.data(),
+                        sizeof(int) * kv.second.size());
         for (auto &kv : P.chain_ring)
             std::memcpy(stage.data() + P.off_chain_ring.at(kv.first), kv.second.data(),
                         sizeof(int) * kv.second.size());
@@ -1394,7 +1430,8 @@ int tune_plan(mapdec_plan *t, hipStream_t s) {
             const FrameLayout &F = L.fl[f];
             if (F.app_tiled && !T.app.count(F.app_bucket)) app_b[F.app_bucket].push_back(f);
             // (checkpointed frames' main-pass descriptors hold no whole chain)
-            if (F.ring_first >= 0 && !F.ck && !T.ring.count(F.ring_bucket))
+            if (F.ring_first >= 0 && !F.ck && !F.pruned &&
+                !T.ring.count(F.ring_bucket))
                 ring_b[F.ring_bucket].push_back(f);
         }
     }

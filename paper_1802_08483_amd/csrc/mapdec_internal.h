@@ -94,6 +94,12 @@ struct FrameDesc {
     // [m_n^-, m_n^+] inside [-mn, mn]).
     int percol, cwi, lim_lo, lim_hi;
     uint32_t cmask;
+    // Path thresholds (theta > 0): the forward chain over the frame drops
+    // every state whose metric is below theta times its row's sum and
+    // records which states it kept in kept ([N+1][Mt] bytes, frame rows);
+    // backward chains and recomputations zero the states it dropped.
+    double theta;
+    uint8_t *kept;
     const double *start_prior;  // [Mt] prior of the frame's start drift, or NULL
     const double *end_prior;  // [Mt] prior of the frame's end drift, or NULL
                               // (known end drift rho - tau): log P(y) takes

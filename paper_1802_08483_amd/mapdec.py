@@ -28,7 +28,7 @@ EXPORTS = ["mapdec_create", "mapdec_destroy", "mapdec_workspace_size", "mapdec_d
            "mapdec_tune_entries",
            "mapdec_tune_reset", "mapdec_last_error",
            "mapdec_strerror", "mapdec_version", "mapdec_decode_noalloc",
-           "mapdec_noalloc_limit", "mapdec_create_general"]
+           "mapdec_noalloc_limit", "mapdec_create_general", "mapdec_with_threshold"]
 
 
 class MapdecError(RuntimeError):
@@ -62,6 +62,8 @@ def lib() -> ctypes.CDLL:
         L.mapdec_create_general.argtypes = [i32, i32, i32, vp, dbl, dbl, dbl, i32, i32, i32,
                                             i32, i32]
         L.mapdec_create_general.restype = vp
+        L.mapdec_with_threshold.argtypes = [vp, dbl]
+        L.mapdec_with_threshold.restype = vp
         L.mapdec_destroy.argtypes = [vp]
         L.mapdec_destroy.restype = None
         L.mapdec_workspace_size.argtypes = [fp, i32, i32, i32, i32]
@@ -125,10 +127,11 @@ class Code:
     ``limits`` = (mt_lo, mt_hi, mn_lo, mn_hi) and/or a codebook array of
     shape (N, q, n) (codebook i for symbol i) select the general scheme
     (mapdec_create_general); ``M`` and ``mn`` are then ignored and become
-    max(-mt_lo, mt_hi) and max(-mn_lo, mn_hi)."""
+    max(-mt_lo, mt_hi) and max(-mn_lo, mn_hi).  ``theta`` > 0: path
+    thresholds (mapdec_with_threshold)."""
 
     def __init__(self, codebook, Pi: float, Pd: float, Ps: float, I: int, M: int = 0,
-                 mn: int = 0, limits=None):
+                 mn: int = 0, limits=None, theta: float = 0.0):
         import numpy as np
         cb = np.ascontiguousarray(np.asarray(codebook, dtype=np.uint8))
         if cb.ndim not in (2, 3):
@@ -152,6 +155,13 @@ class Code:
             what = "mapdec_create_general"
         if not self._h:
             raise MapdecError(lib().mapdec_last_error(), what)
+        self.theta = float(theta)
+        if self.theta:
+            h = lib().mapdec_with_threshold(self._h, self.theta)
+            lib().mapdec_destroy(self._h)
+            self._h = h
+            if not self._h:
+                raise MapdecError(lib().mapdec_last_error(), "mapdec_with_threshold")
 
     @property
     def handle(self) -> int:
@@ -340,11 +350,13 @@ def code_for(frame, cache: Optional[dict] = None) -> Code:
     cbs = getattr(frame, "codebooks", None)
     cb = frame.codebook if cbs is None else cbs
     lim = getattr(frame, "limits", None)
+    theta = getattr(frame, "theta", 0.0) or 0.0
     key = (cb.tobytes(), cb.shape, frame.Pi, frame.Pd, frame.Ps, frame.I, frame.M, frame.mn,
-           lim)
+           lim, theta)
     if cache is not None and key in cache:
         return cache[key]
-    c = Code(cb, frame.Pi, frame.Pd, frame.Ps, frame.I, frame.M, frame.mn, limits=lim)
+    c = Code(cb, frame.Pi, frame.Pd, frame.Ps, frame.I, frame.M, frame.mn, limits=lim,
+             theta=theta)
     if cache is not None:
         cache[key] = c
     return c

@@ -62,6 +62,8 @@ class Frame:
     # are then max(-mt_lo, mt_hi) and max(-mn_lo, mn_hi)
     codebooks: Optional[np.ndarray] = None
     limits: Optional[tuple] = None
+    # path thresholds of the decoder (0: none)
+    theta: float = 0.0
 
     @property
     def tau(self) -> int:

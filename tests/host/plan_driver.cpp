@@ -59,6 +59,11 @@ int main(int argc, char **argv) {
         } else {
             c = mapdec_create(q, n, cb.data(), p, p, 0.01, 2, M, mn);
         }
+        if (mode == 2 && f % 4 == 1) {   // path thresholds
+            mapdec_code *t = mapdec_with_threshold(c, 1e-9);
+            mapdec_destroy(c);
+            c = t;
+        }
         if (!c) {
             printf("create failed: %s\n", mapdec_strerror(mapdec_last_error()));
             return 1;

@@ -40,7 +40,7 @@ def test_exports_every_declared_symbol(L):
     assert set(declared) == set(mapdec.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
-    assert L.mapdec_version() == 105
+    assert L.mapdec_version() == 106
     for st in range(8):
         assert L.mapdec_strerror(st)
 
