@@ -131,6 +131,15 @@ def phase_flops(frames, K=0):
 
 PHASE_KERNEL = {"lattice": "k_lattice", "gamma": "k_gamma", "chain": "k_chain_ring",
                 "app": "k_app_tile", "wgrad": "k_wadj", "adjoint": "k_adjoint"}
+# FP32 frames with one codebook, 16 < q <= 64 and 2M+1 <= 2048 take the APP
+# on the matrix units: per pass k_app_scale, k_app_mfma and k_app_fin, one
+# launch each per configuration.
+APP_MFMA_KERNELS = "k_app_scale+k_app_mfma+k_app_fin"
+
+
+def app_on_mfma(frames, fp64):
+    return not fp64 and all(16 < fr.q <= 64 and getattr(fr, "codebooks", None) is None
+                            and 2 * fr.M + 1 <= 2048 for fr in frames)
 
 
 def measured_traffic(kernel, workload):
@@ -173,10 +182,12 @@ def time_plan(plan, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps
 
 
-def roofline_of(plan, frames, K, steps, workload, precision_peak):
+def roofline_of(plan, frames, K, steps, workload, precision_peak, fp64=False):
     """Per-phase launch times (HIP events on each launch's stream, summed
     per phase, averaged over ``steps`` eager passes of the plan) and the
-    roofline of the phase that takes longest."""
+    roofline of the phase that takes longest.  An APP on the matrix units
+    is priced against the FP32 matrix peak, its three kernels' launches
+    counted as one."""
     acc = {}
     reps = max(1, steps)
     for _ in range(reps):
@@ -190,12 +201,15 @@ def roofline_of(plan, frames, K, steps, workload, precision_peak):
     dom = max((k for k in alg if alg[k] > 0 and k != "chain"),
               key=lambda k: phases.get(k, 0.0))
     nl = max(1, nlaunch.get(dom, 1))
+    kernel, bound = PHASE_KERNEL[dom], "alu"
+    if dom == "app" and app_on_mfma(frames, fp64):
+        kernel, bound, nl = APP_MFMA_KERNELS, "mfma", max(1, nl // 3)
     ms = phases[dom]
     achieved = alg[dom] / (ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": precision_peak,
+    roof = {"bound": bound, "achieved": round(achieved, 3), "peak": precision_peak,
             "unit": "TFLOP/s", "frac": round(achieved / precision_peak, 4),
-            "traffic": measured_traffic(PHASE_KERNEL[dom], workload),
-            "kernel": PHASE_KERNEL[dom], "launches_per_step": nl,
+            "traffic": measured_traffic(kernel, workload),
+            "kernel": kernel, "launches_per_step": nl,
             "flops_per_launch": alg[dom] / nl, "launch_ms": round(ms / nl, 5),
             "recompute_flops_per_launch": extra.get(dom, 0.0) / nl,
             "measured_in": "HIP events around every launch on its stream, one eager pass "

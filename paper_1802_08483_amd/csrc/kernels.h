@@ -92,6 +92,23 @@ constexpr size_t adjoint_lds(int nmax, int mn, size_t tsize) {
 inline bool adjoint_needs_da(double Pi, double Pd) { return !(Pi > 0.0) || 4.0 * Pi < Pd; }
 hipError_t launch_dparams(const FrameDesc *fd, int nframes, hipStream_t st);
 
+// APP on the MFMA units (k_app_mfma.hip; FP32, one codebook, q <= 64):
+// k_app_scale (one item per symbol: the exponent scale E_i into Zexp), then
+// k_app_mfma (item b * parts + p: part p of the span of the block b of
+// kMfmaTB symbols; qt = D tiles of 32) writing partial sums to Up, then
+// k_app_fin (item b: adds the parts, then eqs. 2-3).
+constexpr int kMfmaTB = 64;
+constexpr int kMfmaPartsMax = 8;
+constexpr int kMfmaCS = 32;         // start-index columns per chunk of a block's span
+constexpr int kMfmaMinChunks = 8;   // fewest chunks a part covers
+hipError_t launch_app_scale(int mn, const FrameDesc *fd, const Work *tab, int nitems,
+                            hipStream_t st);
+hipError_t launch_app_mfma(int mn, int qt, const FrameDesc *fd, const Work *tab, int nitems,
+                           size_t lds, hipStream_t st);
+hipError_t launch_app_fin(int qt, const FrameDesc *fd, const Work *tab, int nblocks,
+                          hipStream_t st);
+size_t app_mfma_lds(int mn, int q);
+
 // The fixed device array of the allocation-free decode (scratch.hip): its
 // size, and its address on the current device (taken once per device).
 size_t scratch_bytes();

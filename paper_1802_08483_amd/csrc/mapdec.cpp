@@ -92,6 +92,9 @@ struct FrameLayout {
     // narrower than [-mn, mn])
     bool percol = false, gcol = false, gen = false;
     bool pruned = false;   // path thresholds (theta > 0)
+    bool app_mfma = false; // the APP on the MFMA units
+    int app_parts = 1;     // its parts per block of kMfmaTB symbols
+    size_t off_up = 0;     // its partial sums
     int spw = 0, gspw = 0; // column strides of the whole-frame Gamma (checkpointed frames)
     int ring_shape = -1, ring_chunk = 0, ring_cols = 0;   // ring_shape -1: plain chain
     bool app_tiled = false;
@@ -167,6 +170,14 @@ struct Pass {
     std::map<std::tuple<int, int, int>, size_t> off_app_tile;
     std::vector<Work> app_plain;
     size_t off_app = 0;
+    // the APP on the MFMA units: the scale items (one per symbol) by mn,
+    // the blocks of kMfmaTB symbols by (mn, D tiles)
+    std::map<int, std::vector<Work>> app_scale;
+    std::map<int, size_t> off_app_scale;
+    std::map<std::pair<int, int>, std::vector<Work>> app_mfma;
+    std::map<std::pair<int, int>, size_t> off_app_mfma;
+    std::map<int, std::vector<Work>> app_fin;   // by D tiles: one item per block
+    std::map<int, size_t> off_app_fin;
     std::map<std::tuple<int, int, int, int>, std::vector<Work>> adj;   // (mn, imode, d/da, gen)
     std::map<std::tuple<int, int, int, int>, size_t> off_adj;
 };
@@ -184,6 +195,7 @@ struct Layout {
     size_t chain_lds = 0, app_lds = 0;
     std::map<std::pair<int, int>, size_t> ring_lds;
     std::map<std::tuple<int, int, int>, size_t> app_tile_lds;
+    std::map<std::pair<int, int>, size_t> app_mfma_lds;   // (mn, D tiles)
     std::map<std::tuple<int, int, int, int>, size_t> adj_lds;
     std::vector<FrameLayout> fl;
 };
@@ -282,6 +294,23 @@ size_t device_lds_limit() {
     return cached;
 }
 
+// Compute units of the current device (256 when it cannot be queried).
+int device_cu_count() {
+    static thread_local int cached_dev = -1;
+    static thread_local int cached = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (dev != cached_dev) {
+        int v = 0;
+        cached = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) ==
+                         hipSuccess && v > 0
+                     ? v
+                     : 256;
+        cached_dev = dev;
+    }
+    return cached;
+}
+
 // Validates the frames and lays out the workspace.  ckK > 0 splits every
 // frame into segments of ckK symbols with forward-metric checkpoints.
 int build_layout(const mapdec_frame *frames, int nframes, int precision, int flags, int ckK,
@@ -346,7 +375,17 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             // shares each R column among the symbols of a tile (one codebook)
             const bool fits = (double)c->q * F.Mn * F.sp * L.tsize < 2147483648.0;
             F.app_tiled = fits && tl <= lds_limit && !F.percol;
-            if (F.app_tiled) {
+            // FP32 with one codebook and 16 < q <= 64: the matrix-unit form of
+            // the same sums (at q <= 16 half of every 32-wide D tile would
+            // be idle, and the tile kernel is the faster one)
+            F.app_mfma = !L.fp64 && !F.percol && c->q > 16 && c->q <= 64 && F.Mt <= 2048 &&
+                         app_mfma_lds(c->mn, c->q) <= lds_limit;
+            if (F.app_mfma) {
+                F.app_tiled = false;
+                const auto mk = std::make_pair(c->mn, (c->q + 31) / 32);
+                L.app_mfma_lds[mk] = std::max(L.app_mfma_lds[mk], app_mfma_lds(c->mn, c->q));
+            }
+            if (F.app_tiled && !F.app_mfma) {
                 F.app_bucket = TuneKey{L.fp64, c->q, c->n, c->mn, nw};
                 size_t lds = tl;
                 {
@@ -365,7 +404,7 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                 }
                 F.app_key = std::make_tuple(td, nw, c->mn);
                 L.app_tile_lds[F.app_key] = std::max(L.app_tile_lds[F.app_key], lds);
-            } else {
+            } else if (!F.app_mfma) {
                 L.app_lds = std::max(L.app_lds, (2 * (size_t)F.Mt + 2 * c->mn + c->q) * sizeof(double));
             }
         }
@@ -430,6 +469,31 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             for (int j = 0; j < F.nseg; ++j) {
                 F.gacc_first[j] = F.gacc_n;
                 F.gacc_n += blocks_of(F, segment_of(frames[f], F, j)) * F.dsplit;
+            }
+        }
+    }
+
+    // APP on the MFMA units: when one pass has too few blocks of kMfmaTB
+    // symbols to give each workgroup slot of the device one (two per compute
+    // unit), the span of every block is split into parts of at least
+    // kMfmaMinChunks chunks, whose partial sums k_app_fin adds.
+    {
+        long long blocks = 0;
+        for (int f = 0; f < nframes; ++f)
+            if (L.fl[f].app_mfma) {
+                const Segment g = segment_of(frames[f], L.fl[f], 0);
+                blocks += (g.i1 - g.i0 + kMfmaTB - 1) / kMfmaTB;
+            }
+        if (blocks > 0) {
+            const long long slots = 2LL * device_cu_count();
+            const int parts = (int)std::max<long long>(
+                1, std::min<long long>(kMfmaPartsMax, slots / blocks));
+            for (int f = 0; f < nframes; ++f) {
+                FrameLayout &F = L.fl[f];
+                if (!F.app_mfma) continue;
+                const mapdec_code *c = frames[f].code;
+                const int nch = (c->n * (kMfmaTB - 1) + F.Mt + kMfmaCS - 1) / kMfmaCS;
+                F.app_parts = std::max(1, std::min(parts, nch / kMfmaMinChunks));
             }
         }
     }
@@ -547,7 +611,17 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                 }
                 chains.push_back(std::make_pair(g.i1 - g.i0, f));
             }
-            if (F.app_tiled) {
+            if (F.app_mfma) {
+                auto &sv = P.app_scale[c->mn];
+                for (int i = g.i0; i < g.i1; ++i) sv.push_back(Work{f, i - g.i0});
+                const int qt = (c->q + 31) / 32;
+                auto &v = P.app_mfma[std::make_pair(c->mn, qt)];
+                auto &fv = P.app_fin[qt];
+                for (int b = 0; b * kMfmaTB < g.i1 - g.i0; ++b) {
+                    for (int p = 0; p < F.app_parts; ++p) v.push_back(Work{f, b * F.app_parts + p});
+                    fv.push_back(Work{f, b});
+                }
+            } else if (F.app_tiled) {
                 auto &v = P.app_tile[F.app_key];
                 for (int b = 0; b * kAppTI < g.i1 - g.i0; ++b) v.push_back(Work{f, b});
             } else {
@@ -596,6 +670,9 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             }
         };
         for (auto &kv : P.app_tile) by_slice(kv.second, true);
+        for (auto &kv : P.app_scale) by_slice(kv.second, false);
+        for (auto &kv : P.app_mfma) by_slice(kv.second, true);
+        for (auto &kv : P.app_fin) by_slice(kv.second, false);
         for (auto &kv : P.lat) by_slice(kv.second, true);
         for (auto &kv : P.wlat) by_slice(kv.second, true);
         for (auto &kv : P.gsum) by_slice(kv.second, true);
@@ -637,6 +714,9 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         place(P.adj, P.off_adj);
         place(P.gamma, P.off_gamma);
         place(P.app_tile, P.off_app_tile);
+        place(P.app_scale, P.off_app_scale);
+        place(P.app_mfma, P.off_app_mfma);
+        place(P.app_fin, P.off_app_fin);
         P.off_app = off;
         off += sizeof(Work) * P.app_plain.size();
         for (auto &kv : P.chain_plain) {
@@ -689,6 +769,13 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         off = align_up(off + sizeof(double) * fr.N);
         F.off_Zexp = off;
         off = align_up(off + sizeof(int) * fr.N);
+        if (F.app_mfma) {
+            // the partial sums of the blocks of the longest segment
+            const int nb = (std::min(F.K, fr.N) + kMfmaTB - 1) / kMfmaTB;
+            F.off_up = off;
+            off = align_up(off + sizeof(float) * (size_t)nb * F.app_parts * kMfmaTB * 32 *
+                                     ((c->q + 31) / 32));
+        }
         F.off_gacc = off;   // the partials, then one slot for the boundary-drift means
         off = align_up(off + sizeof(double) * 4 * ((size_t)F.gacc_n + 1));
         if (F.pruned) {
@@ -958,6 +1045,30 @@ struct mapdec_plan {
                 add_work(kPhApp, true, P.app_plain, P.off_app,
                          [=](hipStream_t st, const Work *tab, int nb) {
                              return launch_app(fp64, fd, tab, nb, lds, st);
+                         });
+            }
+            for (auto &kv : P.app_scale) {
+                const int mn = kv.first;
+                add_work(kPhApp, true, kv.second, P.off_app_scale.at(kv.first),
+                         [=](hipStream_t st, const Work *tab, int nb) {
+                             return launch_app_scale(mn, fd, tab, nb, st);
+                         });
+            }
+            deal();
+            for (auto &kv : P.app_mfma) {
+                const int mn = kv.first.first, qt = kv.first.second;
+                const size_t lds = L.app_mfma_lds.at(kv.first);
+                add_work(kPhApp, true, kv.second, P.off_app_mfma.at(kv.first),
+                         [=](hipStream_t st, const Work *tab, int nb) {
+                             return launch_app_mfma(mn, qt, fd, tab, nb, lds, st);
+                         });
+            }
+            if (!P.app_fin.empty()) deal();
+            for (auto &kv : P.app_fin) {
+                const int qt = kv.first;
+                add_work(kPhApp, true, kv.second, P.off_app_fin.at(kv.first),
+                         [=](hipStream_t st, const Work *tab, int nb) {
+                             return launch_app_fin(qt, fd, tab, nb, st);
                          });
             }
             for (auto &kv : P.app_tile) {
@@ -1249,7 +1360,10 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
             d.logA = reinterpret_cast<double *>(base + F.off_logA);
             d.logB = reinterpret_cast<double *>(base + F.off_logB);
             d.Zinv = L.grad ? reinterpret_cast<double *>(base + F.off_Zinv) : nullptr;
-            d.Zexp = L.grad ? reinterpret_cast<int *>(base + F.off_Zexp) : nullptr;
+            // (the MFMA APP keeps its exponent scales there in every plan)
+            d.Zexp = (L.grad || F.app_mfma) ? reinterpret_cast<int *>(base + F.off_Zexp) : nullptr;
+            d.Up = F.app_mfma ? reinterpret_cast<float *>(base + F.off_up) : nullptr;
+            d.app_parts = F.app_parts;
             d.gacc_all = reinterpret_cast<double *>(base + F.off_gacc);
             d.gacc_n = F.gacc_n;
             d.dq = F.dq;
@@ -1360,6 +1474,15 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
         if (!P.app_plain.empty())
             std::memcpy(stage.data() + P.off_app, P.app_plain.data(),
                         sizeof(Work) * P.app_plain.size());
+        for (auto &kv : P.app_scale)
+            std::memcpy(stage.data() + P.off_app_scale.at(kv.first), kv.second.data(),
+                        sizeof(Work) * kv.second.size());
+        for (auto &kv : P.app_mfma)
+            std::memcpy(stage.data() + P.off_app_mfma.at(kv.first), kv.second.data(),
+                        sizeof(Work) * kv.second.size());
+        for (auto &kv : P.app_fin)
+            std::memcpy(stage.data() + P.off_app_fin.at(kv.first), kv.second.data(),
+                        sizeof(Work) * kv.second.size());
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(p->ws, stage.data(), L.head, hipMemcpyHostToDevice, s);

@@ -49,6 +49,9 @@ struct FrameDesc {
     double *logB;         // [N+1] log of the product of backward normalisers
     double *Zinv;         // [N] 1 / Z_i' with Z_i = 2^Zexp[i] Z_i' (gradient passes)
     int *Zexp;            // [N] binary exponent of the APP's row-product scale
+    float *Up;            // APP on the MFMA units: [blocks][parts][64][32 D-tiles]
+                          // partial sums U of each part of a block's span
+    int app_parts;        // parts per block of that APP (1 .. kMfmaPartsMax)
     double *gacc;         // [lattice workgroups of this segment][4] partial
                           // d log P / d(a, d, t1, t0)
     double *gacc_all;     // every segment's partials of the frame, contiguous,

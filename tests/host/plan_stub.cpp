@@ -148,8 +148,8 @@ hipError_t hipGetDevice(int *d) {
     *d = 0;
     return hipSuccess;
 }
-hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t, int) {
-    *v = 160 * 1024;
+hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t a, int) {
+    *v = a == hipDeviceAttributeMultiprocessorCount ? 256 : 160 * 1024;
     return hipSuccess;
 }
 hipError_t hipEventCreate(hipEvent_t *e) {
@@ -319,6 +319,32 @@ hipError_t launch_app_tile(int fp64, int td, int, int nw, const FrameDesc *fd, c
     if (nw < 1 || nw > kAppMaxWaves || lds > 160 * 1024) die("bad tiled-APP launch");
     launch(st, work_frames(t, nb), false);
     return hipSuccess;
+}
+hipError_t launch_app_scale(int mn, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
+    check_fd(fd);
+    if (mn < 0 || mn > kMaxMn) die("bad APP-scale launch");
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
+hipError_t launch_app_mfma(int mn, int qt, const FrameDesc *fd, const Work *t, int nb,
+                           size_t lds, hipStream_t st) {
+    check_fd(fd);
+    if (mn < 0 || mn > kMaxMn || qt < 1 || qt > 2 || lds > 160 * 1024)
+        die("bad MFMA-APP launch");
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
+hipError_t launch_app_fin(int qt, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
+    check_fd(fd);
+    if (qt < 1 || qt > 2) die("bad APP-finish launch");
+    launch(st, work_frames(t, nb), false);
+    return hipSuccess;
+}
+size_t app_mfma_lds(int mn, int q) {
+    const int QT = (q + 31) / 32;
+    const size_t stage = (size_t)2 * 32 * QT * 33 * 4 + 64 * 33 * 8 + 64 * ((32 + 2 * mn) | 1) * 8;
+    const size_t epi = (size_t)4 * 32 * 32 * QT * 4;
+    return stage > epi ? stage : epi;
 }
 hipError_t adj_f32_w(int, int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
