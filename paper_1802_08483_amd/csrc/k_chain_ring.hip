@@ -50,7 +50,9 @@
 // (threads read with a stride of Mn words, which is odd: no bank conflicts).
 // For small state spaces the slots near both ends are duplicated past the
 // ends, so one step's reads never wrap and every read is a base register
-// plus a compile-time offset; large state spaces index the ring modulo RING.
+// plus a compile-time offset; large state spaces mask one base slot per
+// state and step and repeat the ring's first 2 mn slots past its end, so
+// their reads are a base plus compile-time offsets too.
 // The n C columns the next chunk adds are loaded into registers one chunk
 // ahead and written to the ring when that chunk starts, so global-memory
 // latency overlaps a whole chunk of steps.
@@ -90,7 +92,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     const int s0 = uni ? f.s0 : Mt * i0;
     const int s1 = uni ? f.s1 : Mt * i1 - 1;
     const int C = f.ring_chunk, RING = f.ring_cols, mask = RING - 1;
-    const int RPHYS = DUP ? RING + NT * SPL + 2 * MN : RING;
+    const int RPHYS = DUP ? RING + NT * SPL + 2 * MN : RING + 2 * MN;
     using R = double;                                  // metric rows: FP64 always
     R *row0 = (R *)smem;
     R *row1 = ONE ? row0 : row0 + ROWW;
@@ -178,6 +180,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             if (L >= RING - MN) ring[(L - RING + MN) * Mn + kk] = v;
         } else {
             ring[L * Mn + kk] = v;
+            if (L < 2 * MN) ring[(L + RING) * Mn + kk] = v;
         }
     };
 
@@ -298,10 +301,22 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             lexp += e;
             const int sb = (n * i - MC) & mask;
             const R *cb = cur + MN;
+            // ring slot of the thread's state j at drift change x - MN: forward
+            // (column sb + state - x + MN) gb[j] + 2 mn - x, backward (column
+            // sb + state) gb[j]; without the duplicated ring the base is
+            // masked once per state and the first 2 mn slots are repeated past
+            // the end, so every read is the base plus a compile-time offset
+            int gb[SPL];
+#pragma unroll
+            for (int j = 0; j < SPL; ++j)
+                gb[j] = DUP ? 0 : (sb + state(j) - (DIR == 0 ? MN : 0)) & mask;
             // Gamma(column, delta) for the thread's state j and drift change x - MN
             auto gam = [&](int j, int x) -> R {
-                const int c = DIR == 0 ? sb + state(j) - (x - MN) : sb + state(j);
-                return (R)(DUP ? ring[(c + MN) * Mn + x] : ring[(c & mask) * Mn + x]);
+                if (DUP) {
+                    const int c = DIR == 0 ? sb + state(j) - (x - MN) : sb + state(j);
+                    return (R)ring[(c + MN) * Mn + x];
+                }
+                return (R)ring[(gb[j] + (DIR == 0 ? 2 * MN - x : 0)) * Mn + x];
             };
             // the row value that meets it
             auto rowv = [&](int j, int x) -> R {

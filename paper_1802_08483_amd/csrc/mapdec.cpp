@@ -253,7 +253,7 @@ bool ring_fit(int shape, int Mt, int Mn, int n, int mn, bool uniform, size_t tsi
     chunk = std::min({(cols - Mt) / n + 1, (nt * ring_prefetch_regs(rs.nw, tsize)) / (n * Mn), 64});
     if (chunk < 1) return false;
     const size_t roww = (size_t)slots + 2 * mn;
-    const size_t rphys = ring_duplicates(slots) ? cols + roww : cols;
+    const size_t rphys = ring_duplicates(slots) ? cols + roww : cols + 2 * mn;
     // FP64 rows and wave partials, Gamma ring in the batch precision
     lds = ((rs.one_row ? 1 : 2) * roww + 3 * rs.nw) * sizeof(double) + rphys * Mn * tsize;
     return lds <= lds_limit;
