@@ -127,9 +127,11 @@ def _code(codebook, Pi, Pd, Ps, I, M, mn):
 
 
 def decode(codebook, y, N, Pi, Pd, Ps, I, M, mn, prior=None, *, start=None, end=None,
-           grad=False, trace=False, literal=False, check=True):
+           grad=False, trace=False, literal=False, check=True, extrinsic=False):
     """Run the oracle on one frame.  Returns a dict with ``status``, ``logp``,
-    ``app`` (N, q) and, on request, ``dparams`` (3,), ``dprior`` (N, q) and
+    ``app`` (N, q) and, on request, ``dparams`` (3,) and ``dprior`` (N, q)
+    (grad), ``dprior`` alone (extrinsic: the inner decoder's output for
+    iterative decoding, without the gradient's tangents) and
     the trace arrays ``alpha``, ``beta`` ((N+1), 2M+1), ``logA``, ``logB``,
     ``logZ``.  ``start`` / ``end``: priors of the frame's start and end
     drift over [-M, M] (entry m + M), or None for the known boundary."""
@@ -148,6 +150,7 @@ def decode(codebook, y, N, Pi, Pd, Ps, I, M, mn, prior=None, *, start=None, end=
     res = {"app": np.zeros((N, q)), "logp": np.zeros(1)}
     if grad:
         res["dparams"] = np.zeros(3)
+    if grad or extrinsic:
         res["dprior"] = np.zeros((N, q))
     if trace:
         res["alpha"] = np.zeros((N + 1, Mt))

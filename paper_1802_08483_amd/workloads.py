@@ -129,12 +129,14 @@ def encode(codebook: np.ndarray, message: np.ndarray) -> np.ndarray:
 
 
 def _draw_frame(ss: np.random.SeedSequence, q, n, N, sim, dec, I, M, mn,
-                codebook=None, with_prior=False) -> Frame:
-    """Draw one frame: codebook (if not given), message, priors, channel."""
+                codebook=None, with_prior=False, message=None) -> Frame:
+    """Draw one frame: codebook (if not given), message (if not given),
+    priors, channel."""
     rng = np.random.Generator(np.random.PCG64(ss))
     if codebook is None:
         codebook = random_codebook(rng, q, n)
-    message = rng.integers(0, q, size=N)
+    drawn = rng.integers(0, q, size=N)
+    message = drawn if message is None else np.asarray(message, dtype=np.int64)
     prior = None
     if with_prior:
         logits = rng.standard_normal((N, q))
@@ -305,3 +307,162 @@ def with_boundary_priors(frames: List[Frame], spread: int = 4) -> List[Frame]:
                 en[fr.M + mN] += w[k]
         out.append(dataclasses.replace(fr, start_drift=st, end_drift=en))
     return out
+
+
+# --------------------------------------------------------------------------
+# Serial concatenation with an outer code (Sec. II-A): the transmitter.
+# The outer code is a linear code over GF(q), q = 2^p (1 <= p <= 6), with a
+# sparse parity-check matrix of repeat-accumulate shape: the first K = N - m
+# symbols carry the information, each in wc random rows; parity symbol r
+# sits in row r and (r < m - 1) row r + 1, so the parity symbols follow one
+# by one from the rows (an accumulator).  GF(2^p): integers 0 .. q-1 as
+# polynomials over GF(2) (bit k = coefficient of z^k) modulo the primitive
+# polynomial _OUTER_PRIM[p]; this module keeps its own exponent and
+# logarithm tables for the encoder.
+# --------------------------------------------------------------------------
+
+_OUTER_PRIM = {1: 0b11, 2: 0b111, 3: 0b1011, 4: 0b10011, 5: 0b100101, 6: 0b1000011}
+
+
+@dataclasses.dataclass
+class OuterSpec:
+    """Parity-check matrix of an outer code over GF(q): row c holds the
+    symbols col[row_ptr[c]:row_ptr[c+1]] with coefficients coef[...] in
+    1 .. q-1; ``info`` the K information symbols, ``codeword`` the N
+    transmitted symbols (H codeword = 0)."""
+    q: int
+    N: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+    coef: np.ndarray
+    info: np.ndarray
+    codeword: np.ndarray
+
+
+def _gf_exp_log(q: int):
+    p = q.bit_length() - 1
+    if q < 2 or (1 << p) != q or p not in _OUTER_PRIM:
+        raise ValueError("outer alphabet must be 2^p, 1 <= p <= 6")
+    exp = [0] * (2 * q)
+    log = [0] * q
+    e = 1
+    for k in range(q - 1):
+        exp[k] = e
+        log[e] = k
+        e <<= 1
+        if e & q:
+            e ^= _OUTER_PRIM[p]
+    for k in range(q - 1, 2 * q):
+        exp[k] = exp[k - (q - 1)]
+    return exp, log
+
+
+def outer_code(rng: np.random.Generator, q: int, N: int, checks: int, wc: int = 3) -> OuterSpec:
+    """A random repeat-accumulate outer code with ``checks`` rows over
+    GF(q), and one of its codewords for random information symbols."""
+    m, K = int(checks), int(N) - int(checks)
+    if m < 1 or K < 0 or (K > 0 and wc > m):
+        raise ValueError("need 1 <= checks <= N and wc <= checks")
+    exp, log = _gf_exp_log(q)
+
+    def mul(a, b):
+        return 0 if a == 0 or b == 0 else exp[log[a] + log[b]]
+
+    def inv(a):
+        return exp[(q - 1 - log[a]) % (q - 1)]
+
+    rows = [[] for _ in range(m)]
+    for j in range(K):
+        for r in rng.choice(m, size=wc, replace=False):
+            rows[int(r)].append((j, int(rng.integers(1, q))))
+    for r in range(m):
+        rows[r].append((K + r, int(rng.integers(1, q))))
+        if r > 0:
+            rows[r].append((K + r - 1, int(rng.integers(1, q))))
+    info = rng.integers(0, q, size=K)
+    x = np.zeros(N, dtype=np.int64)
+    x[:K] = info
+    for r in range(m):   # h_{r,K+r} x_{K+r} = sum of the row's other terms
+        acc = 0
+        for j, h in rows[r]:
+            if j != K + r:
+                acc ^= mul(h, int(x[j]))
+        h_own = dict(rows[r])[K + r]
+        x[K + r] = mul(inv(h_own), acc)
+    row_ptr, col, coef = [0], [], []
+    for r in range(m):
+        for j, h in sorted(rows[r]):
+            col.append(j)
+            coef.append(h)
+        row_ptr.append(len(col))
+    for r in range(m):   # every row holds
+        acc = 0
+        for k in range(row_ptr[r], row_ptr[r + 1]):
+            acc ^= mul(coef[k], int(x[col[k]]))
+        assert acc == 0
+    return OuterSpec(q=q, N=N, row_ptr=np.asarray(row_ptr, dtype=np.int32),
+                     col=np.asarray(col, dtype=np.int32), coef=np.asarray(coef, dtype=np.uint8),
+                     info=info, codeword=x)
+
+
+def concatenated_frame(seed: int, q: int, n: int, N: int, Pi: float, Pd: float, Ps: float,
+                       I: int, M: int, mn: int, checks: int, wc: int = 3,
+                       codebook: Optional[np.ndarray] = None):
+    """An outer codeword (``checks`` parity rows) sent through the inner
+    code and the channel: returns (OuterSpec, Frame) with the frame's
+    message the outer codeword and uniform priors."""
+    ss = np.random.SeedSequence([SEED_ROOT, 2000, seed])
+    rng = np.random.Generator(np.random.PCG64(ss.spawn(1)[0]))
+    spec = outer_code(rng, q, N, checks, wc)
+    fr = _draw_frame(ss, q, n, N, (Pi, Pd, Ps), (Pi, Pd, Ps), I, M, mn, codebook=codebook,
+                     message=spec.codeword)
+    return spec, fr
+
+
+CONCAT_NAME = "64 frames q16 n10 N500 outer GF(16) code 250 checks, Pi=Pd=0.06 Ps=0.01"
+
+
+def make_concatenated_workload(nframes: int = 64, first: int = 0):
+    """The iterative-decoding workload: frames of the 256-frame batch's
+    shape (one codebook) carrying codewords of one outer code over GF(16)
+    (rate 1/2, 250 checks, information symbols in 3 checks each), at a
+    channel where the inner decoder alone leaves symbol errors."""
+    ss = np.random.SeedSequence([SEED_ROOT, 3000])
+    cb_rng = np.random.Generator(np.random.PCG64(ss.spawn(1)[0]))
+    codebook = random_codebook(cb_rng, 16, 10)
+    code_rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 3001])))
+    spec = outer_code(code_rng, 16, 500, 250, 3)
+    exp, log = _gf_exp_log(16)
+    frames = []
+    M = drift_limit(5000, 0.06)
+    for f in range(first, first + nframes):
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 3002, f])))
+        # a fresh codeword of the same code: the accumulator again
+        info = rng.integers(0, 16, size=250)
+        x = _encode_with(spec, info, exp, log)
+        frames.append(_draw_frame(np.random.SeedSequence([SEED_ROOT, 3003, f]), 16, 10, 500,
+                                  (0.06, 0.06, 0.01), (0.06, 0.06, 0.01), 2, M, 6,
+                                  codebook=codebook, message=x))
+    return spec, frames
+
+
+def _encode_with(spec: OuterSpec, info: np.ndarray, exp, log) -> np.ndarray:
+    q, N = spec.q, spec.N
+    m = spec.row_ptr.shape[0] - 1
+    K = N - m
+
+    def mul(a, b):
+        return 0 if a == 0 or b == 0 else exp[log[a] + log[b]]
+
+    x = np.zeros(N, dtype=np.int64)
+    x[:K] = info
+    for r in range(m):
+        acc, h_own = 0, None
+        for k in range(spec.row_ptr[r], spec.row_ptr[r + 1]):
+            j, h = int(spec.col[k]), int(spec.coef[k])
+            if j == K + r:
+                h_own = h
+            else:
+                acc ^= mul(h, int(x[j]))
+        x[K + r] = mul(exp[(q - 1 - log[h_own]) % (q - 1)], acc)
+    return x
