@@ -377,6 +377,52 @@ def line_general(mapdec, workloads, torch, steps, warmup):
                        "launches": nl}
 
 
+def line_iterative(mapdec, workloads, torch, steps, warmup, passes=3, bp_iters=8):
+    """Iterative decoding with the outer code (Sec. II-A): a step is the
+    whole decoding of the batch, ``passes`` times (the inner FP32 decode as
+    one HIP graph, then ``bp_iters`` iterations of belief propagation),
+    from uniform priors."""
+    import numpy as np
+    spec, frames = workloads.make_concatenated_workload()
+    syms = sum(fr.N for fr in frames)
+    it = mapdec.iterative_from_frames(frames, spec, precision=mapdec.FP32).use_plan()
+
+    class Step:
+        def run(self):
+            it.reset()
+            it.run(passes, bp_iters)
+
+    ms = time_plan(Step(), steps, warmup, torch)
+    # time of the parts: one inner pass (graph), one outer decode
+    ms_inner = time_plan(it.plan, steps, 1, torch)
+
+    class Outer:
+        def run(self):
+            it.outer.decode(it.chan, it.prior, it.post, bp_iters, it.ws)
+
+    ms_outer = time_plan(Outer(), steps, 1, torch)
+    Step().run()
+    torch.cuda.synchronize()
+    Q = it.post.double().cpu().numpy()
+    msg = np.stack([fr.message for fr in frames])
+    errs = int((Q.argmax(2) != msg).sum())
+    it.reset()
+    it.run_pass(bp_iters)
+    torch.cuda.synchronize()
+    inner_errs = int((np.stack([a.double().cpu().numpy() for a in it.batch.apps]).argmax(2)
+                      != msg).sum())
+    out = {"workload": workloads.CONCAT_NAME, "step": f"{passes} passes x (inner decode, "
+           f"{bp_iters} BP iterations)", "value": round(syms / (ms * 1e-3), 1),
+           "unit": "symbols/s", "ms_per_step": round(ms, 4), "frames": len(frames),
+           "inner_pass_ms": round(ms_inner, 4), "outer_decode_ms": round(ms_outer, 4),
+           "symbol_errors_inner_alone": inner_errs, "symbol_errors_after": errs,
+           "symbols": syms}
+    it.plan.close()
+    del it
+    torch.cuda.empty_cache()
+    return out
+
+
 def uneven_batch(mapdec, workloads, torch, steps):
     """FP32 decode of the uneven batch (4096 frames, q in {2, 8, 16}, n in
     [4, 10], N in [50, 2000], Pi = Pd log-uniform in [1e-3, 1e-1]): the eager
@@ -422,9 +468,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workloads", default="5,4,2,6,3,1",
+    ap.add_argument("--workloads", default="5,4,2,6,7,3,1",
                     help="comma-separated workloads to run (5 = the headline line; 6 = the "
-                         "general scheme: a codebook per symbol, a narrower corridor)")
+                         "general scheme: a codebook per symbol, a narrower corridor; 7 = "
+                         "iterative decoding with the outer code)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip every oracle comparison (profiling runs)")
@@ -536,6 +583,10 @@ def main():
         lines["general"] = line
         del bg
         torch.cuda.empty_cache()
+
+    if 7 in wanted:
+        lines["iterative"] = line_iterative(mapdec, workloads, torch, max(3, args.steps // 4),
+                                            1)
 
     if 3 in wanted:
         lines["uneven"] = uneven_batch(mapdec, workloads, torch, max(3, args.steps // 4))

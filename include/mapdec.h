@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define MAPDEC_VERSION 106
+#define MAPDEC_VERSION 107
 
 enum {
     MAPDEC_OK = 0,
@@ -151,8 +151,9 @@ void mapdec_destroy(mapdec_code *code);
  *          (float for MAPDEC_FP32, double for MAPDEC_FP64), used as given;
  *          NULL means 1/q for every entry (eq. 6).
  *   app    device, N*q output APPs [i][D] in the same type as prior, or NULL.
- *   dprior device, N*q output d log P(y) / d prior[i][D] (gradient calls
- *          only), same type, or NULL.
+ *   dprior device, N*q output d log P(y) / d prior[i][D] = U_i(D) / Z_i
+ *          (decode and gradient calls; the inner decoder's extrinsic
+ *          output for iterative decoding), same type, or NULL.
  *   start_drift, end_drift
  *          device, 2M+1 doubles each, entry [m + M] the prior probability
  *          that the frame's first codeword starts at received bit m (start)
@@ -340,7 +341,71 @@ int mapdec_decode_noalloc(const mapdec_frame *frames, int nframes, double *logp,
 /* Bytes of the device array behind mapdec_decode_noalloc. */
 size_t mapdec_noalloc_limit(void);
 
-/* Status of the calling thread's last failed mapdec_create / plan_create. */
+/*
+ * Iterative decoding with an outer code (Sec. II-A: the inner code serially
+ * concatenated with an outer code; Sec. II-C: in iterative decoding the
+ * inner decoder's symbol priors P(D_i = D) come from the outer decoder's
+ * extrinsic information of the previous pass).  A pass is mapdec_decode (or
+ * a plan) with the frames' priors set to the last pass's extrinsic output
+ * (1/q at first) and their dprior set to the buffer that
+ * mapdec_outer_decode then reads as its channel: d log P / d prior_i(D) =
+ * U_i(D) / Z_i is the inner APP with the symbol's own prior divided out
+ * (eqs. 1-3), up to a factor per symbol.
+ *
+ * The outer code is linear over GF(q), q = 2^p, 1 <= p <= 6 (q equals the
+ * inner alphabet): a word x of N symbols is a codeword when
+ * sum_j H[c][j] x_j = 0 for every row c of the parity-check matrix H.
+ * Field elements are the integers 0 .. q-1 read as polynomials over GF(2)
+ * (bit k the coefficient of z^k): addition is bitwise XOR, multiplication
+ * the polynomial product reduced modulo the primitive polynomial
+ * z+1 (p = 1), z^2+z+1, z^3+z+1, z^4+z+1, z^5+z^2+1, z^6+z+1 (p = 6).
+ */
+typedef struct mapdec_outer mapdec_outer;
+
+/* Largest number of entries in one row, and of rows holding one symbol. */
+#define MAPDEC_OUTER_MAX_DEG 32
+
+/*
+ * mapdec_outer_create -- H in compressed rows, host arrays: row_ptr (m+1
+ * int32, row_ptr[0] = 0, nondecreasing), col (row_ptr[m] int32 in [0, N),
+ * no column twice in a row), coef (row_ptr[m] bytes in [1, q-1]).  Every
+ * row and every column has at most MAPDEC_OUTER_MAX_DEG entries.  Copies
+ * the code to the current device.  NULL on failure (mapdec_last_error():
+ * MAPDEC_EINVAL, MAPDEC_EUNSUPPORTED for a degree above the limit,
+ * MAPDEC_ENOMEM, MAPDEC_EDEVICE).
+ */
+mapdec_outer *mapdec_outer_create(int q, int N, int m, const int32_t *row_ptr,
+                                  const int32_t *col, const uint8_t *coef);
+void mapdec_outer_destroy(mapdec_outer *code);
+/* Device workspace bytes of mapdec_outer_decode for nframes frames. */
+size_t mapdec_outer_workspace_size(const mapdec_outer *code, int nframes, int precision);
+
+/*
+ * mapdec_outer_decode -- iters >= 1 iterations of belief propagation
+ * (sum-product, flooding schedule: every check, then every symbol) on
+ * nframes words of the outer code (nframes <= 65535).
+ *   chan  device, [nframes][N][q] in the precision's type: the channel
+ *         distribution of every symbol (each row is divided by its sum, so
+ *         the inner decoder's dprior serves as it is; a row summing to 0
+ *         counts as uniform).
+ *   extr  device, [nframes][N][q] output: the extrinsic distributions,
+ *         proportional to the product of the symbol's incoming check
+ *         messages (the next pass's priors).
+ *   post  device, [nframes][N][q] output (posteriors, proportional to the
+ *         channel times that product), or NULL.
+ * Messages from a check to symbol j are the distribution of
+ * H[c][j]^-1 sum_{k != j} H[c][k] x_k under the symbols' incoming
+ * messages; every message is normalised to sum 1 (a vector summing to 0
+ * becomes uniform).  ws: ws_bytes >= mapdec_outer_workspace_size(...).
+ * Returns MAPDEC_OK, MAPDEC_EINVAL, MAPDEC_ESIZE or MAPDEC_EDEVICE; work is
+ * enqueued on stream.
+ */
+int mapdec_outer_decode(const mapdec_outer *code, int nframes, const void *chan, void *extr,
+                        void *post, int iters, void *ws, size_t ws_bytes, int precision,
+                        void *stream);
+
+/* Status of the calling thread's last failed mapdec_create / plan_create /
+ * mapdec_outer_create. */
 int mapdec_last_error(void);
 /* Static string naming a status code. */
 const char *mapdec_strerror(int status);

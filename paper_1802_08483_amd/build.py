@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmapdec.so")
 SOURCES = ["k_misc.hip", "k_lattice.hip", "k_chain.hip", "k_app.hip", "k_app_mfma.hip",
-           "scratch.hip", "mapdec.cpp"]
+           "k_outer.hip", "scratch.hip", "mapdec.cpp", "outer.cpp"]
 # k_chain_ring.hip is compiled once per (precision, workgroup shape); the
 # shapes (waves, states per thread) match kRingShapes in csrc/kernels.h
 RING_SHAPES = [(1, 1, 0), (2, 1, 0), (4, 1, 0), (4, 2, 0), (8, 2, 0), (16, 2, 0), (16, 2, 1)]

@@ -109,6 +109,11 @@ hipError_t launch_app_fin(int qt, const FrameDesc *fd, const Work *tab, int nblo
                           hipStream_t st);
 size_t app_mfma_lds(int mn, int q);
 
+// Belief propagation of the outer code (k_outer.hip): iters iterations on
+// nframes words; v2c, c2v: [nframes][E][q] message buffers.
+hipError_t launch_outer(int fp64, const OuterDev &c, int nframes, const void *chan, void *extr,
+                        void *post, int iters, void *v2c, void *c2v, hipStream_t st);
+
 // The fixed device array of the allocation-free decode (scratch.hip): its
 // size, and its address on the current device (taken once per device).
 size_t scratch_bytes();

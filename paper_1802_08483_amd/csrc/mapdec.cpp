@@ -41,6 +41,14 @@ int fail(int st) {
     return st;
 }
 
+}  // namespace
+
+namespace mapdec {
+int record_error(int st) { return fail(st); }
+}  // namespace mapdec
+
+namespace {
+
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 

@@ -120,4 +120,22 @@ struct Work {
 enum : int { kStatusOk = 0, kStatusNoPath = 3 };
 enum : int { kChainRows = 0, kChainSweep = 1, kChainSub = 2 };
 
+// Outer code of iterative decoding on the device (see k_outer.hip): H in
+// compressed rows (edge e = row entry), the edges of every symbol, and the
+// multiplication and inverse tables of GF(q).
+constexpr int kOuterMaxDeg = 32;
+struct OuterDev {
+    int q, N, m, E;
+    const int *row_ptr;     // [m+1]
+    const int *col;         // [E]
+    const uint8_t *coef;    // [E]
+    const int *var_ptr;     // [N+1]
+    const int *var_edge;    // [E] edges of symbol j at var_ptr[j] ..
+    const uint8_t *mul;     // [q][q]
+    const uint8_t *inv;     // [q]
+};
+
+// Records a failed call's status for mapdec_last_error; returns it.
+int record_error(int st);
+
 }  // namespace mapdec

@@ -28,7 +28,9 @@ EXPORTS = ["mapdec_create", "mapdec_destroy", "mapdec_workspace_size", "mapdec_d
            "mapdec_tune_entries",
            "mapdec_tune_reset", "mapdec_last_error",
            "mapdec_strerror", "mapdec_version", "mapdec_decode_noalloc",
-           "mapdec_noalloc_limit", "mapdec_create_general", "mapdec_with_threshold"]
+           "mapdec_noalloc_limit", "mapdec_create_general", "mapdec_with_threshold",
+           "mapdec_outer_create", "mapdec_outer_destroy", "mapdec_outer_workspace_size",
+           "mapdec_outer_decode"]
 
 
 class MapdecError(RuntimeError):
@@ -98,6 +100,14 @@ def lib() -> ctypes.CDLL:
         L.mapdec_decode_noalloc.restype = i32
         L.mapdec_noalloc_limit.argtypes = []
         L.mapdec_noalloc_limit.restype = sz
+        L.mapdec_outer_create.argtypes = [i32, i32, i32, vp, vp, vp]
+        L.mapdec_outer_create.restype = vp
+        L.mapdec_outer_destroy.argtypes = [vp]
+        L.mapdec_outer_destroy.restype = None
+        L.mapdec_outer_workspace_size.argtypes = [vp, i32, i32]
+        L.mapdec_outer_workspace_size.restype = sz
+        L.mapdec_outer_decode.argtypes = [vp, i32, vp, vp, vp, i32, vp, sz, i32, vp]
+        L.mapdec_outer_decode.restype = i32
         _lib = L
     return _lib
 
@@ -201,7 +211,8 @@ class Batch:
     """
 
     def __init__(self, frames: Sequence, precision: int = FP32, grad: bool = False,
-                 device=None, checkpoint_K: int = 0, workspace: bool = True):
+                 device=None, checkpoint_K: int = 0, workspace: bool = True,
+                 dpriors: Optional[Sequence] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("libmapdec needs a GPU; no device is visible")
         self.device = torch.device(device or "cuda")
@@ -230,7 +241,13 @@ class Batch:
                     raise TypeError("prior must be (N, q) in the batch precision")
                 prior = prior.contiguous()
             app = torch.empty((N, code.q), dtype=self.dtype, device=self.device)
-            dpr = torch.empty((N, code.q), dtype=self.dtype, device=self.device) if grad else None
+            if dpriors is not None:   # the caller's (N, q) output buffers (iterative decoding)
+                dpr = dpriors[f]
+                if (dpr.dtype != self.dtype or tuple(dpr.shape) != (N, code.q)
+                        or not dpr.is_contiguous()):
+                    raise TypeError("dprior buffers must be contiguous (N, q) in the batch precision")
+            else:
+                dpr = torch.empty((N, code.q), dtype=self.dtype, device=self.device) if grad else None
             self.codes.append(code)
             self.ys.append(y)
             self.priors.append(prior)
@@ -379,3 +396,124 @@ def batch_from_frames(frames: List, precision: int = FP32, grad: bool = False,
         items.append((code, y, fr.N, prior, bnd[0], bnd[1]))
     return Batch(items, precision=precision, grad=grad, device=dev, checkpoint_K=checkpoint_K,
                  workspace=workspace)
+
+
+class Outer:
+    """An outer code over GF(q) for iterative decoding (mapdec_outer_*):
+    parity-check matrix in compressed rows (row_ptr, col, coef)."""
+
+    def __init__(self, q: int, N: int, row_ptr, col, coef):
+        import numpy as np
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        cf = np.ascontiguousarray(coef, dtype=np.uint8)
+        self.q, self.N, self.m = int(q), int(N), int(rp.shape[0] - 1)
+        self._keep = (rp, cl, cf)
+        h = lib().mapdec_outer_create(self.q, self.N, self.m, rp.ctypes.data, cl.ctypes.data,
+                                      cf.ctypes.data)
+        if not h:
+            raise MapdecError(lib().mapdec_last_error(), "mapdec_outer_create")
+        self.handle = h
+
+    @classmethod
+    def from_spec(cls, spec) -> "Outer":
+        return cls(spec.q, spec.N, spec.row_ptr, spec.col, spec.coef)
+
+    def workspace_size(self, nframes: int, precision: int) -> int:
+        return int(lib().mapdec_outer_workspace_size(self.handle, nframes, precision))
+
+    def decode(self, chan: torch.Tensor, extr: torch.Tensor, post: Optional[torch.Tensor],
+               iters: int, ws: torch.Tensor, stream=None) -> None:
+        """Belief propagation on chan [F, N, q] -> extr (and post)."""
+        precision = FP64 if chan.dtype == torch.float64 else FP32
+        F = chan.shape[0]
+        for t in (chan, extr) + ((post,) if post is not None else ()):
+            if (tuple(t.shape) != (F, self.N, self.q) or t.dtype != chan.dtype
+                    or not t.is_contiguous() or not t.is_cuda):
+                raise TypeError("chan / extr / post must be contiguous (F, N, q) CUDA tensors")
+        rc = lib().mapdec_outer_decode(self.handle, F, chan.data_ptr(), extr.data_ptr(),
+                                       _ptr(post), int(iters), ws.data_ptr(), ws.numel(),
+                                       precision, _stream_handle(stream))
+        if rc != OK:
+            raise MapdecError(rc, "mapdec_outer_decode")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.mapdec_outer_destroy(h)
+            self.handle = None
+
+
+class Iterative:
+    """Iterative decoding of frames that carry codewords of one outer code
+    (Sec. II-A): per pass the inner decoder (libmapdec) with the priors in
+    ``prior`` (1/q at first), its d log P / d prior into ``chan``, then
+    ``bp_iters`` iterations of belief propagation writing the next priors
+    (the outer extrinsic output) into ``prior`` and the posteriors into
+    ``post``.  Every buffer is one (F, N, q) device tensor; the frames'
+    priors and dprior outputs are its rows.
+
+    ``frames``: (code, y, N) or (code, y, N, start, end) as for Batch,
+    without priors (they are the iteration's)."""
+
+    def __init__(self, frames: Sequence, outer: Outer, precision: int = FP32,
+                 checkpoint_K: int = 0, device=None):
+        self.outer = outer
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        dev = torch.device(device or "cuda")
+        F = len(frames)
+        q, N = outer.q, outer.N
+        self.prior = torch.full((F, N, q), 1.0 / q, dtype=self.dtype, device=dev)
+        self.chan = torch.zeros((F, N, q), dtype=self.dtype, device=dev)
+        self.post = torch.zeros((F, N, q), dtype=self.dtype, device=dev)
+        items = []
+        for f, fr in enumerate(frames):
+            code, y, n_sym = fr[:3]
+            if n_sym != N or code.q != q:
+                raise ValueError("every frame must have the outer code's N and q")
+            items.append((code, y, n_sym, self.prior[f]) + tuple(fr[3:5]))
+        self.batch = Batch(items, precision=precision, device=dev, checkpoint_K=checkpoint_K,
+                           dpriors=[self.chan[f] for f in range(F)])
+        self.ws = torch.empty(outer.workspace_size(F, precision), dtype=torch.uint8, device=dev)
+        self.precision = precision
+
+        self.plan = None
+
+    def use_plan(self, graph: bool = True, stream=None) -> "Iterative":
+        """Replay the inner decode as a plan (one HIP graph with graph=True):
+        its buffers stay fixed, only their contents change between passes."""
+        self.plan = Plan(self.batch, graph=graph, stream=stream)
+        return self
+
+    def reset(self) -> None:
+        """Back to uniform priors (the first pass)."""
+        self.prior.fill_(1.0 / self.outer.q)
+
+    def run_pass(self, bp_iters: int, stream=None) -> None:
+        if self.plan is not None:
+            self.plan.run(stream)
+        else:
+            self.batch.decode(stream=stream)
+        self.outer.decode(self.chan, self.prior, self.post, bp_iters, self.ws, stream=stream)
+
+    def run(self, passes: int, bp_iters: int, stream=None) -> None:
+        for _ in range(passes):
+            self.run_pass(bp_iters, stream)
+
+
+def iterative_from_frames(frames: List, spec, precision: int = FP32,
+                          checkpoint_K: int = 0, device=None) -> Iterative:
+    """Uploads workloads.Frame objects carrying codewords of the outer code
+    ``spec`` (workloads.OuterSpec) and builds an :class:`Iterative`."""
+    dev = torch.device(device or "cuda")
+    cache: dict = {}
+    items = []
+    for fr in frames:
+        code = code_for(fr, cache)
+        y = torch.from_numpy(fr.y).to(dev)
+        bnd = [None if getattr(fr, k, None) is None
+               else torch.as_tensor(getattr(fr, k), dtype=torch.float64).contiguous().to(dev)
+               for k in ("start_drift", "end_drift")]
+        items.append((code, y, fr.N, bnd[0], bnd[1]))
+    return Iterative(items, Outer.from_spec(spec), precision=precision,
+                     checkpoint_K=checkpoint_K, device=dev)

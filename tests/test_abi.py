@@ -40,7 +40,7 @@ def test_exports_every_declared_symbol(L):
     assert set(declared) == set(mapdec.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
-    assert L.mapdec_version() == 106
+    assert L.mapdec_version() == 107
     for st in range(8):
         assert L.mapdec_strerror(st)
 
@@ -186,3 +186,27 @@ def test_frame_struct_layout_matches_header(tmp_path):
     vals = [int(v) for v in out.stdout.split()]
     assert vals[0] == ctypes.sizeof(mapdec._Frame)
     assert vals[1:] == [getattr(mapdec._Frame, f).offset for f in fields]
+
+
+def test_outer_code_validation(L):
+    # host-side checks before any device call: every case returns NULL
+    import numpy as np
+    rp = np.array([0, 3], np.int32)
+    cl = np.array([0, 1, 2], np.int32)
+    cf = np.array([1, 2, 3], np.uint8)
+    def create(q, N, m, rp, cl, cf):
+        return L.mapdec_outer_create(q, N, m, rp.ctypes.data, cl.ctypes.data, cf.ctypes.data)
+    for args, st in [((6, 3, 1, rp, cl, cf), mapdec.EINVAL),            # q not a power of 2
+                     ((128, 3, 1, rp, cl, cf), mapdec.EINVAL),          # q above 64
+                     ((4, 3, 1, rp, cl, np.array([1, 0, 3], np.uint8)), mapdec.EINVAL),  # zero
+                     ((4, 3, 1, rp, cl, np.array([1, 2, 4], np.uint8)), mapdec.EINVAL),  # >= q
+                     ((4, 3, 1, rp, np.array([0, 1, 1], np.int32), cf), mapdec.EINVAL),  # repeat
+                     ((4, 2, 1, rp, cl, cf), mapdec.EINVAL),            # column >= N
+                     ((4, 3, 1, np.array([1, 3], np.int32), cl, cf), mapdec.EINVAL),
+                     ((4, 40, 1, np.array([0, 33], np.int32), np.arange(33, dtype=np.int32),
+                       np.ones(33, np.uint8)), mapdec.EUNSUPPORTED)]:   # row degree 33
+        assert not create(*args)
+        assert L.mapdec_last_error() == st
+    assert L.mapdec_outer_workspace_size(None, 1, mapdec.FP32) == 0
+    assert L.mapdec_outer_decode(None, 1, None, None, None, 1, None, 0, mapdec.FP32,
+                                 None) == mapdec.EINVAL
