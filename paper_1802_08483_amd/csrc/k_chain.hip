@@ -217,7 +217,7 @@ namespace mapdec {
 
 // One object per (precision, shape) built from k_chain_ring.hip.
 #define MAPDEC_RING_DECL(name)                                                            \
-    hipError_t name(int mn, int nchains, int dirs, size_t lds, hipStream_t st,            \
+    hipError_t name(int mn, int waves, int nchains, int dirs, size_t lds, hipStream_t st,  \
                     const FrameDesc *fd, const int *frames);
 MAPDEC_RING_DECL(chain_ring_f32_0)
 MAPDEC_RING_DECL(chain_ring_f32_1)
@@ -235,11 +235,13 @@ MAPDEC_RING_DECL(chain_ring_f64_5)
 MAPDEC_RING_DECL(chain_ring_f64_6)
 #undef MAPDEC_RING_DECL
 
-hipError_t launch_chain_ring(int fp64, int shape, int mn, const FrameDesc *fd, const int *frames,
-                             int nchains, int dirs, size_t lds, hipStream_t st) {
+hipError_t launch_chain_ring(int fp64, int shape, int mn, int waves, const FrameDesc *fd,
+                             const int *frames, int nchains, int dirs, size_t lds,
+                             hipStream_t st) {
     if (nchains == 0) return hipSuccess;
     if (dirs < 1 || dirs > 3) return hipErrorInvalidValue;
-    using Fn = hipError_t (*)(int, int, int, size_t, hipStream_t, const FrameDesc *, const int *);
+    using Fn = hipError_t (*)(int, int, int, int, size_t, hipStream_t, const FrameDesc *,
+                              const int *);
     static const Fn f32[kNumRingShapes] = {chain_ring_f32_0, chain_ring_f32_1, chain_ring_f32_2,
                                            chain_ring_f32_3, chain_ring_f32_4, chain_ring_f32_5,
                                            chain_ring_f32_6};
@@ -247,7 +249,8 @@ hipError_t launch_chain_ring(int fp64, int shape, int mn, const FrameDesc *fd, c
                                            chain_ring_f64_3, chain_ring_f64_4, chain_ring_f64_5,
                                            chain_ring_f64_6};
     if (shape < 0 || shape >= kNumRingShapes) return hipErrorInvalidValue;
-    return (fp64 ? f64 : f32)[shape](mn, nchains, dirs, lds, st, fd, frames);
+    if (waves < 1 || waves > kRingShapes[shape].nw) return hipErrorInvalidValue;
+    return (fp64 ? f64 : f32)[shape](mn, waves, nchains, dirs, lds, st, fd, frames);
 }
 
 }  // namespace mapdec

@@ -5,11 +5,14 @@
 // build with -DCHAIN_T=float|double -DCHAIN_NW=<waves> -DCHAIN_SPL=<states>
 // -DCHAIN_FN=<launcher name>.
 //
-// One workgroup of NT = 64 NW threads runs one chain; thread t owns
-// drift-state index t (SPL = 1) or SPL of them: the adjacent indices SPL t ..
-// SPL t + SPL - 1 (FP32 Gamma) or t, t + NT, .. (FP64).  Rows are padded to
-// NT SPL states (zero beyond 2M+1) plus mn zeros on each side, so no thread
-// branches on its state.  One workgroup barrier per step.
+// One workgroup of nt = 64 nw threads runs one chain, nw the waves the
+// state space needs (at most the compiled NW, NT = 64 NW): a step's issue
+// time grows with the waves that share a SIMD, so none are launched only to
+// hold zeros.  Thread t owns drift-state index t (SPL = 1) or SPL of them:
+// the adjacent indices SPL t .. SPL t + SPL - 1 (FP32 Gamma) or t, t + nt,
+// .. (FP64).  Rows are padded to NT SPL states (zero beyond 2M+1) plus mn
+// zeros on each side, so no thread branches on its state.  One workgroup
+// barrier per step.
 //
 // Rows are FP64 at every precision (their spread within a row can exceed
 // the FP32 range); Gamma stays in the batch precision.  Each step scales its
@@ -99,18 +102,20 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     R *part = row1 + ROWW;                             // [2][NW] wave partial sums
     R *red = part + 2 * NW;                            // [NW] partial sums of a new row
     T *ring = (T *)(part + 3 * NW);                    // [RPHYS][Mn], batch precision
-    const int tid = threadIdx.x, wv = tid >> 6;
+    // the launch's threads: nt = 64 nw <= NT (as many waves as the state
+    // space needs)
+    const int tid = threadIdx.x, wv = tid >> 6, nt = blockDim.x, nw = nt >> 6;
     // drift-state index of the thread's j-th state: with several states per
     // thread (FP32 Gamma) they are adjacent (SPL tid + j), so the row windows
     // of a thread's states overlap and pair up in LDS reads; FP64 Gamma keeps
-    // them NT apart (fewer live registers)
+    // them nt apart (fewer live registers)
     constexpr bool ADJ = SPL > 1 && sizeof(T) == 4;
-    auto state = [&](int j) { return ADJ ? SPL * tid + j : tid + NT * j; };
+    auto state = [&](int j) { return ADJ ? SPL * tid + j : tid + nt * j; };
     const gptr<const T> G = to_global((const T *)f.G);   // [Mn][gsp]
     const size_t sp = (size_t)f.gsp;
 
-    for (int j = tid; j < (ONE ? 1 : 2) * ROWW + 3 * NW; j += NT) row0[j] = R(0);
-    for (int j = tid; j < RPHYS * Mn; j += NT) ring[j] = T(0);
+    for (int j = tid; j < (ONE ? 1 : 2) * ROWW + 3 * NW; j += nt) row0[j] = R(0);
+    for (int j = tid; j < RPHYS * Mn; j += nt) ring[j] = T(0);
     __syncthreads();
     const int m0 = DIR == 0 ? 0 : f.rho - f.tau;
     const double *init = DIR == 0 ? f.a_init : f.b_init;
@@ -134,7 +139,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     const bool pr = f.theta > 0.0;
     const bool decide = pr && DIR == 0 && mode != kChainSub;
     const gptr<uint8_t> kept = to_global(f.kept);
-    for (int mi = tid; mi < Mt; mi += NT) {
+    for (int mi = tid; mi < Mt; mi += nt) {
         R v = init ? (R)init[mi] : ((mi == m0 + M) ? R(1) : R(0));
         if (prior_row && (pos0 + mi - M < 0 || pos0 + mi - M > f.rho)) v = R(0);
         if (mi < lo_i || mi > hi_i) v = R(0);
@@ -144,14 +149,14 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     if (decide) {   // the start row against its own sum
         __syncthreads();
         R t = R(0);
-        for (int mi = tid; mi < Mt; mi += NT) t += row0[MN + mi];
+        for (int mi = tid; mi < Mt; mi += nt) t += row0[MN + mi];
         t = wave_sum_dpp(t);
         if ((tid & 63) == 0) red[wv] = t;
         __syncthreads();
         R sum = R(0);
-        for (int w = 0; w < NW; ++w) sum += red[w];
+        for (int w = 0; w < nw; ++w) sum += red[w];
         const R cut = (R)f.theta * sum;
-        for (int mi = tid; mi < Mt; mi += NT) {
+        for (int mi = tid; mi < Mt; mi += nt) {
             const R v = row0[MN + mi];
             const bool k = v > R(0) && !(v < cut);
             row0[MN + mi] = k ? v : R(0);
@@ -159,7 +164,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
         }
     }
     if (put_init)
-        for (int mi = tid; mi < Mt; mi += NT) out[slot(rowA) + mi] = row0[MN + mi];
+        for (int mi = tid; mi < Mt; mi += nt) out[slot(rowA) + mi] = row0[MN + mi];
     double *logX = DIR == 0 ? f.logA : f.logB;
     const double lbase =
         (mode != kChainSub && (DIR == 0 ? i0 > 0 : i1 < N)) ? logX[rowA] : 0.0;
@@ -184,12 +189,12 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
         }
     };
 
-    // Prefetch registers: element p = tid + NT r is column base + (p mod nC)
-    // of drift change p / nC.  (kk, col) advance by (NT / nC, NT mod nC)
+    // Prefetch registers: element p = tid + nt r is column base + (p mod nC)
+    // of drift change p / nC.  (kk, col) advance by (nt / nC, nt mod nC)
     // per register with one carry test; loads are unconditional (clamped
     // address) so all of them stay in flight, validity kept as a bit mask.
     const int nC = n * C;
-    const int dq = NT / nC, dr = NT - dq * nC;
+    const int dq = nt / nC, dr = nt - dq * nC;
     T pre[PF];
     uint32_t pvalid = 0;
     auto issue = [&](int base) {
@@ -284,6 +289,9 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
             const int i = DIR == 0 ? i0 + k * C + t : i1 - 1 - k * C - t;
             R csum = R(0);
 #pragma unroll
+            // (partials of waves not launched stay 0 from the start: the
+            // loop keeps its compile-time trip count and its loads issue
+            // together)
             for (int w = 0; w < NW; ++w) csum += part[pp * NW + w];
             dead |= !(csum > R(0));
             int m1;
@@ -428,7 +436,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     }
     double *fin = DIR == 0 ? f.a_fin : f.b_fin;
     if (fin)
-        for (int mi = tid; mi < Mt; mi += NT) fin[mi] = cur[MN + mi];
+        for (int mi = tid; mi < Mt; mi += nt) fin[mi] = cur[MN + mi];
     if (tid != 0 || mode == kChainSub) return;
     logX[DIR == 0 ? i1 : i0] = lsum;
     if (DIR == 1 && i0 == 0 && f.grad && f.start_prior) {
@@ -486,7 +494,7 @@ __global__ __launch_bounds__(64 * NW) void k_chain_ring(const FrameDesc *__restr
 }
 
 template <int MN>
-static hipError_t ring_launch(int nchains, int dirs, size_t lds, hipStream_t st,
+static hipError_t ring_launch(int waves, int nchains, int dirs, size_t lds, hipStream_t st,
                               const FrameDesc *fd, const int *frames) {
     auto kern = k_chain_ring<CHAIN_T, CHAIN_NW, CHAIN_SPL, MN, CHAIN_ONEROW != 0>;
     if (lds > 65536) {
@@ -494,23 +502,23 @@ static hipError_t ring_launch(int nchains, int dirs, size_t lds, hipStream_t st,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(nchains * (dirs == 3 ? 2 : 1)), dim3(64 * CHAIN_NW), lds, st,
+    hipLaunchKernelGGL(kern, dim3(nchains * (dirs == 3 ? 2 : 1)), dim3(64 * waves), lds, st,
                        fd, frames, dirs);
     return hipGetLastError();
 }
 
-hipError_t CHAIN_FN(int mn, int nchains, int dirs, size_t lds, hipStream_t st,
+hipError_t CHAIN_FN(int mn, int waves, int nchains, int dirs, size_t lds, hipStream_t st,
                     const FrameDesc *fd, const int *frames) {
     switch (mn) {
-        case 0: return ring_launch<0>(nchains, dirs, lds, st, fd, frames);
-        case 1: return ring_launch<1>(nchains, dirs, lds, st, fd, frames);
-        case 2: return ring_launch<2>(nchains, dirs, lds, st, fd, frames);
-        case 3: return ring_launch<3>(nchains, dirs, lds, st, fd, frames);
-        case 4: return ring_launch<4>(nchains, dirs, lds, st, fd, frames);
-        case 5: return ring_launch<5>(nchains, dirs, lds, st, fd, frames);
-        case 6: return ring_launch<6>(nchains, dirs, lds, st, fd, frames);
-        case 7: return ring_launch<7>(nchains, dirs, lds, st, fd, frames);
-        case 8: return ring_launch<8>(nchains, dirs, lds, st, fd, frames);
+        case 0: return ring_launch<0>(waves, nchains, dirs, lds, st, fd, frames);
+        case 1: return ring_launch<1>(waves, nchains, dirs, lds, st, fd, frames);
+        case 2: return ring_launch<2>(waves, nchains, dirs, lds, st, fd, frames);
+        case 3: return ring_launch<3>(waves, nchains, dirs, lds, st, fd, frames);
+        case 4: return ring_launch<4>(waves, nchains, dirs, lds, st, fd, frames);
+        case 5: return ring_launch<5>(waves, nchains, dirs, lds, st, fd, frames);
+        case 6: return ring_launch<6>(waves, nchains, dirs, lds, st, fd, frames);
+        case 7: return ring_launch<7>(waves, nchains, dirs, lds, st, fd, frames);
+        case 8: return ring_launch<8>(waves, nchains, dirs, lds, st, fd, frames);
         default: return hipErrorInvalidValue;
     }
 }

@@ -42,9 +42,11 @@ hipError_t launch_chain(int fp64, const FrameDesc *fd, const int *frames, int nc
                         int dirs, size_t lds_bytes, hipStream_t st);
 // Chains for uniform priors with Gamma in an LDS ring (k_chain_ring.hip):
 // shape = index into kRingShapes; every frame of the launch has drift
-// limit mn.
-hipError_t launch_chain_ring(int fp64, int shape, int mn, const FrameDesc *fd, const int *frames,
-                             int nchains, int dirs, size_t lds_bytes, hipStream_t st);
+// limit mn; waves (1 .. the shape's nw) per workgroup, at least
+// ring_waves(shape, 2M+1) of every frame of the launch.
+hipError_t launch_chain_ring(int fp64, int shape, int mn, int waves, const FrameDesc *fd,
+                             const int *frames, int nchains, int dirs, size_t lds_bytes,
+                             hipStream_t st);
 
 // Workgroup shapes of the ring chain kernel: waves per chain, drift states
 // per thread, and one metric row in LDS instead of two; a frame takes the
@@ -57,6 +59,19 @@ constexpr RingShape kRingShapes[] = {{1, 1, 0}, {2, 1, 0}, {4, 1, 0}, {4, 2, 0},
 constexpr int kNumRingShapes = 7;
 // Rings of at most this many padded states duplicate their edge slots.
 constexpr bool ring_duplicates(int slots) { return slots <= 512; }
+// Waves a chain of Mt drift states needs in a shape: enough for Mt states
+// at spl per thread (the shape's nw at most).
+constexpr int ring_waves(int shape, int Mt) {
+    const int per = 64 * kRingShapes[shape].spl;
+    const int w = (Mt + per - 1) / per;
+    return w < 1 ? 1 : (w > kRingShapes[shape].nw ? kRingShapes[shape].nw : w);
+}
+// Waves a chain is launched with: ring_waves for uniform priors; the whole
+// shape for general priors, whose steps each prefetch Mt columns (the
+// prefetch registers of every thread are needed).
+constexpr int chain_waves(int shape, int Mt, bool uniform) {
+    return uniform ? ring_waves(shape, Mt) : kRingShapes[shape].nw;
+}
 hipError_t launch_app(int fp64, const FrameDesc *fd, const Work *tab, int nblocks,
                       size_t lds_bytes, hipStream_t st);
 // Tiled APP (k_app_tile.hip): td symbol values per D tile (2, 4 or 8; at

@@ -253,7 +253,9 @@ bool ring_fit(int shape, int Mt, int Mn, int n, int mn, bool uniform, size_t tsi
               size_t lds_limit, int &chunk, int &cols, size_t &lds) {
     const RingShape &rs = kRingShapes[shape];
     if (64 * rs.nw * rs.spl < Mt) return false;
-    const int nt = 64 * rs.nw, slots = nt * rs.spl;
+    // the prefetch is spread over the threads the chain is launched with;
+    // rows and ring duplication follow the compiled shape
+    const int nt = 64 * chain_waves(shape, Mt, uniform), slots = 64 * rs.nw * rs.spl;
     // ring: a power of two covering the window of at least 8 steps; the
     // chunk is as long as the ring and the prefetch registers allow
     cols = 1;
@@ -1038,12 +1040,16 @@ struct mapdec_plan {
             for (auto &kv : P.chain_ring) {
                 const int shape = std::get<0>(kv.first), mn = std::get<1>(kv.first);
                 const size_t lds = L.ring_lds.at(std::make_pair(shape, mn));
+                int waves = 1;   // enough for every chain of the group
+                for (int dsc : kv.second)
+                    waves = std::max(waves, chain_waves(shape, L.fl[frame_of(dsc)].Mt,
+                                                        !L.fl[frame_of(dsc)].gcol));
                 for (int dd : std::get<2>(kv.first) ? std::vector<int>{kDirFwd, kDirBwd}
                                                    : std::vector<int>{dirs})
                     add_chains(kv.second, P.off_chain_ring.at(kv.first), steps(kv.second.front()),
                                [=](hipStream_t st, const int *tab, int nc) {
-                                   return launch_chain_ring(fp64, shape, mn, fd, tab, nc, dd, lds,
-                                                            st);
+                                   return launch_chain_ring(fp64, shape, mn, waves, fd, tab, nc,
+                                                            dd, lds, st);
                                });
             }
             deal();
@@ -1646,9 +1652,12 @@ int tune_plan(mapdec_plan *t, hipStream_t s) {
             std::vector<FrameDesc> patched = fd_host;
             size_t lds = 0;
             bool ok = true;
+            int waves = 1;
             for (int f : used) {
                 const FrameLayout &F = L.fl[f];
-                const bool uni = fd_host[f].uniform != 0;
+                const bool uni = !F.gcol;
+                if (64 * kRingShapes[shape].nw * kRingShapes[shape].spl >= F.Mt)
+                    waves = std::max(waves, chain_waves(shape, F.Mt, uni));
                 int ch, co;
                 size_t l;
                 if (!ring_fit(shape, F.Mt, F.Mn, uni ? fd_host[f].n : F.Mt, mn, uni, L.tsize,
@@ -1670,7 +1679,8 @@ int tune_plan(mapdec_plan *t, hipStream_t s) {
             const int nc = (int)used.size();
             float ms = 0.f;
             e = time_launch(s, e0, e1, 2, [&](hipStream_t st) {
-                return launch_chain_ring(fp64, shape, mn, fd_tmp, list, nc, kDirBoth, lds, st);
+                return launch_chain_ring(fp64, shape, mn, waves, fd_tmp, list, nc, kDirBoth, lds,
+                                         st);
             }, ms);
             if (e != hipSuccess) break;
             if (best_ms < 0.f || ms < best_ms) {

@@ -299,10 +299,11 @@ hipError_t launch_chain(int, const FrameDesc *fd, const int *fr, int nc, int, si
     launch(st, chain_frames(fd, fr, nc), false);
     return hipSuccess;
 }
-hipError_t launch_chain_ring(int, int shape, int, const FrameDesc *fd, const int *fr, int nc,
-                             int, size_t lds, hipStream_t st) {
+hipError_t launch_chain_ring(int, int shape, int, int waves, const FrameDesc *fd, const int *fr,
+                             int nc, int, size_t lds, hipStream_t st) {
     check_fd(fd);
     if (shape < 0 || shape >= kNumRingShapes || lds > 160 * 1024) die("bad ring launch");
+    if (waves < 1 || waves > kRingShapes[shape].nw) die("bad ring wave count");
     launch(st, chain_frames(fd, fr, nc), false);
     return hipSuccess;
 }
