@@ -344,15 +344,22 @@ def line_grad(mapdec, workloads, torch, k, K, steps, warmup, graph=True):
                        "value": round(syms / (ms * 1e-3), 1), "unit": "symbols/s",
                        "ms_per_step": round(ms, 4), "frames": len(frames),
                        "checkpoint_K": K, "workspace_bytes": b.ws_bytes,
-                       "schedule": "one HIP graph" if graph else "eager plan",
+                       "schedule": "one HIP graph" if graph else
+                       "eager plan (launch groups and sweep parts forked over streams)",
                        "roofline": roof,
                        "phases_ms": {p: round(v, 4) for p, v in phases.items()},
                        "launches": nl,
-                       # one launch runs the whole frame's recursions (the
-                       # sweep when checkpointed): its time per step
+                       # time per step of the whole frame's recursions (the
+                       # sweep when checkpointed): one launch over N steps
+                       # (both directions), or, with the sweep in parts, a
+                       # forward and a backward launch per part over N /
+                       # parts steps each
                        "chain_step_us": round(phases.get("chain", 0.0) * 1e3 /
                                               max(1, nl.get("chain", 1)) /
-                                              max(fr.N for fr in frames), 4)}
+                                              (max(fr.N for fr in frames) /
+                                               max(1, nl.get("chain", 1) // 2)
+                                               if K and nl.get("chain", 1) > 1
+                                               else max(fr.N for fr in frames)), 4)}
 
 
 def line_general(mapdec, workloads, torch, steps, warmup):
@@ -510,7 +517,14 @@ def main():
         fr0 = workloads.make_workload(HEADLINE, nframes=1)[0]
         K = int(math.ceil(math.sqrt(fr0.N)))
         b5, frames5, head = line_grad(mapdec, workloads, torch, HEADLINE, K, args.steps,
-                                      args.warmup)
+                                      args.warmup, graph=False)
+        # the one-stream HIP graph of the same step (the sweep in one launch,
+        # no main pass beside it)
+        pg = b5.plan(graph=True)
+        msg = time_plan(pg, max(2, args.steps // 2), 1, torch)
+        pg.close()
+        head["graph_replay"] = {"value": round(sum(f.N for f in frames5) / (msg * 1e-3), 1),
+                                "ms_per_step": round(msg, 4), "schedule": "one HIP graph"}
         if not args.no_oracle:
             head["accuracy"] = golden_accuracy(b5)
         # the FP64 plain decode of the same frames (same checkpoints)
@@ -634,6 +648,7 @@ def main():
         "phases_ms": head["phases_ms"],
         "launches": head["launches"],
         "chain_step_us": head["chain_step_us"],
+        "graph_replay": head.get("graph_replay"),
         "other_workloads": lines,
     }
     print(json.dumps(line))

@@ -166,8 +166,16 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     if (put_init)
         for (int mi = tid; mi < Mt; mi += nt) out[slot(rowA) + mi] = row0[MN + mi];
     double *logX = DIR == 0 ? f.logA : f.logB;
+    // A sweep in parts carries its row-scale predictor from part to part
+    // (f.sweep_state, per direction: the stale sum the next step reads, the
+    // predictor's three exponents and the exponent total), so the parts
+    // apply the scales the sweep in one launch would, and their logs are the
+    // same bits.
+    double *sst = mode == kChainSweep && f.sweep_state ? f.sweep_state + 8 * DIR : nullptr;
+    const bool resume = sst && (DIR == 0 ? i0 > 0 : i1 < N);
+    const bool suspend = sst && (DIR == 0 ? i1 < N : i0 > 0);
     const double lbase =
-        (mode != kChainSub && (DIR == 0 ? i0 > 0 : i1 < N)) ? logX[rowA] : 0.0;
+        (!resume && mode != kChainSub && (DIR == 0 ? i0 > 0 : i1 < N)) ? logX[rowA] : 0.0;
 
     // chunk k covers steps i0+kC .. i0+kC+C-1 (forward) or i1-1-kC down to
     // i1-C-kC (backward), which read s in [n i_lo - M, n i_hi + M]
@@ -257,6 +265,16 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     // two steps ago; first: the step has no earlier measurement
     int m2 = 0, u1 = 0, u2 = 0;
     bool first = true;
+    if (resume) {   // where the previous part stopped
+        m2 = (int)sst[1];
+        u1 = (int)sst[2];
+        u2 = (int)sst[3];
+        lexp = (long long)sst[4];
+        first = false;
+        // the stale sum as the first step's partials (plus exact zeros)
+        if (tid < NW) part[tid] = tid == 0 ? sst[0] : R(0);
+        __syncthreads();
+    }
     bool dead = false;
     // applied decisions of the rows KPF steps ahead, loaded that early so
     // that their latency stays off the step (kq[0] is this step's row)
@@ -427,6 +445,15 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
         }
     }
     const double lsum = lbase + (double)lexp * 0.69314718055994530942;
+    if (suspend && !dead && tid == 0) {
+        R c = R(0);   // the sum the next step would read, summed as it would
+        for (int w = 0; w < NW; ++w) c += part[pp * NW + w];
+        sst[0] = c;
+        sst[1] = m2;
+        sst[2] = u1;
+        sst[3] = u2;
+        sst[4] = (double)lexp;
+    }
     if (dead) {
         if (tid == 0) {
             atomicOr(f.status, kStatusNoPath);

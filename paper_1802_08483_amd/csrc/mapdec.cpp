@@ -94,6 +94,10 @@ struct FrameLayout {
     int nwords = 0, sp = 0, gsp = 0, Mt = 0, Mn = 0, pack_blocks = 0;
     int K = 0, nseg = 1;   // symbols per main pass (group) and groups (1 unless checkpointed)
     int ck = 0, nck = 1;   // checkpoint spacing (0: none) and checkpoint segments
+    // sweep in parts: forward part p covers rows [swa[p], swa[p+1]), backward
+    // part p rows [swb[p+1], swb[p]) (checkpoint rows, swa[0] = 0, swb[0] = N)
+    std::vector<int> swa, swb;
+    size_t off_sws = 0;   // the sweep's carried scale predictor (parts > 1)
     // percol: a codebook per symbol, R by (symbol, drift state); gcol: Gamma
     // by (symbol, drift state) (general priors, or percol); gen: the lattice
     // and adjoint kernels' general-scheme instance (percol, or a corridor
@@ -155,6 +159,7 @@ enum PassKind { kPassPre, kPassSweep, kPassMain };
 struct Pass {
     int kind = kPassMain;
     int seg = 0;
+    int part = 0;    // sweep: the part; main: the sweep part after which its checkpoints exist
     size_t off_fd = 0;
     std::vector<int> sub_frame;   // frame of descriptor nframes + k
     std::vector<int> sub_seg;     // its checkpoint segment
@@ -194,6 +199,8 @@ struct Layout {
     int nframes = 0, fp64 = 0, grad = 0, ckK = 0;
     // frame slices of an eager forked plan (1: none) and each frame's slice
     int slices = 1;
+    // parts of the sweep of checkpointed frames (1: one launch)
+    int sweep_parts = 1;
     std::vector<int> fslice;
     size_t tsize = 4;
     size_t off_pack = 0, head = 0, total = 0;
@@ -226,6 +233,10 @@ HeadOwners &head_owners() {
 // chains (a latency-bound recursion) run beside another slice's
 // compute-bound launches.
 constexpr int kSlices = 4;
+// Eager plans of checkpointed frames run the sweep in this many parts, so
+// that the main passes of groups whose checkpoints are done run beside the
+// rest of it (the sweep holds one workgroup per chain and direction).
+constexpr int kSweepParts = 8;
 constexpr int kSliceMinFrames = 16;
 
 // Reorders a work list so that the workgroups the dispatcher sends to one
@@ -551,17 +562,62 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
         P.seg = j;
         L.passes.push_back(P);
     }
-    if (any_ck) {
-        Pass P;
-        P.kind = kPassSweep;
-        L.passes.push_back(P);
+    // The sweep in parts (eager plans without path thresholds or frame
+    // slices): the forward chains advance from the start, the backward ones
+    // from the end, so the checkpoints of the middle groups are done first.
+    bool pruned_ck = false;
+    for (int f = 0; f < nframes; ++f)
+        if (L.fl[f].ck && L.fl[f].pruned) pruned_ck = true;
+    L.sweep_parts = (any_ck && !pruned_ck && L.slices == 1 &&
+                     !(flags & (MAPDEC_FLAG_GRAPH | MAPDEC_FLAG_SERIAL)))
+                        ? kSweepParts : 1;
+    const int SP = L.sweep_parts;
+    for (int f = 0; f < nframes; ++f) {
+        FrameLayout &F = L.fl[f];
+        if (!F.ck) continue;
+        const long long N = frames[f].N, K = F.ck;
+        F.swa.assign(SP + 1, 0);
+        F.swb.assign(SP + 1, 0);
+        for (int p = 0; p <= SP; ++p) {
+            F.swa[p] = p == SP ? (int)N : (int)(N * p / SP / K * K);
+            F.swb[p] = p == 0 ? (int)N : (int)((N - N * p / SP) / K * K);
+        }
     }
+    if (any_ck)
+        for (int p = 0; p < SP; ++p) {
+            Pass P;
+            P.kind = kPassSweep;
+            P.part = p;
+            L.passes.push_back(P);
+        }
+    std::vector<Pass> mains;
     for (int j = smax - 1; j >= 0; --j) {
         Pass P;
         P.kind = kPassMain;
         P.seg = j;
-        L.passes.push_back(P);
+        // the first sweep part after which every checkpoint this group's
+        // segments start from exists: forward row (last segment) k1 K,
+        // backward row (first segment) (k0 + 1) K (the end prior beyond)
+        int ready = 0;
+        for (int f = 0; f < nframes && SP > 1; ++f) {
+            const FrameLayout &F = L.fl[f];
+            if (!F.ck || j >= F.nseg) continue;
+            const Segment g = segment_of(frames[f], F, j);
+            const int k0 = g.i0 / F.ck, k1 = (g.i1 - 1) / F.ck;
+            const int ra = k1 * F.ck, rb = (k0 + 1) * F.ck;
+            int pa = 0, pb = 0;
+            while (pa < SP - 1 && F.swa[pa + 1] < ra) ++pa;
+            if (k0 + 1 < F.nck)
+                while (pb < SP - 1 && F.swb[pb + 1] > rb) ++pb;
+            ready = std::max(ready, std::max(pa, pb));
+        }
+        P.part = ready;
+        mains.push_back(P);
     }
+    // main passes in the order their checkpoints are done
+    std::stable_sort(mains.begin(), mains.end(),
+                     [](const Pass &a, const Pass &b) { return a.part < b.part; });
+    for (Pass &P : mains) L.passes.push_back(P);
     for (Pass &P : L.passes) {
         const int j = P.seg;
         std::vector<std::pair<int, int>> chains;   // (steps, descriptor)
@@ -570,7 +626,22 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             const mapdec_code *c = fr.code;
             const FrameLayout &F = L.fl[f];
             if (P.kind == kPassSweep) {
-                if (F.ck) chains.push_back(std::make_pair(fr.N, f));
+                if (!F.ck) continue;
+                if (L.sweep_parts == 1) {
+                    chains.push_back(std::make_pair(fr.N, f));
+                    continue;
+                }
+                // the part's forward chain (descriptor f) and backward chain
+                // (an extra descriptor), each when its rows are not empty
+                const int p = P.part;
+                if (F.swa[p + 1] > F.swa[p])
+                    chains.push_back(std::make_pair(F.swa[p + 1] - F.swa[p], f));
+                if (F.swb[p] > F.swb[p + 1]) {
+                    const int d = nframes + (int)P.sub_frame.size();
+                    P.sub_frame.push_back(f);
+                    P.sub_seg.push_back(p);
+                    chains.push_back(std::make_pair(F.swb[p] - F.swb[p + 1], d));
+                }
                 continue;
             }
             if (P.kind == kPassPre) {
@@ -792,6 +863,10 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             F.off_kept = off;    // the states the thresholds kept, a byte per (row, state)
             off = align_up(off + (size_t)(fr.N + 1) * F.Mt);
         }
+        if (F.ck && L.sweep_parts > 1) {
+            F.off_sws = off;
+            off = align_up(off + sizeof(double) * 16);
+        }
         if (F.ck) {
             F.off_ck = off;      // alpha rows 0, ck, 2 ck, .. (row j ck at index j)
             off = align_up(off + sizeof(double) * (size_t)(F.nck + 1) * F.Mt);
@@ -819,6 +894,7 @@ struct Op {
     int stream = 0;            // 0: the run's stream, k > 0: forked stream k - 1
     int slice = -1;            // frame slice, or -1
     int after = -1;            // an earlier op this one also waits for, or -1
+    std::vector<int> afters;   // more earlier ops it waits for (sweep parts)
     std::function<hipError_t(hipStream_t)> fn;
 };
 
@@ -904,9 +980,17 @@ struct mapdec_plan {
     // waits for the same group's launch of the slice before, so that the
     // compute-bound phases advance slice by slice while each slice's chains
     // run beside them.
+    // With the sweep in parts, its forward launches run on forked stream 1
+    // and its backward ones on stream 2, each tracked as a resource of its
+    // own per frame (nf + f, 2 nf + f); the other launches keep streams 0
+    // and 3, and every launch of a main pass also waits for the sweep part
+    // after which its group's checkpoints exist.
     void build_ops() {
         const int nf = L.nframes;
         const bool sliced = L.slices > 1;
+        const bool split = L.sweep_parts > 1;
+        std::vector<int> sweep_fwd(L.sweep_parts, -1), sweep_bwd(L.sweep_parts, -1);
+        std::vector<int> pre_ops;   // the pre-passes' launches (the first part waits for them)
         auto add = [&](int phase, std::vector<int> frames, bool all,
                        std::function<hipError_t(hipStream_t)> fn) {
             Op o;
@@ -926,6 +1010,7 @@ struct mapdec_plan {
         const int fp64 = L.fp64;
         for (const Pass &P : L.passes) {
             const FrameDesc *fd = at<FrameDesc>(P.off_fd);
+            const size_t first_op = ops.size();
             // size of each group, for dealing the groups of a phase to streams
             std::vector<std::pair<long long, size_t>> group;
             auto deal = [&]() {
@@ -941,7 +1026,8 @@ struct mapdec_plan {
                                      return a.first > b.first;
                                  });
                 for (size_t g = 0; g < group.size(); ++g)
-                    ops[group[g].second].stream = (int)(g % (kForkStreams + 1));
+                    ops[group[g].second].stream =
+                        split ? (g % 2 ? kForkStreams : 0) : (int)(g % (kForkStreams + 1));
                 if (group.size() > 1) forked = true;
                 group.clear();
             };
@@ -1015,6 +1101,49 @@ struct mapdec_plan {
                          });
             }
             deal();
+            if (P.kind == kPassSweep && split) {
+                // forward descriptors (frames) first, then backward (extra)
+                auto emit = [&](const std::vector<int> &list, size_t off,
+                                std::function<hipError_t(hipStream_t, const int *, int, int)> launch) {
+                    size_t na = 0;
+                    while (na < list.size() && list[na] < nf) ++na;
+                    for (int dir = 0; dir < 2; ++dir) {
+                        const size_t a = dir ? na : 0, b = dir ? list.size() : na;
+                        if (a == b) continue;
+                        std::vector<int> res;
+                        for (size_t k = a; k < b; ++k) res.push_back((dir ? 2 : 1) * nf + frame_of(list[k]));
+                        const int *tab = at<int>(off) + a;
+                        const int nc = (int)(b - a), dd = dir ? kDirBwd : kDirFwd;
+                        add(kPhChain, sorted_frames(res), false,
+                            [=](hipStream_t st) { return launch(st, tab, nc, dd); });
+                        ops.back().stream = dir ? 2 : 1;
+                        if (P.part == 0) ops.back().afters = pre_ops;
+                        (dir ? sweep_bwd : sweep_fwd)[P.part] = (int)ops.size() - 1;
+                    }
+                };
+                for (auto &kv : P.chain_plain) {
+                    const size_t lds = L.chain_lds;
+                    emit(kv.second, P.off_chain.at(kv.first),
+                         [=](hipStream_t st, const int *tab, int nc, int dd) {
+                             return launch_chain(fp64, fd, tab, nc, dd, lds, st);
+                         });
+                }
+                for (auto &kv : P.chain_ring) {
+                    const int shape = std::get<0>(kv.first), mn = std::get<1>(kv.first);
+                    const size_t lds = L.ring_lds.at(std::make_pair(shape, mn));
+                    int waves = 1;
+                    for (int dsc : kv.second)
+                        waves = std::max(waves, chain_waves(shape, L.fl[frame_of(dsc)].Mt,
+                                                            !L.fl[frame_of(dsc)].gcol));
+                    emit(kv.second, P.off_chain_ring.at(kv.first),
+                         [=](hipStream_t st, const int *tab, int nc, int dd) {
+                             return launch_chain_ring(fp64, shape, mn, waves, fd, tab, nc, dd,
+                                                      lds, st);
+                         });
+                }
+                forked = true;
+                continue;
+            }
             const int dirs = kDirBoth;
             auto steps = [&](int d) {
                 const int f = frame_of(d);
@@ -1053,6 +1182,8 @@ struct mapdec_plan {
                                });
             }
             deal();
+            if (P.kind == kPassPre)
+                for (size_t k = first_op; k < ops.size(); ++k) pre_ops.push_back((int)k);
             if (P.kind != kPassMain) continue;
             if (!P.app_plain.empty()) {
                 const size_t lds = L.app_lds;
@@ -1117,6 +1248,19 @@ struct mapdec_plan {
                          });
             }
             deal();
+            if (split && P.kind == kPassMain) {
+                // the newest launch of each direction up to the part (a part
+                // whose rows are empty for every frame has none)
+                int wf = -1, wb = -1;
+                for (int p = 0; p <= P.part; ++p) {
+                    wf = std::max(wf, sweep_fwd[p]);
+                    wb = std::max(wb, sweep_bwd[p]);
+                }
+                for (size_t k = first_op; k < ops.size(); ++k) {
+                    if (wf >= 0) ops[k].afters.push_back(wf);
+                    if (wb >= 0) ops[k].afters.push_back(wb);
+                }
+            }
         }
         if (L.grad) {
             const FrameDesc *fdl = at<FrameDesc>(L.passes.back().off_fd);
@@ -1152,7 +1296,9 @@ struct mapdec_plan {
         }
         hipStream_t sx[NS] = {st};
         for (int x = 1; x < NS; ++x) sx[x] = side[x - 1];
-        std::vector<int> last(L.nframes, 0);   // per frame: event of its last launch
+        // per resource (frame, then the sweep's forward and backward parts of
+        // every frame): event of its last launch
+        std::vector<int> last(3 * (size_t)L.nframes, 0);
         int tail[NS];                         // per stream: event of its last launch
         int seen[NS][NS];                     // newest event of stream y that x waited for
         std::vector<int> ev_stream(ops.size() + 1, 0);
@@ -1173,6 +1319,7 @@ struct mapdec_plan {
                 for (int f : o.frames) need.push_back(last[f]);
             }
             if (o.after >= 0) need.push_back(o.after + 1);
+            for (int a : o.afters) need.push_back(a + 1);
             if (tail[x] < 0) need.push_back(0);   // first launch on a forked stream
             for (int d : need) {
                 const int y = ev_stream[d];
@@ -1377,6 +1524,7 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
             // (the MFMA APP keeps its exponent scales there in every plan)
             d.Zexp = (L.grad || F.app_mfma) ? reinterpret_cast<int *>(base + F.off_Zexp) : nullptr;
             d.Up = F.app_mfma ? reinterpret_cast<float *>(base + F.off_up) : nullptr;
+            d.sweep_state = F.off_sws ? reinterpret_cast<double *>(base + F.off_sws) : nullptr;
             d.app_parts = F.app_parts;
             d.gacc_all = reinterpret_cast<double *>(base + F.off_gacc);
             d.gacc_n = F.gacc_n;
@@ -1427,19 +1575,40 @@ mapdec_plan *plan_create(const mapdec_frame *frames, int nframes, double *logp, 
                 d.beta = ckb;
                 d.chain_mode = kChainSweep;
                 d.ck_stride = F.ck;
+                if (L.sweep_parts > 1) {   // the forward chain of part P.part
+                    const int p = P.part;
+                    d.i0 = F.swa[p];
+                    d.i1 = F.swa[p + 1];
+                    // from the checkpoint the previous parts left (the
+                    // start state while no part has covered a row)
+                    if (F.swa[p] > 0) d.a_init = cka + (size_t)(F.swa[p] / F.ck) * F.Mt;
+                    // Gamma by symbol: the table from the part's first symbol
+                    // (the chains address it relative to i0)
+                    if (F.gcol) d.G = Gw + T * (size_t)d.i0 * F.Mt;
+                }
             } else if (fr.prior) {
                 // main pass: Gamma stays in the whole-frame table
                 d.G = Gw + T * (size_t)g.i0 * F.Mt;
                 d.gsp = F.gspw;
             }
         }
-        // the chains of each checkpoint segment of a main pass's groups
+        // the chains of each checkpoint segment of a main pass's groups, or
+        // the backward chains of a sweep part
         for (size_t k = 0; k < P.sub_frame.size(); ++k) {
             const int f = P.sub_frame[k], j = P.sub_seg[k];
             const mapdec_frame &fr = frames[f];
             const FrameLayout &F = L.fl[f];
             FrameDesc &d = fd[nframes + k];
             d = fd[f];
+            if (P.kind == kPassSweep) {
+                double *ckb = reinterpret_cast<double *>(base + F.off_ckb);
+                d.i0 = F.swb[j + 1];
+                d.i1 = F.swb[j];
+                d.b_init = F.swb[j] < fr.N ? ckb + (size_t)(F.swb[j] / F.ck) * F.Mt
+                                           : fr.end_drift;
+                if (F.gcol) d.G = base + F.off_Gw + L.tsize * (size_t)d.i0 * F.Mt;
+                continue;
+            }
             const Segment g = segment_of(fr, F, P.seg);
             d.i0 = j * F.ck;
             d.i1 = std::min(fr.N, d.i0 + F.ck);

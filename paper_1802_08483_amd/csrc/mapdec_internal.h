@@ -52,6 +52,8 @@ struct FrameDesc {
     float *Up;            // APP on the MFMA units: [blocks][parts][64][32 D-tiles]
                           // partial sums U of each part of a block's span
     int app_parts;        // parts per block of that APP (1 .. kMfmaPartsMax)
+    double *sweep_state;  // sweep in parts: [2 directions][8] ring-chain scale
+                          // predictor carried from part to part, or NULL
     double *gacc;         // [lattice workgroups of this segment][4] partial
                           // d log P / d(a, d, t1, t0)
     double *gacc_all;     // every segment's partials of the frame, contiguous,

@@ -9,6 +9,11 @@
 // launch must be ordered after the previous launch of every frame it
 // touches (same stream, or through waited events), and when the caller's
 // stream is synchronised it must be ordered after every launch so far.
+// The sweep of checkpointed frames is tracked apart: its forward and
+// backward chains own the frame's forward and backward checkpoint rows (a
+// sweep launch must follow every earlier launch of the frame, and the
+// previous sweep launch of its direction), and a chain that starts from
+// checkpoints must follow the sweep launches that wrote those rows.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -50,6 +55,10 @@ struct Last {
 };
 std::vector<Last> g_last;   // per frame: the stream and tick of its last launch
 Last g_any[kMaxStreams];    // per stream: its last launch
+// per frame and direction: the last sweep launch, and the writer of every
+// checkpoint row
+std::vector<Last> g_sweep[2];
+std::vector<std::map<int, Last>> g_ckrow[2];
 
 [[noreturn]] void die(const char *what) {
     fprintf(stderr, "plan_stub: %s\n", what);
@@ -137,6 +146,10 @@ void stub_set_workspace(void *p, size_t bytes, size_t alloc, int nframes) {
     g_ws_alloc = alloc;
     g_nframes = nframes;
     g_last.assign(nframes, Last{});
+    for (int dir = 0; dir < 2; ++dir) {
+        g_sweep[dir].assign(nframes, Last{});
+        g_ckrow[dir].assign(nframes, {});
+    }
     for (Last &l : g_any) l = Last{};
 }
 long stub_launches() { return g_launches; }
@@ -293,18 +306,92 @@ hipError_t launch_gamma(int, int, const FrameDesc *fd, const Work *t, int nb, hi
     launch(st, work_frames(t, nb), false);
     return hipSuccess;
 }
-hipError_t launch_chain(int, const FrameDesc *fd, const int *fr, int nc, int, size_t,
+namespace {
+// A chain launch: sweep chains (checkpoint rows) apart from the rest.
+void chain_launch(hipStream_t st, const FrameDesc *fd, const int *fr, int nc, int dirs) {
+    const std::vector<int> frames = chain_frames(fd, fr, nc);
+    const std::vector<int> descs = list_frames(fr, nc);
+    if (frames.size() != descs.size() || frames.empty()) {   // not materialised
+        launch(st, frames, false);
+        return;
+    }
+    bool sweep = false;
+    for (int d : descs) sweep |= fd[d].chain_mode == kChainSweep;
+    if (!sweep) {
+        SStream *x = S(st);
+        for (size_t k = 0; k < descs.size(); ++k) {
+            const FrameDesc &d = fd[descs[k]];
+            if (d.chain_mode != kChainSub) continue;
+            const int f = frames[k];
+            // forward row i0 and backward row i1 come from checkpoints
+            if (d.i0 > 0) {
+                auto it = g_ckrow[0][f].find(d.i0);
+                if (it == g_ckrow[0][f].end() || !happened(it->second, x->vc))
+                    die("segment chain not ordered after its forward checkpoint");
+            }
+            if (d.i1 < d.N) {
+                auto it = g_ckrow[1][f].find(d.i1);
+                if (it == g_ckrow[1][f].end() || !happened(it->second, x->vc))
+                    die("segment chain not ordered after its backward checkpoint");
+            }
+        }
+        launch(st, frames, false);
+        return;
+    }
+    SStream *x = S(st);
+    for (size_t k = 0; k < descs.size(); ++k) {
+        const FrameDesc &d = fd[descs[k]];
+        if (d.chain_mode != kChainSweep) die("sweep and other chains in one launch");
+        const int f = frames[k];
+        if (!happened(g_last[f], x->vc)) die("sweep not ordered after the frame's earlier launches");
+        for (int dir = 0; dir < 2; ++dir)
+            if (dirs & (1 << dir))
+                if (!happened(g_sweep[dir][f], x->vc)) die("sweep part not ordered after the previous one");
+        // a part that starts from a checkpoint row: written before it
+        const double *ck[2] = {d.alpha, d.beta};
+        const double *init[2] = {d.a_init, d.b_init};
+        const int row[2] = {d.i0, d.i1};
+        for (int dir = 0; dir < 2; ++dir) {
+            if (!(dirs & (1 << dir)) || !init[dir]) continue;
+            const bool from_ck = init[dir] >= ck[dir] &&
+                                 init[dir] <= ck[dir] + (size_t)(d.N / d.ck_stride + 1) * d.Mt;
+            if (!from_ck) continue;
+            if (init[dir] != ck[dir] + (size_t)(row[dir] / d.ck_stride) * d.Mt)
+                die("sweep part starts from another checkpoint row than its first");
+            auto it = g_ckrow[dir][f].find(row[dir]);
+            if (it == g_ckrow[dir][f].end() || !happened(it->second, x->vc))
+                die("sweep part starts from a checkpoint row not written before it");
+        }
+    }
+    x->vc.t[x->id] += 1;
+    const Last me{x->id, x->vc.t[x->id]};
+    for (size_t k = 0; k < descs.size(); ++k) {
+        const FrameDesc &d = fd[descs[k]];
+        const int f = frames[k];
+        for (int dir = 0; dir < 2; ++dir) {
+            if (!(dirs & (1 << dir))) continue;
+            g_sweep[dir][f] = me;
+            for (int r = d.i0; r <= d.i1; ++r)
+                if (r % d.ck_stride == 0) g_ckrow[dir][f][r] = me;
+        }
+    }
+    g_any[x->id] = me;
+    ++g_launches;
+}
+}  // namespace
+
+hipError_t launch_chain(int, const FrameDesc *fd, const int *fr, int nc, int dirs, size_t,
                         hipStream_t st) {
     check_fd(fd);
-    launch(st, chain_frames(fd, fr, nc), false);
+    chain_launch(st, fd, fr, nc, dirs);
     return hipSuccess;
 }
 hipError_t launch_chain_ring(int, int shape, int, int waves, const FrameDesc *fd, const int *fr,
-                             int nc, int, size_t lds, hipStream_t st) {
+                             int nc, int dirs, size_t lds, hipStream_t st) {
     check_fd(fd);
     if (shape < 0 || shape >= kNumRingShapes || lds > 160 * 1024) die("bad ring launch");
     if (waves < 1 || waves > kRingShapes[shape].nw) die("bad ring wave count");
-    launch(st, chain_frames(fd, fr, nc), false);
+    chain_launch(st, fd, fr, nc, dirs);
     return hipSuccess;
 }
 hipError_t launch_app(int, const FrameDesc *fd, const Work *t, int nb, size_t, hipStream_t st) {

@@ -130,11 +130,14 @@ def _golden(f):
     return json.load(open(path))
 
 
-def test_long_frame_workload_against_stored_oracle_values():
+@pytest.mark.parametrize("graph", [True, False])
+def test_long_frame_workload_against_stored_oracle_values(graph):
+    # graph: one stream, the sweep in one launch; eager: the sweep in parts
+    # beside the main passes of the groups whose checkpoints are done
     frames = wl.make_workload(5)
     K = 100
     b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=True, checkpoint_K=K)
-    p = b.plan(graph=True)
+    p = b.plan(graph=graph)
     p.run()
     torch.cuda.synchronize()
     p.close()
