@@ -236,7 +236,7 @@ constexpr int kSlices = 4;
 // Eager plans of checkpointed frames run the sweep in this many parts, so
 // that the main passes of groups whose checkpoints are done run beside the
 // rest of it (the sweep holds one workgroup per chain and direction).
-constexpr int kSweepParts = 8;
+constexpr int kSweepParts = 16;
 constexpr int kSliceMinFrames = 16;
 
 // Reorders a work list so that the workgroups the dispatcher sends to one
