@@ -302,7 +302,8 @@ __global__ __launch_bounds__(256) void k_app_fin(const FrameDesc *__restrict__ f
     const Work w = tab[blockIdx.x];
     const FrameDesc &f = fd[w.frame];
     if (*f.status != kStatusOk) return;
-    __shared__ float Ush[kTB * 32 * QT];
+    constexpr int US = 32 * QT + 1;   // odd row stride: a symbol per lane without bank conflicts
+    __shared__ float Ush[kTB * US];
     __shared__ double Zsh[kTB];
     const int tid = threadIdx.x, q = f.q, parts = f.app_parts;
     const int i0 = f.i0 + w.item * kTB;
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(256) void k_app_fin(const FrameDesc *__restrict__ f
     for (int x = tid; x < kTB * 32 * QT; x += 256) {
         float u = 0.f;
         for (int p = 0; p < parts; ++p) u += Up[(size_t)p * kTB * 32 * QT + x];
-        Ush[x] = u;
+        Ush[(x / (32 * QT)) * US + x % (32 * QT)] = u;
     }
     __syncthreads();
     const float up = 1.f / (float)q;
@@ -319,14 +320,14 @@ __global__ __launch_bounds__(256) void k_app_fin(const FrameDesc *__restrict__ f
         const int i = i0 + tid;
         const float *pr = f.uniform ? nullptr : (const float *)f.prior + (size_t)i * q;
         double Z = 0.0;
-        for (int D = 0; D < q; ++D) Z += (double)((pr ? pr[D] : up) * Ush[tid * 32 * QT + D]);
+        for (int D = 0; D < q; ++D) Z += (double)((pr ? pr[D] : up) * Ush[tid * US + D]);
         Zsh[tid] = Z;
         if (f.Zinv) f.Zinv[i] = Z > 0.0 ? 1.0 / Z : 0.0;
     }
     __syncthreads();
     for (int x = tid; x < nsym * q; x += 256) {
         const int j = x / q, D = x - j * q, i = i0 + j;
-        const float u = Ush[j * 32 * QT + D];
+        const float u = Ush[j * US + D];
         const float p = f.uniform ? up : ((const float *)f.prior)[(size_t)i * q + D];
         const float Zi = (float)Zsh[j];
         if (f.app) ((float *)f.app)[(size_t)i * q + D] = p * u / Zi;

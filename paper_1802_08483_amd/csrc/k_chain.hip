@@ -52,7 +52,11 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
     const int mode = f.chain_mode, cks = f.ck_stride;
     auto stored = [&](int r) { return mode != kChainSweep || r % cks == 0; };
     auto slot = [&](int r) { return (size_t)(mode == kChainSweep ? r / cks : r - i0) * Mt; };
-    const bool put_init = mode == kChainSub ? ((f.wr_init >> dir) & 1) != 0 : stored(row0);
+    // a sweep part after the first starts from the checkpoint (and its log)
+    // the previous part wrote, which main passes may be reading already
+    const bool resumed = mode == kChainSweep && (dir == 0 ? i0 > 0 : i1 < N);
+    const bool put_init = mode == kChainSub ? ((f.wr_init >> dir) & 1) != 0
+                                            : stored(row0) && !resumed;
     const bool logs = mode != kChainSub;
     const double lbase = (logs && (dir == 0 ? i0 > 0 : i1 < N)) ? logX[row0] : 0.0;
     // a boundary prior's entries whose received position (m at the start,
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(kChainThreads) void k_chain(const FrameDesc *__rest
     }
     if (put_init)
         for (int mi = tid; mi < Mt; mi += nth) out[slot(row0) + mi] = buf0[mn + mi];
-    if (tid == 0 && logs) logX[row0] = lbase;
+    if (tid == 0 && logs && !resumed) logX[row0] = lbase;
     __syncthreads();
 
     const T *G = (const T *)f.G;

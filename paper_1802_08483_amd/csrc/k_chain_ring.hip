@@ -131,7 +131,11 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     const int mode = f.chain_mode, cks = f.ck_stride;
     auto stored = [&](int r) { return mode != kChainSweep || r % cks == 0; };
     auto slot = [&](int r) { return (size_t)(mode == kChainSweep ? r / cks : r - i0) * Mt; };
-    const bool put_init = mode == kChainSub ? ((f.wr_init >> DIR) & 1) != 0 : stored(rowA);
+    // a sweep part after the first starts from the checkpoint the previous
+    // part wrote, which main passes may be reading already: not rewritten
+    const bool resumed = mode == kChainSweep && (DIR == 0 ? i0 > 0 : i1 < N);
+    const bool put_init = mode == kChainSub ? ((f.wr_init >> DIR) & 1) != 0
+                                            : stored(rowA) && !resumed;
     // drift states kept (asymmetric limits): indices [lo_i, hi_i]
     const int lo_i = f.lim_lo + M, hi_i = f.lim_hi + M;
     // path thresholds: the forward chain over the frame decides which
@@ -172,7 +176,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     // apply the scales the sweep in one launch would, and their logs are the
     // same bits.
     double *sst = mode == kChainSweep && f.sweep_state ? f.sweep_state + 8 * DIR : nullptr;
-    const bool resume = sst && (DIR == 0 ? i0 > 0 : i1 < N);
+    const bool resume = sst && resumed;
     const bool suspend = sst && (DIR == 0 ? i1 < N : i0 > 0);
     const double lbase =
         (!resume && mode != kChainSub && (DIR == 0 ? i0 > 0 : i1 < N)) ? logX[rowA] : 0.0;

@@ -990,7 +990,7 @@ struct mapdec_plan {
         const bool sliced = L.slices > 1;
         const bool split = L.sweep_parts > 1;
         std::vector<int> sweep_fwd(L.sweep_parts, -1), sweep_bwd(L.sweep_parts, -1);
-        std::vector<int> pre_ops;   // the pre-passes' launches (the first part waits for them)
+        std::vector<int> pre_ops;   // the pre-passes' launches (each sweep direction's first launch waits for them)
         auto add = [&](int phase, std::vector<int> frames, bool all,
                        std::function<hipError_t(hipStream_t)> fn) {
             Op o;
@@ -1117,8 +1117,12 @@ struct mapdec_plan {
                         add(kPhChain, sorted_frames(res), false,
                             [=](hipStream_t st) { return launch(st, tab, nc, dd); });
                         ops.back().stream = dir ? 2 : 1;
-                        if (P.part == 0) ops.back().afters = pre_ops;
-                        (dir ? sweep_bwd : sweep_fwd)[P.part] = (int)ops.size() - 1;
+                        // the direction's first launch waits for the pre-passes
+                        // (its first parts may be empty for every frame)
+                        std::vector<int> &mine = dir ? sweep_bwd : sweep_fwd;
+                        if (*std::max_element(mine.begin(), mine.end()) < 0)
+                            ops.back().afters = pre_ops;
+                        mine[P.part] = (int)ops.size() - 1;
                     }
                 };
                 for (auto &kv : P.chain_plain) {
@@ -1185,6 +1189,21 @@ struct mapdec_plan {
             if (P.kind == kPassPre)
                 for (size_t k = first_op; k < ops.size(); ++k) pre_ops.push_back((int)k);
             if (P.kind != kPassMain) continue;
+            // every launch of a main pass waits for the newest launch of each
+            // sweep direction up to the part after which its checkpoints
+            // exist (a part whose rows are empty for every frame has none)
+            auto wait_sweep = [&]() {
+                if (!split) return;
+                int wf = -1, wb = -1;
+                for (int p = 0; p <= P.part; ++p) {
+                    wf = std::max(wf, sweep_fwd[p]);
+                    wb = std::max(wb, sweep_bwd[p]);
+                }
+                for (size_t k = first_op; k < ops.size(); ++k) {
+                    if (wf >= 0) ops[k].afters.push_back(wf);
+                    if (wb >= 0) ops[k].afters.push_back(wb);
+                }
+            };
             if (!P.app_plain.empty()) {
                 const size_t lds = L.app_lds;
                 add_work(kPhApp, true, P.app_plain, P.off_app,
@@ -1226,7 +1245,10 @@ struct mapdec_plan {
                          });
             }
             deal();
-            if (!L.grad) continue;
+            if (!L.grad) {
+                wait_sweep();
+                continue;
+            }
             for (auto &kv : P.wlat) {
                 const int mn = std::get<0>(kv.first), uni = std::get<1>(kv.first),
                           pc = std::get<2>(kv.first);
@@ -1248,19 +1270,7 @@ struct mapdec_plan {
                          });
             }
             deal();
-            if (split && P.kind == kPassMain) {
-                // the newest launch of each direction up to the part (a part
-                // whose rows are empty for every frame has none)
-                int wf = -1, wb = -1;
-                for (int p = 0; p <= P.part; ++p) {
-                    wf = std::max(wf, sweep_fwd[p]);
-                    wb = std::max(wb, sweep_bwd[p]);
-                }
-                for (size_t k = first_op; k < ops.size(); ++k) {
-                    if (wf >= 0) ops[k].afters.push_back(wf);
-                    if (wb >= 0) ops[k].afters.push_back(wb);
-                }
-            }
+            wait_sweep();
         }
         if (L.grad) {
             const FrameDesc *fdl = at<FrameDesc>(L.passes.back().off_fd);

@@ -326,8 +326,12 @@ void chain_launch(hipStream_t st, const FrameDesc *fd, const int *fr, int nc, in
             // forward row i0 and backward row i1 come from checkpoints
             if (d.i0 > 0) {
                 auto it = g_ckrow[0][f].find(d.i0);
-                if (it == g_ckrow[0][f].end() || !happened(it->second, x->vc))
+                if (it == g_ckrow[0][f].end() || !happened(it->second, x->vc)) {
+                    fprintf(stderr, "plan_stub: frame %d rows [%d, %d) of %d: row %d %s\n", f, d.i0,
+                            d.i1, d.N, d.i0,
+                            it == g_ckrow[0][f].end() ? "never written" : "written later");
                     die("segment chain not ordered after its forward checkpoint");
+                }
             }
             if (d.i1 < d.N) {
                 auto it = g_ckrow[1][f].find(d.i1);
@@ -371,7 +375,12 @@ void chain_launch(hipStream_t st, const FrameDesc *fd, const int *fr, int nc, in
         for (int dir = 0; dir < 2; ++dir) {
             if (!(dirs & (1 << dir))) continue;
             g_sweep[dir][f] = me;
-            for (int r = d.i0; r <= d.i1; ++r)
+            // the rows the chain computes, and its starting row unless it
+            // resumes from a checkpoint (not rewritten)
+            const bool resumed = dir == 0 ? d.i0 > 0 : d.i1 < d.N;
+            const int lo = dir == 0 && resumed ? d.i0 + 1 : d.i0;
+            const int hi = dir == 1 && resumed ? d.i1 - 1 : d.i1;
+            for (int r = lo; r <= hi; ++r)
                 if (r % d.ck_stride == 0) g_ckrow[dir][f][r] = me;
         }
     }

@@ -146,3 +146,40 @@ def test_long_frame_workload_full_size():
         _compare(ck, f, full.apps[f].double().cpu().numpy(), float(full.logp[f]),
                  full.dparams[f].cpu().numpy(), full.dpriors[f].double().cpu().numpy(),
                  SELF_TOL[mapdec.FP32], f"long frame {f}")
+
+
+@pytest.mark.parametrize("grad", [False, True])
+def test_sweep_parts_eager_equal_serial(grad):
+    # Eager plans run the checkpoint sweep in parts on streams of their own.
+    # With N = 150 and K = 13 the first forward part holds no rows
+    # (150 / 16 < 13), so the forward sweep's first launch belongs to a later
+    # part and must still wait for Gamma; decode-only plans must wait for the
+    # parts their checkpoints come from.  Three eager runs give the serial
+    # plan's bits, and both meet the oracle's bars.
+    N = 150
+    M = wl.drift_limit(12 * N, 0.1)
+    frames = [wl.random_frame(70 + f, 64, 12, N, 0.1, 0.1, 0.0, 2, M, 8) for f in range(2)]
+    K = 13
+    assert N * 1 // 16 // K == 0
+    refs = [oracle.decode_frame(fr, grad=grad) for fr in frames]
+
+    def outputs(serial):
+        b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=grad, checkpoint_K=K)
+        p = b.plan(graph=False, serial=serial)
+        p.run()
+        torch.cuda.synchronize()
+        out = [b.status.cpu().clone(), b.logp.cpu().clone()] + [a.cpu().clone() for a in b.apps]
+        if grad:
+            out += [g.cpu().clone() for g in b.dparams] + [d.cpu().clone() for d in b.dpriors]
+        for f, ref in enumerate(refs):
+            _compare(b, f, ref["app"], ref["logp"], ref["dparams"] if grad else None,
+                     ref["dprior"] if grad else None, ORACLE_TOL[mapdec.FP32],
+                     f"{'serial' if serial else 'eager'} frame {f}")
+        p.close()
+        return out
+
+    want = outputs(True)
+    for rep in range(3):
+        got = outputs(False)
+        for k, (g, w) in enumerate(zip(got, want)):
+            assert torch.equal(g, w), f"eager run {rep}: output {k}"

@@ -47,6 +47,9 @@ def driver(tmp_path_factory):
     (160, 0, GRAD | TUNE, 0),          # tuning plan, then the tuned plan
     (32, 0, GRAD | GRAPH, 1),          # uniform batch: one group per phase
     (32, 40, GRAD, 1),
+    (2, 13, 0, 1),                     # sweep in parts whose first forward part is empty
+    (2, 13, GRAD, 1),
+    (8, 13, 0, 0),                     # decode only, sweep in parts
     (128, 0, GRAD, 1),                 # eager uniform batch in frame slices
     (128, 0, GRAD | SERIAL, 1),
     (60, 0, GRAD, 2),                  # with general-scheme frames
