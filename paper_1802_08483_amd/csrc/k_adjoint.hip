@@ -209,8 +209,10 @@ __global__ __launch_bounds__(64) void k_wadj_col(const FrameDesc *__restrict__ f
 // ---------------------------------------------------------------------------
 // Backward sweep through the lattices.  Lane = start index s, loop over D
 // (codeword bits are wave-uniform).  The even forward rows F_2, F_4, .. below
-// row n are parked in LDS as 16-byte slots ([row][slot][lane],
-// conflict-free) and each odd row is recomputed from the even row under it
+// row n are parked in LDS, 2 mn + 1 values per lane and row with no padding
+// (16-byte slots [row][slot][lane] for the first values, then the last
+// values one by one, [row][value][lane]), and each odd row is recomputed
+// from the even row under it
 // when the sweep needs it (half the LDS, so twice the waves per SIMD, for
 // one extra forward row per two rows); the sweep then
 // runs from the last row up, with corridor coordinates k = j - r + MN as in
@@ -265,7 +267,8 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
     constexpr int KW = 2 * MN + 1;
     constexpr int NB = kMaxN + MN;
     constexpr int VE = Slot<T>::E;
-    constexpr int KV = (KW + VE - 1) / VE;
+    constexpr int KV = KW / VE;          // full 16-byte slots of a parked row
+    constexpr int KT = KW - KV * VE;     // values after them
     extern __shared__ __align__(16) unsigned char smem[];
     const Work w = tab[blockIdx.x];
     const FrameDesc &f = fd[w.frame];
@@ -290,7 +293,9 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
     }
     const uint32_t cmask = GEN ? f.cmask : 0xffffffffu;
     const T d = (T)f.d, t1 = (T)f.t1, t0 = (T)f.t0;
-    Slot<T> *rows = (Slot<T> *)smem;   // [(n - 1) / 2][KV][64]: F_2, F_4, ..
+    // parked row r / 2 - 1 (F_r): 64 KW values from smem + (r / 2 - 1) 64 KW
+    // sizeof(T), a multiple of 16 bytes
+    auto row_at = [&](int r) { return smem + (size_t)(r / 2 - 1) * 64 * KW * sizeof(T); };
 
     T apow[IM + 1], dapow[IM + 1];
     {
@@ -328,24 +333,30 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
     const size_t sp = (size_t)f.sp;
     double ga = 0.0, gd = 0.0, g1 = 0.0, g0 = 0.0;
 
-    // slot r / 2 - 1 holds the even row F_r
     auto park = [&](int r, const T(&F)[KW]) {
+        Slot<T> *sl = (Slot<T> *)row_at(r);
+        T *tl = (T *)(sl + KV * 64);
 #pragma unroll
         for (int c = 0; c < KV; ++c) {
             Slot<T> sv;
 #pragma unroll
-            for (int e = 0; e < VE; ++e) sv.v[e] = (c * VE + e < KW) ? F[c * VE + e] : T(0);
-            rows[((r / 2 - 1) * KV + c) * 64 + lane] = sv;
+            for (int e = 0; e < VE; ++e) sv.v[e] = F[c * VE + e];
+            sl[c * 64 + lane] = sv;
         }
+#pragma unroll
+        for (int t = 0; t < KT; ++t) tl[t * 64 + lane] = F[KV * VE + t];
     };
     auto unpark = [&](int r, T(&F)[KW]) {
+        const Slot<T> *sl = (const Slot<T> *)row_at(r);
+        const T *tl = (const T *)(sl + KV * 64);
 #pragma unroll
         for (int c = 0; c < KV; ++c) {
-            const Slot<T> sv = rows[((r / 2 - 1) * KV + c) * 64 + lane];
+            const Slot<T> sv = sl[c * 64 + lane];
 #pragma unroll
-            for (int e = 0; e < VE; ++e)
-                if (c * VE + e < KW) F[c * VE + e] = sv.v[e];
+            for (int e = 0; e < VE; ++e) F[c * VE + e] = sv.v[e];
         }
+#pragma unroll
+        for (int t = 0; t < KT; ++t) F[KV * VE + t] = tl[t * 64 + lane];
     };
 
     const int Dlo = chunk * f.dq, Dhi = min(q, Dlo + f.dq);

@@ -97,10 +97,9 @@ hipError_t adj_f32_lattice(int mn, int imode, int sa, int gen, const FrameDesc *
 hipError_t adj_f64_lattice(int mn, int imode, int sa, int gen, const FrameDesc *fd,
                            const Work *tab, int nblocks, size_t lds, hipStream_t st);
 // LDS bytes of one adjoint workgroup: the even rows F_2, F_4, .. below row
-// n of 64 lattices, each row in 16-byte slots
+// n of 64 lattices, 2 mn + 1 values of each row per lattice
 constexpr size_t adjoint_lds(int nmax, int mn, size_t tsize) {
-    return (size_t)(nmax > 1 ? (nmax - 1) / 2 : 0) *
-           (((size_t)(2 * mn + 1) + 16 / tsize - 1) / (16 / tsize)) * 64 * 16;
+    return (size_t)(nmax > 1 ? (nmax - 1) / 2 : 0) * (size_t)(2 * mn + 1) * 64 * tsize;
 }
 // The sweep accumulates d/da itself when a g_a = rho - tau + d g_d would be
 // a small difference of larger terms (Pi zero or below Pd / 4).
