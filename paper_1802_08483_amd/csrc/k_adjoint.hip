@@ -209,10 +209,11 @@ __global__ __launch_bounds__(64) void k_wadj_col(const FrameDesc *__restrict__ f
 // ---------------------------------------------------------------------------
 // Backward sweep through the lattices.  Lane = start index s, loop over D
 // (codeword bits are wave-uniform).  The even forward rows F_2, F_4, .. below
-// row n are parked in LDS, 2 mn + 1 values per lane and row with no padding
-// (16-byte slots [row][slot][lane] for the first values, then the last
-// values one by one, [row][value][lane]), and each odd row is recomputed
-// from the even row under it
+// row n are parked in LDS with no padding: 16-byte slots [slot][lane] of
+// 16 / sizeof(T) corridor coordinates each, then the last coordinates one
+// by one, [value][lane]; a slot wholly below mn - r is not stored (a node
+// there would have consumed fewer than 0 received bits: always zero).  Each
+// odd row is recomputed from the even row under it
 // when the sweep needs it (half the LDS, so twice the waves per SIMD, for
 // one extra forward row per two rows); the sweep then
 // runs from the last row up, with corridor coordinates k = j - r + MN as in
@@ -267,8 +268,6 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
     constexpr int KW = 2 * MN + 1;
     constexpr int NB = kMaxN + MN;
     constexpr int VE = Slot<T>::E;
-    constexpr int KV = KW / VE;          // full 16-byte slots of a parked row
-    constexpr int KT = KW - KV * VE;     // values after them
     extern __shared__ __align__(16) unsigned char smem[];
     const Work w = tab[blockIdx.x];
     const FrameDesc &f = fd[w.frame];
@@ -293,9 +292,12 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
     }
     const uint32_t cmask = GEN ? f.cmask : 0xffffffffu;
     const T d = (T)f.d, t1 = (T)f.t1, t0 = (T)f.t0;
-    // parked row r / 2 - 1 (F_r): 64 KW values from smem + (r / 2 - 1) 64 KW
-    // sizeof(T), a multiple of 16 bytes
-    auto row_at = [&](int r) { return smem + (size_t)(r / 2 - 1) * 64 * KW * sizeof(T); };
+    // parked row F_r (r even): park_values(MN, r, VE) values of 64 lanes from
+    // value park_offset<MN>(r, VE) of the region (64 sizeof(T) bytes per
+    // value: every row starts on a 16-byte boundary)
+    auto row_at = [&](int r) {
+        return smem + (size_t)park_offset<MN>(r, VE) * 64 * sizeof(T);
+    };
 
     T apow[IM + 1], dapow[IM + 1];
     {
@@ -333,11 +335,16 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
     const size_t sp = (size_t)f.sp;
     double ga = 0.0, gd = 0.0, g1 = 0.0, g0 = 0.0;
 
+    // (r is a constant in every call: the row loops are unrolled)
+    constexpr int KV = KW / VE;        // 16-byte slots of a row, then KT values
+    constexpr int KT = KW - KV * VE;
     auto park = [&](int r, const T(&F)[KW]) {
-        Slot<T> *sl = (Slot<T> *)row_at(r);
+        const int c0 = park_first<MN>(r) / VE;   // slots below c0 hold zeros only
+        Slot<T> *sl = (Slot<T> *)row_at(r) - c0 * 64;
         T *tl = (T *)(sl + KV * 64);
 #pragma unroll
         for (int c = 0; c < KV; ++c) {
+            if (c < c0) continue;
             Slot<T> sv;
 #pragma unroll
             for (int e = 0; e < VE; ++e) sv.v[e] = F[c * VE + e];
@@ -347,10 +354,16 @@ __global__ __launch_bounds__(64) void k_adjoint(const FrameDesc *__restrict__ fd
         for (int t = 0; t < KT; ++t) tl[t * 64 + lane] = F[KV * VE + t];
     };
     auto unpark = [&](int r, T(&F)[KW]) {
-        const Slot<T> *sl = (const Slot<T> *)row_at(r);
+        const int c0 = park_first<MN>(r) / VE;
+        const Slot<T> *sl = (const Slot<T> *)row_at(r) - c0 * 64;
         const T *tl = (const T *)(sl + KV * 64);
 #pragma unroll
         for (int c = 0; c < KV; ++c) {
+            if (c < c0) {
+#pragma unroll
+                for (int e = 0; e < VE; ++e) F[c * VE + e] = T(0);
+                continue;
+            }
             const Slot<T> sv = sl[c * 64 + lane];
 #pragma unroll
             for (int e = 0; e < VE; ++e) F[c * VE + e] = sv.v[e];

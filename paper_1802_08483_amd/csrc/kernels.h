@@ -96,10 +96,29 @@ hipError_t adj_f32_lattice(int mn, int imode, int sa, int gen, const FrameDesc *
                            const Work *tab, int nblocks, size_t lds, hipStream_t st);
 hipError_t adj_f64_lattice(int mn, int imode, int sa, int gen, const FrameDesc *fd,
                            const Work *tab, int nblocks, size_t lds, hipStream_t st);
-// LDS bytes of one adjoint workgroup: the even rows F_2, F_4, .. below row
-// n of 64 lattices, 2 mn + 1 values of each row per lattice
+// The adjoint parks the even forward rows F_2, F_4, .. below row n of its
+// 64 lattices in LDS, each in 16-byte slots of E = 16 / sizeof(T) corridor
+// coordinates, then the last 2 mn + 1 - E floor((2 mn + 1) / E) one by one;
+// row r leaves out the first park_first(r) / E slots (coordinates below
+// mn - r: a node there would have consumed fewer than 0 received bits, so
+// it is zero).  park_values(r) values of 64 lanes per row, park_offset(r)
+// before row r.
+template <int MN>
+__host__ __device__ constexpr int park_first(int r) { return MN > r ? MN - r : 0; }
+__host__ __device__ constexpr int park_values(int mn, int r, int e) {
+    return 2 * mn + 1 - (mn > r ? mn - r : 0) / e * e;
+}
+template <int MN>
+__host__ __device__ constexpr int park_offset(int r, int e) {
+    int o = 0;
+    for (int p = 2; p < r; p += 2) o += park_values(MN, p, e);
+    return o;
+}
+// LDS bytes of one adjoint workgroup for codewords of up to nmax bits
 constexpr size_t adjoint_lds(int nmax, int mn, size_t tsize) {
-    return (size_t)(nmax > 1 ? (nmax - 1) / 2 : 0) * (size_t)(2 * mn + 1) * 64 * tsize;
+    size_t v = 0;
+    for (int r = 2; r <= nmax - 1; r += 2) v += (size_t)park_values(mn, r, (int)(16 / tsize));
+    return v * 64 * tsize;
 }
 // The sweep accumulates d/da itself when a g_a = rho - tau + d g_d would be
 // a small difference of larger terms (Pi zero or below Pd / 4).
