@@ -98,6 +98,10 @@ struct FrameLayout {
     // part p rows [swb[p+1], swb[p]) (checkpoint rows, swa[0] = 0, swb[0] = N)
     std::vector<int> swa, swb;
     size_t off_sws = 0;   // the sweep's carried scale predictor (parts > 1)
+    // Gamma pre-pass in rounds (sweep in parts, Gamma by start index): the
+    // round of each block of kLatticeLanes start indices, the first whose
+    // sweep parts read it
+    std::vector<int> pre_round;
     // percol: a codebook per symbol, R by (symbol, drift state); gcol: Gamma
     // by (symbol, drift state) (general priors, or percol); gen: the lattice
     // and adjoint kernels' general-scheme instance (percol, or a corridor
@@ -201,6 +205,7 @@ struct Layout {
     int slices = 1;
     // parts of the sweep of checkpointed frames (1: one launch)
     int sweep_parts = 1;
+    bool pre_rounds = false;   // the Gamma pre-pass in rounds beside the sweep parts
     std::vector<int> fslice;
     size_t tsize = 4;
     size_t off_pack = 0, head = 0, total = 0;
@@ -549,25 +554,18 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
     // passes: pre-passes and the sweep (checkpointed frames), then main
     // passes over groups S-1 .. 0 (the last pass covers group 0)
     int npre = 0;
-    bool any_ck = false;
+    bool any_ck = false, gcol_ck = false, pruned_ck = false;
     for (int f = 0; f < nframes; ++f) {
         const FrameLayout &F = L.fl[f];
         if (!F.ck) continue;
         any_ck = true;
+        gcol_ck |= F.gcol;
+        pruned_ck |= F.pruned;
         npre = std::max(npre, F.gcol ? F.nseg : 1);
-    }
-    for (int j = 0; j < npre; ++j) {
-        Pass P;
-        P.kind = kPassPre;
-        P.seg = j;
-        L.passes.push_back(P);
     }
     // The sweep in parts (eager plans without path thresholds or frame
     // slices): the forward chains advance from the start, the backward ones
     // from the end, so the checkpoints of the middle groups are done first.
-    bool pruned_ck = false;
-    for (int f = 0; f < nframes; ++f)
-        if (L.fl[f].ck && L.fl[f].pruned) pruned_ck = true;
     L.sweep_parts = (any_ck && !pruned_ck && L.slices == 1 &&
                      !(flags & (MAPDEC_FLAG_GRAPH | MAPDEC_FLAG_SERIAL)))
                         ? kSweepParts : 1;
@@ -582,6 +580,41 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
             F.swa[p] = p == SP ? (int)N : (int)(N * p / SP / K * K);
             F.swb[p] = p == 0 ? (int)N : (int)((N - N * p / SP) / K * K);
         }
+    }
+    // With the sweep in parts and Gamma by start index, the pre-pass runs in
+    // rounds beside the sweep: round r holds the blocks of start indices
+    // that forward or backward part r reads first (rows [i0, i1) read
+    // Gamma at n i0 - M .. n (i1 - 1) + M), and part r waits for rounds
+    // 0 .. r only.
+    L.pre_rounds = SP > 1 && !gcol_ck;
+    if (L.pre_rounds) {
+        npre = SP;
+        for (int f = 0; f < nframes; ++f) {
+            FrameLayout &F = L.fl[f];
+            if (!F.ck) continue;
+            const mapdec_frame &fr = frames[f];
+            const int n = fr.code->n, M = fr.code->M;
+            const int nb = (fr.rho + kLatticeLanes) / kLatticeLanes;
+            F.pre_round.assign(nb, -1);
+            auto mark = [&](int r, int i0, int i1) {
+                if (i1 <= i0) return;
+                const int lo = std::max(0, n * i0 - M), hi = std::min(fr.rho, n * (i1 - 1) + M);
+                for (int b = lo / kLatticeLanes; b <= hi / kLatticeLanes; ++b)
+                    if (F.pre_round[b] < 0) F.pre_round[b] = r;
+            };
+            for (int r = 0; r < SP; ++r) {
+                mark(r, F.swa[r], F.swa[r + 1]);
+                mark(r, F.swb[r + 1], F.swb[r]);
+            }
+            for (int &r : F.pre_round)   // start indices no chain reads
+                if (r < 0) r = SP - 1;
+        }
+    }
+    for (int j = 0; j < npre; ++j) {
+        Pass P;
+        P.kind = kPassPre;
+        P.seg = j;
+        L.passes.push_back(P);
     }
     if (any_ck)
         for (int p = 0; p < SP; ++p) {
@@ -645,13 +678,16 @@ int build_layout(const mapdec_frame *frames, int nframes, int precision, int fla
                 continue;
             }
             if (P.kind == kPassPre) {
-                if (!F.ck || j >= (F.gcol ? F.nseg : 1)) continue;
-                auto &lv = P.lat[std::make_tuple(c->mn, frame_imode(c), F.gen ? 1 : 0)];
-                if (!F.gcol) {   // every start index, Gamma only
+                if (!F.ck || j >= (L.pre_rounds ? L.sweep_parts : F.gcol ? F.nseg : 1)) continue;
+                const auto lkey = std::make_tuple(c->mn, frame_imode(c), F.gen ? 1 : 0);
+                if (!F.gcol) {   // every start index (of the round), Gamma only
                     const int nb = (fr.rho + kLatticeLanes) / kLatticeLanes;
-                    for (int b = 0; b < nb; ++b) lv.push_back(Work{f, b * kLatticeLanes});
+                    for (int b = 0; b < nb; ++b)
+                        if (!L.pre_rounds || F.pre_round[b] == j)
+                            P.lat[lkey].push_back(Work{f, b * kLatticeLanes});
                     continue;
                 }
+                auto &lv = P.lat[lkey];
                 const Segment g = segment_of(fr, F, j);
                 const int nb = blocks_of(F, g);
                 for (int b = 0; b < nb; ++b)
@@ -990,7 +1026,10 @@ struct mapdec_plan {
         const bool sliced = L.slices > 1;
         const bool split = L.sweep_parts > 1;
         std::vector<int> sweep_fwd(L.sweep_parts, -1), sweep_bwd(L.sweep_parts, -1);
-        std::vector<int> pre_ops;   // the pre-passes' launches (each sweep direction's first launch waits for them)
+        // the pre-passes' launches, by pre-pass (with rounds: sweep part p
+        // waits for those of rounds 0 .. p; else each sweep direction's
+        // first launch waits for all)
+        std::vector<std::vector<int>> pre_ops(1);
         auto add = [&](int phase, std::vector<int> frames, bool all,
                        std::function<hipError_t(hipStream_t)> fn) {
             Op o;
@@ -1120,8 +1159,13 @@ struct mapdec_plan {
                         // the direction's first launch waits for the pre-passes
                         // (its first parts may be empty for every frame)
                         std::vector<int> &mine = dir ? sweep_bwd : sweep_fwd;
-                        if (*std::max_element(mine.begin(), mine.end()) < 0)
-                            ops.back().afters = pre_ops;
+                        if (L.pre_rounds) {
+                            for (int r = 0; r <= P.part && r < (int)pre_ops.size(); ++r)
+                                for (int k : pre_ops[r]) ops.back().afters.push_back(k);
+                        } else if (*std::max_element(mine.begin(), mine.end()) < 0) {
+                            for (const auto &v : pre_ops)
+                                for (int k : v) ops.back().afters.push_back(k);
+                        }
                         mine[P.part] = (int)ops.size() - 1;
                     }
                 };
@@ -1186,8 +1230,11 @@ struct mapdec_plan {
                                });
             }
             deal();
-            if (P.kind == kPassPre)
-                for (size_t k = first_op; k < ops.size(); ++k) pre_ops.push_back((int)k);
+            if (P.kind == kPassPre) {
+                const size_t j = L.pre_rounds ? (size_t)P.seg : 0;
+                if (pre_ops.size() <= j) pre_ops.resize(j + 1);
+                for (size_t k = first_op; k < ops.size(); ++k) pre_ops[j].push_back((int)k);
+            }
             if (P.kind != kPassMain) continue;
             // every launch of a main pass waits for the newest launch of each
             // sweep direction up to the part after which its checkpoints

@@ -11,9 +11,11 @@
 // stream is synchronised it must be ordered after every launch so far.
 // The sweep of checkpointed frames is tracked apart: its forward and
 // backward chains own the frame's forward and backward checkpoint rows (a
-// sweep launch must follow every earlier launch of the frame, and the
-// previous sweep launch of its direction), and a chain that starts from
-// checkpoints must follow the sweep launches that wrote those rows.
+// sweep launch must follow every earlier launch of the frame other than the
+// pre-passes that write Gamma by start index, the writer of every block of
+// start indices its rows read, and the previous sweep launch of its
+// direction), and a chain that starts from checkpoints must follow the
+// sweep launches that wrote those rows.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -54,6 +56,10 @@ struct Last {
     int stream = -1, tick = 0;
 };
 std::vector<Last> g_last;   // per frame: the stream and tick of its last launch
+std::vector<Last> g_lastx;  // per frame: its last launch other than a Gamma-only pre-pass
+// writers of the blocks of start indices of each whole-frame Gamma table
+// (Gamma-only pre-pass lattices), by table
+std::map<const void *, std::map<int, Last>> g_gblock;
 Last g_any[kMaxStreams];    // per stream: its last launch
 // per frame and direction: the last sweep launch, and the writer of every
 // checkpoint row
@@ -85,8 +91,9 @@ bool readable(const void *p, size_t n) {
 }
 bool happened(const Last &l, const Clock &now) { return l.stream < 0 || now.t[l.stream] >= l.tick; }
 
-// One launch on st touching frames (all frames when all is set).
-void launch(hipStream_t st, const std::vector<int> &frames, bool all) {
+// One launch on st touching frames (all frames when all is set); returns
+// its stream and tick.
+Last launch(hipStream_t st, const std::vector<int> &frames, bool all, bool gamma_only = false) {
     SStream *x = S(st);
     for (int f : frames)
         if (f < 0 || f >= g_nframes) die("work item names a frame out of range");
@@ -100,12 +107,18 @@ void launch(hipStream_t st, const std::vector<int> &frames, bool all) {
     }
     x->vc.t[x->id] += 1;
     const Last me{x->id, x->vc.t[x->id]};
-    if (all)
+    if (all) {
         for (Last &l : g_last) l = me;
-    else
-        for (int f : frames) g_last[f] = me;
+        for (Last &l : g_lastx) l = me;
+    } else {
+        for (int f : frames) {
+            g_last[f] = me;
+            if (!gamma_only) g_lastx[f] = me;
+        }
+    }
     g_any[x->id] = me;
     ++g_launches;
+    return me;
 }
 std::vector<int> work_frames(const mapdec::Work *t, int n) {
     if (n && !in_range(t, sizeof(mapdec::Work) * n)) die("work table outside the workspace");
@@ -146,6 +159,8 @@ void stub_set_workspace(void *p, size_t bytes, size_t alloc, int nframes) {
     g_ws_alloc = alloc;
     g_nframes = nframes;
     g_last.assign(nframes, Last{});
+    g_lastx.assign(nframes, Last{});
+    g_gblock.clear();
     for (int dir = 0; dir < 2; ++dir) {
         g_sweep[dir].assign(nframes, Last{});
         g_ckrow[dir].assign(nframes, {});
@@ -293,7 +308,15 @@ hipError_t launch_pack(const FrameDesc *fd, const Work *t, int nb, hipStream_t s
 hipError_t launch_lattice(int, int, int, int, const FrameDesc *fd, const Work *t, int nb,
                           hipStream_t st) {
     check_fd(fd);
-    launch(st, work_frames(t, nb), false);
+    const std::vector<int> frames = work_frames(t, nb);
+    // a pre-pass writing only the whole-frame Gamma table (no R)
+    bool gamma_only = !frames.empty() && readable(fd, sizeof(FrameDesc));
+    for (int f : frames)
+        if (gamma_only && (!readable(fd + f, sizeof(FrameDesc)) || fd[f].R != nullptr))
+            gamma_only = false;
+    const Last me = launch(st, frames, false, gamma_only);
+    if (gamma_only)
+        for (int i = 0; i < nb; ++i) g_gblock[fd[t[i].frame].G][t[i].item / kLatticeLanes] = me;
     return hipSuccess;
 }
 hipError_t launch_gsum(int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
@@ -347,7 +370,22 @@ void chain_launch(hipStream_t st, const FrameDesc *fd, const int *fr, int nc, in
         const FrameDesc &d = fd[descs[k]];
         if (d.chain_mode != kChainSweep) die("sweep and other chains in one launch");
         const int f = frames[k];
-        if (!happened(g_last[f], x->vc)) die("sweep not ordered after the frame's earlier launches");
+        if (!happened(g_lastx[f], x->vc)) die("sweep not ordered after the frame's earlier launches");
+        // Gamma by start index: every block the part's rows read (n i0 - M
+        // .. n (i1 - 1) + M) written before it
+        auto gt = g_gblock.find(d.G);
+        if (gt != g_gblock.end() && d.i1 > d.i0) {
+            const int lo = std::max(0, d.n * d.i0 - d.M);
+            const int hi = std::min(d.rho, d.n * (d.i1 - 1) + d.M);
+            for (int b = lo / kLatticeLanes; b <= hi / kLatticeLanes; ++b) {
+                auto w = gt->second.find(b);
+                if (w == gt->second.end() || !happened(w->second, x->vc)) {
+                    fprintf(stderr, "plan_stub: frame %d rows [%d, %d): Gamma block %d %s\n", f,
+                            d.i0, d.i1, b, w == gt->second.end() ? "never written" : "written later");
+                    die("sweep part reads Gamma not written before it");
+                }
+            }
+        }
         for (int dir = 0; dir < 2; ++dir)
             if (dirs & (1 << dir))
                 if (!happened(g_sweep[dir][f], x->vc)) die("sweep part not ordered after the previous one");

@@ -5,7 +5,9 @@ g++ against a stub of the HIP runtime calls and kernel launchers
 reads every launch's work table and checks, with vector clocks over
 streams and events, that each launch is ordered after the previous launch
 of every frame it touches and that the caller's stream is joined with
-every forked stream; it aborts otherwise.  Eager plans of many frames run
+every forked stream; it aborts otherwise.  Sweep parts of checkpointed
+frames must also follow the writers of the Gamma blocks their rows read
+(the pre-pass runs in rounds beside them).  Eager plans of many frames run
 in frame slices (one stream each, compute-bound launches staggered slice
 by slice).  No kernel runs.
 """
@@ -50,6 +52,8 @@ def driver(tmp_path_factory):
     (2, 13, 0, 1),                     # sweep in parts whose first forward part is empty
     (2, 13, GRAD, 1),
     (8, 13, 0, 0),                     # decode only, sweep in parts
+    (4, 7, GRAD, 1),                   # Gamma pre-pass in rounds beside the sweep parts
+    (4, 7, 0, 1),
     (128, 0, GRAD, 1),                 # eager uniform batch in frame slices
     (128, 0, GRAD | SERIAL, 1),
     (60, 0, GRAD, 2),                  # with general-scheme frames
