@@ -1236,9 +1236,17 @@ struct mapdec_plan {
                 for (size_t k = first_op; k < ops.size(); ++k) pre_ops[j].push_back((int)k);
             }
             if (P.kind != kPassMain) continue;
-            // every launch of a main pass waits for the newest launch of each
-            // sweep direction up to the part after which its checkpoints
-            // exist (a part whose rows are empty for every frame has none)
+            // With the sweep in parts, every launch of a main pass waits for
+            // the newest launch of each sweep direction up to the part after
+            // which its checkpoints exist (a part whose rows are empty for
+            // every frame has none).  The group's alpha / beta rows are a
+            // resource of their own per frame (3 nf + f): the recomputation
+            // of the checkpoint segments reads only the pre-pass's Gamma and
+            // the checkpoints and writes only the rows, so with Gamma by start
+            // index (pre-pass rounds) it runs on stream 3 as soon as the
+            // previous group's APP and W have read them, beside that group's
+            // adjoint and this group's lattice; the APP and W launches take
+            // both resources.
             auto wait_sweep = [&]() {
                 if (!split) return;
                 int wf = -1, wb = -1;
@@ -1247,8 +1255,20 @@ struct mapdec_plan {
                     wb = std::max(wb, sweep_bwd[p]);
                 }
                 for (size_t k = first_op; k < ops.size(); ++k) {
-                    if (wf >= 0) ops[k].afters.push_back(wf);
-                    if (wb >= 0) ops[k].afters.push_back(wb);
+                    Op &o = ops[k];
+                    if (wf >= 0) o.afters.push_back(wf);
+                    if (wb >= 0) o.afters.push_back(wb);
+                    if (o.phase == kPhRechain && L.pre_rounds) {
+                        for (int &f : o.frames)
+                            if (f < nf) f += 3 * nf;
+                        o.stream = kForkStreams;
+                        for (const auto &v : pre_ops) o.afters.insert(o.afters.end(), v.begin(), v.end());
+                    } else if (o.phase == kPhApp || o.phase == kPhWgrad || o.phase == kPhChain ||
+                               o.phase == kPhRechain) {
+                        const size_t nfr = o.frames.size();
+                        for (size_t x = 0; x < nfr; ++x)
+                            if (o.frames[x] < nf) o.frames.push_back(3 * nf + o.frames[x]);
+                    }
                 }
             };
             if (!P.app_plain.empty()) {
@@ -1353,9 +1373,10 @@ struct mapdec_plan {
         }
         hipStream_t sx[NS] = {st};
         for (int x = 1; x < NS; ++x) sx[x] = side[x - 1];
-        // per resource (frame, then the sweep's forward and backward parts of
-        // every frame): event of its last launch
-        std::vector<int> last(3 * (size_t)L.nframes, 0);
+        // per resource (frame, the sweep's forward and backward parts of
+        // every frame, the rows of every frame's group): event of its last
+        // launch
+        std::vector<int> last(4 * (size_t)L.nframes, 0);
         int tail[NS];                         // per stream: event of its last launch
         int seen[NS][NS];                     // newest event of stream y that x waited for
         std::vector<int> ev_stream(ops.size() + 1, 0);

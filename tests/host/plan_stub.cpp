@@ -55,7 +55,10 @@ int g_nframes = 0;
 struct Last {
     int stream = -1, tick = 0;
 };
-std::vector<Last> g_last;   // per frame: the stream and tick of its last launch
+// Per frame: the stream and tick of its last launch touching the buffers
+// other than the group's alpha / beta rows (g_last), and the rows (g_rows).
+constexpr int kBufMain = 1, kBufRows = 2;
+std::vector<Last> g_last, g_rows;
 std::vector<Last> g_lastx;  // per frame: its last launch other than a Gamma-only pre-pass
 // writers of the blocks of start indices of each whole-frame Gamma table
 // (Gamma-only pre-pass lattices), by table
@@ -91,9 +94,10 @@ bool readable(const void *p, size_t n) {
 }
 bool happened(const Last &l, const Clock &now) { return l.stream < 0 || now.t[l.stream] >= l.tick; }
 
-// One launch on st touching frames (all frames when all is set); returns
-// its stream and tick.
-Last launch(hipStream_t st, const std::vector<int> &frames, bool all, bool gamma_only = false) {
+// One launch on st touching buffers bufs of frames (all frames and buffers
+// when all is set); returns its stream and tick.
+Last launch(hipStream_t st, const std::vector<int> &frames, bool all, bool gamma_only = false,
+            int bufs = kBufMain) {
     SStream *x = S(st);
     for (int f : frames)
         if (f < 0 || f >= g_nframes) die("work item names a frame out of range");
@@ -102,17 +106,23 @@ Last launch(hipStream_t st, const std::vector<int> &frames, bool all, bool gamma
         for (int y = 0; y < g_nstreams; ++y)
             if (!happened(g_any[y], now)) die("launch over all frames not ordered after every launch");
     } else {
-        for (int f : frames)
-            if (!happened(g_last[f], now)) die("launch not ordered after the last launch of its frame");
+        for (int f : frames) {
+            if ((bufs & kBufMain) && !happened(g_last[f], now))
+                die("launch not ordered after the last launch of its frame");
+            if ((bufs & kBufRows) && !happened(g_rows[f], now))
+                die("launch not ordered after the last launch on its frame's rows");
+        }
     }
     x->vc.t[x->id] += 1;
     const Last me{x->id, x->vc.t[x->id]};
     if (all) {
         for (Last &l : g_last) l = me;
+        for (Last &l : g_rows) l = me;
         for (Last &l : g_lastx) l = me;
     } else {
         for (int f : frames) {
-            g_last[f] = me;
+            if (bufs & kBufMain) g_last[f] = me;
+            if (bufs & kBufRows) g_rows[f] = me;
             if (!gamma_only) g_lastx[f] = me;
         }
     }
@@ -159,6 +169,7 @@ void stub_set_workspace(void *p, size_t bytes, size_t alloc, int nframes) {
     g_ws_alloc = alloc;
     g_nframes = nframes;
     g_last.assign(nframes, Last{});
+    g_rows.assign(nframes, Last{});
     g_lastx.assign(nframes, Last{});
     g_gblock.clear();
     for (int dir = 0; dir < 2; ++dir) {
@@ -330,22 +341,51 @@ hipError_t launch_gamma(int, int, const FrameDesc *fd, const Work *t, int nb, hi
     return hipSuccess;
 }
 namespace {
+// Whether Gamma by start index is tracked for d's table; if so, every block
+// that rows [i0, i1) read (n i0 - M .. n (i1 - 1) + M) must have been
+// written before now.
+bool gamma_blocks_checked(const FrameDesc &d, int f, const Clock &now, const char *who) {
+    auto gt = g_gblock.find(d.G);
+    if (gt == g_gblock.end()) return false;
+    if (d.i1 <= d.i0) return true;
+    const int lo = std::max(0, d.n * d.i0 - d.M);
+    const int hi = std::min(d.rho, d.n * (d.i1 - 1) + d.M);
+    for (int b = lo / kLatticeLanes; b <= hi / kLatticeLanes; ++b) {
+        auto w = gt->second.find(b);
+        if (w == gt->second.end() || !happened(w->second, now)) {
+            fprintf(stderr, "plan_stub: frame %d rows [%d, %d): Gamma block %d %s\n", f, d.i0, d.i1,
+                    b, w == gt->second.end() ? "never written" : "written later");
+            die(who);
+        }
+    }
+    return true;
+}
 // A chain launch: sweep chains (checkpoint rows) apart from the rest.
 void chain_launch(hipStream_t st, const FrameDesc *fd, const int *fr, int nc, int dirs) {
     const std::vector<int> frames = chain_frames(fd, fr, nc);
     const std::vector<int> descs = list_frames(fr, nc);
     if (frames.size() != descs.size() || frames.empty()) {   // not materialised
-        launch(st, frames, false);
+        launch(st, frames, false, false, kBufMain | kBufRows);
         return;
     }
     bool sweep = false;
     for (int d : descs) sweep |= fd[d].chain_mode == kChainSweep;
     if (!sweep) {
         SStream *x = S(st);
+        // segment recomputations (every descriptor of the launch, or none)
+        // write only the rows; with Gamma by start index tracked they need
+        // not follow the frame's other launches, only the writers of the
+        // Gamma blocks they read
+        bool sub = true, blocks = true;
         for (size_t k = 0; k < descs.size(); ++k) {
             const FrameDesc &d = fd[descs[k]];
-            if (d.chain_mode != kChainSub) continue;
+            if (d.chain_mode != kChainSub) {
+                sub = blocks = false;
+                continue;
+            }
             const int f = frames[k];
+            blocks &= gamma_blocks_checked(d, f, x->vc,
+                                           "segment chain reads Gamma not written before it");
             // forward row i0 and backward row i1 come from checkpoints
             if (d.i0 > 0) {
                 auto it = g_ckrow[0][f].find(d.i0);
@@ -362,7 +402,7 @@ void chain_launch(hipStream_t st, const FrameDesc *fd, const int *fr, int nc, in
                     die("segment chain not ordered after its backward checkpoint");
             }
         }
-        launch(st, frames, false);
+        launch(st, frames, false, false, sub && blocks ? kBufRows : kBufMain | kBufRows);
         return;
     }
     SStream *x = S(st);
@@ -371,21 +411,7 @@ void chain_launch(hipStream_t st, const FrameDesc *fd, const int *fr, int nc, in
         if (d.chain_mode != kChainSweep) die("sweep and other chains in one launch");
         const int f = frames[k];
         if (!happened(g_lastx[f], x->vc)) die("sweep not ordered after the frame's earlier launches");
-        // Gamma by start index: every block the part's rows read (n i0 - M
-        // .. n (i1 - 1) + M) written before it
-        auto gt = g_gblock.find(d.G);
-        if (gt != g_gblock.end() && d.i1 > d.i0) {
-            const int lo = std::max(0, d.n * d.i0 - d.M);
-            const int hi = std::min(d.rho, d.n * (d.i1 - 1) + d.M);
-            for (int b = lo / kLatticeLanes; b <= hi / kLatticeLanes; ++b) {
-                auto w = gt->second.find(b);
-                if (w == gt->second.end() || !happened(w->second, x->vc)) {
-                    fprintf(stderr, "plan_stub: frame %d rows [%d, %d): Gamma block %d %s\n", f,
-                            d.i0, d.i1, b, w == gt->second.end() ? "never written" : "written later");
-                    die("sweep part reads Gamma not written before it");
-                }
-            }
-        }
+        gamma_blocks_checked(d, f, x->vc, "sweep part reads Gamma not written before it");
         for (int dir = 0; dir < 2; ++dir)
             if (dirs & (1 << dir))
                 if (!happened(g_sweep[dir][f], x->vc)) die("sweep part not ordered after the previous one");
@@ -443,7 +469,7 @@ hipError_t launch_chain_ring(int, int shape, int, int waves, const FrameDesc *fd
 }
 hipError_t launch_app(int, const FrameDesc *fd, const Work *t, int nb, size_t, hipStream_t st) {
     check_fd(fd);
-    launch(st, work_frames(t, nb), false);
+    launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
     return hipSuccess;
 }
 hipError_t launch_app_tile(int fp64, int td, int, int nw, const FrameDesc *fd, const Work *t,
@@ -452,13 +478,13 @@ hipError_t launch_app_tile(int fp64, int td, int, int nw, const FrameDesc *fd, c
     if (td != 2 && td != 4 && td != 8) die("bad D tile");
     if (fp64 && td > 4) die("FP64 D tile above 4");
     if (nw < 1 || nw > kAppMaxWaves || lds > 160 * 1024) die("bad tiled-APP launch");
-    launch(st, work_frames(t, nb), false);
+    launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
     return hipSuccess;
 }
 hipError_t launch_app_scale(int mn, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
     if (mn < 0 || mn > kMaxMn) die("bad APP-scale launch");
-    launch(st, work_frames(t, nb), false);
+    launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
     return hipSuccess;
 }
 hipError_t launch_app_mfma(int mn, int qt, const FrameDesc *fd, const Work *t, int nb,
@@ -466,13 +492,13 @@ hipError_t launch_app_mfma(int mn, int qt, const FrameDesc *fd, const Work *t, i
     check_fd(fd);
     if (mn < 0 || mn > kMaxMn || qt < 1 || qt > 2 || lds > 160 * 1024)
         die("bad MFMA-APP launch");
-    launch(st, work_frames(t, nb), false);
+    launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
     return hipSuccess;
 }
 hipError_t launch_app_fin(int qt, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
     if (qt < 1 || qt > 2) die("bad APP-finish launch");
-    launch(st, work_frames(t, nb), false);
+    launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
     return hipSuccess;
 }
 size_t app_mfma_lds(int mn, int q) {
@@ -483,12 +509,12 @@ size_t app_mfma_lds(int mn, int q) {
 }
 hipError_t adj_f32_w(int, int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
-    launch(st, work_frames(t, nb), false);
+    launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
     return hipSuccess;
 }
 hipError_t adj_f64_w(int, int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
-    launch(st, work_frames(t, nb), false);
+    launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
     return hipSuccess;
 }
 hipError_t adj_f32_lattice(int, int, int, int, const FrameDesc *fd, const Work *t, int nb, size_t,

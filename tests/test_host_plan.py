@@ -7,7 +7,8 @@ streams and events, that each launch is ordered after the previous launch
 of every frame it touches and that the caller's stream is joined with
 every forked stream; it aborts otherwise.  Sweep parts of checkpointed
 frames must also follow the writers of the Gamma blocks their rows read
-(the pre-pass runs in rounds beside them).  Eager plans of many frames run
+(the pre-pass runs in rounds beside them), and segment recomputations,
+which touch only the group's rows, must follow the Gamma blocks they read.  Eager plans of many frames run
 in frame slices (one stream each, compute-bound launches staggered slice
 by slice).  No kernel runs.
 """
@@ -54,6 +55,7 @@ def driver(tmp_path_factory):
     (8, 13, 0, 0),                     # decode only, sweep in parts
     (4, 7, GRAD, 1),                   # Gamma pre-pass in rounds beside the sweep parts
     (4, 7, 0, 1),
+    (16, 100, GRAD, 1),                # one segment per group: its recomputation waits for Gamma
     (128, 0, GRAD, 1),                 # eager uniform batch in frame slices
     (128, 0, GRAD | SERIAL, 1),
     (60, 0, GRAD, 2),                  # with general-scheme frames
