@@ -88,31 +88,58 @@ __global__ __launch_bounds__(64) void k_wadj(const FrameDesc *__restrict__ fd,
         // beta_{i+1} over the wave's window (drifts sa - n i - mn ..
         // sa + 63 - n i + mn), split into (mantissa, exponent) once per value
         // and staged in LDS, where each lane reads its 2 mn + 1 neighbours
-        // (one wave: LDS operations stay in program order)
+        // (one wave: LDS operations stay in program order).  The loads of
+        // symbol i + 1 (its window, alpha, 1/Z) are issued before symbol i's
+        // products, so their latency overlaps them.
         constexpr int WIN = 64 + 2 * MN;
+        static_assert(WIN <= 128, "two window values per lane");
         __shared__ double bm[2][WIN];
         __shared__ int bx[2][WIN];
         const int lane = threadIdx.x;
         double acc[KW];
 #pragma unroll
         for (int k = 0; k < KW; ++k) acc[k] = 0.0;
+        // raw values of one symbol: window slots lane and lane + 64, alpha
+        // of the lane's drift state (addresses clamped into the rows)
+        double rb0 = 0.0, rb1 = 0.0, ra = 0.0, rz = 0.0;
+        int rze = 0;
+        auto fetch = [&](int i) {
+            const size_t rb = (size_t)(i + 1 - ib) * Mt + M;
+            const int base = sa - n * i - MN;
+            rb0 = B[rb + min(max(base + lane, -M), M)];
+            if (lane + 64 < WIN) rb1 = B[rb + min(max(base + lane + 64, -M), M)];
+            ra = A[(size_t)(i - ib) * Mt + M + min(max(s - n * i, -M), M)];
+            rz = Zi[i];
+            rze = Ze[i];
+        };
+        if (ilo <= ihi) fetch(ilo);
         for (int i = ilo; i <= ihi; ++i) {
             const int buf = (i - ilo) & 1;
             const int base = sa - n * i - MN;   // drift of window slot 0
-            for (int t = lane; t < WIN; t += 64) {
-                const int m = base + t;
-                const int cm = min(max(m, -M), M);
+            {
                 int e;
-                const double v = frexp(B[(size_t)(i + 1 - ib) * Mt + cm + M], &e);
-                bm[buf][t] = (m >= -M && m <= M) ? v : 0.0;
-                bx[buf][t] = e;
+                const int m = base + lane;
+                const double v = frexp(rb0, &e);
+                bm[buf][lane] = (m >= -M && m <= M) ? v : 0.0;
+                bx[buf][lane] = e;
+            }
+            if (lane + 64 < WIN) {
+                int e;
+                const int m = base + lane + 64;
+                const double v = frexp(rb1, &e);
+                bm[buf][lane + 64] = (m >= -M && m <= M) ? v : 0.0;
+                bx[buf][lane + 64] = e;
             }
             const int mp = s - n * i;
             const double in = (live && mp >= -M && mp <= M) ? 1.0 : 0.0;
-            const int mc = min(max(mp, -M), M);
             int ea;
-            const double av = frexp(A[(size_t)(i - ib) * Mt + mc + M], &ea) * Zi[i] * in;
-            const int ae = ea - Ze[i];
+            double av = frexp(ra, &ea) * rz * in;
+            int ae = ea - rze;
+            // this symbol's loads are used up before the next ones are issued
+            // (load counters drain in order: a later use of an older load
+            // would wait for the newer loads too)
+            asm volatile("" : "+v"(av), "+v"(ae) : : "memory");
+            if (i < ihi) fetch(i + 1);
             lds_wave_sync();
 #pragma unroll
             for (int k = 0; k < KW; ++k)
