@@ -94,6 +94,12 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
     const int MC = uni ? M : 0;
     const int s0 = uni ? f.s0 : Mt * i0;
     const int s1 = uni ? f.s1 : Mt * i1 - 1;
+    // columns the chain's rows read (its chunks load up to C - 1 steps
+    // more): loads outside them take 0, so a chain never depends on table
+    // columns beyond its own rows (a sweep part runs beside the pre-pass
+    // rounds that write the later columns)
+    const int ld_lo = min(max(s0, n * i0 - MC), s1);
+    const int ld_hi = max(min(s1, n * (i1 - 1) - MC + Mt - 1), ld_lo);
     const int C = f.ring_chunk, RING = f.ring_cols, mask = RING - 1;
     const int RPHYS = DUP ? RING + NT * SPL + 2 * MN : RING + 2 * MN;
     using R = double;                                  // metric rows: FP64 always
@@ -215,7 +221,7 @@ __device__ __forceinline__ void chain_ring_body(const FrameDesc &f, unsigned cha
 #pragma unroll
         for (int r = 0; r < PF; ++r) {
             const int s = base + col;
-            const int sc = min(max(s, s0), s1);   // the table holds [s0, s1]
+            const int sc = min(max(s, ld_lo), ld_hi);   // inside the table [s0, s1]
             const int kc = min(kk, Mn - 1);
             pre[r] = G[(size_t)kc * sp + (sc - s0)];
             pvalid |= (s == sc) ? (1u << r) : 0u;

@@ -183,3 +183,31 @@ def test_sweep_parts_eager_equal_serial(grad):
         got = outputs(False)
         for k, (g, w) in enumerate(zip(got, want)):
             assert torch.equal(g, w), f"eager run {rep}: output {k}"
+
+
+@pytest.mark.parametrize("grad", [False, True])
+def test_sweep_parts_on_a_stale_workspace(grad):
+    # The eager sweep parts run beside the rounds of the Gamma pre-pass, so
+    # a part must not depend on table columns beyond its own rows (the ring
+    # chains load whole chunks).  A workspace holding NaN patterns from
+    # earlier use (every byte 0xFF) gives the oracle's results, equal to
+    # the serial plan's bit for bit.
+    N = 150
+    M = wl.drift_limit(12 * N, 0.1)
+    frames = [wl.random_frame(70 + f, 64, 12, N, 0.1, 0.1, 0.0, 2, M, 8) for f in range(2)]
+    refs = [oracle.decode_frame(fr, grad=grad) for fr in frames]
+    outs = []
+    for serial in (False, True):
+        b = mapdec.batch_from_frames(frames, precision=mapdec.FP32, grad=grad, checkpoint_K=13)
+        b.ws.fill_(255)
+        p = b.plan(graph=False, serial=serial)
+        p.run()
+        torch.cuda.synchronize()
+        for f, ref in enumerate(refs):
+            _compare(b, f, ref["app"], ref["logp"], ref["dparams"] if grad else None,
+                     ref["dprior"] if grad else None, ORACLE_TOL[mapdec.FP32],
+                     f"{'serial' if serial else 'eager'} frame {f}")
+        outs.append([b.logp.cpu().clone()] + [a.cpu().clone() for a in b.apps])
+        p.close()
+    for k, (e, s) in enumerate(zip(*outs)):
+        assert torch.equal(e, s), f"output {k}"
