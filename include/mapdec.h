@@ -263,8 +263,16 @@ int mapdec_grad(const mapdec_frame *frames, int nframes, double *logp, double *d
  * stream k, every launch other than the chains also waiting for the same
  * launch of the slice before: the compute-bound phases then advance slice
  * by slice while each slice's chains (a latency-bound recursion) run
- * beside them.  Graph plans record every launch in order on one stream.
- * Results do not depend on the order.
+ * beside them.  With checkpointed frames (checkpoint_K > 0, no path
+ * thresholds, no frame slices) such a plan also runs the sweep that writes
+ * the checkpoints in 16 parts, its forward chains on one of those streams
+ * and its backward chains on another, while the groups of segments whose
+ * checkpoints exist already run on the others (the middle of the frames
+ * first); with Gamma by start index the pre-pass that computes it for the
+ * sweep runs in 16 rounds beside the parts.  Graph plans record every
+ * launch in order on one stream.  Results do not depend on the order: the
+ * parts carry the row-scale predictor from one to the next, so every
+ * schedule gives the same bits.
  */
 typedef struct mapdec_plan mapdec_plan;
 
