@@ -931,6 +931,7 @@ struct Op {
     int slice = -1;            // frame slice, or -1
     int after = -1;            // an earlier op this one also waits for, or -1
     std::vector<int> afters;   // more earlier ops it waits for (sweep parts)
+    bool rows_only = false;    // reads only the group's rows (the APP's scale pass)
     std::function<hipError_t(hipStream_t)> fn;
 };
 
@@ -1245,8 +1246,9 @@ struct mapdec_plan {
             // the checkpoints and writes only the rows, so with Gamma by start
             // index (pre-pass rounds) it runs on stream 3 as soon as the
             // previous group's APP and W have read them, beside that group's
-            // adjoint and this group's lattice; the APP and W launches take
-            // both resources.
+            // adjoint and this group's lattice, followed there by the APP's
+            // scale pass (rows in, the scale of the group's own symbols out);
+            // the other APP launches and W take both resources.
             auto wait_sweep = [&]() {
                 if (!split) return;
                 int wf = -1, wb = -1;
@@ -1263,6 +1265,13 @@ struct mapdec_plan {
                             if (f < nf) f += 3 * nf;
                         o.stream = kForkStreams;
                         for (const auto &v : pre_ops) o.afters.insert(o.afters.end(), v.begin(), v.end());
+                    } else if (o.rows_only && L.pre_rounds) {
+                        // the APP's scale pass reads the rows and writes the
+                        // scale of the group's own symbols only: it follows
+                        // the recomputation on stream 3
+                        for (int &f : o.frames)
+                            if (f < nf) f += 3 * nf;
+                        o.stream = kForkStreams;
                     } else if (o.phase == kPhApp || o.phase == kPhWgrad || o.phase == kPhChain ||
                                o.phase == kPhRechain) {
                         const size_t nfr = o.frames.size();
@@ -1280,10 +1289,12 @@ struct mapdec_plan {
             }
             for (auto &kv : P.app_scale) {
                 const int mn = kv.first;
+                const size_t a = ops.size();
                 add_work(kPhApp, true, kv.second, P.off_app_scale.at(kv.first),
                          [=](hipStream_t st, const Work *tab, int nb) {
                              return launch_app_scale(mn, fd, tab, nb, st);
                          });
+                for (size_t k = a; k < ops.size(); ++k) ops[k].rows_only = true;
             }
             deal();
             for (auto &kv : P.app_mfma) {

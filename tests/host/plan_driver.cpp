@@ -2,7 +2,8 @@
 // creation, runs, profiling, tuning and destruction on uneven and uniform
 // batches; the stub aborts on any out-of-range table, unknown handle or
 // launch not ordered after an earlier launch of one of its frames.
-//   plan_driver <frames> <checkpoint_K> <flags> <mode: 0 uneven, 1 uniform, 2 general>
+//   plan_driver <frames> <checkpoint_K> <flags> <mode: 0 uneven, 1 uniform, 2 general,
+//                                                3 uniform frames of the long-frame code>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -19,9 +20,10 @@ int stub_live_objects();
 int main(int argc, char **argv) {
     if (argc < 5) return 2;
     const int nf = atoi(argv[1]), K = atoi(argv[2]), flags = atoi(argv[3]);
-    // mode: 0 uneven batch, 1 uniform batch, 2 uneven with general-scheme frames
+    // mode: 0 uneven batch, 1 uniform batch, 2 uneven with general-scheme
+    // frames, 3 uniform batch of 64 codewords of 12 bits (the MFMA APP)
     const int mode = atoi(argv[4]);
-    const bool uniform = mode == 1;
+    const bool uniform = mode == 1 || mode == 3;
     std::mt19937 rng(1802);
     std::vector<mapdec_code *> codes;
     std::vector<mapdec_frame> fr(nf);
@@ -29,6 +31,13 @@ int main(int argc, char **argv) {
     for (int f = 0; f < nf; ++f) {
         int q = 16, n = 10, N = 200, mn = 6;
         double p = 0.05;
+        if (mode == 3) {
+            q = 64;
+            n = 12;
+            N = 150;
+            mn = 8;
+            p = 0.1;
+        }
         if (!uniform) {
             const int qs[3] = {2, 8, 16};
             q = qs[rng() % 3];
@@ -39,12 +48,13 @@ int main(int argc, char **argv) {
             mn = 3 + (int)(rng() % 5);
         }
         int M = (int)std::ceil(6.0 * std::sqrt(n * N * p / (1.0 - p))) + 2;
+        if (mode == 3) M = 85;
         if (M < mn) M = mn;
         std::vector<uint8_t> cb((size_t)q * n);
         for (int D = 0; D < q; ++D)
             for (int r = 0; r < n; ++r) cb[(size_t)D * n + r] = (uint8_t)((D >> (r % 5)) & 1);
-        for (int D = 0; D < q; ++D)   // distinct: the low bits of D in the first 5 positions
-            for (int r = 0; r < 5 && r < n; ++r) cb[(size_t)D * n + r] = (uint8_t)((D >> r) & 1);
+        for (int D = 0; D < q; ++D)   // distinct: the low bits of D in the first 6 positions
+            for (int r = 0; r < 6 && r < n; ++r) cb[(size_t)D * n + r] = (uint8_t)((D >> r) & 1);
         mapdec_code *c = nullptr;
         if (mode == 2 && f % 3 == 0) {
             // the general scheme: a codebook per symbol (the same words,

@@ -63,6 +63,9 @@ std::vector<Last> g_lastx;  // per frame: its last launch other than a Gamma-onl
 // writers of the blocks of start indices of each whole-frame Gamma table
 // (Gamma-only pre-pass lattices), by table
 std::map<const void *, std::map<int, Last>> g_gblock;
+// per frame: the writer of each symbol's APP scale (Zexp), which the APP's
+// scale pass writes for its group's symbols and the APP and W read
+std::vector<std::map<int, Last>> g_zexp;
 Last g_any[kMaxStreams];    // per stream: its last launch
 // per frame and direction: the last sweep launch, and the writer of every
 // checkpoint row
@@ -172,6 +175,7 @@ void stub_set_workspace(void *p, size_t bytes, size_t alloc, int nframes) {
     g_rows.assign(nframes, Last{});
     g_lastx.assign(nframes, Last{});
     g_gblock.clear();
+    g_zexp.assign(nframes, {});
     for (int dir = 0; dir < 2; ++dir) {
         g_sweep[dir].assign(nframes, Last{});
         g_ckrow[dir].assign(nframes, {});
@@ -341,6 +345,22 @@ hipError_t launch_gamma(int, int, const FrameDesc *fd, const Work *t, int nb, hi
     return hipSuccess;
 }
 namespace {
+// Launches that read the APP scale of their group's symbols ([i0, i1) of
+// each work item's frame descriptor) follow its writers.
+void zexp_read(hipStream_t st, const FrameDesc *fd, const Work *t, int nb) {
+    if (!nb || !readable(t, sizeof(Work) * nb)) return;
+    const Clock &now = S(st)->vc;
+    std::set<int> seen;
+    for (int k = 0; k < nb; ++k) {
+        const int f = t[k].frame;
+        if (!seen.insert(f).second) continue;
+        for (int i = fd[f].i0; i < fd[f].i1; ++i) {
+            auto w = g_zexp[f].find(i);
+            if (w != g_zexp[f].end() && !happened(w->second, now))
+                die("launch reads an APP scale not written before it");
+        }
+    }
+}
 // Whether Gamma by start index is tracked for d's table; if so, every block
 // that rows [i0, i1) read (n i0 - M .. n (i1 - 1) + M) must have been
 // written before now.
@@ -484,7 +504,10 @@ hipError_t launch_app_tile(int fp64, int td, int, int nw, const FrameDesc *fd, c
 hipError_t launch_app_scale(int mn, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
     if (mn < 0 || mn > kMaxMn) die("bad APP-scale launch");
-    launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
+    // reads the group's rows, writes the scale of the group's symbols
+    const Last me = launch(st, work_frames(t, nb), false, false, kBufRows);
+    if (nb && readable(t, sizeof(Work) * nb))
+        for (int k = 0; k < nb; ++k) g_zexp[t[k].frame][fd[t[k].frame].i0 + t[k].item] = me;
     return hipSuccess;
 }
 hipError_t launch_app_mfma(int mn, int qt, const FrameDesc *fd, const Work *t, int nb,
@@ -492,12 +515,14 @@ hipError_t launch_app_mfma(int mn, int qt, const FrameDesc *fd, const Work *t, i
     check_fd(fd);
     if (mn < 0 || mn > kMaxMn || qt < 1 || qt > 2 || lds > 160 * 1024)
         die("bad MFMA-APP launch");
+    zexp_read(st, fd, t, nb);
     launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
     return hipSuccess;
 }
 hipError_t launch_app_fin(int qt, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
     if (qt < 1 || qt > 2) die("bad APP-finish launch");
+    zexp_read(st, fd, t, nb);
     launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
     return hipSuccess;
 }
@@ -509,11 +534,13 @@ size_t app_mfma_lds(int mn, int q) {
 }
 hipError_t adj_f32_w(int, int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
+    zexp_read(st, fd, t, nb);
     launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
     return hipSuccess;
 }
 hipError_t adj_f64_w(int, int, int, const FrameDesc *fd, const Work *t, int nb, hipStream_t st) {
     check_fd(fd);
+    zexp_read(st, fd, t, nb);
     launch(st, work_frames(t, nb), false, false, kBufMain | kBufRows);
     return hipSuccess;
 }

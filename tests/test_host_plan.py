@@ -56,6 +56,8 @@ def driver(tmp_path_factory):
     (4, 7, GRAD, 1),                   # Gamma pre-pass in rounds beside the sweep parts
     (4, 7, 0, 1),
     (16, 100, GRAD, 1),                # one segment per group: its recomputation waits for Gamma
+    (2, 13, GRAD, 3),                  # the MFMA APP: its scale pass follows the recomputation
+    (2, 13, 0, 3),
     (128, 0, GRAD, 1),                 # eager uniform batch in frame slices
     (128, 0, GRAD | SERIAL, 1),
     (60, 0, GRAD, 2),                  # with general-scheme frames
