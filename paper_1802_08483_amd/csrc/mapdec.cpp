@@ -1237,10 +1237,10 @@ struct mapdec_plan {
                 for (size_t k = first_op; k < ops.size(); ++k) pre_ops[j].push_back((int)k);
             }
             if (P.kind != kPassMain) continue;
-            // With the sweep in parts, every launch of a main pass waits for
-            // the newest launch of each sweep direction up to the part after
-            // which its checkpoints exist (a part whose rows are empty for
-            // every frame has none).  The group's alpha / beta rows are a
+            // With the sweep in parts, every launch of a main pass but its
+            // lattice waits for the newest launch of each sweep direction up
+            // to the part after which its checkpoints exist (a part whose
+            // rows are empty for every frame has none).  The group's alpha / beta rows are a
             // resource of their own per frame (3 nf + f): the recomputation
             // of the checkpoint segments reads only the pre-pass's Gamma and
             // the checkpoints and writes only the rows, so with Gamma by start
@@ -1258,8 +1258,12 @@ struct mapdec_plan {
                 }
                 for (size_t k = first_op; k < ops.size(); ++k) {
                     Op &o = ops[k];
-                    if (wf >= 0) o.afters.push_back(wf);
-                    if (wb >= 0) o.afters.push_back(wb);
+                    // (the group's lattice reads no checkpoint: the first
+                    // group's runs while the sweep approaches the middle)
+                    if (o.phase != kPhLattice) {
+                        if (wf >= 0) o.afters.push_back(wf);
+                        if (wb >= 0) o.afters.push_back(wb);
+                    }
                     if (o.phase == kPhRechain && L.pre_rounds) {
                         for (int &f : o.frames)
                             if (f < nf) f += 3 * nf;
